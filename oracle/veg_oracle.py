@@ -1,0 +1,549 @@
+"""CPU oracle for the VEG splatting rasterizer.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
+may import this module.  It shares no code with the HIP library and never calls it.
+
+What the rasterizer computes (paper, section "Rendering of VEGs", Eq. 1): each Gaussian
+carries position mu, scale S, rotation R and a scalar v (plus an optional trainable weight w).
+The transfer function is applied first, per Gaussian: colour c = C(v), opacity
+A = O(v) * w, with C and O linearly interpolated between the table's control points.
+The 3D covariance R S S^T R^T is projected to a 2D screen covariance with Zwicker's EWA
+linearisation; each pixel evaluates the 2D Gaussian at its centre and composites the
+Gaussians front to back, C = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j).  Tiling and
+sorting only make this faster, so the oracle computes the definition by brute force.
+
+Three parts:
+
+* O1 ``footprint_f32`` / ``key_list`` -- the integer decisions of the tiled renderer
+  (cull, depth key, 16x16 tile rectangle, tile count, the sorted (tile, depth, index) key
+  list and per-tile ranges).  A float decides each of these integers, so this part takes
+  the decisions in the kernel's precision: float32 for covariance and extent, float64 for
+  the projected centre, each operation rounded in the order stated next to the code (no
+  fused multiply-add).  exp and log here are float32 functions built from Cody-Waite range
+  reduction and truncated series (``exp32``, ``log32``).
+* O2 ``project_f64`` / ``render_pixels`` -- float64 brute force: every kept Gaussian is
+  evaluated at every requested pixel, in O1's depth order, with no tiles.  It also
+  returns per-pixel decision-margin flags (pixels where an alpha-skip or a stop test lies
+  within rounding distance of its threshold, so float32 and float64 may legitimately
+  decide differently).
+* O3 ``gradients`` -- the gradient of a linear functional of O2's image, by torch
+  autograd in float64 on the CPU.
+
+Readings where the paper is silent (tile size, thresholds, footprint rule, low-pass,
+guard band, near plane, stop semantics, knot derivative) follow the renderer options:
+alpha clamp 0.99, skip alpha < 1/255, stop once T < 1e-4 after blending the Gaussian that
+crossed it, low-pass 0.3 px^2, guard 1.3, near 0.2.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+__all__ = [
+    "TILE", "QNORM2_MIN", "exp32", "log32", "footprint_f32", "key_list", "project_f64",
+    "render_pixels", "render_image", "gradients", "quat_to_rot_f64", "OracleProjection",
+    "depth_order", "frame_pairs",
+]
+
+TILE = 16
+QNORM2_MIN = np.float32(1e-24)   # |q|^2 below this (or non-finite) culls the Gaussian
+
+_f = np.float32
+_LOG2E = _f(float.fromhex("0x1.715476p+0"))
+_LN2_HI = _f(0.693359375)                        # few significant bits: k*_LN2_HI is exact
+_LN2_LO = _f(float.fromhex("-0x1.bd0106p-13"))   # ln2 - _LN2_HI
+_SQRT2 = _f(float.fromhex("0x1.6a09e6p+0"))
+_EXP_HI = _f(88.0)
+_EXP_LO = _f(-87.0)
+
+
+# ---------------------------------------------------------------------------------------
+# O1: float32 exp / log (Cody & Waite range reduction + truncated series)
+# ---------------------------------------------------------------------------------------
+
+def exp32(x):
+    """exp(x) in float32.  x = k ln2 + r with k = floor(x log2e + 1/2) and the reduction
+    done in two parts (Cody & Waite); exp(r) by its Taylor series up to r^7 (Horner, with
+    coefficients 1/n! rounded to float32); the result scaled by 2^k exactly.
+    Domain clamps: x >= 88 gives +inf, x < -87 gives 0 (no subnormal results)."""
+    x = np.asarray(x, dtype=np.float32)
+    k = np.floor(x * _LOG2E + _f(0.5)).astype(np.float32)
+    r = (x - k * _LN2_HI) - k * _LN2_LO
+    p = _f(1.0) / _f(5040.0)
+    for fac in (720.0, 120.0, 24.0, 6.0, 2.0, 1.0, 1.0):
+        p = p * r + _f(1.0) / _f(fac)
+    ki = np.clip(k, -126, 127).astype(np.int32)
+    scale = ((ki + 127).astype(np.uint32) << np.uint32(23)).view(np.float32)
+    out = (p * scale).astype(np.float32)
+    out = np.where(x >= _EXP_HI, _f(np.inf), out)
+    out = np.where(x < _EXP_LO, _f(0.0), out)
+    return out.astype(np.float32)
+
+
+def log32(x):
+    """log(x) in float32 for positive normal x.  x = m 2^e with m in [sqrt(1/2), sqrt(2));
+    log m = 2 atanh(u), u = (m-1)/(m+1), by the odd series up to u^9 (Horner in u^2,
+    coefficients 1/(2j+1) rounded to float32); log x = e*ln2_hi + (e*ln2_lo + log m)."""
+    x = np.asarray(x, dtype=np.float32)
+    bits = x.view(np.uint32)
+    e = (bits >> np.uint32(23)).astype(np.int32) - 127
+    m = ((bits & np.uint32(0x7FFFFF)) | np.uint32(0x3F800000)).view(np.float32)
+    big = m > _SQRT2
+    m = np.where(big, m * _f(0.5), m).astype(np.float32)
+    e = np.where(big, e + 1, e)
+    u = (m - _f(1.0)) / (m + _f(1.0))
+    u2 = u * u
+    p = _f(1.0) / _f(9.0)
+    for d in (7.0, 5.0, 3.0):
+        p = p * u2 + _f(1.0) / _f(d)
+    s = p * u2
+    t = u + u * s
+    logm = t + t
+    ef = e.astype(np.float32)
+    return (ef * _LN2_HI + (ef * _LN2_LO + logm)).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------------------
+# O1: footprint in the kernel's precision
+# ---------------------------------------------------------------------------------------
+
+@dataclass
+class Footprint:
+    keep: np.ndarray        # [n] bool
+    depth: np.ndarray       # [n] float32 camera-space z (computed for every Gaussian)
+    depth_bits: np.ndarray  # [n] uint32
+    rect: np.ndarray        # [n,4] int32 tile rectangle (x0, y0, x1, y1), inclusive
+    count: np.ndarray       # [n] int64 tiles covered (0 when culled)
+    mx: np.ndarray          # [n] float64 projected centre
+    my: np.ndarray
+    ex: np.ndarray          # [n] float32 half extents of the alpha >= alpha_min ellipse
+    ey: np.ndarray
+
+
+def _finite_rows(*arrs):
+    ok = None
+    for a in arrs:
+        if a is None:
+            continue
+        a2 = a.reshape(a.shape[0], -1)
+        r = np.isfinite(a2).all(axis=1)
+        ok = r if ok is None else ok & r
+    return ok
+
+
+def footprint_f32(g, cam, lut, opts) -> Footprint:
+    """Cull, depth key and tile rectangle per Gaussian, in the kernel's precision.
+
+    Order of operations (each line rounds once, no fused multiply-add):
+      t     = ((V0 mu_x + V1 mu_y) + V2 mu_z) + V3 per row, float64
+      depth = float32(t_z); cull unless depth > near
+      xn = t_x / t_z, yn = t_y / t_z, mx = fx xn + cx, my = fy yn + cy, float64
+      TF:   vc = clamp(v,0,1); t = vc (K-1); i = min(floor t, K-2); f = t - i;
+            X = L[i] (1-f) + L[i+1] f; A = O w
+      cull unless A >= alpha_min, unless |q|^2 >= 1e-24
+      q normalised by 1/sqrt(|q|^2); R(q); s = exp32(log s)
+      Q = Vr R; P = Q diag(s); J from float32 depth and clamped float32 xn, yn;
+      G = J P; S = G G^T + lowpass I; det = S00 S11 - S01^2 (cull unless > 0)
+      tau = 2 log32(A / alpha_min); ex = sqrt(tau S00), ey = sqrt(tau S11)
+      pixel range x in [ceil(mx - ex - 0.5), floor(mx + ex - 0.5)] (float64), clipped to the
+      image; tile rectangle = pixel range // 16; count = its area.
+    """
+    f32 = np.float32
+    n = g.means.shape[0]
+    V = np.asarray(cam.view, np.float32).reshape(3, 4)
+    Vd = V.astype(np.float64)
+    mu = g.means.astype(np.float64)
+    t = [((Vd[r, 0] * mu[:, 0] + Vd[r, 1] * mu[:, 1]) + Vd[r, 2] * mu[:, 2]) + Vd[r, 3] for r in range(3)]
+    tx, ty, tz = t
+    with np.errstate(all="ignore"):
+        depth = tz.astype(np.float32)
+        fx, fy, cx, cy = (f32(cam.fx), f32(cam.fy), f32(cam.cx), f32(cam.cy))
+        W, H = int(cam.width), int(cam.height)
+        xn = tx / tz
+        yn = ty / tz
+        mx = float(fx) * xn + float(cx)
+        my = float(fy) * yn + float(cy)
+
+        finite = _finite_rows(g.means, g.log_scales, g.quats, g.scalars[:, None],
+                              None if g.weights is None else g.weights[:, None])
+        # transfer function
+        K = lut.shape[0]
+        v = g.scalars.astype(np.float32)
+        v = np.where(np.isfinite(v), v, f32(0))
+        vc = np.where(v < f32(0), f32(0), np.where(v > f32(1), f32(1), v)).astype(np.float32)
+        tpos = vc * f32(K - 1)
+        i = np.minimum(np.floor(tpos).astype(np.int64), K - 2)
+        fr = tpos - i.astype(np.float32)
+        om = f32(1) - fr
+        O = lut[i, 3] * om + lut[i + 1, 3] * fr
+        A = O if g.weights is None else O * g.weights.astype(np.float32)
+
+        q = g.quats.astype(np.float32)
+        n2 = ((q[:, 0] * q[:, 0] + q[:, 1] * q[:, 1]) + q[:, 2] * q[:, 2]) + q[:, 3] * q[:, 3]
+        inv = f32(1) / np.sqrt(n2)
+        w_, x_, y_, z_ = (q[:, 0] * inv, q[:, 1] * inv, q[:, 2] * inv, q[:, 3] * inv)
+        two = f32(2)
+        one = f32(1)
+        R = np.empty((n, 3, 3), np.float32)
+        R[:, 0, 0] = one - two * (y_ * y_ + z_ * z_)
+        R[:, 0, 1] = two * (x_ * y_ - w_ * z_)
+        R[:, 0, 2] = two * (x_ * z_ + w_ * y_)
+        R[:, 1, 0] = two * (x_ * y_ + w_ * z_)
+        R[:, 1, 1] = one - two * (x_ * x_ + z_ * z_)
+        R[:, 1, 2] = two * (y_ * z_ - w_ * x_)
+        R[:, 2, 0] = two * (x_ * z_ - w_ * y_)
+        R[:, 2, 1] = two * (y_ * z_ + w_ * x_)
+        R[:, 2, 2] = one - two * (x_ * x_ + y_ * y_)
+        s = exp32(g.log_scales.astype(np.float32))
+
+        Q = np.empty((n, 3, 3), np.float32)
+        for j in range(3):
+            for k in range(3):
+                Q[:, j, k] = (V[j, 0] * R[:, 0, k] + V[j, 1] * R[:, 1, k]) + V[j, 2] * R[:, 2, k]
+        P = Q * s[:, None, :]
+
+        limx = f32(opts["guard"]) * ((f32(0.5) * f32(W)) / fx)
+        limy = f32(opts["guard"]) * ((f32(0.5) * f32(H)) / fy)
+        xnf = xn.astype(np.float32)
+        ynf = yn.astype(np.float32)
+        xc = np.minimum(np.maximum(xnf, -limx), limx)
+        yc = np.minimum(np.maximum(ynf, -limy), limy)
+        J00 = fx / depth
+        J02 = -(fx * xc) / depth
+        J11 = fy / depth
+        J12 = -(fy * yc) / depth
+        G0 = J00[:, None] * P[:, 0, :] + J02[:, None] * P[:, 2, :]
+        G1 = J11[:, None] * P[:, 1, :] + J12[:, None] * P[:, 2, :]
+        lp = f32(opts["lowpass"])
+        S00 = ((G0[:, 0] * G0[:, 0] + G0[:, 1] * G0[:, 1]) + G0[:, 2] * G0[:, 2]) + lp
+        S01 = (G0[:, 0] * G1[:, 0] + G0[:, 1] * G1[:, 1]) + G0[:, 2] * G1[:, 2]
+        S11 = ((G1[:, 0] * G1[:, 0] + G1[:, 1] * G1[:, 1]) + G1[:, 2] * G1[:, 2]) + lp
+        det = S00 * S11 - S01 * S01
+
+        amin = f32(opts["alpha_min"])
+        keep = finite & (depth > f32(opts["near_z"])) & (A >= amin) & (n2 >= QNORM2_MIN) & (det > f32(0))
+        ratio = np.where(keep, A / amin, f32(1))
+        tau = two * log32(ratio)
+        ex = np.sqrt(tau * S00).astype(np.float32)
+        ey = np.sqrt(tau * S11).astype(np.float32)
+        xlo = np.ceil((mx - ex.astype(np.float64)) - 0.5)
+        xhi = np.floor((mx + ex.astype(np.float64)) - 0.5)
+        ylo = np.ceil((my - ey.astype(np.float64)) - 0.5)
+        yhi = np.floor((my + ey.astype(np.float64)) - 0.5)
+        xlo = np.maximum(xlo, 0.0)
+        ylo = np.maximum(ylo, 0.0)
+        xhi = np.minimum(xhi, float(W - 1))
+        yhi = np.minimum(yhi, float(H - 1))
+        keep = keep & (xlo <= xhi) & (ylo <= yhi)
+    rect = np.zeros((n, 4), np.int32)
+    kk = keep
+    rect[kk, 0] = xlo[kk].astype(np.int64) // TILE
+    rect[kk, 1] = ylo[kk].astype(np.int64) // TILE
+    rect[kk, 2] = xhi[kk].astype(np.int64) // TILE
+    rect[kk, 3] = yhi[kk].astype(np.int64) // TILE
+    count = np.where(kk, (rect[:, 2] - rect[:, 0] + 1).astype(np.int64) * (rect[:, 3] - rect[:, 1] + 1), 0)
+    return Footprint(keep=keep, depth=depth, depth_bits=depth.view(np.uint32).copy(), rect=rect,
+                     count=count, mx=mx, my=my, ex=ex, ey=ey)
+
+
+def tiles_of(cam):
+    return (cam.width + TILE - 1) // TILE, (cam.height + TILE - 1) // TILE
+
+
+def key_list(fps, cams):
+    """Sorted key list over several frames.
+
+    ``fps[f]`` is frame f's Footprint (all frames over the same n Gaussians), ``cams[f]``
+    its camera.  Global tile id = tile_base[f] + ty * tiles_x + tx with tile_base the
+    prefix sum of the frames' tile counts; pair id = f * n + i.  Entries are sorted by
+    (global tile, depth bits, pair id).  Returns (tile_ids, depth_bits, pair_ids) of the
+    sorted list and ranges[total_tiles, 2] = [start, end)."""
+    n = fps[0].keep.shape[0]
+    tiles, depths, pairs = [], [], []
+    tile_base = 0
+    bases = []
+    for f, (fp, cam) in enumerate(zip(fps, cams)):
+        tx_n, ty_n = tiles_of(cam)
+        bases.append(tile_base)
+        idx = np.nonzero(fp.count > 0)[0]
+        cnt = fp.count[idx]
+        rep = np.repeat(idx, cnt)
+        start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        local = np.arange(rep.shape[0], dtype=np.int64) - start
+        r = fp.rect[rep]
+        wdt = (r[:, 2] - r[:, 0] + 1).astype(np.int64)
+        txs = r[:, 0] + local % wdt
+        tys = r[:, 1] + local // wdt
+        tiles.append(tile_base + tys * tx_n + txs)
+        depths.append(fp.depth_bits[rep])
+        pairs.append(f * n + rep)
+        tile_base += tx_n * ty_n
+    tiles = np.concatenate(tiles) if tiles else np.zeros(0, np.int64)
+    depths = np.concatenate(depths) if depths else np.zeros(0, np.uint32)
+    pairs = np.concatenate(pairs) if pairs else np.zeros(0, np.int64)
+    order = np.lexsort((pairs, depths, tiles))
+    tiles, depths, pairs = tiles[order], depths[order], pairs[order]
+    ranges = np.zeros((tile_base, 2), np.int64)
+    if tiles.shape[0]:
+        starts = np.searchsorted(tiles, np.arange(tile_base), side="left")
+        ends = np.searchsorted(tiles, np.arange(tile_base), side="right")
+        ranges[:, 0] = np.where(ends > starts, starts, 0)
+        ranges[:, 1] = np.where(ends > starts, ends, 0)
+    return tiles, depths, pairs, ranges, np.asarray(bases, np.int64)
+
+
+def frame_pairs(n, n_frames):
+    return n * n_frames
+
+
+def depth_order(fp: Footprint, kept: np.ndarray) -> np.ndarray:
+    """Indices of ``kept`` Gaussians ordered front to back by (float32 depth bits, index)."""
+    idx = np.nonzero(kept)[0]
+    return idx[np.lexsort((idx, fp.depth_bits[idx]))]
+
+
+# ---------------------------------------------------------------------------------------
+# O2: float64 brute force
+# ---------------------------------------------------------------------------------------
+
+def quat_to_rot_f64(q):
+    """Rotation matrix of unit quaternions (w, x, y, z), [n,4] -> [n,3,3] (torch)."""
+    w, x, y, z = q.unbind(-1)
+    return torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1),
+    ], -2)
+
+
+@dataclass
+class OracleProjection:
+    mean2d: torch.Tensor   # [n,2] pixel coordinates of the projected centre
+    conic: torch.Tensor    # [n,3] (a, b, c) of the inverse 2D covariance [[a,b],[b,c]]
+    cov2d: torch.Tensor    # [n,3] (S00, S01, S11)
+    rgb: torch.Tensor      # [n,3] C(v)
+    A: torch.Tensor        # [n]   O(v) * w
+    depth: torch.Tensor    # [n]   camera-space z
+    kept: np.ndarray       # [n]   bool (float64 decisions)
+
+
+def _t64(a):
+    if isinstance(a, torch.Tensor):
+        return a.to(torch.float64)
+    return torch.as_tensor(np.asarray(a, np.float64))
+
+
+def project_f64(means, log_scales, quats, scalars, weights, cam, lut, opts) -> OracleProjection:
+    """Per-Gaussian quantities in float64 (torch, differentiable).
+
+    TF first (paper: colour and opacity from the transfer function before rasterizing;
+    alpha = O(v) w; linear interpolation between control points), then the 3D covariance
+    Sigma = R S S^T R^T, then Zwicker's EWA projection Sigma' = J W Sigma W^T J^T + lowpass I
+    with J the Jacobian of the pinhole map at the camera-space centre (its x/z, y/z clamped
+    to the guard band), conic = Sigma'^-1.
+    """
+    means, log_scales, quats, scalars = map(_t64, (means, log_scales, quats, scalars))
+    weights = None if weights is None else _t64(weights)
+    lut = _t64(lut)
+    V = _t64(np.asarray(cam.view, np.float32)).reshape(3, 4)
+    Wr, b = V[:, :3], V[:, 3]
+    fx, fy, cx, cy = (float(np.float32(cam.fx)), float(np.float32(cam.fy)),
+                      float(np.float32(cam.cx)), float(np.float32(cam.cy)))
+    t = means @ Wr.T + b
+    tx, ty, tz = t.unbind(-1)
+
+    K = lut.shape[0]
+    vc = scalars.clamp(0.0, 1.0)
+    tpos = vc * (K - 1)
+    with torch.no_grad():
+        i = torch.floor(tpos).clamp(max=K - 2).long()
+    fr = (tpos - i.to(tpos.dtype))[:, None]
+    rgba = lut[i] * (1 - fr) + lut[i + 1] * fr
+    rgb = rgba[:, :3]
+    A = rgba[:, 3] if weights is None else rgba[:, 3] * weights
+
+    qn2 = (quats * quats).sum(-1)
+    qhat = quats / torch.sqrt(qn2)[:, None]
+    R = quat_to_rot_f64(qhat)
+    s2 = torch.exp(2 * log_scales)
+    Sigma = (R * s2[:, None, :]) @ R.transpose(-1, -2)
+    Sigma_c = Wr @ Sigma @ Wr.T
+
+    W_img, H_img = int(cam.width), int(cam.height)
+    limx = float(opts["guard"]) * (0.5 * W_img / fx)
+    limy = float(opts["guard"]) * (0.5 * H_img / fy)
+    xn, yn = tx / tz, ty / tz
+    xc, yc = xn.clamp(-limx, limx), yn.clamp(-limy, limy)
+    zero = torch.zeros_like(tz)
+    J = torch.stack([torch.stack([fx / tz, zero, -fx * xc / tz], -1),
+                     torch.stack([zero, fy / tz, -fy * yc / tz], -1)], -2)
+    S2 = J @ Sigma_c @ J.transpose(-1, -2) + float(opts["lowpass"]) * torch.eye(2, dtype=torch.float64)
+    S00, S01, S11 = S2[:, 0, 0], S2[:, 0, 1], S2[:, 1, 1]
+    det = S00 * S11 - S01 * S01
+    conic = torch.stack([S11 / det, -S01 / det, S00 / det], -1)
+    mean2d = torch.stack([fx * xn + cx, fy * yn + cy], -1)
+
+    with torch.no_grad():
+        def fin(x):
+            return torch.isfinite(x.reshape(x.shape[0], -1)).all(1)
+        ok = fin(means) & fin(log_scales) & fin(quats) & torch.isfinite(scalars)
+        if weights is not None:
+            ok &= torch.isfinite(weights)
+        amin = float(np.float32(opts["alpha_min"]))
+        ok &= (tz > float(np.float32(opts["near_z"]))) & (A >= amin) & (qn2 >= float(QNORM2_MIN)) & (det > 0)
+        ok &= torch.isfinite(conic).all(1) & torch.isfinite(mean2d).all(1)
+    return OracleProjection(mean2d=mean2d, conic=conic, cov2d=torch.stack([S00, S01, S11], -1),
+                            rgb=rgb, A=A, depth=tz, kept=ok.numpy().copy())
+
+
+@dataclass
+class PixelResult:
+    color: torch.Tensor      # [P,3] C + T bg
+    T: torch.Tensor          # [P]   final transmittance
+    last: np.ndarray         # [P]   position in ``order`` of the last blended Gaussian, -1 if none
+    n_eval: np.ndarray       # [P]   Gaussians visited up to the stop (brute-force count)
+    flag: np.ndarray         # [P]   image decision-margin flag
+    flag_grad: np.ndarray    # [P]   additional gradient flag (alpha within margin of the clamp)
+
+
+def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray, opts,
+                  bg=(0.0, 0.0, 0.0), batch: int = 0, skip_margin=1e-4, stop_margin=1e-3,
+                  clamp_margin=1e-5, t_min: Optional[float] = None) -> PixelResult:
+    """Front-to-back compositing (Eq. 1) at pixel centres (x+0.5, y+0.5), brute force.
+
+    For each pixel and each Gaussian of ``order`` (front to back):
+      sigma = 1/2 d^T conic d with d = p - mean2d; a = A exp(-sigma);
+      a < alpha_min: skipped; otherwise alpha = min(alpha_clamp, a), C += c alpha T,
+      T *= 1 - alpha, and if T < t_min the pixel stops (the Gaussian that crossed the
+      threshold is blended).  Output C + T bg.
+    """
+    aclamp = float(np.float32(opts["alpha_clamp"]))
+    amin = float(np.float32(opts["alpha_min"]))
+    tmin = float(np.float32(opts["t_min"] if t_min is None else t_min))
+    order_t = torch.as_tensor(np.asarray(order, np.int64))
+    mu = proj.mean2d[order_t]
+    con = proj.conic[order_t]
+    rgb = proj.rgb[order_t]
+    A = proj.A[order_t]
+    M = int(order_t.shape[0])
+    P = int(pixels.shape[0])
+    bgt = torch.as_tensor(np.asarray(bg, np.float64))
+    if batch <= 0:
+        batch = max(1, min(P, (1 << 23) // max(M, 1)))
+    cols, Ts, lasts, nevs, flags, gflags = [], [], [], [], [], []
+    for s in range(0, P, batch):
+        pix = torch.as_tensor(np.asarray(pixels[s:s + batch], np.float64))
+        if M == 0:
+            cols.append(bgt.expand(pix.shape[0], 3).clone())
+            Ts.append(torch.ones(pix.shape[0], dtype=torch.float64))
+            lasts.append(np.full(pix.shape[0], -1))
+            nevs.append(np.zeros(pix.shape[0], np.int64))
+            flags.append(np.zeros(pix.shape[0], bool))
+            gflags.append(np.zeros(pix.shape[0], bool))
+            continue
+        dx = (pix[:, 0:1] + 0.5) - mu[None, :, 0]
+        dy = (pix[:, 1:2] + 0.5) - mu[None, :, 1]
+        sigma = 0.5 * (con[None, :, 0] * dx * dx + 2.0 * con[None, :, 1] * dx * dy + con[None, :, 2] * dy * dy)
+        a = A[None, :] * torch.exp(-sigma)
+        blend = a >= amin
+        alpha = torch.where(blend, torch.where(a < aclamp, a, torch.full_like(a, aclamp)), torch.zeros_like(a))
+        T_incl = torch.cumprod(1.0 - alpha, dim=1)
+        with torch.no_grad():
+            stop = T_incl < tmin
+            has_stop = stop.any(1)
+            k = torch.where(has_stop, stop.to(torch.int8).argmax(1), torch.full_like(has_stop, M - 1, dtype=torch.int64))
+            ar = torch.arange(M)[None, :]
+            upto = ar <= k[:, None]
+        T_excl = torch.cat([torch.ones_like(T_incl[:, :1]), T_incl[:, :-1]], dim=1)
+        wgt = alpha * T_excl * upto.to(alpha.dtype)
+        C = wgt @ rgb
+        T_fin = T_incl.gather(1, k[:, None])[:, 0]
+        cols.append(C + T_fin[:, None] * bgt[None, :])
+        Ts.append(T_fin)
+        with torch.no_grad():
+            bl = blend & upto
+            lastpos = torch.where(bl.any(1), (bl.to(torch.int64) * (ar + 1)).max(1).values - 1, torch.full_like(k, -1))
+            lasts.append(lastpos.numpy())
+            nevs.append((k + 1).numpy())
+            ad = a.detach()
+            near_skip = ((ad - amin).abs() < skip_margin * amin) & upto
+            near_stop = ((T_incl.detach() - tmin).abs() < stop_margin * tmin) & bl
+            flags.append((near_skip.any(1) | near_stop.any(1)).numpy())
+            near_clamp = ((ad - aclamp).abs() < clamp_margin) & bl
+            gflags.append(near_clamp.any(1).numpy())
+    return PixelResult(color=torch.cat(cols, 0), T=torch.cat(Ts, 0), last=np.concatenate(lasts),
+                       n_eval=np.concatenate(nevs), flag=np.concatenate(flags),
+                       flag_grad=np.concatenate(gflags))
+
+
+def render_image(g, cam, lut, opts, pixels=None, bg=None, t_min=None, **kw):
+    """Convenience: O1 depth order + O2 for one frame.  Returns (PixelResult, proj, order, fp)."""
+    fp = footprint_f32(g, cam, lut, opts)
+    proj = project_f64(g.means, g.log_scales, g.quats, g.scalars, g.weights, cam, lut, opts)
+    order = depth_order(fp, proj.kept)
+    if pixels is None:
+        ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+        pixels = np.stack([xs.reshape(-1), ys.reshape(-1)], 1)
+    bg = opts.get("bg", (0.0, 0.0, 0.0)) if bg is None else bg
+    res = render_pixels(proj, order, pixels, opts, bg=bg, t_min=t_min, **kw)
+    return res, proj, order, fp
+
+
+# ---------------------------------------------------------------------------------------
+# O3: gradients by autograd through O2
+# ---------------------------------------------------------------------------------------
+
+@dataclass
+class OracleGrads:
+    d_means: np.ndarray
+    d_log_scales: np.ndarray
+    d_quats: np.ndarray
+    d_scalars: np.ndarray
+    d_weights: Optional[np.ndarray]
+    # per-Gaussian screen-space gradients (the blend adjoint's output)
+    d_mean2d: np.ndarray
+    d_conic: np.ndarray
+    d_rgb: np.ndarray
+    d_A: np.ndarray
+    loss: float
+
+
+def gradients(g, cam, lut, opts, d_color, pixels=None, bg=None, batch: int = 0) -> OracleGrads:
+    """Gradient of L = sum_p sum_ch d_color[p,ch] * image[p,ch] w.r.t. every Gaussian
+    parameter (float64 autograd through ``project_f64`` and ``render_pixels``).
+
+    The screen-space gradients are taken w.r.t. mean2d, the conic (a, b, c) as it enters
+    sigma = 1/2 (a dx^2 + 2 b dx dy + c dy^2), rgb and A."""
+    fp = footprint_f32(g, cam, lut, opts)
+    leaves = [torch.tensor(np.asarray(x, np.float64), requires_grad=True)
+              for x in (g.means, g.log_scales, g.quats, g.scalars)]
+    w = None if g.weights is None else torch.tensor(np.asarray(g.weights, np.float64), requires_grad=True)
+    proj = project_f64(*leaves, w, cam, lut, opts)
+    inter = [proj.mean2d, proj.conic, proj.rgb, proj.A]
+    for t in inter:
+        t.retain_grad()
+    order = depth_order(fp, proj.kept)
+    if pixels is None:
+        ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+        pixels = np.stack([xs.reshape(-1), ys.reshape(-1)], 1)
+    bg = opts.get("bg", (0.0, 0.0, 0.0)) if bg is None else bg
+    d_color = torch.as_tensor(np.asarray(d_color, np.float64))
+    if batch <= 0:
+        batch = max(1, min(pixels.shape[0], (1 << 22) // max(len(order), 1)))
+    total = 0.0
+    for s in range(0, pixels.shape[0], batch):
+        res = render_pixels(proj, order, pixels[s:s + batch], opts, bg=bg, batch=batch)
+        L = (res.color * d_color[s:s + batch]).sum()
+        total += float(L.detach())
+        L.backward(retain_graph=True)
+
+    def gnp(t):
+        return np.zeros(tuple(t.shape)) if t.grad is None else t.grad.detach().numpy().copy()
+    return OracleGrads(d_means=gnp(leaves[0]), d_log_scales=gnp(leaves[1]), d_quats=gnp(leaves[2]),
+                       d_scalars=gnp(leaves[3]), d_weights=None if w is None else gnp(w),
+                       d_mean2d=gnp(proj.mean2d), d_conic=gnp(proj.conic), d_rgb=gnp(proj.rgb),
+                       d_A=gnp(proj.A), loss=total)
