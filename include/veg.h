@@ -1,0 +1,380 @@
+/*
+ * veg.h -- C ABI of the VEG splatting rasterizer for AMD Instinct MI355X (gfx950).
+ *
+ * Volume Encoding Gaussians (Dyken et al., arXiv 2504.13339) represent a volume by 3D
+ * Gaussians that carry a scalar value v instead of a colour and an opacity
+ * (section "The VEG Representation").  At render time a 1D transfer function maps v to
+ * colour C(v) and opacity O(v), applied per Gaussian before rasterizing, with
+ * alpha = O(v) * w for an optional trainable weight w (section "Rendering of VEGs").
+ * The 3D covariance from scale S and rotation R is projected to a 2D screen covariance
+ * (Zwicker's EWA splatting), Gaussians are binned to 16x16 tiles, sorted front to back,
+ * and composited per pixel with the emission-absorption sum of Eq. 1:
+ *     P = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j).
+ * Gradients flow back to position, scaling, rotation, scalar value and weight
+ * (section "Rendering of VEGs", manual backward; Fig. 2).
+ *
+ * Conventions for every call below
+ * --------------------------------
+ * Memory:   the caller owns every buffer.  Pointers documented as "device" must be HIP
+ *           device memory on the current device; "host" pointers are read during the call
+ *           and may be freed when it returns.  The stateless calls allocate no device
+ *           memory.  Buffer sizes come from the *_bytes / *_count queries.
+ * Streams:  every call is asynchronous and ordered on `stream` (a hipStream_t; NULL is
+ *           the legacy default stream).  Inputs must stay alive until the stream reaches
+ *           the call.  The only calls that synchronise are veg_bin_count with a non-NULL
+ *           host counter and the serving wait/poll calls.
+ * Results:  gradient outputs are ACCUMULATED (+=); the caller zeroes them first.
+ * Errors:   functions return a veg_status; no exception crosses the ABI, nothing aborts.
+ *           Argument errors are detected synchronously and return VEG_ERR_INVALID_ARG
+ *           with nothing enqueued.  A HIP launch or runtime error returns VEG_ERR_HIP;
+ *           asynchronous device faults surface as VEG_ERR_HIP from a later call.
+ *           veg_last_error() gives a thread-local message for the last failure.
+ * Numerics: float32 on the device.  Cull, depth key and tile rectangle follow the
+ *           operation order documented at veg_project (float32, projected centre in
+ *           float64, no fused multiply-add), so they are reproducible bit for bit.
+ * Layouts:  [a,b] means row-major with the last index fastest.  Images are planar
+ *           [frames,3,H,W]; per-pixel outputs are [frames,H,W].
+ */
+#ifndef VEG_H
+#define VEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VEG_VERSION 1
+#define VEG_TILE 16                /* tile edge in pixels */
+#define VEG_MAX_FRAMES 4096        /* frames per stateless call */
+#define VEG_MAX_DIM 8192           /* width/height limit (keeps per-block entry counts in 32 bits) */
+#define VEG_REC_FLOATS 12          /* floats per (frame, Gaussian) projection record */
+#define VEG_G2D_COMPONENTS 9       /* screen-space gradient components per (frame, Gaussian) */
+
+typedef void* veg_stream_t;        /* hipStream_t */
+
+typedef enum {
+  VEG_OK = 0,
+  VEG_ERR_INVALID_ARG = 1,   /* bad pointer, size or option; nothing was enqueued */
+  VEG_ERR_CAPACITY = 2,      /* key list larger than the buffers given */
+  VEG_ERR_OUT_OF_BUDGET = 3, /* serving: request can never fit the memory budget */
+  VEG_ERR_NOT_FOUND = 4,     /* serving: unknown model or request id */
+  VEG_ERR_BUSY = 5,          /* serving: request not finished yet */
+  VEG_ERR_HIP = 6,           /* HIP runtime / launch error */
+  VEG_ERR_TIMEOUT = 7,       /* serving: wait timed out */
+  VEG_ERR_SHUTDOWN = 8       /* serving: server is shutting down */
+} veg_status;
+
+const char* veg_status_str(int status);
+const char* veg_last_error(void);   /* thread-local; "" when there was none */
+int veg_version(void);
+
+/* ----------------------------------------------------------------------------------
+ * Inputs
+ * ---------------------------------------------------------------------------------- */
+
+/* A VEG model, device SoA (section "The VEG Representation": centre mu, scaling S,
+ * rotation R, scalar value v, weight w).  Lighting attributes are not part of this ABI.
+ *   means      [n,3]  world-space centres
+ *   log_scales [n,3]  log of the three axis scales (S = diag(exp(log_scales)))
+ *   quats      [n,4]  rotation as an unnormalised quaternion (w,x,y,z); normalised inside
+ *   scalars    [n]    scalar value, already activated (the paper stores it through a
+ *                     sigmoid; apply it before the call); used clamped to [0,1]
+ *   weights    [n]    trainable opacity weight, already activated, or NULL meaning 1
+ * Gaussians with any non-finite input are culled, never an error. */
+typedef struct {
+  int64_t n;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* scalars;
+  const float* weights;
+} veg_gaussians;
+
+/* Pinhole camera (host struct).  view = world->camera 3x4 row-major [R|t]; camera axes
+ * x right, y down, z forward.  Pixel (i,j) has centre (i+0.5, j+0.5); the projected
+ * centre is (fx x/z + cx, fy y/z + cy). */
+typedef struct {
+  float view[12];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} veg_camera;
+
+/* Transfer function: k RGBA control points, device [k,4], straight (not premultiplied)
+ * colour and opacity, node-centred at v = j/(k-1), linearly interpolated between them
+ * (section "Rendering of VEGs": linear interpolation between an arbitrary number of
+ * control points).  k >= 2. */
+typedef struct {
+  const float* rgba;
+  int32_t k;
+} veg_tf;
+
+/* Renderer options.  The paper names the rasterizer it builds on but not its constants;
+ * these defaults (veg_opts_default) are the readings of this library:
+ *   alpha_clamp 0.99   alpha = min(alpha_clamp, A exp(-sigma))
+ *   alpha_min   1/255  a Gaussian-pixel pair with A exp(-sigma) < alpha_min is skipped
+ *   t_min       1e-4   a pixel stops after blending the Gaussian that takes T below t_min
+ *   lowpass     0.3    px^2 added to the diagonal of the 2D covariance (EWA low-pass)
+ *   near_z      0.2    Gaussians with camera z <= near_z are culled
+ *   guard       1.3    x/z, y/z clamped to guard * (W/2)/fx, (H/2)/fy when forming J
+ *   bg          0,0,0  background colour: output = C + T_final * bg */
+typedef struct {
+  float alpha_clamp, alpha_min, t_min, lowpass, near_z, guard;
+  float bg[3];
+} veg_opts;
+
+void veg_opts_default(veg_opts* opts);
+
+/* ----------------------------------------------------------------------------------
+ * Projection  (transfer function first, then EWA projection and footprint)
+ * ---------------------------------------------------------------------------------- */
+
+/* Projection state of `n_frames` frames over one Gaussian set; pair p = f*n + i.
+ * Host struct holding caller-owned device buffers; veg_project fills the buffers and
+ * the host fields marked "out".
+ *   frames  device, veg_frames_bytes(n_frames) bytes: per-frame descriptors
+ *   rec     device [n_frames*n][12] float: per pair, for kept pairs only:
+ *           {mx', my', conic a, conic b, conic c, A, R, G, B, rect01, rect23, frame} where
+ *           (mx', my') is the projected centre minus 16*(tile x0, tile y0), conic (a,b,c)
+ *           is the inverse 2D covariance [[a,b],[b,c]], A = O(v) w, RGB = C(v), and
+ *           rect01 / rect23 hold the tile rectangle (x0 | y0<<16, x1 | y1<<16) as uint32
+ *   count   device [n_frames*n] uint32: tiles covered, 0 when culled
+ *   depth   device [n_frames*n] uint32: float32 bits of camera z (kept pairs only)   */
+typedef struct {
+  int64_t n;            /* in: Gaussians per frame */
+  int32_t n_frames;     /* in */
+  int32_t width, height;             /* out: image size (all frames share it) */
+  int32_t tiles_x, tiles_y;          /* out */
+  int64_t total_tiles;               /* out: n_frames * tiles_x * tiles_y */
+  void* frames;
+  float* rec;
+  uint32_t* count;
+  uint32_t* depth;
+} veg_proj;
+
+size_t veg_frames_bytes(int32_t n_frames);
+
+/* veg_project -- per (frame, Gaussian): transfer-function lookup and cull, EWA projection,
+ * conic, projected centre, depth key and tile rectangle (section "Rendering of VEGs": the
+ * TF is applied as the first step so low-opacity Gaussians are culled at once; the 3D
+ * covariance R S S^T R^T is projected with Zwicker's method).
+ *   g          device model; all frames use it
+ *   n_frames   1..VEG_MAX_FRAMES; frame f uses cams[f] and tfs[f] (host arrays)
+ *   cams       host [n_frames]; every frame must have the same width and height
+ *   tfs        host [n_frames]; rgba pointers are device memory
+ *   opts       host; NULL = defaults
+ *   proj       in/out; proj->n must equal g->n and proj->n_frames must equal n_frames
+ * Footprint contract (bit-reproducible; the oracle mirrors it):
+ *   t = ((V0 mu_x + V1 mu_y) + V2 mu_z) + V3 per row in float64; depth = float32(t_z);
+ *   cull unless depth > near_z; xn = t_x/t_z, yn = t_y/t_z, mx = fx xn + cx,
+ *   my = fy yn + cy in float64; TF: vc = clamp(v,0,1), t = vc (k-1),
+ *   i = min(floor t, k-2), f = t - i, X = L[i](1-f) + L[i+1] f, A = O w; cull unless
+ *   A >= alpha_min and |q|^2 >= 1e-24 (float32); q scaled by 1/sqrt(|q|^2);
+ *   s = exp32(log s) (Cody-Waite reduction, Taylor to r^7); Q = Vr R; P = Q diag(s);
+ *   J00 = fx/depth, J02 = -(fx xc)/depth, J11 = fy/depth, J12 = -(fy yc)/depth with
+ *   xc, yc = float32(xn), float32(yn) clamped to the guard band; G = J P;
+ *   S = G G^T + lowpass I (sums left to right); cull unless det > 0;
+ *   tau = 2 log32(A/alpha_min) (atanh series to u^9); ex = sqrt(tau S00),
+ *   ey = sqrt(tau S11); pixel x range [ceil((mx - ex) - 0.5), floor((mx + ex) - 0.5)]
+ *   in float64 clipped to the image (same for y); tile rectangle = range / 16;
+ *   count = its area (0 if empty).  Every pixel whose centre has
+ *   A exp(-sigma) >= alpha_min lies inside the rectangle, so the tiling loses nothing.
+ * Errors: VEG_ERR_INVALID_ARG (NULL pointers, n < 0, n_frames out of range, k < 2,
+ *   width/height outside 1..VEG_MAX_DIM or differing between frames,
+ *   n_frames * n >= 2^31). */
+veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camera* cams,
+                       const veg_tf* tfs, const veg_opts* opts, veg_proj* proj,
+                       veg_stream_t stream);
+
+/* ----------------------------------------------------------------------------------
+ * Binning and sorting  (the tile-based rasterizer's key list)
+ * ---------------------------------------------------------------------------------- */
+
+/* Sorted key list.  Entry j is (keys[j] = global tile id, vals[j] = pair id); global tile
+ * id = f * tiles_x * tiles_y + ty * tiles_x + tx.  Entries are ordered by (tile, depth
+ * key, Gaussian index).  ranges[2t], ranges[2t+1] = [start, end) of tile t (0,0 if empty).
+ *   keys, vals          device [capacity] uint32 (final sorted list)
+ *   keys_alt, vals_alt  device [capacity] uint32 (ping-pong buffers)
+ *   ranges              device [2 * total_tiles] uint32
+ *   capacity            entries the buffers hold (<= 2^31 - 1) */
+typedef struct {
+  uint32_t* keys;
+  uint32_t* vals;
+  uint32_t* keys_alt;
+  uint32_t* vals_alt;
+  uint32_t* ranges;
+  int64_t capacity;
+} veg_bins;
+
+/* Scratch for veg_bin_count / veg_bin_sort of `n_pairs` pairs and `capacity` entries. */
+size_t veg_bin_workspace_bytes(int64_t n_pairs, int64_t capacity);
+
+/* veg_bin_count -- compacts the kept pairs, sorts them front to back by (depth key,
+ * pair id) with a stable LSD radix sort, and prefix-sums their tile counts in that order.
+ *   ws, ws_bytes     device scratch, >= veg_bin_workspace_bytes(pairs, capacity) where
+ *                    capacity is the value later passed to veg_bin_sort (may be 0 here if
+ *                    the same ws is re-queried: only the first part is used by this call)
+ *   n_entries        host out (optional): total key-list length E.  When non-NULL the
+ *                    call synchronises `stream` to read it; when NULL nothing waits and
+ *                    E stays on the device for veg_bin_sort.
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+veg_status veg_bin_count(const veg_proj* proj, void* ws, size_t ws_bytes, int64_t* n_entries,
+                         veg_stream_t stream);
+
+/* veg_bin_sort -- writes every (tile, pair) entry of the kept pairs in front-to-back
+ * order, sorts the list stably by tile (LSD radix over the bits of the largest tile id),
+ * and derives the per-tile ranges.  Needs the workspace state left by veg_bin_count.
+ * If the device-side E exceeds bins->capacity, only the first `capacity` entries are
+ * written, the ranges are not valid, and the overflow flag read by veg_bin_overflow is
+ * set (no synchronisation happens here).
+ * Errors: VEG_ERR_INVALID_ARG (capacity < 0, NULL buffers with capacity > 0),
+ *   VEG_ERR_HIP. */
+veg_status veg_bin_sort(const veg_proj* proj, void* ws, size_t ws_bytes, const veg_bins* bins,
+                        veg_stream_t stream);
+
+/* Reads (synchronising `stream`) the entry count and overflow flag left in `ws`. */
+veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32_t* overflow,
+                            veg_stream_t stream);
+
+/* ----------------------------------------------------------------------------------
+ * Forward and backward blending  (Eq. 1 and its adjoint)
+ * ---------------------------------------------------------------------------------- */
+
+/* veg_render_fwd -- per pixel, front-to-back compositing of the tile's list (Eq. 1):
+ * sigma = 1/2 d^T conic d, d = pixel centre - projected centre; a = A exp(-sigma);
+ * pairs with a < alpha_min are skipped; alpha = min(alpha_clamp, a); C += c alpha T;
+ * T *= 1 - alpha; the pixel stops after the Gaussian that takes T below t_min.
+ *   image    device [n_frames,3,H,W] out: C + T bg
+ *   t_final  device [n_frames,H,W] out: final transmittance
+ *   n_last   device [n_frames,H,W] out: index into the key list of the last blended
+ *            entry, -1 if none (needed by veg_render_bwd)
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts,
+                          float* image, float* t_final, int32_t* n_last, veg_stream_t stream);
+
+/* veg_render_bwd -- adjoint of veg_render_fwd (section "Rendering of VEGs": gradients
+ * computed manually through the rasterizer).  Walks each tile's list backwards from
+ * n_last, recovering T before each entry as T / (1 - alpha), and accumulates per pair
+ * the gradient w.r.t. the screen-space quantities.
+ *   t_final, n_last  device, as written by veg_render_fwd for the same proj/bins
+ *   d_image          device [n_frames,3,H,W] dL/dimage
+ *   g2d              device [9][n_frames*n] float, ACCUMULATED: per pair
+ *                    d mx, d my, d conic a, d conic b, d conic c, d R, d G, d B, d A,
+ *                    where conic b enters sigma as 1/2 (a dx^2 + 2 b dx dy + c dy^2)
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts,
+                          const float* t_final, const int32_t* n_last, const float* d_image,
+                          float* g2d, veg_stream_t stream);
+
+/* Parameter gradients, device, ACCUMULATED (+=).  d_weights may be NULL (then not
+ * computed); it must be non-NULL only when the model has weights. */
+typedef struct {
+  float* d_means;       /* [n,3] */
+  float* d_log_scales;  /* [n,3] */
+  float* d_quats;       /* [n,4] */
+  float* d_scalars;     /* [n]   */
+  float* d_weights;     /* [n] or NULL */
+} veg_grads;
+
+/* veg_project_bwd -- chains g2d through the conic inverse, the EWA projection, the
+ * covariance R S S^T R^T, the quaternion normalisation, exp of the log-scales, the
+ * projected centre, and the transfer function's piecewise-linear segments (slope of the
+ * segment to the right of a control point; zero outside [0,1]) to the model parameters,
+ * summed over the frames of `proj`.
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+veg_status veg_project_bwd(const veg_gaussians* g, const veg_proj* proj, const veg_opts* opts,
+                           const float* g2d, const veg_grads* grads, veg_stream_t stream);
+
+/* ----------------------------------------------------------------------------------
+ * Loss and utilities
+ * ---------------------------------------------------------------------------------- */
+
+/* veg_l1_loss -- the L1 part of the training loss (section "Training": (1-lambda) L1 +
+ * lambda SSIM; SSIM is not in this ABI):
+ *   loss   += scale * sum |image - target|            (device double, ACCUMULATED)
+ *   d_image =  scale * sign(image - target)           (device float, overwritten;
+ *                                                      sign(0) = 0)
+ * over `count` floats.  scale is normally 1/(total pixel-channels of the step).
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+veg_status veg_l1_loss(const float* image, const float* target, int64_t count, float scale,
+                       double* loss, float* d_image, veg_stream_t stream);
+
+/* Fills `count` 32-bit words at device pointer `dst` with `value` (a kernel, so it is
+ * safe inside captured graphs). */
+veg_status veg_fill_u32(void* dst, int64_t count, uint32_t value, veg_stream_t stream);
+
+/* Diagnostics: runs the device's float32 helper `op` on n inputs (0 = exp32 of the
+ * footprint contract, 1 = log32, 2 = division x/y, 3 = sqrt, 4 = wave prefix sum of
+ * uint32 (bit pattern of x), 5 = wave sum of float) so tests can compare them with the
+ * oracle.  in_x, in_y, out: device [n]. */
+veg_status veg_debug_math(int32_t op, const float* in_x, const float* in_y, float* out,
+                          int64_t n, veg_stream_t stream);
+
+/* ----------------------------------------------------------------------------------
+ * Serving: resident models, continuous batching of render requests
+ * ---------------------------------------------------------------------------------- */
+
+typedef struct veg_server veg_server;
+
+typedef struct {
+  void* arena;               /* device memory the server sub-allocates (caller-owned) */
+  size_t arena_bytes;
+  size_t budget_bytes;       /* admission budget for in-flight request memory (<= arena) */
+  int32_t max_batch;         /* requests per batch (1..64) */
+  int32_t n_streams;         /* concurrent batches (1..8) */
+  int32_t use_graphs;        /* 1: replay captured hipGraphs per batch slot */
+  int32_t max_width, max_height;   /* largest request resolution */
+  int64_t max_gaussians;     /* largest resident model */
+  int64_t max_entries;       /* key-list capacity per batch (entries) */
+} veg_serve_config;
+
+typedef struct {
+  int32_t model_id;
+  veg_camera camera;
+  const float* tf_rgba;      /* HOST [tf_k,4]; copied at submit */
+  int32_t tf_k;
+  float* out_image;          /* device [3,H,W], caller-owned, written on completion */
+  float* out_t_final;        /* device [H,W] or NULL */
+  veg_opts opts;             /* per request */
+} veg_request;
+
+typedef struct {
+  int64_t submitted, completed, rejected, batches, retries;
+  double mean_batch;
+  double p50_ms, p99_ms;         /* submit -> completion observed by the scheduler */
+  double throughput_rps;         /* completed / (last completion - first submit) */
+  double mpix_per_s;
+  double gpu_busy_frac;          /* fraction of wall time with >= 1 batch in flight */
+  int64_t peak_bytes;
+} veg_serve_stats;
+
+enum { VEG_REQ_QUEUED = 0, VEG_REQ_RUNNING = 1, VEG_REQ_DONE = 2, VEG_REQ_FAILED = 3 };
+
+/* Creates a server; a scheduler thread admits queued requests while their estimated
+ * memory fits budget - in_use, packs them into batches of up to max_batch requests of
+ * any model, camera, TF and resolution, and runs each batch (projection, binning,
+ * sorting, blending) on one of n_streams streams so batches overlap.  Memory of a batch
+ * returns to the budget when its completion event fires, which admits waiting requests.
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+veg_status veg_serve_create(const veg_serve_config* cfg, veg_server** out);
+/* Registers a resident model (device SoA, caller-owned, must outlive the server). */
+veg_status veg_serve_add_model(veg_server* s, const veg_gaussians* g, int32_t* model_id);
+/* Queues a request (any thread).  VEG_ERR_OUT_OF_BUDGET if it can never fit,
+ * VEG_ERR_NOT_FOUND for an unknown model, VEG_ERR_INVALID_ARG for a bad request. */
+veg_status veg_serve_submit(veg_server* s, const veg_request* r, uint64_t* req_id);
+/* State of a request (VEG_REQ_*); VEG_ERR_NOT_FOUND for an unknown id. */
+veg_status veg_serve_poll(veg_server* s, uint64_t req_id, int32_t* state);
+/* Waits until the request is done or failed (timeout_ms < 0: forever).  VEG_OK when its
+ * image is complete, VEG_ERR_TIMEOUT, or the request's failure status. */
+veg_status veg_serve_wait(veg_server* s, uint64_t req_id, int32_t timeout_ms);
+/* Latency/throughput statistics over the requests completed since the last reset. */
+veg_status veg_serve_stats_get(veg_server* s, veg_serve_stats* out);
+veg_status veg_serve_stats_reset(veg_server* s);
+/* Drains in-flight work, stops the scheduler and frees host resources. */
+veg_status veg_serve_destroy(veg_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VEG_H */

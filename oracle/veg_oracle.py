@@ -406,13 +406,15 @@ class PixelResult:
     T: torch.Tensor          # [P]   final transmittance
     last: np.ndarray         # [P]   position in ``order`` of the last blended Gaussian, -1 if none
     n_eval: np.ndarray       # [P]   Gaussians visited up to the stop (brute-force count)
-    flag: np.ndarray         # [P]   image decision-margin flag
-    flag_grad: np.ndarray    # [P]   additional gradient flag (alpha within margin of the clamp)
+    flag: np.ndarray         # [P]   image decision-margin flag (slack >= skip_impact)
+    flag_grad: np.ndarray    # [P]   any near-threshold decision (skip, stop, clamp): gradient tests
+    slack: np.ndarray        # [P]   bound on how far float32 may legitimately differ from float64
+                             #       through near-threshold decisions (sum of their impact bounds)
 
 
 def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray, opts,
                   bg=(0.0, 0.0, 0.0), batch: int = 0, skip_margin=1e-4, stop_margin=1e-3,
-                  clamp_margin=1e-5, t_min: Optional[float] = None) -> PixelResult:
+                  clamp_margin=1e-5, skip_impact=2.5e-5, t_min: Optional[float] = None) -> PixelResult:
     """Front-to-back compositing (Eq. 1) at pixel centres (x+0.5, y+0.5), brute force.
 
     For each pixel and each Gaussian of ``order`` (front to back):
@@ -420,6 +422,17 @@ def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray,
       a < alpha_min: skipped; otherwise alpha = min(alpha_clamp, a), C += c alpha T,
       T *= 1 - alpha, and if T < t_min the pixel stops (the Gaussian that crossed the
       threshold is blended).  Output C + T bg.
+
+    Decision margins.  A skip test with |a - alpha_min| < skip_margin * alpha_min may be
+    decided either way by float32 arithmetic; flipping it moves the pixel by at most
+    alpha_min * T_before * max|c - S| <= alpha_min * T_before * (1 + skip_margin) (colours
+    and background in [0,1]).  A stop test with |T - t_min| < stop_margin * t_min may also
+    flip; then one side blends the Gaussians the other one drops until its T falls below
+    t_min, which moves the pixel by at most (stop_margin + alpha_max_after) * T, with
+    alpha_max_after the largest alpha blended after that point.  ``slack`` sums these
+    bounds per pixel; ``flag`` marks pixels whose slack reaches ``skip_impact``;
+    ``flag_grad`` marks every pixel with any near-threshold skip, stop or clamp decision
+    (where the gradient is discontinuous).
     """
     aclamp = float(np.float32(opts["alpha_clamp"]))
     amin = float(np.float32(opts["alpha_min"]))
@@ -434,7 +447,7 @@ def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray,
     bgt = torch.as_tensor(np.asarray(bg, np.float64))
     if batch <= 0:
         batch = max(1, min(P, (1 << 23) // max(M, 1)))
-    cols, Ts, lasts, nevs, flags, gflags = [], [], [], [], [], []
+    cols, Ts, lasts, nevs, flags, gflags, slacks = [], [], [], [], [], [], []
     for s in range(0, P, batch):
         pix = torch.as_tensor(np.asarray(pixels[s:s + batch], np.float64))
         if M == 0:
@@ -444,6 +457,7 @@ def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray,
             nevs.append(np.zeros(pix.shape[0], np.int64))
             flags.append(np.zeros(pix.shape[0], bool))
             gflags.append(np.zeros(pix.shape[0], bool))
+            slacks.append(np.zeros(pix.shape[0]))
             continue
         dx = (pix[:, 0:1] + 0.5) - mu[None, :, 0]
         dy = (pix[:, 1:2] + 0.5) - mu[None, :, 1]
@@ -470,14 +484,21 @@ def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray,
             lasts.append(lastpos.numpy())
             nevs.append((k + 1).numpy())
             ad = a.detach()
+            al = alpha.detach()
+            Ti, Te = T_incl.detach(), T_excl.detach()
             near_skip = ((ad - amin).abs() < skip_margin * amin) & upto
-            near_stop = ((T_incl.detach() - tmin).abs() < stop_margin * tmin) & bl
-            flags.append((near_skip.any(1) | near_stop.any(1)).numpy())
+            near_stop = ((Ti - tmin).abs() < stop_margin * tmin) & bl
+            amax_from = torch.flip(torch.cummax(torch.flip(al, [1]), 1).values, [1])
+            amax_after = torch.cat([amax_from[:, 1:], torch.zeros_like(amax_from[:, :1])], 1)
+            slack = (near_skip.to(al.dtype) * (amin * (1 + skip_margin)) * Te).sum(1) + \
+                    (near_stop.to(al.dtype) * (stop_margin + amax_after) * Ti * (1 + stop_margin)).sum(1)
+            slacks.append(slack.numpy())
+            flags.append((slack >= skip_impact).numpy())
             near_clamp = ((ad - aclamp).abs() < clamp_margin) & bl
-            gflags.append(near_clamp.any(1).numpy())
+            gflags.append((near_skip.any(1) | near_stop.any(1) | near_clamp.any(1)).numpy())
     return PixelResult(color=torch.cat(cols, 0), T=torch.cat(Ts, 0), last=np.concatenate(lasts),
                        n_eval=np.concatenate(nevs), flag=np.concatenate(flags),
-                       flag_grad=np.concatenate(gflags))
+                       flag_grad=np.concatenate(gflags), slack=np.concatenate(slacks))
 
 
 def render_image(g, cam, lut, opts, pixels=None, bg=None, t_min=None, **kw):

@@ -1,0 +1,364 @@
+// extern "C" entry points of libveg: argument checks, descriptor upload, launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "veg_internal.h"
+
+using namespace veg;
+
+namespace {
+
+thread_local std::string g_err;
+
+veg_status fail(veg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+veg_status hip_status(hipError_t e, const char* where) {
+  if (e == hipSuccess) return VEG_OK;
+  return fail(VEG_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define VEG_CHECK_HIP(expr, where)                     \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_status(e_, where); \
+  } while (0)
+
+veg_status check_opts(const veg_opts* o) {
+  if (!(o->alpha_min > 0.0f) || !(o->alpha_clamp > o->alpha_min) || !(o->alpha_clamp <= 1.0f))
+    return fail(VEG_ERR_INVALID_ARG, "opts: need 0 < alpha_min < alpha_clamp <= 1");
+  if (!(o->t_min >= 0.0f) || !(o->t_min < 1.0f)) return fail(VEG_ERR_INVALID_ARG, "opts: need 0 <= t_min < 1");
+  if (!(o->lowpass >= 0.0f) || !(o->near_z > 0.0f) || !(o->guard > 0.0f))
+    return fail(VEG_ERR_INVALID_ARG, "opts: need lowpass >= 0, near_z > 0, guard > 0");
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(o->bg[c])) return fail(VEG_ERR_INVALID_ARG, "opts: background must be finite");
+  return VEG_OK;
+}
+
+KOpts kopts(const veg_opts* o) {
+  KOpts k;
+  k.alpha_clamp = o->alpha_clamp;
+  k.alpha_min = o->alpha_min;
+  k.t_min = o->t_min;
+  k.lowpass = o->lowpass;
+  k.near_z = o->near_z;
+  k.guard = o->guard;
+  k.log2_alpha_min = std::log2(o->alpha_min);
+  k.bg0 = o->bg[0];
+  k.bg1 = o->bg[1];
+  k.bg2 = o->bg[2];
+  return k;
+}
+
+veg_status resolve_opts(const veg_opts* in, veg_opts* out) {
+  if (in) *out = *in;
+  else veg_opts_default(out);
+  return check_opts(out);
+}
+
+veg_status check_proj(const veg_proj* p) {
+  if (!p) return fail(VEG_ERR_INVALID_ARG, "proj is NULL");
+  if (p->n < 0 || p->n_frames < 1 || p->n_frames > VEG_MAX_FRAMES)
+    return fail(VEG_ERR_INVALID_ARG, "proj: bad n (%lld) or n_frames (%d)", (long long)p->n, p->n_frames);
+  if ((int64_t)p->n_frames * p->n >= ((int64_t)1 << 31))
+    return fail(VEG_ERR_INVALID_ARG, "proj: n_frames * n must be < 2^31");
+  if (!p->frames || (p->n > 0 && (!p->rec || !p->count || !p->depth)))
+    return fail(VEG_ERR_INVALID_ARG, "proj: NULL buffer");
+  return VEG_OK;
+}
+
+veg_status check_projected(const veg_proj* p) {
+  veg_status s = check_proj(p);
+  if (s != VEG_OK) return s;
+  if (p->width < 1 || p->height < 1 || p->tiles_x < 1 || p->tiles_y < 1 ||
+      p->total_tiles != (int64_t)p->n_frames * p->tiles_x * p->tiles_y)
+    return fail(VEG_ERR_INVALID_ARG, "proj: not filled by veg_project");
+  return VEG_OK;
+}
+
+veg_status check_gaussians(const veg_gaussians* g) {
+  if (!g) return fail(VEG_ERR_INVALID_ARG, "gaussians is NULL");
+  if (g->n < 0) return fail(VEG_ERR_INVALID_ARG, "gaussians: n < 0");
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->scalars))
+    return fail(VEG_ERR_INVALID_ARG, "gaussians: NULL parameter array");
+  if (g->quats && (reinterpret_cast<uintptr_t>(g->quats) & 15u))
+    return fail(VEG_ERR_INVALID_ARG, "gaussians: quats must be 16-byte aligned");
+  return VEG_OK;
+}
+
+size_t pairs_of(const veg_proj* p) { return (size_t)p->n_frames * (size_t)p->n; }
+
+}  // namespace
+
+extern "C" {
+
+const char* veg_status_str(int s) {
+  switch (s) {
+    case VEG_OK: return "ok";
+    case VEG_ERR_INVALID_ARG: return "invalid argument";
+    case VEG_ERR_CAPACITY: return "key list capacity exceeded";
+    case VEG_ERR_OUT_OF_BUDGET: return "request exceeds the memory budget";
+    case VEG_ERR_NOT_FOUND: return "not found";
+    case VEG_ERR_BUSY: return "busy";
+    case VEG_ERR_HIP: return "HIP error";
+    case VEG_ERR_TIMEOUT: return "timeout";
+    case VEG_ERR_SHUTDOWN: return "server shutting down";
+    default: return "unknown status";
+  }
+}
+
+const char* veg_last_error(void) { return g_err.c_str(); }
+
+int veg_version(void) { return VEG_VERSION; }
+
+void veg_opts_default(veg_opts* o) {
+  if (!o) return;
+  o->alpha_clamp = 0.99f;
+  o->alpha_min = 1.0f / 255.0f;
+  o->t_min = 1e-4f;
+  o->lowpass = 0.3f;
+  o->near_z = 0.2f;
+  o->guard = 1.3f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+}
+
+size_t veg_frames_bytes(int32_t n_frames) { return n_frames > 0 ? (size_t)n_frames * sizeof(FrameDesc) : 0; }
+
+veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camera* cams, const veg_tf* tfs,
+                       const veg_opts* opts, veg_proj* proj, veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_gaussians(g);
+  if (s != VEG_OK) return s;
+  if (!cams || !tfs) return fail(VEG_ERR_INVALID_ARG, "cams/tfs is NULL");
+  if (n_frames < 1 || n_frames > VEG_MAX_FRAMES) return fail(VEG_ERR_INVALID_ARG, "n_frames out of range");
+  s = check_proj(proj);
+  if (s != VEG_OK) return s;
+  if (proj->n != g->n || proj->n_frames != n_frames)
+    return fail(VEG_ERR_INVALID_ARG, "proj->n / n_frames do not match the call");
+  veg_opts o;
+  s = resolve_opts(opts, &o);
+  if (s != VEG_OK) return s;
+  const int W = cams[0].width, H = cams[0].height;
+  for (int f = 0; f < n_frames; ++f) {
+    const veg_camera& c = cams[f];
+    if (c.width != W || c.height != H) return fail(VEG_ERR_INVALID_ARG, "frame %d: all frames need one size", f);
+    if (c.width < 1 || c.height < 1 || c.width > VEG_MAX_DIM || c.height > VEG_MAX_DIM)
+      return fail(VEG_ERR_INVALID_ARG, "frame %d: width/height out of range", f);
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+      return fail(VEG_ERR_INVALID_ARG, "frame %d: need fx, fy > 0 and finite cx, cy", f);
+    for (int k = 0; k < 12; ++k)
+      if (!std::isfinite(c.view[k])) return fail(VEG_ERR_INVALID_ARG, "frame %d: non-finite view matrix", f);
+    if (!tfs[f].rgba || tfs[f].k < 2) return fail(VEG_ERR_INVALID_ARG, "frame %d: TF needs k >= 2 points", f);
+    if (reinterpret_cast<uintptr_t>(tfs[f].rgba) & 15u)
+      return fail(VEG_ERR_INVALID_ARG, "frame %d: TF table must be 16-byte aligned", f);
+  }
+  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+  const int64_t total_tiles = (int64_t)n_frames * tiles_x * tiles_y;
+  if (total_tiles >= ((int64_t)1 << 31)) return fail(VEG_ERR_INVALID_ARG, "too many tiles");
+  std::vector<FrameDesc> descs(n_frames);
+  for (int f = 0; f < n_frames; ++f) {
+    FrameDesc& d = descs[f];
+    std::memset(&d, 0, sizeof(d));
+    d.means = g->means;
+    d.log_scales = g->log_scales;
+    d.quats = g->quats;
+    d.scalars = g->scalars;
+    d.weights = g->weights;
+    d.lut = tfs[f].rgba;
+    d.K = tfs[f].k;
+    d.n = (int32_t)g->n;
+    d.W = W;
+    d.H = H;
+    d.tiles_x = tiles_x;
+    d.tiles_y = tiles_y;
+    d.pair_base = (uint32_t)((int64_t)f * g->n);
+    d.tile_base = (uint32_t)((int64_t)f * tiles_x * tiles_y);
+    d.pix_base = (uint32_t)((int64_t)f * W * H);
+    std::memcpy(d.view, cams[f].view, sizeof(d.view));
+    d.fx = cams[f].fx;
+    d.fy = cams[f].fy;
+    d.cx = cams[f].cx;
+    d.cy = cams[f].cy;
+    d.bg[0] = o.bg[0];
+    d.bg[1] = o.bg[1];
+    d.bg[2] = o.bg[2];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int per_chunk = kBlobMaxBytes / (int)sizeof(FrameDesc);
+  for (int f0 = 0; f0 < n_frames; f0 += per_chunk) {
+    const int nf = std::min(per_chunk, n_frames - f0);
+    VEG_CHECK_HIP(write_blob((FrameDesc*)proj->frames + f0, &descs[f0], nf * sizeof(FrameDesc), st),
+                  "veg_project: descriptor upload");
+  }
+  proj->width = W;
+  proj->height = H;
+  proj->tiles_x = tiles_x;
+  proj->tiles_y = tiles_y;
+  proj->total_tiles = total_tiles;
+  if (g->n > 0)
+    VEG_CHECK_HIP(launch_project((const FrameDesc*)proj->frames, n_frames, (int)g->n, kopts(&o), (float4*)proj->rec,
+                                 proj->count, proj->depth, true, st),
+                  "veg_project");
+  return VEG_OK;
+}
+
+size_t veg_bin_workspace_bytes(int64_t n_pairs, int64_t capacity) {
+  (void)capacity;
+  return bin_ws_bytes(n_pairs);
+}
+
+veg_status veg_bin_count(const veg_proj* proj, void* ws, size_t ws_bytes, int64_t* n_entries, veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  const size_t pairs = pairs_of(proj);
+  if (!ws || ws_bytes < bin_ws_bytes((int64_t)pairs)) return fail(VEG_ERR_INVALID_ARG, "bin workspace too small");
+  BinWs w;
+  carve_bin_ws(ws, (int64_t)pairs, &w);
+  hipStream_t st = (hipStream_t)stream;
+  if (pairs > 0) {
+    VEG_CHECK_HIP(launch_bin_count(proj->count, proj->depth, (uint32_t)pairs, w, st), "veg_bin_count");
+  } else {
+    VEG_CHECK_HIP(launch_fill_u32(w.counters, 64, 0u, st), "veg_bin_count");
+  }
+  if (n_entries) {
+    uint32_t e[2];
+    VEG_CHECK_HIP(hipMemcpyAsync(e, w.counters + 1, sizeof(e), hipMemcpyDeviceToHost, st), "veg_bin_count: read");
+    VEG_CHECK_HIP(hipStreamSynchronize(st), "veg_bin_count: sync");
+    *n_entries = (int64_t)((uint64_t)e[0] | ((uint64_t)e[1] << 32));
+  }
+  return VEG_OK;
+}
+
+veg_status veg_bin_sort(const veg_proj* proj, void* ws, size_t ws_bytes, const veg_bins* bins, veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  if (!bins) return fail(VEG_ERR_INVALID_ARG, "bins is NULL");
+  if (bins->capacity < 0 || bins->capacity >= ((int64_t)1 << 31))
+    return fail(VEG_ERR_INVALID_ARG, "bins: capacity must be in [0, 2^31)");
+  if (bins->capacity > 0 && (!bins->keys || !bins->vals || !bins->keys_alt || !bins->vals_alt))
+    return fail(VEG_ERR_INVALID_ARG, "bins: NULL key buffer");
+  if (!bins->ranges) return fail(VEG_ERR_INVALID_ARG, "bins: NULL ranges");
+  const size_t pairs = pairs_of(proj);
+  if (!ws || ws_bytes < bin_ws_bytes((int64_t)pairs)) return fail(VEG_ERR_INVALID_ARG, "bin workspace too small");
+  BinWs w;
+  carve_bin_ws(ws, (int64_t)pairs, &w);
+  hipStream_t st = (hipStream_t)stream;
+  VEG_CHECK_HIP(launch_bin_sort((const FrameDesc*)proj->frames, proj->n_frames, (const float4*)proj->rec, proj->count,
+                                (uint32_t)pairs, (uint32_t)proj->total_tiles, w, bins->keys, bins->vals,
+                                bins->keys_alt, bins->vals_alt, bins->ranges,
+                                pairs > 0 ? (uint32_t)bins->capacity : 0u, st),
+                "veg_bin_sort");
+  return VEG_OK;
+}
+
+veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32_t* overflow, veg_stream_t stream) {
+  g_err.clear();
+  if (!ws || ws_bytes < bin_ws_bytes(1)) return fail(VEG_ERR_INVALID_ARG, "bin workspace too small");
+  BinWs w;
+  carve_bin_ws(ws, 1, &w);   // the counters' offset does not depend on the pair count
+  uint32_t c[4];
+  hipStream_t st = (hipStream_t)stream;
+  VEG_CHECK_HIP(hipMemcpyAsync(c, w.counters, sizeof(c), hipMemcpyDeviceToHost, st), "veg_bin_overflow: read");
+  VEG_CHECK_HIP(hipStreamSynchronize(st), "veg_bin_overflow: sync");
+  if (n_entries) *n_entries = (int64_t)((uint64_t)c[1] | ((uint64_t)c[2] << 32));
+  if (overflow) *overflow = (int32_t)c[3];
+  return VEG_OK;
+}
+
+veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts, float* image,
+                          float* t_final, int32_t* n_last, veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  if (!bins || !bins->ranges || !image) return fail(VEG_ERR_INVALID_ARG, "render_fwd: NULL argument");
+  if (proj->n > 0 && bins->capacity > 0 && !bins->vals) return fail(VEG_ERR_INVALID_ARG, "render_fwd: NULL vals");
+  veg_opts o;
+  s = resolve_opts(opts, &o);
+  if (s != VEG_OK) return s;
+  VEG_CHECK_HIP(launch_blend_fwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
+                                 kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, image, t_final, n_last,
+                                 (hipStream_t)stream),
+                "veg_render_fwd");
+  return VEG_OK;
+}
+
+veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts, const float* t_final,
+                          const int32_t* n_last, const float* d_image, float* g2d, veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  if (!bins || !bins->ranges || !t_final || !n_last || !d_image || (proj->n > 0 && !g2d))
+    return fail(VEG_ERR_INVALID_ARG, "render_bwd: NULL argument");
+  veg_opts o;
+  s = resolve_opts(opts, &o);
+  if (s != VEG_OK) return s;
+  VEG_CHECK_HIP(launch_blend_bwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
+                                 kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, t_final, n_last,
+                                 d_image, g2d, (uint32_t)pairs_of(proj), (hipStream_t)stream),
+                "veg_render_bwd");
+  return VEG_OK;
+}
+
+veg_status veg_project_bwd(const veg_gaussians* g, const veg_proj* proj, const veg_opts* opts, const float* g2d,
+                           const veg_grads* grads, veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_gaussians(g);
+  if (s != VEG_OK) return s;
+  s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  if (proj->n != g->n) return fail(VEG_ERR_INVALID_ARG, "project_bwd: proj->n != g->n");
+  if (!grads || (g->n > 0 && (!g2d || !grads->d_means || !grads->d_log_scales || !grads->d_quats ||
+                              !grads->d_scalars)))
+    return fail(VEG_ERR_INVALID_ARG, "project_bwd: NULL gradient buffer");
+  if (grads->d_weights && !g->weights)
+    return fail(VEG_ERR_INVALID_ARG, "project_bwd: d_weights given but the model has no weights");
+  veg_opts o;
+  s = resolve_opts(opts, &o);
+  if (s != VEG_OK) return s;
+  VEG_CHECK_HIP(launch_project_bwd((const FrameDesc*)proj->frames, proj->n_frames, (int)g->n, kopts(&o), g2d,
+                                   (uint32_t)pairs_of(proj), grads->d_means, grads->d_log_scales, grads->d_quats,
+                                   grads->d_scalars, grads->d_weights, (hipStream_t)stream),
+                "veg_project_bwd");
+  return VEG_OK;
+}
+
+veg_status veg_l1_loss(const float* image, const float* target, int64_t count, float scale, double* loss,
+                       float* d_image, veg_stream_t stream) {
+  g_err.clear();
+  if (count < 0) return fail(VEG_ERR_INVALID_ARG, "l1_loss: count < 0");
+  if (count > 0 && (!image || !target || !loss || !d_image)) return fail(VEG_ERR_INVALID_ARG, "l1_loss: NULL");
+  if (!std::isfinite(scale)) return fail(VEG_ERR_INVALID_ARG, "l1_loss: scale must be finite");
+  VEG_CHECK_HIP(launch_l1(image, target, count, scale, loss, d_image, (hipStream_t)stream), "veg_l1_loss");
+  return VEG_OK;
+}
+
+veg_status veg_fill_u32(void* dst, int64_t count, uint32_t value, veg_stream_t stream) {
+  g_err.clear();
+  if (count < 0 || (count > 0 && !dst)) return fail(VEG_ERR_INVALID_ARG, "fill: bad arguments");
+  VEG_CHECK_HIP(launch_fill_u32((uint32_t*)dst, count, value, (hipStream_t)stream), "veg_fill_u32");
+  return VEG_OK;
+}
+
+veg_status veg_debug_math(int32_t op, const float* in_x, const float* in_y, float* out, int64_t n,
+                          veg_stream_t stream) {
+  g_err.clear();
+  if (op < 0 || op > 5 || n < 0 || (n > 0 && (!in_x || !out || (op == 2 && !in_y))))
+    return fail(VEG_ERR_INVALID_ARG, "debug_math: bad arguments");
+  VEG_CHECK_HIP(launch_debug_math(op, in_x, in_y, out, n, (hipStream_t)stream), "veg_debug_math");
+  return VEG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,539 @@
+// Binning and sorting for the tile-based rasterizer (paper, section "Rendering of VEGs":
+// the 2D Gaussians intersecting the screen are rasterized tile by tile, blended front to
+// back).  The key list is built depth-first:
+//   1. compact the kept (frame, Gaussian) pairs and sort them by (depth key, pair id)
+//      with a stable LSD radix sort over the 31 depth-key bits;
+//   2. prefix-sum their tile counts in that order and emit one (tile, pair) entry per
+//      covered tile -- so within each tile the entries are already front to back;
+//   3. stable LSD radix sort by tile id over just the bits of the largest tile id;
+//   4. per-tile [start, end) ranges from the key boundaries.
+// The result equals the list sorted by (tile, depth key, pair id).  Every kernel reads its
+// element count from device memory, so the pipeline needs no host synchronisation.
+#include "veg_internal.h"
+
+namespace veg {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kIpt = 8;                      // items per thread per tile
+constexpr int kTileItems = kThreads * kIpt;  // 2048
+
+// Block b's contiguous segment of [0, n) when n is split over G blocks in whole tiles.
+__device__ __forceinline__ void segment_of(uint32_t n, int G, int b, uint32_t& begin, uint32_t& end) {
+  uint64_t per = ((uint64_t)n + (uint64_t)G - 1) / (uint64_t)G;
+  per = (per + kTileItems - 1) / kTileItems * kTileItems;
+  const uint64_t bg = (uint64_t)b * per;
+  begin = (uint32_t)(bg < n ? bg : n);
+  const uint64_t en = bg + per;
+  end = (uint32_t)(en < n ? en : n);
+}
+
+__device__ __forceinline__ uint32_t read_count(const uint32_t* n_ptr, uint32_t n_cap) {
+  if (!n_ptr) return n_cap;
+  const uint32_t v = *n_ptr;
+  return v < n_cap ? v : n_cap;
+}
+
+// Exclusive scan over the 256 threads of a block; *total gets the block sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan_u32(v);
+  if (lane == 63) s_tmp[w] = incl;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    const uint32_t t = s_tmp[k];
+    base += (k < w) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + incl - v;
+}
+
+__device__ __forceinline__ uint32_t block_reduce(uint32_t v, uint32_t* s_tmp) {
+  uint32_t tot;
+  block_excl_scan(v, s_tmp, &tot);
+  return tot;
+}
+
+// ------------------------------------------------------------------------------ scans
+// Three item kinds share the reduce-then-scan machinery:
+//   kVis : item i of the pairs, value = count[i] > 0   (compaction of kept pairs)
+//   kCnt : item j of the depth-sorted kept pairs, value = count[vals[j]]   (entry offsets)
+//   kRaw : value = data[i]   (radix histogram scan)
+enum ScanKind { kVis = 0, kCnt = 1, kRaw = 2 };
+
+struct ScanSrc {
+  const uint32_t* count;   // kVis, kCnt
+  const uint32_t* vals;    // kCnt
+  const uint32_t* data;    // kRaw
+};
+
+template <int KIND>
+__device__ __forceinline__ uint32_t item_value(const ScanSrc& s, uint32_t i) {
+  if (KIND == kVis) return s.count[i] > 0u ? 1u : 0u;
+  if (KIND == kCnt) return s.count[s.vals[i]];
+  return s.data[i];
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(ScanSrc src, const uint32_t* n_ptr, uint32_t n_cap,
+                                                               uint64_t* partials, int G) {
+  __shared__ uint32_t s_tmp[kWaves];
+  const uint32_t n = read_count(n_ptr, n_cap);
+  uint32_t begin, end;
+  segment_of(n, G, blockIdx.x, begin, end);
+  uint64_t acc = 0;
+  for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kIpt; ++k) {
+      const uint32_t i = t0 + k * kThreads + threadIdx.x;
+      if (i < end) s += item_value<KIND>(src, i);
+    }
+    acc += block_reduce(s, s_tmp);
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// Exclusive scan of G <= 4096 partial sums in place (one block of 1024 threads).  The total
+// goes to out_total[0..1] as (low, high) 32-bit words; out_u32 (optional) gets it
+// saturated to 32 bits.
+__global__ __launch_bounds__(1024) void scan_partials_kernel(uint64_t* partials, int G, uint32_t* out_total,
+                                                             uint32_t* out_u32) {
+  __shared__ uint64_t s[1024];
+  const int t = threadIdx.x;
+  uint64_t v[4];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = 4 * t + k;
+    v[k] = i < G ? partials[i] : 0ull;
+    sum += v[k];
+  }
+  s[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint64_t add = t >= off ? s[t - off] : 0ull;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  uint64_t run = s[t] - sum;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = 4 * t + k;
+    if (i < G) partials[i] = run;
+    run += v[k];
+  }
+  if (t == 1023) {
+    const uint64_t tot = s[1023];
+    if (out_total) {
+      out_total[0] = (uint32_t)tot;
+      out_total[1] = (uint32_t)(tot >> 32);
+    }
+    if (out_u32) *out_u32 = tot > 0xffffffffull ? 0xffffffffu : (uint32_t)tot;
+  }
+}
+
+// Downsweep of the compaction: kept pair i goes to (dkey, dval)[pos] = (depth[i], i).
+__global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __restrict__ count,
+                                                           const uint32_t* __restrict__ depth, uint32_t n,
+                                                           const uint64_t* __restrict__ partials, int G,
+                                                           uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval) {
+  __shared__ uint32_t s_tmp[kWaves];
+  uint32_t begin, end;
+  segment_of(n, G, blockIdx.x, begin, end);
+  uint64_t base = partials[blockIdx.x];
+  for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
+    // thread-contiguous items so the scan order equals the index order
+    const uint32_t i0 = t0 + threadIdx.x * kIpt;
+    uint32_t flags = 0, s = 0;
+#pragma unroll
+    for (int k = 0; k < kIpt; ++k) {
+      const uint32_t i = i0 + k;
+      const uint32_t f = (i < end && count[i] > 0u) ? 1u : 0u;
+      flags |= f << k;
+      s += f;
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(s, s_tmp, &tot);
+#pragma unroll
+    for (int k = 0; k < kIpt; ++k) {
+      if ((flags >> k) & 1u) {
+        const uint64_t pos = base + off;
+        dkey[pos] = depth[i0 + k];
+        dval[pos] = i0 + k;
+        ++off;
+      }
+    }
+    base += tot;
+  }
+}
+
+// Downsweep of the entry-offset scan fused with emission: the j-th depth-sorted kept pair p
+// writes (global tile, p) for every tile of its rectangle (row-major), starting at its offset.
+__global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restrict__ descs,
+                                                        const float4* __restrict__ rec,
+                                                        const uint32_t* __restrict__ count,
+                                                        const uint32_t* __restrict__ sorted_vals,
+                                                        const uint32_t* __restrict__ v_ptr, uint32_t v_cap,
+                                                        const uint64_t* __restrict__ partials, int G,
+                                                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                        uint32_t capacity) {
+  __shared__ uint32_t s_tmp[kWaves];
+  const uint32_t n = read_count(v_ptr, v_cap);
+  uint32_t begin, end;
+  segment_of(n, G, blockIdx.x, begin, end);
+  uint64_t base = partials[blockIdx.x];
+  for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
+    const uint32_t j0 = t0 + threadIdx.x * kIpt;
+    uint32_t pr[kIpt], cn[kIpt];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kIpt; ++k) {
+      const uint32_t j = j0 + k;
+      pr[k] = j < end ? sorted_vals[j] : 0u;
+      cn[k] = j < end ? count[pr[k]] : 0u;
+      s += cn[k];
+    }
+    uint32_t tot;
+    const uint32_t off = block_excl_scan(s, s_tmp, &tot);
+    uint64_t pos = base + off;
+#pragma unroll
+    for (int k = 0; k < kIpt; ++k) {
+      if (cn[k] == 0u) continue;
+      const float4 r2 = rec[3 * (size_t)pr[k] + 2];
+      const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
+      const uint32_t f = __float_as_uint(r2.w);
+      const FrameDesc& d = descs[f];
+      const uint32_t x0 = a & 0xffffu, y0 = a >> 16, x1 = b & 0xffffu, y1 = b >> 16;
+      const uint32_t tb = d.tile_base, tx_n = (uint32_t)d.tiles_x;
+      for (uint32_t ty = y0; ty <= y1; ++ty) {
+        for (uint32_t tx = x0; tx <= x1; ++tx) {
+          if (pos < capacity) {
+            keys[pos] = tb + ty * tx_n + tx;
+            vals[pos] = pr[k];
+          }
+          ++pos;
+        }
+      }
+    }
+    base += tot;
+  }
+}
+
+// In-place exclusive scan of `data` (downsweep of the kRaw reduce-then-scan).
+__global__ __launch_bounds__(kThreads) void hist_scan_down_kernel(uint32_t* __restrict__ data, uint32_t n,
+                                                                  const uint64_t* __restrict__ partials, int G) {
+  __shared__ uint32_t s_tmp[kWaves];
+  uint32_t begin, end;
+  segment_of(n, G, blockIdx.x, begin, end);
+  uint64_t base = partials[blockIdx.x];
+  for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
+    const uint32_t i0 = t0 + threadIdx.x * kIpt;
+    uint32_t v[kIpt], s = 0;
+#pragma unroll
+    for (int k = 0; k < kIpt; ++k) {
+      v[k] = (i0 + k < end) ? data[i0 + k] : 0u;
+      s += v[k];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(s, s_tmp, &tot);
+#pragma unroll
+    for (int k = 0; k < kIpt; ++k) {
+      if (i0 + k < end) data[i0 + k] = (uint32_t)(base + off);
+      off += v[k];
+    }
+    base += tot;
+  }
+}
+
+// ------------------------------------------------------------------------------ radix sort
+
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbits) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return valid ? peers : 0ull;
+}
+
+// Per-block digit histogram of its segment, hist[d * G + b].  Lanes with equal digits are
+// grouped (ballot match) so skewed digits do not serialise on one LDS counter.
+__global__ __launch_bounds__(kThreads) void rs_upsweep_kernel(const uint32_t* __restrict__ keys,
+                                                              const uint32_t* n_ptr, uint32_t n_cap, int shift,
+                                                              int nbits, uint32_t* __restrict__ hist, int G) {
+  __shared__ uint32_t s_h[kWaves][kRadix];
+  for (int k = threadIdx.x; k < kWaves * kRadix; k += kThreads) (&s_h[0][0])[k] = 0u;
+  __syncthreads();
+  const uint32_t n = read_count(n_ptr, n_cap);
+  uint32_t begin, end;
+  segment_of(n, G, blockIdx.x, begin, end);
+  const int w = threadIdx.x >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+  const uint64_t lt = lanemask_lt();
+  for (uint32_t i0 = begin; i0 < end; i0 += kThreads) {
+    const uint32_t i = i0 + threadIdx.x;
+    const bool valid = i < end;
+    const uint32_t d = valid ? (keys[i] >> shift) & mask : 0u;
+    const uint64_t peers = match_digit(d, valid, nbits);
+    if (valid && (peers & lt) == 0ull) atomicAdd(&s_h[w][d], (uint32_t)__popcll(peers));
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kThreads) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) s += s_h[k][d];
+    hist[(size_t)d * G + blockIdx.x] = s;
+  }
+}
+
+// Stable scatter of one digit pass.  Each tile of 2048 items is ranked in LDS (per-wave
+// digit counters updated by the lowest lane of each equal-digit group), reordered by digit
+// in LDS, and written out so that equal digits land in consecutive global slots.
+__global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* n_ptr, uint32_t n_cap, int shift, int nbits,
+    const uint32_t* __restrict__ hist, int G) {
+  __shared__ uint32_t s_cnt[kWaves][kRadix];
+  __shared__ uint32_t s_off[kRadix];
+  __shared__ uint32_t s_glob[kRadix];
+  __shared__ uint32_t s_keys[kTileItems];
+  __shared__ uint32_t s_vals[kTileItems];
+  __shared__ uint32_t s_tmp[kWaves];
+  const uint32_t n = read_count(n_ptr, n_cap);
+  uint32_t begin, end;
+  segment_of(n, G, blockIdx.x, begin, end);
+  if (begin >= end) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+  const uint64_t lt = lanemask_lt();
+  s_glob[t] = hist[(size_t)t * G + blockIdx.x];
+  for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
+    for (int k = t; k < kWaves * kRadix; k += kThreads) (&s_cnt[0][0])[k] = 0u;
+    __syncthreads();
+    uint32_t key[kIpt], val[kIpt], rank[kIpt];
+#pragma unroll
+    for (int r = 0; r < kIpt; ++r) {
+      const uint32_t i = t0 + (uint32_t)(w * (kTileItems / kWaves) + r * 64 + lane);
+      const bool valid = i < end;
+      key[r] = valid ? kin[i] : 0u;
+      val[r] = valid ? vin[i] : 0u;
+      const uint32_t d = (key[r] >> shift) & mask;
+      const uint64_t peers = match_digit(d, valid, nbits);
+      const uint32_t below = (uint32_t)__popcll(peers & lt);
+      const uint32_t old = valid ? s_cnt[w][d] : 0u;
+      if (valid && below == 0u) s_cnt[w][d] = old + (uint32_t)__popcll(peers);
+      rank[r] = valid ? old + below : 0xffffffffu;
+    }
+    __syncthreads();
+    uint32_t c[kWaves], tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      c[k] = s_cnt[k][t];
+      tot += c[k];
+    }
+    uint32_t dummy;
+    const uint32_t excl = block_excl_scan(tot, s_tmp, &dummy);
+    s_off[t] = excl;
+    uint32_t run = excl;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      s_cnt[k][t] = run;
+      run += c[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kIpt; ++r) {
+      if (rank[r] != 0xffffffffu) {
+        const uint32_t d = (key[r] >> shift) & mask;
+        const uint32_t pos = s_cnt[w][d] + rank[r];
+        s_keys[pos] = key[r];
+        s_vals[pos] = val[r];
+      }
+    }
+    __syncthreads();
+    const uint32_t nt = min((uint32_t)kTileItems, end - t0);
+    for (uint32_t i = t; i < nt; i += kThreads) {
+      const uint32_t k2 = s_keys[i];
+      const uint32_t d = (k2 >> shift) & mask;
+      const uint32_t g = s_glob[d] + (i - s_off[d]);
+      kout[g] = k2;
+      vout[g] = s_vals[i];
+    }
+    __syncthreads();
+    s_glob[t] += tot;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------ misc
+
+__global__ void finalize_kernel(uint32_t* counters, uint32_t capacity) {
+  const uint64_t e = (uint64_t)counters[1] | ((uint64_t)counters[2] << 32);
+  counters[3] = e > (uint64_t)capacity ? 1u : 0u;
+  counters[4] = e > (uint64_t)capacity ? capacity : (uint32_t)e;   // entries actually written
+}
+
+__global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ e_ptr, uint32_t capacity,
+                                                          uint32_t* __restrict__ ranges) {
+  const uint32_t E = read_count(e_ptr, capacity);
+  for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < E; j += gridDim.x * kThreads) {
+    const uint32_t k = keys[j];
+    if (j == 0 || keys[j - 1] != k) ranges[2 * (size_t)k] = j;
+    if (j + 1 == E || keys[j + 1] != k) ranges[2 * (size_t)k + 1] = j + 1;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void fill_kernel(uint32_t* __restrict__ dst, int64_t count, uint32_t value) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < count; i += (int64_t)gridDim.x * kThreads)
+    dst[i] = value;
+}
+
+int blocks_for(int64_t n, int items_per_block, int max_blocks) {
+  int64_t b = (n + items_per_block - 1) / items_per_block;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+int scan_blocks(int64_t n) { return blocks_for(n, 2 * kTileItems, kMaxScanBlocks); }
+int sort_blocks(int64_t n) { return blocks_for(n, 2 * kTileItems, kMaxSortBlocks); }
+
+// LSD radix sort of (key, val) over bits [0, bits): ping-pongs between (k0,v0) and (k1,v1);
+// the result ends in (k0,v0) when the number of passes is even, else in (k1,v1).
+hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_ptr, uint32_t n_cap,
+                      int bits, uint32_t* hist, uint64_t* partials, hipStream_t stream) {
+  const int G = sort_blocks(n_cap);
+  uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  for (int shift = 0; shift < bits; shift += kRadixBits) {
+    const int nb = min(kRadixBits, bits - shift);
+    hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, n_ptr, n_cap, shift, nb, hist, G);
+    // exclusive scan of the digit-major histogram (kRadix * G values)
+    const uint32_t hn = (uint32_t)(kRadix * G);
+    const int Gs = scan_blocks(hn);
+    ScanSrc src{nullptr, nullptr, hist};
+    hipLaunchKernelGGL(scan_reduce_kernel<kRaw>, dim3(Gs), dim3(kThreads), 0, stream, src, nullptr, hn, partials, Gs);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, partials, Gs, nullptr, nullptr);
+    hipLaunchKernelGGL(hist_scan_down_kernel, dim3(Gs), dim3(kThreads), 0, stream, hist, hn, partials, Gs);
+    hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, vi, ko, vo, n_ptr, n_cap, shift,
+                       nb, hist, G);
+    uint32_t* tk = ki; ki = ko; ko = tk;
+    uint32_t* tv = vi; vi = vo; vo = tv;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t bin_ws_bytes(int64_t pairs) {
+  const size_t p = (size_t)(pairs > 0 ? pairs : 1);
+  size_t b = 0;
+  b += 4 * p * sizeof(uint32_t);                       // depth-sort ping-pong
+  b += kMaxScanBlocks * sizeof(uint64_t);              // scan partials (entry offsets)
+  b += kMaxScanBlocks * sizeof(uint64_t);              // scan partials (scratch)
+  b += (size_t)kRadix * kMaxSortBlocks * sizeof(uint32_t);  // radix histograms
+  b += 64 * sizeof(uint32_t);                          // counters
+  return b + 9 * 256;                                  // alignment slack
+}
+
+void carve_bin_ws(void* ws, int64_t pairs, BinWs* out) {
+  const size_t p = (size_t)(pairs > 0 ? pairs : 1);
+  uintptr_t a = ((uintptr_t)ws + 255) & ~(uintptr_t)255;
+  auto take = [&](size_t bytes) {
+    void* r = (void*)a;
+    a = (a + bytes + 255) & ~(uintptr_t)255;
+    return r;
+  };
+  // counters first: their offset does not depend on the pair count
+  out->counters = (uint32_t*)take(64 * 4);
+  out->partials = (uint32_t*)take(kMaxScanBlocks * 8);
+  out->partials_tmp = (uint32_t*)take(kMaxScanBlocks * 8);
+  out->hist = (uint32_t*)take((size_t)kRadix * kMaxSortBlocks * 4);
+  out->dkeyA = (uint32_t*)take(p * 4);
+  out->dvalA = (uint32_t*)take(p * 4);
+  out->dkeyB = (uint32_t*)take(p * 4);
+  out->dvalB = (uint32_t*)take(p * 4);
+  out->depth_sorted_vals = out->dvalA;
+}
+
+hipError_t launch_bin_count(const uint32_t* count, const uint32_t* depth, uint32_t n_pairs, const BinWs& ws,
+                            hipStream_t stream) {
+  uint64_t* partials = (uint64_t*)ws.partials;
+  uint64_t* ptmp = (uint64_t*)ws.partials_tmp;
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, stream, ws.counters, (int64_t)64, 0u);
+  // 1. compaction of kept pairs
+  const int Gv = scan_blocks(n_pairs);
+  ScanSrc vis{count, nullptr, nullptr};
+  hipLaunchKernelGGL(scan_reduce_kernel<kVis>, dim3(Gv), dim3(kThreads), 0, stream, vis, nullptr, n_pairs, ptmp, Gv);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, ptmp, Gv, ws.counters + 8,
+                     ws.counters + 0);
+  hipLaunchKernelGGL(compact_kernel, dim3(Gv), dim3(kThreads), 0, stream, count, depth, n_pairs, ptmp, Gv,
+                     ws.dkeyA, ws.dvalA);
+  // 2. front-to-back order: 31 depth-key bits (camera z > 0)
+  hipError_t e = radix_sort(ws.dkeyA, ws.dvalA, ws.dkeyB, ws.dvalB, ws.counters + 0, n_pairs, 31, ws.hist, ptmp,
+                            stream);
+  if (e != hipSuccess) return e;
+  // 4 passes: the sorted list is back in (dkeyA, dvalA)
+  // 3. entry offsets in that order; block offsets stay in `partials` for the emission
+  const int Gc = scan_blocks(n_pairs);
+  ScanSrc cnt{count, ws.dvalA, nullptr};
+  hipLaunchKernelGGL(scan_reduce_kernel<kCnt>, dim3(Gc), dim3(kThreads), 0, stream, cnt, ws.counters + 0, n_pairs,
+                     partials, Gc);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, partials, Gc, ws.counters + 1, nullptr);
+  return hipGetLastError();
+}
+
+int tile_bits(uint32_t total_tiles) {
+  int b = 0;
+  while (b < 32 && ((uint64_t)1 << b) < (uint64_t)total_tiles) ++b;
+  return b;
+}
+
+hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* rec, const uint32_t* count,
+                           uint32_t n_pairs, uint32_t total_tiles, const BinWs& ws, uint32_t* keys, uint32_t* vals,
+                           uint32_t* keys_alt, uint32_t* vals_alt, uint32_t* ranges, uint32_t capacity,
+                           hipStream_t stream) {
+  (void)n_frames;
+  uint64_t* partials = (uint64_t*)ws.partials;
+  uint64_t* ptmp = (uint64_t*)ws.partials_tmp;
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1), 0, stream, ws.counters, capacity);
+  const int bits = tile_bits(total_tiles);
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  uint32_t* ek = (passes % 2) ? keys_alt : keys;
+  uint32_t* ev = (passes % 2) ? vals_alt : vals;
+  uint32_t* ok = (passes % 2) ? keys : keys_alt;
+  uint32_t* ov = (passes % 2) ? vals : vals_alt;
+  const int Gc = scan_blocks(n_pairs);
+  if (capacity > 0) {
+    hipLaunchKernelGGL(emit_kernel, dim3(Gc), dim3(kThreads), 0, stream, descs, rec, count, ws.dvalA,
+                       ws.counters + 0, n_pairs, partials, Gc, ek, ev, capacity);
+    if (passes > 0) {
+      hipError_t e = radix_sort(ek, ev, ok, ov, ws.counters + 4, capacity, bits, ws.hist, ptmp, stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  const int64_t rn = 2 * (int64_t)total_tiles;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(rn, kThreads * 4, 4096)), dim3(kThreads), 0, stream, ranges, rn,
+                     0u);
+  if (capacity > 0)
+    hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(capacity, kThreads * 4, 8192)), dim3(kThreads), 0, stream,
+                       keys, ws.counters + 4, capacity, ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* dst, int64_t count, uint32_t value, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(count, kThreads * 4, 8192)), dim3(kThreads), 0, stream, dst, count,
+                     value);
+  return hipGetLastError();
+}
+
+}  // namespace veg

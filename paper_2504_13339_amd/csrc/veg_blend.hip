@@ -1,0 +1,287 @@
+// Front-to-back blending (paper, Eq. 1) and its adjoint.
+//
+// One 64-lane wave per 16x16 tile; lane l owns the four pixels of column l & 15, rows
+// 4*(l >> 4) .. +3, so the x-offset work of an entry is shared by its four pixels.  The
+// tile's list is staged through LDS in batches of 64 entries: each lane fetches one
+// record, turns it into tile-local, log2-scaled form, and the wave then walks the batch
+// with every lane reading the same LDS slot (a broadcast).  A pixel stops after the
+// Gaussian that takes its transmittance below t_min; the wave leaves the tile when all 256
+// pixels have stopped (ballot).
+//
+// Forward and backward must take identical skip decisions, so both evaluate the exponent
+// through the same inline functions, written with explicit fmaf and no contraction.
+#include "veg_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace veg {
+namespace {
+
+constexpr int kBatch = 64;
+constexpr float kLog2e = 0x1.715476p+0f;
+
+struct Staged {
+  float mx, my;   // centre relative to the tile origin (pixels)
+  float q0, q1, q2;  // conic scaled so that sigma * log2(e) = q0 dx^2 + q1 dx dy + q2 dy^2
+  float l2A;      // log2(A)
+};
+
+__device__ __forceinline__ Staged stage(const float4 r0, const float4 r1, const float4 r2, int tx, int ty) {
+  const uint32_t rect01 = __float_as_uint(r2.y);
+  const int x0 = (int)(rect01 & 0xffffu), y0 = (int)(rect01 >> 16);
+  Staged s;
+  // r0.x is measured from pixel 16*x0; the tile origin is 16*tx.  Exact in float32.
+  s.mx = r0.x - (float)(kTile * (tx - x0));
+  s.my = r0.y - (float)(kTile * (ty - y0));
+  s.q0 = r0.z * (0.5f * kLog2e);
+  s.q1 = r0.w * kLog2e;
+  s.q2 = r1.x * (0.5f * kLog2e);
+  s.l2A = __log2f(r1.y);
+  return s;
+}
+
+// log2 of A exp(-sigma) for a pixel centre at (px, py) in tile-local coordinates:
+//   base = l2A - q0 dx^2,  e = base - dy (q2 dy + q1 dx).
+__device__ __forceinline__ float exponent_base(float q0, float l2A, float dx) { return fmaf(-q0 * dx, dx, l2A); }
+__device__ __forceinline__ float exponent(float base, float q1dx, float q2, float dy) {
+  return fmaf(-dy, fmaf(q2, dy, q1dx), base);
+}
+
+__global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
+                                                       const float4* __restrict__ rec,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const uint2* __restrict__ ranges, float* __restrict__ image,
+                                                       float* __restrict__ tfinal, int32_t* __restrict__ nlast) {
+  const FrameDesc& d = descs[blockIdx.y];
+  const int tile = blockIdx.x;
+  if (tile >= d.tiles_x * d.tiles_y) return;
+  const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
+  const uint2 rg = ranges[d.tile_base + tile];
+  const int lane = threadIdx.x;
+  const int col = lane & 15, row0 = (lane >> 4) * 4;
+  const int px = tx * kTile + col;
+  const float pxl = (float)col + 0.5f;
+
+  __shared__ float4 s_geo[kBatch];   // mx, my, q0, q1
+  __shared__ float4 s_col[kBatch];   // q2, l2A, R, G
+  __shared__ float s_b[kBatch];      // B
+
+  float T[4], C[4][3];
+  int last[4];
+  bool done[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int py = ty * kTile + row0 + r;
+    T[r] = 1.0f;
+    C[r][0] = C[r][1] = C[r][2] = 0.0f;
+    last[r] = -1;
+    done[r] = !(px < d.W && py < d.H);
+  }
+  const float l2min = o.log2_alpha_min;
+  for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
+    if (__all(done[0] && done[1] && done[2] && done[3])) break;
+    const uint32_t j = base + lane;
+    if (j < rg.y) {
+      const uint32_t p = vals[j];
+      const float4* rp = rec + 3 * (size_t)p;
+      const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
+      const Staged s = stage(r0, r1, r2, tx, ty);
+      s_geo[lane] = make_float4(s.mx, s.my, s.q0, s.q1);
+      s_col[lane] = make_float4(s.q2, s.l2A, r1.z, r1.w);
+      s_b[lane] = r2.x;
+    }
+    __syncthreads();
+    const int n = (int)min((uint32_t)kBatch, rg.y - base);
+    for (int k = 0; k < n; ++k) {
+      const float4 g = s_geo[k];
+      const float4 c = s_col[k];
+      const float dx = pxl - g.x;
+      const float eb = exponent_base(g.z, c.y, dx);
+      const float q1dx = g.w * dx;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float dy = ((float)(row0 + r) + 0.5f) - g.y;
+        const float e = exponent(eb, q1dx, c.x, dy);
+        if (!done[r] && e >= l2min) {
+          const float a = __builtin_amdgcn_exp2f(e);
+          const float alpha = fminf(a, o.alpha_clamp);
+          const float w = alpha * T[r];
+          C[r][0] = fmaf(w, c.z, C[r][0]);
+          C[r][1] = fmaf(w, c.w, C[r][1]);
+          C[r][2] = fmaf(w, s_b[k], C[r][2]);
+          T[r] = fmaf(-alpha, T[r], T[r]);
+          last[r] = (int)(base + k);
+          if (T[r] < o.t_min) done[r] = true;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const size_t HW = (size_t)d.W * d.H;
+  const bool own = d.out_image != nullptr;   // per-frame outputs (server batches)
+  float* img = own ? d.out_image : image + (size_t)blockIdx.y * 3 * HW;
+  float* tf = own ? d.out_tfinal : (tfinal ? tfinal + (size_t)blockIdx.y * HW : nullptr);
+  int32_t* nl = own ? d.out_nlast : (nlast ? nlast + (size_t)blockIdx.y * HW : nullptr);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int py = ty * kTile + row0 + r;
+    if (px < d.W && py < d.H) {
+      const size_t pi = (size_t)py * d.W + px;
+      img[pi] = C[r][0] + T[r] * o.bg0;
+      img[HW + pi] = C[r][1] + T[r] * o.bg1;
+      img[2 * HW + pi] = C[r][2] + T[r] * o.bg2;
+      if (tf) tf[pi] = T[r];
+      if (nl) nl[pi] = last[r];
+    }
+  }
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+
+__global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
+                                                       const float4* __restrict__ rec,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const uint2* __restrict__ ranges,
+                                                       const float* __restrict__ tfinal,
+                                                       const int32_t* __restrict__ nlast,
+                                                       const float* __restrict__ dimage, float* __restrict__ g2d,
+                                                       uint32_t n_pairs) {
+  const FrameDesc& d = descs[blockIdx.y];
+  const int tile = blockIdx.x;
+  if (tile >= d.tiles_x * d.tiles_y) return;
+  const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
+  const uint2 rg = ranges[d.tile_base + tile];
+  if (rg.y <= rg.x) return;
+  const int lane = threadIdx.x;
+  const int col = lane & 15, row0 = (lane >> 4) * 4;
+  const int px = tx * kTile + col;
+  const float pxl = (float)col + 0.5f;
+  const size_t HW = (size_t)d.W * d.H;
+  const float* tfp = tfinal + (size_t)blockIdx.y * HW;
+  const int32_t* nlp = nlast + (size_t)blockIdx.y * HW;
+  const float* dip = dimage + (size_t)blockIdx.y * 3 * HW;
+
+  __shared__ float4 s_geo[kBatch];   // mx, my, q0, q1
+  __shared__ float4 s_q[kBatch];     // q2, l2A, 1/A, pair id (bits)
+  __shared__ float4 s_con[kBatch];   // conic a, b, c, B
+  __shared__ float2 s_rg[kBatch];    // R, G
+
+  float T[4], S[4][3], gr[4][3];
+  int last[4];
+  int jmax = -1;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int py = ty * kTile + row0 + r;
+    const bool in = px < d.W && py < d.H;
+    const size_t pi = (size_t)py * d.W + px;
+    T[r] = in ? tfp[pi] : 1.0f;
+    last[r] = in ? nlp[pi] : -1;
+    gr[r][0] = in ? dip[pi] : 0.0f;
+    gr[r][1] = in ? dip[HW + pi] : 0.0f;
+    gr[r][2] = in ? dip[2 * HW + pi] : 0.0f;
+    S[r][0] = o.bg0;
+    S[r][1] = o.bg1;
+    S[r][2] = o.bg2;
+    jmax = max(jmax, last[r]);
+  }
+  jmax = min(wave_max_i32(jmax), (int)rg.y - 1);   // n_last lies inside this tile's range
+  if (jmax < (int)rg.x) return;
+  const float l2min = o.log2_alpha_min;
+  const float aclamp = o.alpha_clamp;
+  for (int hi = jmax + 1; hi > (int)rg.x; hi -= kBatch) {
+    const int lo = max((int)rg.x, hi - kBatch);
+    const int j = lo + lane;
+    if (j < hi) {
+      const uint32_t p = vals[j];
+      const float4* rp = rec + 3 * (size_t)p;
+      const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
+      const Staged s = stage(r0, r1, r2, tx, ty);
+      s_geo[lane] = make_float4(s.mx, s.my, s.q0, s.q1);
+      s_q[lane] = make_float4(s.q2, s.l2A, 1.0f / r1.y, __uint_as_float(p));
+      s_con[lane] = make_float4(r0.z, r0.w, r1.x, r2.x);
+      s_rg[lane] = make_float2(r1.z, r1.w);
+    }
+    __syncthreads();
+    for (int k = hi - 1 - lo; k >= 0; --k) {
+      const int jj = lo + k;
+      const float4 g = s_geo[k];
+      const float4 q = s_q[k];
+      const float4 cn = s_con[k];
+      const float2 rgc = s_rg[k];
+      const float rgbv[3] = {rgc.x, rgc.y, cn.w};
+      const float dx = pxl - g.x;
+      const float eb = exponent_base(g.z, q.y, dx);
+      const float q1dx = g.w * dx;
+      float acc[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+      bool contrib = false;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float dy = ((float)(row0 + r) + 0.5f) - g.y;
+        const float e = exponent(eb, q1dx, q.x, dy);
+        if (jj <= last[r] && e >= l2min) {
+          contrib = true;
+          const float a = __builtin_amdgcn_exp2f(e);
+          const bool clamped = !(a < aclamp);
+          const float alpha = clamped ? aclamp : a;
+          const float Tk = T[r] * __builtin_amdgcn_rcpf(1.0f - alpha);
+          const float w = alpha * Tk;
+          float dalpha = 0.0f;
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const float diff = rgbv[ch] - S[r][ch];
+            acc[5 + ch] = fmaf(w, gr[r][ch], acc[5 + ch]);
+            dalpha = fmaf(gr[r][ch], diff, dalpha);
+            S[r][ch] = fmaf(alpha, diff, S[r][ch]);
+          }
+          dalpha *= Tk;
+          T[r] = Tk;
+          if (!clamped) {
+            const float dsig = -dalpha * a;          // dL/dsigma
+            acc[8] = fmaf(dalpha * a, q.z, acc[8]);  // dL/dA = dL/dalpha * exp(-sigma)
+            acc[2] = fmaf(0.5f * dx * dx, dsig, acc[2]);
+            acc[3] = fmaf(dx * dy, dsig, acc[3]);
+            acc[4] = fmaf(0.5f * dy * dy, dsig, acc[4]);
+            acc[0] = fmaf(-dsig, fmaf(cn.x, dx, cn.y * dy), acc[0]);
+            acc[1] = fmaf(-dsig, fmaf(cn.y, dx, cn.z * dy), acc[1]);
+          }
+        }
+      }
+      if (__any(contrib)) {
+        const uint32_t p = __float_as_uint(q.w);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const float v = wave_sum_to_lane63(acc[c]);
+          if (lane == 63 && v != 0.0f) unsafeAtomicAdd(g2d + (size_t)c * n_pairs + p, v);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o, const float4* rec,
+                            const uint32_t* vals, const uint32_t* ranges, float* image, float* tfinal, int32_t* nlast,
+                            hipStream_t stream) {
+  if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(blend_fwd_kernel, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
+                     (const uint2*)ranges, image, tfinal, nlast);
+  return hipGetLastError();
+}
+
+hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o, const float4* rec,
+                            const uint32_t* vals, const uint32_t* ranges, const float* tfinal, const int32_t* nlast,
+                            const float* dimage, float* g2d, uint32_t n_pairs, hipStream_t stream) {
+  if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(blend_bwd_kernel, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
+                     (const uint2*)ranges, tfinal, nlast, dimage, g2d, n_pairs);
+  return hipGetLastError();
+}
+
+}  // namespace veg

@@ -1,0 +1,151 @@
+// Internal declarations shared by the HIP translation units of libveg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "veg.h"
+
+namespace veg {
+
+constexpr int kTile = VEG_TILE;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// Per-frame descriptor in device memory.  The stateless API writes one per frame in
+// veg_project; the server writes one per request of a batch.  Kernels read it with
+// wave-uniform (scalar) loads.
+struct alignas(16) FrameDesc {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* scalars;
+  const float* weights;      // may be null
+  const float* lut;          // [K,4]
+  float* out_image;          // per-frame outputs (server); null in the stateless API
+  float* out_tfinal;
+  int32_t* out_nlast;
+  int32_t K;
+  int32_t n;                 // Gaussians of this frame
+  int32_t W, H, tiles_x, tiles_y;
+  uint32_t pair_base;        // first pair id of this frame
+  uint32_t tile_base;        // first global tile id of this frame
+  uint32_t pix_base;         // first pixel of this frame in batched per-pixel buffers
+  uint32_t pad0;
+  float view[12];
+  float fx, fy, cx, cy;
+  float bg[3];
+  float pad1;
+};
+static_assert(sizeof(FrameDesc) == 192, "FrameDesc layout");
+
+// Options as the kernels use them (derived once on the host).
+struct KOpts {
+  float alpha_clamp, alpha_min, t_min, lowpass, near_z, guard;
+  float log2_alpha_min;      // skip test in the log2 domain of the blend kernels
+  float bg0, bg1, bg2;
+};
+
+// ---------------------------------------------------------------------------------------
+// wave64 primitives (DPP)
+// ---------------------------------------------------------------------------------------
+
+// DPP controls (gfx9): row_shr:n = 0x110+n, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_shift(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (lanes that are inactive contribute
+// whatever they hold, so call with the whole wave active).  Row-level Hillis-Steele steps
+// with row_shr 1,2,4,8, then row_bcast:15 and row_bcast:31 carry the row totals.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  v += dpp_shift<0x111, 0xf>(v);
+  v += dpp_shift<0x112, 0xf>(v);
+  v += dpp_shift<0x114, 0xf>(v);
+  v += dpp_shift<0x118, 0xf>(v);
+  v += dpp_shift<0x142, 0xa>(v);
+  v += dpp_shift<0x143, 0xc>(v);
+  return v;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_shift_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Sum over the 64 lanes; the total is valid in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += dpp_shift_f<0x111, 0xf>(v);
+  v += dpp_shift_f<0x112, 0xf>(v);
+  v += dpp_shift_f<0x114, 0xf>(v);
+  v += dpp_shift_f<0x118, 0xf>(v);
+  v += dpp_shift_f<0x142, 0xa>(v);
+  v += dpp_shift_f<0x143, 0xc>(v);
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// ---------------------------------------------------------------------------------------
+// Host-side launchers (one translation unit each)
+// ---------------------------------------------------------------------------------------
+
+// Copies `bytes` (multiple of 4, <= kBlobMaxBytes) from host to device through kernel
+// arguments, so the host buffer may be freed at once and no pageable copy is needed.
+constexpr int kBlobMaxBytes = 3072;
+hipError_t write_blob(void* dst_dev, const void* src_host, size_t bytes, hipStream_t stream);
+
+hipError_t launch_project(const FrameDesc* descs, int n_frames, int n_max, const KOpts& o,
+                          float4* rec, uint32_t* count, uint32_t* depth, bool shared_model,
+                          hipStream_t stream);
+hipError_t launch_project_bwd(const FrameDesc* descs, int n_frames, int n, const KOpts& o,
+                              const float* g2d, uint32_t n_pairs, float* d_means, float* d_ls,
+                              float* d_quats, float* d_scalars, float* d_weights, hipStream_t stream);
+
+// Binning pipeline (workspace-based).  `pairs` and `capacity` bound the device counts.
+struct BinWs {
+  uint32_t* dkeyA;
+  uint32_t* dvalA;
+  uint32_t* dkeyB;
+  uint32_t* dvalB;
+  uint32_t* partials;       // [kMaxScanBlocks] uint64: entry-offset scan, kept from count to sort
+  uint32_t* partials_tmp;   // [kMaxScanBlocks] uint64: scratch for the other scans
+  uint32_t* hist;       // [kRadix * kMaxSortBlocks]
+  uint32_t* counters;   // [0] kept pairs V, [1..2] entries E (uint64), [3] overflow flag,
+                        // [4] entries written min(E, capacity), [8..9] V (uint64)
+  uint32_t* depth_sorted_vals;  // points at whichever of dvalA/dvalB holds the sorted result
+};
+constexpr int kMaxScanBlocks = 4096;
+constexpr int kMaxSortBlocks = 2048;
+size_t bin_ws_bytes(int64_t pairs);
+void carve_bin_ws(void* ws, int64_t pairs, BinWs* out);
+
+hipError_t launch_bin_count(const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,
+                            const BinWs& ws, hipStream_t stream);
+hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* rec,
+                           const uint32_t* count, uint32_t n_pairs, uint32_t total_tiles,
+                           const BinWs& ws, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                           uint32_t* vals_alt, uint32_t* ranges, uint32_t capacity,
+                           hipStream_t stream);
+
+hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
+                            const float4* rec, const uint32_t* vals, const uint32_t* ranges,
+                            float* image, float* tfinal, int32_t* nlast, hipStream_t stream);
+hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
+                            const float4* rec, const uint32_t* vals, const uint32_t* ranges,
+                            const float* tfinal, const int32_t* nlast, const float* dimage,
+                            float* g2d, uint32_t n_pairs, hipStream_t stream);
+
+hipError_t launch_l1(const float* image, const float* target, int64_t count, float scale,
+                     double* loss, float* dimage, hipStream_t stream);
+hipError_t launch_fill_u32(uint32_t* dst, int64_t count, uint32_t value, hipStream_t stream);
+hipError_t launch_debug_math(int op, const float* x, const float* y, float* out, int64_t n,
+                             hipStream_t stream);
+
+}  // namespace veg

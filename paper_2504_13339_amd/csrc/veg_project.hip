@@ -1,0 +1,431 @@
+// Projection (transfer function first, EWA projection, footprint) and its adjoint.
+//
+// Paper, section "Rendering of VEGs": the transfer function maps each Gaussian's scalar to
+// colour and opacity before rasterizing (alpha = O(v) w), so low-opacity Gaussians are culled
+// at once; the 3D covariance from S and R is projected to a 2D screen covariance with
+// Zwicker's EWA method.  Gradients reach position, scaling, rotation, scalar and weight.
+//
+// The whole file is compiled without floating-point contraction so that the footprint (cull,
+// depth key, tile rectangle) follows the documented operation order bit for bit.
+#include "veg_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace veg {
+namespace {
+
+// float32 exp: Cody & Waite reduction x = k ln2 + r (ln2 split in a short high part and a
+// correction), exp(r) by the Taylor series to r^7 in Horner form, scaled by 2^k exactly.
+// x >= 88 gives +inf, x < -87 gives 0.
+__device__ __forceinline__ float exp32(float x) {
+  const float kLog2e = 0x1.715476p+0f;
+  const float kLn2Hi = 0.693359375f;
+  const float kLn2Lo = -0x1.bd0106p-13f;
+  const float k = floorf(x * kLog2e + 0.5f);
+  const float r = (x - k * kLn2Hi) - k * kLn2Lo;
+  float p = 1.0f / 5040.0f;
+  p = p * r + 1.0f / 720.0f;
+  p = p * r + 1.0f / 120.0f;
+  p = p * r + 1.0f / 24.0f;
+  p = p * r + 1.0f / 6.0f;
+  p = p * r + 1.0f / 2.0f;
+  p = p * r + 1.0f;
+  p = p * r + 1.0f;
+  const int ki = (int)fminf(fmaxf(k, -126.0f), 127.0f);
+  float out = p * __uint_as_float((uint32_t)(ki + 127) << 23);
+  if (x >= 88.0f) out = __builtin_inff();
+  if (x < -87.0f) out = 0.0f;
+  return out;
+}
+
+// float32 log for positive normal x: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
+// log m = 2 atanh(u), u = (m-1)/(m+1), odd series to u^9 (Horner in u^2),
+// log x = e ln2_hi + (e ln2_lo + log m).
+__device__ __forceinline__ float log32(float x) {
+  const float kLn2Hi = 0.693359375f;
+  const float kLn2Lo = -0x1.bd0106p-13f;
+  const float kSqrt2 = 0x1.6a09e6p+0f;
+  const uint32_t bits = __float_as_uint(x);
+  int e = (int)(bits >> 23) - 127;
+  float m = __uint_as_float((bits & 0x7fffffu) | 0x3f800000u);
+  if (m > kSqrt2) {
+    m = m * 0.5f;
+    e += 1;
+  }
+  const float u = (m - 1.0f) / (m + 1.0f);
+  const float u2 = u * u;
+  float p = 1.0f / 9.0f;
+  p = p * u2 + 1.0f / 7.0f;
+  p = p * u2 + 1.0f / 5.0f;
+  p = p * u2 + 1.0f / 3.0f;
+  const float s = p * u2;
+  const float t = u + u * s;
+  const float logm = t + t;
+  const float ef = (float)e;
+  return ef * kLn2Hi + (ef * kLn2Lo + logm);
+}
+
+__device__ __forceinline__ bool finite3(const float* p) {
+  return __builtin_isfinite(p[0]) && __builtin_isfinite(p[1]) && __builtin_isfinite(p[2]);
+}
+
+// Frame-independent per-Gaussian state.
+struct GParams {
+  float mu[3];
+  float ls[3];
+  float q[4];
+  float v, w;
+  bool finite;
+  float n2, inv;       // |q|^2, 1/|q|
+  float qh[4];         // normalised quaternion
+  float R[9];          // rotation, row-major
+  float s[3];          // scales
+};
+
+__device__ __forceinline__ void load_params(const FrameDesc& d, int i, GParams& g) {
+  const float* m = d.means + 3 * (size_t)i;
+  const float* l = d.log_scales + 3 * (size_t)i;
+  const float4 qq = *reinterpret_cast<const float4*>(d.quats + 4 * (size_t)i);
+  g.mu[0] = m[0]; g.mu[1] = m[1]; g.mu[2] = m[2];
+  g.ls[0] = l[0]; g.ls[1] = l[1]; g.ls[2] = l[2];
+  g.q[0] = qq.x; g.q[1] = qq.y; g.q[2] = qq.z; g.q[3] = qq.w;
+  g.v = d.scalars[i];
+  g.w = d.weights ? d.weights[i] : 1.0f;
+  g.finite = finite3(g.mu) && finite3(g.ls) && __builtin_isfinite(g.q[0]) && __builtin_isfinite(g.q[1]) &&
+             __builtin_isfinite(g.q[2]) && __builtin_isfinite(g.q[3]) && __builtin_isfinite(g.v) &&
+             __builtin_isfinite(g.w);
+  g.n2 = ((g.q[0] * g.q[0] + g.q[1] * g.q[1]) + g.q[2] * g.q[2]) + g.q[3] * g.q[3];
+  g.inv = 1.0f / sqrtf(g.n2);
+  const float w = g.q[0] * g.inv, x = g.q[1] * g.inv, y = g.q[2] * g.inv, z = g.q[3] * g.inv;
+  g.qh[0] = w; g.qh[1] = x; g.qh[2] = y; g.qh[3] = z;
+  g.R[0] = 1.0f - 2.0f * (y * y + z * z);
+  g.R[1] = 2.0f * (x * y - w * z);
+  g.R[2] = 2.0f * (x * z + w * y);
+  g.R[3] = 2.0f * (x * y + w * z);
+  g.R[4] = 1.0f - 2.0f * (x * x + z * z);
+  g.R[5] = 2.0f * (y * z - w * x);
+  g.R[6] = 2.0f * (x * z - w * y);
+  g.R[7] = 2.0f * (y * z + w * x);
+  g.R[8] = 1.0f - 2.0f * (x * x + y * y);
+  g.s[0] = exp32(g.ls[0]);
+  g.s[1] = exp32(g.ls[1]);
+  g.s[2] = exp32(g.ls[2]);
+}
+
+struct TfSample {
+  float rgb[3], O;
+  float slope[4];   // d/dv of R,G,B,O on the active segment (0 outside [0,1])
+};
+
+__device__ __forceinline__ void tf_lookup(const FrameDesc& d, float v, TfSample& t) {
+  const float vc = v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v);
+  const float tp = vc * (float)(d.K - 1);
+  int i = (int)floorf(tp);
+  if (i > d.K - 2) i = d.K - 2;
+  const float fr = tp - (float)i;
+  const float om = 1.0f - fr;
+  const float4 L0 = reinterpret_cast<const float4*>(d.lut)[i];
+  const float4 L1 = reinterpret_cast<const float4*>(d.lut)[i + 1];
+  t.rgb[0] = L0.x * om + L1.x * fr;
+  t.rgb[1] = L0.y * om + L1.y * fr;
+  t.rgb[2] = L0.z * om + L1.z * fr;
+  t.O = L0.w * om + L1.w * fr;
+  const bool in = (v >= 0.0f) && (v <= 1.0f);
+  const float km1 = (float)(d.K - 1);
+  t.slope[0] = in ? (L1.x - L0.x) * km1 : 0.0f;
+  t.slope[1] = in ? (L1.y - L0.y) * km1 : 0.0f;
+  t.slope[2] = in ? (L1.z - L0.z) * km1 : 0.0f;
+  t.slope[3] = in ? (L1.w - L0.w) * km1 : 0.0f;
+}
+
+// Per-frame projection of one Gaussian (footprint contract of veg_project).
+struct Proj {
+  double tx, ty, tz, xn, yn, mx, my;
+  float depth;
+  float xc, yc;
+  bool clampx, clampy;
+  float J00, J02, J11, J12;
+  float Q[9], P[9];
+  float G0[3], G1[3];
+  float S00, S01, S11, det;
+};
+
+__device__ __forceinline__ void project_one(const FrameDesc& d, const KOpts& o, const GParams& g, Proj& p) {
+  const float* V = d.view;
+  p.tx = (((double)V[0] * g.mu[0] + (double)V[1] * g.mu[1]) + (double)V[2] * g.mu[2]) + (double)V[3];
+  p.ty = (((double)V[4] * g.mu[0] + (double)V[5] * g.mu[1]) + (double)V[6] * g.mu[2]) + (double)V[7];
+  p.tz = (((double)V[8] * g.mu[0] + (double)V[9] * g.mu[1]) + (double)V[10] * g.mu[2]) + (double)V[11];
+  p.depth = (float)p.tz;
+  p.xn = p.tx / p.tz;
+  p.yn = p.ty / p.tz;
+  p.mx = (double)d.fx * p.xn + (double)d.cx;
+  p.my = (double)d.fy * p.yn + (double)d.cy;
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) {
+      p.Q[3 * j + k] = (V[4 * j + 0] * g.R[k] + V[4 * j + 1] * g.R[3 + k]) + V[4 * j + 2] * g.R[6 + k];
+      p.P[3 * j + k] = p.Q[3 * j + k] * g.s[k];
+    }
+  const float limx = o.guard * ((0.5f * (float)d.W) / d.fx);
+  const float limy = o.guard * ((0.5f * (float)d.H) / d.fy);
+  const float xnf = (float)p.xn, ynf = (float)p.yn;
+  p.xc = fminf(fmaxf(xnf, -limx), limx);
+  p.yc = fminf(fmaxf(ynf, -limy), limy);
+  p.clampx = (xnf < -limx) || (xnf > limx);
+  p.clampy = (ynf < -limy) || (ynf > limy);
+  p.J00 = d.fx / p.depth;
+  p.J02 = -(d.fx * p.xc) / p.depth;
+  p.J11 = d.fy / p.depth;
+  p.J12 = -(d.fy * p.yc) / p.depth;
+  for (int k = 0; k < 3; ++k) {
+    p.G0[k] = p.J00 * p.P[k] + p.J02 * p.P[6 + k];
+    p.G1[k] = p.J11 * p.P[3 + k] + p.J12 * p.P[6 + k];
+  }
+  p.S00 = ((p.G0[0] * p.G0[0] + p.G0[1] * p.G0[1]) + p.G0[2] * p.G0[2]) + o.lowpass;
+  p.S01 = (p.G0[0] * p.G1[0] + p.G0[1] * p.G1[1]) + p.G0[2] * p.G1[2];
+  p.S11 = ((p.G1[0] * p.G1[0] + p.G1[1] * p.G1[1]) + p.G1[2] * p.G1[2]) + o.lowpass;
+  p.det = p.S00 * p.S11 - p.S01 * p.S01;
+}
+
+struct Blob {
+  uint32_t w[kBlobMaxBytes / 4];
+};
+
+__global__ __launch_bounds__(256) void blob_kernel(uint32_t* dst, const uint32_t nwords, const Blob blob) {
+  for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = blob.w[i];
+}
+
+// One thread per Gaussian; blockIdx.y selects a chunk of `fpb` frames processed in a loop,
+// so a model shared by the frames is read from HBM once per chunk.
+__global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restrict__ descs, int n_frames,
+                                                      int fpb, KOpts o, float4* __restrict__ rec,
+                                                      uint32_t* __restrict__ count,
+                                                      uint32_t* __restrict__ depth) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int f0 = blockIdx.y * fpb;
+  const int f1 = min(n_frames, f0 + fpb);
+  GParams g;
+  const float* cur = nullptr;
+  const float* cur_v = nullptr;
+  const float* cur_w = nullptr;
+  for (int f = f0; f < f1; ++f) {
+    const FrameDesc& d = descs[f];
+    if (i >= d.n) continue;
+    if (d.means != cur || d.scalars != cur_v || d.weights != cur_w) {
+      load_params(d, i, g);
+      cur = d.means;
+      cur_v = d.scalars;
+      cur_w = d.weights;
+    }
+    const uint32_t pid = d.pair_base + (uint32_t)i;
+    bool keep = g.finite && g.n2 >= 1e-24f;
+    TfSample tf;
+    tf_lookup(d, keep ? g.v : 0.0f, tf);
+    const float A = tf.O * g.w;
+    keep = keep && (A >= o.alpha_min);
+    Proj p;
+    project_one(d, o, g, p);
+    keep = keep && (p.depth > o.near_z) && (p.det > 0.0f);
+    if (!keep) {
+      count[pid] = 0u;
+      continue;
+    }
+    const float tau = 2.0f * log32(A / o.alpha_min);
+    const float ex = sqrtf(tau * p.S00);
+    const float ey = sqrtf(tau * p.S11);
+    double xlo = ceil((p.mx - (double)ex) - 0.5);
+    double xhi = floor((p.mx + (double)ex) - 0.5);
+    double ylo = ceil((p.my - (double)ey) - 0.5);
+    double yhi = floor((p.my + (double)ey) - 0.5);
+    xlo = fmax(xlo, 0.0);
+    ylo = fmax(ylo, 0.0);
+    xhi = fmin(xhi, (double)(d.W - 1));
+    yhi = fmin(yhi, (double)(d.H - 1));
+    if (!(xlo <= xhi) || !(ylo <= yhi)) {
+      count[pid] = 0u;
+      continue;
+    }
+    const uint32_t x0 = (uint32_t)xlo / kTile, x1 = (uint32_t)xhi / kTile;
+    const uint32_t y0 = (uint32_t)ylo / kTile, y1 = (uint32_t)yhi / kTile;
+    count[pid] = (x1 - x0 + 1) * (y1 - y0 + 1);
+    depth[pid] = __float_as_uint(p.depth);
+    const float c0 = p.S11 / p.det, c1 = -p.S01 / p.det, c2 = p.S00 / p.det;
+    const float mxr = (float)(p.mx - 16.0 * (double)x0);
+    const float myr = (float)(p.my - 16.0 * (double)y0);
+    float4* r = rec + 3 * (size_t)pid;
+    r[0] = make_float4(mxr, myr, c0, c1);
+    r[1] = make_float4(c2, A, tf.rgb[0], tf.rgb[1]);
+    r[2] = make_float4(tf.rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
+                       __uint_as_float((uint32_t)f));
+  }
+}
+
+// Adjoint of the projection: one thread per Gaussian, loop over the frames (which share the
+// model), accumulate in registers, add once to the parameter gradients.
+__global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __restrict__ descs, int n_frames,
+                                                          int n, KOpts o, const float* __restrict__ g2d,
+                                                          uint32_t n_pairs, float* __restrict__ d_means,
+                                                          float* __restrict__ d_ls, float* __restrict__ d_quats,
+                                                          float* __restrict__ d_scalars,
+                                                          float* __restrict__ d_weights) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  GParams g;
+  load_params(descs[0], i, g);
+  if (!g.finite || !(g.n2 >= 1e-24f)) return;
+  float dmu[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ds[3] = {0, 0, 0};
+  float dv = 0.0f, dw = 0.0f;
+  for (int f = 0; f < n_frames; ++f) {
+    const FrameDesc& d = descs[f];
+    const size_t pid = (size_t)d.pair_base + (size_t)i;
+    float gg[9];
+    bool any = false;
+    for (int c = 0; c < 9; ++c) {
+      gg[c] = g2d[(size_t)c * n_pairs + pid];
+      any |= (gg[c] != 0.0f);
+    }
+    if (!any) continue;
+    Proj p;
+    project_one(d, o, g, p);
+    TfSample tf;
+    tf_lookup(d, g.v, tf);
+    const float dmx = gg[0], dmy = gg[1], dc0 = gg[2], dc1 = gg[3], dc2 = gg[4];
+    const float dA = gg[8];
+    // transfer function: A = O w, rgb = C(v)
+    dv += (dA * g.w) * tf.slope[3] + gg[5] * tf.slope[0] + gg[6] * tf.slope[1] + gg[7] * tf.slope[2];
+    dw += dA * tf.O;
+    // projected centre
+    const float tz = p.depth;
+    const float invz = 1.0f / tz;
+    const float xn = (float)p.xn, yn = (float)p.yn;
+    float dt[3];
+    dt[0] = dmx * d.fx * invz;
+    dt[1] = dmy * d.fy * invz;
+    dt[2] = -(dmx * d.fx * xn + dmy * d.fy * yn) * invz;
+    // conic = inverse(S)
+    const float c0 = p.S11 / p.det, c1 = -p.S01 / p.det, c2 = p.S00 / p.det;
+    const float dS00 = -(dc0 * c0 * c0 + dc1 * c0 * c1 + dc2 * c1 * c1);
+    const float dS11 = -(dc0 * c1 * c1 + dc1 * c1 * c2 + dc2 * c2 * c2);
+    const float dS01 = -(2.0f * dc0 * c0 * c1 + dc1 * (c0 * c2 + c1 * c1) + 2.0f * dc2 * c1 * c2);
+    // S = G G^T + lowpass I
+    float dG0[3], dG1[3];
+    for (int k = 0; k < 3; ++k) {
+      dG0[k] = 2.0f * dS00 * p.G0[k] + dS01 * p.G1[k];
+      dG1[k] = 2.0f * dS11 * p.G1[k] + dS01 * p.G0[k];
+    }
+    // G = J P
+    float dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0, dP[9];
+    for (int k = 0; k < 3; ++k) {
+      dJ00 += dG0[k] * p.P[k];
+      dJ02 += dG0[k] * p.P[6 + k];
+      dJ11 += dG1[k] * p.P[3 + k];
+      dJ12 += dG1[k] * p.P[6 + k];
+      dP[k] = p.J00 * dG0[k];
+      dP[3 + k] = p.J11 * dG1[k];
+      dP[6 + k] = p.J02 * dG0[k] + p.J12 * dG1[k];
+    }
+    // J(t): J00 = fx/z, J11 = fy/z, J02 = -fx xc/z, J12 = -fy yc/z (xc = x/z unless clamped)
+    dt[2] += -dJ00 * p.J00 * invz - dJ11 * p.J11 * invz;
+    if (!p.clampx) {
+      dt[0] += dJ02 * (-d.fx * invz * invz);
+      dt[2] += dJ02 * (-2.0f * p.J02 * invz);
+    } else {
+      dt[2] += dJ02 * (-p.J02 * invz);
+    }
+    if (!p.clampy) {
+      dt[1] += dJ12 * (-d.fy * invz * invz);
+      dt[2] += dJ12 * (-2.0f * p.J12 * invz);
+    } else {
+      dt[2] += dJ12 * (-p.J12 * invz);
+    }
+    // P = Q diag(s), Q = Vr R, t = Vr mu + b
+    const float* V = d.view;
+    for (int k = 0; k < 3; ++k) {
+      float dQ[3];
+      for (int j = 0; j < 3; ++j) {
+        dQ[j] = dP[3 * j + k] * g.s[k];
+        ds[k] += dP[3 * j + k] * p.Q[3 * j + k];
+      }
+      for (int m = 0; m < 3; ++m) dR[3 * m + k] += V[m] * dQ[0] + V[4 + m] * dQ[1] + V[8 + m] * dQ[2];
+    }
+    for (int m = 0; m < 3; ++m) dmu[m] += V[m] * dt[0] + V[4 + m] * dt[1] + V[8 + m] * dt[2];
+  }
+  // rotation from the normalised quaternion (w,x,y,z)
+  const float w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
+  float dqh[4];
+  dqh[0] = -2 * z * dR[1] + 2 * y * dR[2] + 2 * z * dR[3] - 2 * x * dR[5] - 2 * y * dR[6] + 2 * x * dR[7];
+  dqh[1] = 2 * y * dR[1] + 2 * z * dR[2] + 2 * y * dR[3] - 4 * x * dR[4] - 2 * w * dR[5] + 2 * z * dR[6] +
+           2 * w * dR[7] - 4 * x * dR[8];
+  dqh[2] = -4 * y * dR[0] + 2 * x * dR[1] + 2 * w * dR[2] + 2 * x * dR[3] + 2 * z * dR[5] - 2 * w * dR[6] +
+           2 * z * dR[7] - 4 * y * dR[8];
+  dqh[3] = -4 * z * dR[0] - 2 * w * dR[1] + 2 * x * dR[2] + 2 * w * dR[3] - 4 * z * dR[4] + 2 * y * dR[5] +
+           2 * x * dR[6] + 2 * y * dR[7];
+  const float dot = dqh[0] * w + dqh[1] * x + dqh[2] * y + dqh[3] * z;
+  for (int k = 0; k < 3; ++k) {
+    d_means[3 * (size_t)i + k] += dmu[k];
+    d_ls[3 * (size_t)i + k] += ds[k] * g.s[k];
+  }
+  for (int k = 0; k < 4; ++k) d_quats[4 * (size_t)i + k] += (dqh[k] - g.qh[k] * dot) * g.inv;
+  d_scalars[i] += dv;
+  if (d_weights) d_weights[i] += dw;
+}
+
+__global__ void debug_math_kernel(int op, const float* x, const float* y, float* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (op == 4 || op == 5) {
+    // wave-level primitives: every lane of the wave must participate
+    const float xv = i < n ? x[i] : 0.0f;
+    float r;
+    if (op == 4) r = __uint_as_float(wave_incl_scan_u32(__float_as_uint(xv)));
+    else r = wave_sum_to_lane63(xv);
+    if (i < n) out[i] = r;
+    return;
+  }
+  if (i >= n) return;
+  float r = 0.0f;
+  switch (op) {
+    case 0: r = exp32(x[i]); break;
+    case 1: r = log32(x[i]); break;
+    case 2: r = x[i] / y[i]; break;
+    case 3: r = sqrtf(x[i]); break;
+    default: r = 0.0f;
+  }
+  out[i] = r;
+}
+
+}  // namespace
+
+hipError_t write_blob(void* dst_dev, const void* src_host, size_t bytes, hipStream_t stream) {
+  if (bytes % 4 != 0 || bytes > (size_t)kBlobMaxBytes) return hipErrorInvalidValue;
+  Blob b;
+  __builtin_memset(&b, 0, sizeof(b));
+  __builtin_memcpy(&b, src_host, bytes);
+  hipLaunchKernelGGL(blob_kernel, dim3(1), dim3(256), 0, stream, (uint32_t*)dst_dev, (uint32_t)(bytes / 4), b);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const FrameDesc* descs, int n_frames, int n_max, const KOpts& o, float4* rec,
+                          uint32_t* count, uint32_t* depth, bool shared_model, hipStream_t stream) {
+  if (n_frames <= 0 || n_max <= 0) return hipSuccess;
+  const int fpb = shared_model ? 8 : 1;
+  dim3 grid((n_max + 255) / 256, (n_frames + fpb - 1) / fpb);
+  hipLaunchKernelGGL(project_kernel, grid, dim3(256), 0, stream, descs, n_frames, fpb, o, rec, count, depth);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const FrameDesc* descs, int n_frames, int n, const KOpts& o, const float* g2d,
+                              uint32_t n_pairs, float* d_means, float* d_ls, float* d_quats, float* d_scalars,
+                              float* d_weights, hipStream_t stream) {
+  if (n <= 0 || n_frames <= 0) return hipSuccess;
+  hipLaunchKernelGGL(project_bwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, descs, n_frames, n, o, g2d,
+                     n_pairs, d_means, d_ls, d_quats, d_scalars, d_weights);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_math(int op, const float* x, const float* y, float* out, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(debug_math_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, op, x, y, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace veg

@@ -1,0 +1,208 @@
+"""Rendering, backward and the multi-view x multi-TF training step on top of the C ABI.
+
+All arithmetic runs in libveg's kernels; this module only sequences the calls and owns
+the device buffers (torch tensors).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import veg as V
+
+
+@dataclass
+class FwdState:
+    proj: V.Proj
+    bins: V.Bins
+    ws: torch.Tensor
+    image: torch.Tensor
+    t_final: torch.Tensor
+    n_last: torch.Tensor
+    n_entries: int
+    opts: object
+
+
+class _NoTimer:
+    def __call__(self, name):
+        return self
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
+
+
+NO_TIMER = _NoTimer()
+
+
+class EventTimer:
+    """Records HIP events on the current stream around named library calls; no host sync."""
+
+    def __init__(self):
+        self.pairs = {}
+        self._name = None
+
+    def __call__(self, name):
+        self._name = name
+        return self
+
+    def __enter__(self):
+        self._s = torch.cuda.Event(enable_timing=True)
+        self._e = torch.cuda.Event(enable_timing=True)
+        self._s.record()
+        return self
+
+    def __exit__(self, *a):
+        self._e.record()
+        self.pairs.setdefault(self._name, []).append((self._s, self._e))
+        return False
+
+    def totals_ms(self):
+        torch.cuda.synchronize()
+        return {k: [s.elapsed_time(e) for s, e in v] for k, v in self.pairs.items()}
+
+
+def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=None, stream=None,
+           capacity: Optional[int] = None, timer=NO_TIMER) -> FwdState:
+    """Forward render of len(cams) frames (one model, one image size).
+
+    With ``capacity`` None the key-list length is read back (one stream synchronisation)
+    and the buffers are sized exactly; otherwise ``capacity`` entries are allocated, no
+    synchronisation happens, and an overflow must be checked with ``veg_bin_overflow``."""
+    o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
+    dev = g.means.device
+    proj = V.alloc_proj(g.n, len(cams), device=dev)
+    ws = V.alloc_bin_workspace(proj, device=dev)
+    with timer("project"):
+        V.veg_project(g, cams, tfs, o, proj=proj, stream=stream)
+    with timer("bin_count"):
+        V.veg_bin_count(proj, ws, sync=False, stream=stream)
+    if capacity is None:
+        E, _ = V.veg_bin_overflow(ws, stream=stream)
+        cap = E
+    else:
+        E, cap = -1, int(capacity)
+    bins = V.alloc_bins(proj, cap, device=dev)
+    with timer("bin_sort"):
+        V.veg_bin_sort(proj, ws, bins, stream=stream)
+    F, H, W = len(cams), int(proj.struct.height), int(proj.struct.width)
+    image = torch.empty((F, 3, H, W), dtype=torch.float32, device=dev)
+    t_final = torch.empty((F, H, W), dtype=torch.float32, device=dev)
+    n_last = torch.empty((F, H, W), dtype=torch.int32, device=dev)
+    with timer("blend_fwd"):
+        V.veg_render_fwd(proj, bins, o, image, t_final, n_last, stream=stream)
+    return FwdState(proj, bins, ws, image, t_final, n_last, E, o)
+
+
+@dataclass
+class Grads:
+    d_means: torch.Tensor
+    d_log_scales: torch.Tensor
+    d_quats: torch.Tensor
+    d_scalars: torch.Tensor
+    d_weights: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def zeros(g: V.Gaussians, stream=None) -> "Grads":
+        def z(shape):
+            t = torch.empty(shape, dtype=torch.float32, device=g.means.device)
+            V.veg_fill_u32(t, 0, stream=stream)
+            return t
+        n = g.n
+        return Grads(z((n, 3)), z((n, 3)), z((n, 4)), z((n,)), z((n,)) if g.weights is not None else None)
+
+    def zero_(self, stream=None):
+        for t in (self.d_means, self.d_log_scales, self.d_quats, self.d_scalars, self.d_weights):
+            if t is not None:
+                V.veg_fill_u32(t, 0, stream=stream)
+
+
+def alloc_g2d(proj: V.Proj, stream=None) -> torch.Tensor:
+    g2d = torch.empty(max(1, 9 * proj.n_pairs), dtype=torch.float32, device=proj.rec.device)
+    V.veg_fill_u32(g2d, 0, stream=stream)
+    return g2d
+
+
+def render_backward(g: V.Gaussians, st: FwdState, d_image: torch.Tensor, grads: Grads, stream=None,
+                    g2d: Optional[torch.Tensor] = None, timer=NO_TIMER) -> torch.Tensor:
+    """Accumulates dL/dparams into ``grads`` given dL/dimage; returns the screen-space g2d."""
+    if g2d is None:
+        with timer("zero_g2d"):
+            g2d = alloc_g2d(st.proj, stream=stream)
+    with timer("blend_bwd"):
+        V.veg_render_bwd(st.proj, st.bins, st.opts, st.t_final, st.n_last, d_image.contiguous(), g2d, stream=stream)
+    with timer("project_bwd"):
+        V.veg_project_bwd(g, st.proj, st.opts, g2d, grads.d_means, grads.d_log_scales, grads.d_quats,
+                          grads.d_scalars, grads.d_weights, stream=stream)
+    return g2d
+
+
+class VEGRender(torch.autograd.Function):
+    """image[F,3,H,W] = render(means, log_scales, quats, scalars, weights; cams, tfs).
+
+    ``scalars`` and ``weights`` are the activated values (apply the sigmoid before)."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, scalars, weights, cams, tfs, opts):
+        g = V.Gaussians(means.detach().contiguous(), log_scales.detach().contiguous(), quats.detach().contiguous(),
+                        scalars.detach().contiguous(), None if weights is None else weights.detach().contiguous())
+        st = render(g, cams, tfs, opts)
+        ctx.g = g
+        ctx.st = st
+        ctx.has_w = weights is not None
+        return st.image
+
+    @staticmethod
+    def backward(ctx, d_image):
+        grads = Grads.zeros(ctx.g)
+        render_backward(ctx.g, ctx.st, d_image.contiguous(), grads)
+        return (grads.d_means, grads.d_log_scales, grads.d_quats, grads.d_scalars,
+                grads.d_weights if ctx.has_w else None, None, None, None)
+
+
+def render_autograd(means, log_scales, quats, scalars, weights, cams, tfs, opts=None):
+    return VEGRender.apply(means, log_scales, quats, scalars, weights, cams, tfs, opts)
+
+
+@dataclass
+class StepResult:
+    loss: float
+    n_entries: List[int]
+
+
+def train_step_l1(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], frames: Sequence[tuple],
+                  targets: torch.Tensor, grads: Grads, group: int, opts=None, stream=None,
+                  loss_acc: Optional[torch.Tensor] = None, read_loss: bool = True, timer=NO_TIMER,
+                  on_group=None) -> StepResult:
+    """One multi-view x multi-TF training step with L1 loss (mean over all frames).
+
+    Frames are processed in groups of ``group``: each group is projected, binned, blended,
+    differentiated and its key lists are released before the next group starts, so only
+    one group's per-pixel state is alive (forward recomputation per group instead of
+    storing all frames' lists).  The L1 mean is separable over frames, so the accumulated
+    gradient equals the full-step gradient."""
+    o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
+    F = len(frames)
+    H, W = int(targets.shape[-2]), int(targets.shape[-1])
+    scale = 1.0 / float(F * 3 * H * W)
+    if loss_acc is None:
+        loss_acc = torch.empty(1, dtype=torch.float64, device=g.means.device)
+    V.veg_fill_u32(loss_acc, 0, stream=stream)
+    entries = []
+    for f0 in range(0, F, group):
+        fr = frames[f0:f0 + group]
+        st = render(g, [cams[c] for c, _ in fr], [tfs[t] for _, t in fr], o, stream=stream, timer=timer)
+        entries.append(st.n_entries)
+        d_image = torch.empty_like(st.image)
+        with timer("l1_loss"):
+            V.veg_l1_loss(st.image, targets[f0:f0 + len(fr)].contiguous(), scale, loss_acc, d_image, stream=stream)
+        render_backward(g, st, d_image, grads, stream=stream, timer=timer)
+        if on_group is not None:
+            on_group(f0, st)
+        del st, d_image
+    loss = float(loss_acc.item()) if read_loss else float("nan")
+    return StepResult(loss, entries)

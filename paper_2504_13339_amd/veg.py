@@ -1,0 +1,228 @@
+"""Thin Python binding of libveg: the C entry points under the same names.
+
+Each function marshals torch tensors and Python objects into the C structs of
+include/veg.h and calls the library; every step of the rasterizer runs in the HIP kernels.
+Device memory is owned by torch tensors held in the small container classes below.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+__all__ = [
+    "Gaussians", "Proj", "Bins", "default_opts", "make_opts", "veg_project", "veg_bin_count", "veg_bin_sort",
+    "veg_bin_overflow", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
+    "veg_debug_math", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
+]
+
+
+def stream_handle(stream: Optional[torch.cuda.Stream] = None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Gaussians:
+    """Device SoA model: means [n,3], log_scales [n,3], quats [n,4], scalars [n], weights [n] or None."""
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    scalars: torch.Tensor
+    weights: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    def struct(self) -> _lib.veg_gaussians:
+        for name in ("means", "log_scales", "quats", "scalars", "weights"):
+            t = getattr(self, name)
+            if t is not None and t.dtype != torch.float32:
+                raise ValueError(f"{name} must be float32")
+        return _lib.veg_gaussians(self.n, _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats),
+                                  _ptr(self.scalars), _ptr(self.weights))
+
+    @staticmethod
+    def from_numpy(g, device="cuda") -> "Gaussians":
+        def t(a):
+            return None if a is None else torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
+        return Gaussians(t(g.means), t(g.log_scales), t(g.quats), t(g.scalars), t(getattr(g, "weights", None)))
+
+
+def default_opts() -> _lib.veg_opts:
+    o = _lib.veg_opts()
+    load().veg_opts_default(ctypes.byref(o))
+    return o
+
+
+def make_opts(d: Optional[dict] = None) -> _lib.veg_opts:
+    o = default_opts()
+    if d:
+        for k, v in d.items():
+            if k == "bg":
+                o.bg[0], o.bg[1], o.bg[2] = (float(x) for x in v)
+            else:
+                setattr(o, k, float(v))
+    return o
+
+
+def camera_struct(c) -> _lib.veg_camera:
+    cs = _lib.veg_camera()
+    view = list(map(float, c.view))
+    for k in range(12):
+        cs.view[k] = view[k]
+    cs.fx, cs.fy, cs.cx, cs.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+    cs.width, cs.height = int(c.width), int(c.height)
+    return cs
+
+
+@dataclass
+class Proj:
+    struct: _lib.veg_proj
+    frames: torch.Tensor
+    rec: torch.Tensor
+    count: torch.Tensor
+    depth: torch.Tensor
+    keep: list = field(default_factory=list)   # keeps TF tables alive while the stream uses them
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.struct.n) * int(self.struct.n_frames)
+
+
+def alloc_proj(n: int, n_frames: int, device="cuda") -> Proj:
+    pairs = max(1, n * n_frames)
+    frames = torch.empty(load().veg_frames_bytes(n_frames), dtype=torch.uint8, device=device)
+    rec = torch.empty(pairs * _lib.VEG_REC_FLOATS, dtype=torch.float32, device=device)
+    count = torch.empty(pairs, dtype=torch.int32, device=device)
+    depth = torch.empty(pairs, dtype=torch.int32, device=device)
+    st = _lib.veg_proj(n, n_frames, 0, 0, 0, 0, 0, _ptr(frames), _ptr(rec), _ptr(count), _ptr(depth))
+    return Proj(st, frames, rec, count, depth)
+
+
+def veg_project(g: Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=None, proj: Optional[Proj] = None,
+                stream=None) -> Proj:
+    """Projection of len(cams) frames over one model; tfs[f] is a device [k,4] float32 table."""
+    nf = len(cams)
+    if len(tfs) != nf:
+        raise ValueError("one TF per camera")
+    if proj is None:
+        proj = alloc_proj(g.n, nf, device=g.means.device)
+    cam_arr = (_lib.veg_camera * nf)(*[camera_struct(c) for c in cams])
+    tf_arr = (_lib.veg_tf * nf)(*[_lib.veg_tf(_ptr(t), int(t.shape[0])) for t in tfs])
+    proj.keep = list(tfs)
+    o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
+    gs = g.struct()
+    check(load().veg_project(ctypes.byref(gs), nf, cam_arr, tf_arr, ctypes.byref(o), ctypes.byref(proj.struct),
+                             stream_handle(stream)), "veg_project")
+    return proj
+
+
+def alloc_bin_workspace(proj: Proj, device="cuda") -> torch.Tensor:
+    nbytes = load().veg_bin_workspace_bytes(proj.n_pairs, 0)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def veg_bin_count(proj: Proj, ws: torch.Tensor, sync: bool = True, stream=None) -> Optional[int]:
+    e = ctypes.c_int64(-1)
+    check(load().veg_bin_count(ctypes.byref(proj.struct), _ptr(ws), ws.numel(), ctypes.byref(e) if sync else None,
+                               stream_handle(stream)), "veg_bin_count")
+    return int(e.value) if sync else None
+
+
+@dataclass
+class Bins:
+    struct: _lib.veg_bins
+    keys: torch.Tensor
+    vals: torch.Tensor
+    keys_alt: torch.Tensor
+    vals_alt: torch.Tensor
+    ranges: torch.Tensor
+
+    @property
+    def capacity(self) -> int:
+        return int(self.struct.capacity)
+
+
+def alloc_bins(proj: Proj, capacity: int, device="cuda") -> Bins:
+    cap = max(1, int(capacity))
+    k = torch.empty(cap, dtype=torch.int32, device=device)
+    v = torch.empty(cap, dtype=torch.int32, device=device)
+    ka = torch.empty(cap, dtype=torch.int32, device=device)
+    va = torch.empty(cap, dtype=torch.int32, device=device)
+    r = torch.empty(max(1, 2 * int(proj.struct.total_tiles)), dtype=torch.int32, device=device)
+    st = _lib.veg_bins(_ptr(k), _ptr(v), _ptr(ka), _ptr(va), _ptr(r), int(capacity))
+    return Bins(st, k, v, ka, va, r)
+
+
+def veg_bin_sort(proj: Proj, ws: torch.Tensor, bins: Bins, stream=None) -> Bins:
+    check(load().veg_bin_sort(ctypes.byref(proj.struct), _ptr(ws), ws.numel(), ctypes.byref(bins.struct),
+                              stream_handle(stream)), "veg_bin_sort")
+    return bins
+
+
+def veg_bin_overflow(ws: torch.Tensor, stream=None):
+    e = ctypes.c_int64(0)
+    ov = ctypes.c_int32(0)
+    check(load().veg_bin_overflow(_ptr(ws), ws.numel(), ctypes.byref(e), ctypes.byref(ov), stream_handle(stream)),
+          "veg_bin_overflow")
+    return int(e.value), bool(ov.value)
+
+
+def veg_render_fwd(proj: Proj, bins: Bins, opts, image: torch.Tensor, t_final: Optional[torch.Tensor],
+                   n_last: Optional[torch.Tensor], stream=None):
+    o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
+    check(load().veg_render_fwd(ctypes.byref(proj.struct), ctypes.byref(bins.struct), ctypes.byref(o), _ptr(image),
+                                _ptr(t_final), _ptr(n_last), stream_handle(stream)), "veg_render_fwd")
+
+
+def veg_render_bwd(proj: Proj, bins: Bins, opts, t_final: torch.Tensor, n_last: torch.Tensor, d_image: torch.Tensor,
+                   g2d: torch.Tensor, stream=None):
+    o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
+    check(load().veg_render_bwd(ctypes.byref(proj.struct), ctypes.byref(bins.struct), ctypes.byref(o), _ptr(t_final),
+                                _ptr(n_last), _ptr(d_image), _ptr(g2d), stream_handle(stream)), "veg_render_bwd")
+
+
+def veg_project_bwd(g: Gaussians, proj: Proj, opts, g2d: torch.Tensor, d_means, d_log_scales, d_quats, d_scalars,
+                    d_weights=None, stream=None):
+    o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
+    gs = g.struct()
+    gr = _lib.veg_grads(_ptr(d_means), _ptr(d_log_scales), _ptr(d_quats), _ptr(d_scalars), _ptr(d_weights))
+    check(load().veg_project_bwd(ctypes.byref(gs), ctypes.byref(proj.struct), ctypes.byref(o), _ptr(g2d),
+                                 ctypes.byref(gr), stream_handle(stream)), "veg_project_bwd")
+
+
+def veg_l1_loss(image: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.Tensor, d_image: torch.Tensor,
+                stream=None):
+    if loss.dtype != torch.float64:
+        raise ValueError("loss accumulator must be float64")
+    check(load().veg_l1_loss(_ptr(image), _ptr(target), image.numel(), float(scale), _ptr(loss), _ptr(d_image),
+                             stream_handle(stream)), "veg_l1_loss")
+
+
+def veg_fill_u32(t: torch.Tensor, value: int = 0, stream=None):
+    nwords = t.numel() * t.element_size() // 4
+    check(load().veg_fill_u32(_ptr(t), nwords, ctypes.c_uint32(value & 0xFFFFFFFF), stream_handle(stream)),
+          "veg_fill_u32")
+
+
+def veg_debug_math(op: int, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    out = torch.empty_like(x)
+    check(load().veg_debug_math(op, _ptr(x), _ptr(y), _ptr(out), x.numel(), stream_handle(stream)), "veg_debug_math")
+    return out
