@@ -28,12 +28,22 @@ if ROOT not in sys.path:
 
 METRIC = "fwd & fwd+bwd Mpix/s at 1M Gaussians; serve p50/p99 ms vs plain render loop"
 
-# Per-unit algorithmic work of the blend kernels (one unit = one Gaussian-pixel
-# evaluation visited before the pixel stops): ~20 VALU lane-operations forward, 2.5x that
-# backward.  Peak: 256 CUs x 64 lanes x 2.4 GHz of non-packed FP32 issue.
-FWD_OPS_PER_EVAL = 20.0
-BWD_OPS_PER_EVAL = 50.0
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12          # 39.32 T lane-ops/s
+# Algorithmic FLOPs of the blend kernels, counted from the definition (each add, multiply,
+# compare, min and exp counts 1):
+#   every visited Gaussian-pixel pair (both passes): d = p - mu' (2), the quadratic form
+#     sigma = 1/2 (a dx^2 + 2b dx dy + c dy^2) (8), a = A exp(-sigma) (2), skip test (1) = 13
+#   every blended pair, forward: alpha = min (1), w = alpha T (1), C += w c (6),
+#     T *= 1 - alpha (2), stop test (1) = 11
+#   every blended pair, backward: alpha, 1 - alpha, T / (1 - alpha), w (4), dL/dc (6),
+#     dL/dalpha (9), colour-behind update (6), dL/dA and dL/dsigma (3), dL/dconic (10),
+#     dL/dmu' (10) = 48
+# Peak: 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s of non-packed FP32 (the build
+# disables packed FP32; the packed figure, 157.3, is reported beside it).
+FLOPS_VISIT = 13.0
+FLOPS_BLEND_FWD = 11.0
+FLOPS_BLEND_BWD = 48.0
+VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12    # 78.64
+VALU_PACKED_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
@@ -85,7 +95,8 @@ def eval_counts(st, t_min):
     stopped = st.t_final.reshape(-1) < t_min
     bwd = torch.where(nl >= 0, nl - start + 1, torch.zeros_like(nl))
     fwd = torch.where(stopped, nl - start + 1, end - start)
-    return int(fwd.sum()), int(bwd.sum())
+    blended = int(st.n_contrib.long().sum()) if st.n_contrib is not None else 0
+    return int(fwd.sum()), int(bwd.sum()), blended
 
 
 def cpu_baseline(w, n_pixels, seed=5):
@@ -111,6 +122,89 @@ def cpu_baseline(w, n_pixels, seed=5):
                       f"{dt:.1f} s"}
 
 
+def serve_bench(rates, n_per_rate, max_batch=8, n_streams=3, use_graphs=True):
+    """Serving workload: 4 resident shell-clustered models (100k, 500k, 1M, 3M Gaussians),
+    open-loop Poisson arrivals, each request a random model, camera on a sphere of radius
+    2.5-4, fresh random 256-entry TF and a resolution from {512^2, 1024^2, 1920x1080}.
+    The server (continuous batching) and the plain loop (stateless API, one request at a
+    time in arrival order) serve the same trace; latency = completion - arrival."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_13339_amd import render as R
+    from paper_2504_13339_amd import veg as V
+    from paper_2504_13339_amd.serve import Server
+
+    models_np, _ = synth.serve_trace(1.0, 1)
+    models = [V.Gaussians.from_numpy(m) for m in models_np]
+    opts = synth.DEFAULT_OPTS
+    results = {"models": [m.n for m in models], "resolutions": ["512x512", "1024x1024", "1920x1080"],
+                "max_batch": max_batch, "streams": n_streams, "graphs": bool(use_graphs), "rates": {}}
+    srv = Server(max_gaussians=max(m.n for m in models), max_entries=64_000_000, max_batch=max_batch,
+                 n_streams=n_streams, use_graphs=use_graphs, max_width=1920, max_height=1080, max_tf_k=256)
+    mids = [srv.add_model(m) for m in models]
+    ring = {}
+
+    def out_for(cam, i):
+        key = (cam.width, cam.height)
+        bufs = ring.setdefault(key, [torch.empty((3, cam.height, cam.width), device="cuda") for _ in range(48)])
+        return bufs[i % len(bufs)]
+
+    def run_server(reqs):
+        srv.reset_stats()
+        t0 = time.perf_counter() + 0.05
+        ids = []
+        for i, r in enumerate(reqs):
+            target = t0 + r.arrival_s
+            while True:
+                d = target - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(d - 0.0005 if d > 0.001 else 0)
+            ids.append(srv.submit(mids[r.model], r.camera, r.tf, out_for(r.camera, i)))
+        for rid in ids:
+            srv.wait(rid)
+        return srv.stats()
+
+    def run_plain(reqs):
+        luts = [torch.as_tensor(r.tf).cuda() for r in reqs]
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter() + 0.05
+        for i, r in enumerate(reqs):
+            target = t0 + r.arrival_s
+            while time.perf_counter() < target:
+                pass
+            st = R.render(models[r.model], [r.camera], [luts[i]], opts)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - target) * 1e3)
+            del st
+        span = time.perf_counter() - t0
+        lat = np.sort(np.asarray(lat))
+        pix = sum(r.camera.width * r.camera.height for r in reqs)
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "max_ms": float(lat[-1]), "throughput_rps": len(reqs) / span, "mpix_per_s": pix / span / 1e6}
+
+    # warm-up (graph capture, allocator)
+    _, warm = synth.serve_trace(500.0, 2 * max_batch * n_streams, build_models=False, seed_sub=99)
+    run_server(warm)
+    run_plain(warm[:4])
+    for k, rate in enumerate(rates):
+        _, reqs = synth.serve_trace(float(rate), int(n_per_rate), build_models=False, seed_sub=k)
+        log(f"bench: serving {len(reqs)} requests at {rate} req/s")
+        st = run_server(reqs)
+        pl = run_plain(reqs)
+        results["rates"][str(rate)] = {
+            "server": {k2: round(float(st[k2]), 3) for k2 in ("p50_ms", "p99_ms", "max_ms", "throughput_rps",
+                                                              "mpix_per_s", "mean_batch", "gpu_busy_frac")} |
+                      {"completed": int(st["completed"]), "retries": int(st["retries"])},
+            "plain": {k2: round(v, 3) for k2, v in pl.items()},
+            "requests": len(reqs)}
+    srv.close()
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,7 +217,20 @@ def main():
     ap.add_argument("--res", type=int, default=None)
     ap.add_argument("--cpu-pixels", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s); '' to skip")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 3 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(frames would be split across GPUs with one gradient all-reduce; not built)", file=sys.stderr)
@@ -142,20 +249,21 @@ def main():
     t_min = float(w.opts["t_min"])
 
     # warm-up; the first warm-up step also counts the visited evaluations per group
-    counts = {"fwd": 0, "bwd": 0}
+    counts = {"fwd": 0, "bwd": 0, "blended": 0}
 
     def count_group(f0, st):
-        a, b = eval_counts(st, t_min)
+        a, b, c = eval_counts(st, t_min)
         counts["fwd"] += a
         counts["bwd"] += b
+        counts["blended"] += c
 
+    # the counting pass is an extra (untimed) step that also asks the forward for n_contrib
+    res = R.train_step_l1(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, loss_acc=loss_acc,
+                          on_group=count_group, want_contrib=True)
+    log(f"bench: counting step loss {res.loss:.6f} entries {res.n_entries}")
     for k in range(args.warmup):
-        res = R.train_step_l1(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, loss_acc=loss_acc,
-                              on_group=count_group if k == 0 else None)
-        log(f"bench: warm-up step {k} loss {res.loss:.6f} entries {res.n_entries}")
-    if args.warmup == 0:
-        R.train_step_l1(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, loss_acc=loss_acc,
-                        on_group=count_group)
+        res = R.train_step_l1(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, loss_acc=loss_acc)
+        log(f"bench: warm-up step {k} loss {res.loss:.6f}")
 
     # timed steps
     timer = R.EventTimer()
@@ -186,16 +294,21 @@ def main():
     fwd_mpix = F * H * W * args.steps / (time.perf_counter() - t1) / 1e6
 
     # roofline of the dominant kernel (blend forward or backward: VALU-bound)
+    def blend_roof(name):
+        visits = counts["bwd"] if name == "blend_bwd" else counts["fwd"]
+        blend_flops = FLOPS_BLEND_BWD if name == "blend_bwd" else FLOPS_BLEND_FWD
+        n_launch = launches[name]
+        avg_ms = per_step[name] / n_launch
+        flops = (visits * FLOPS_VISIT + counts["blended"] * blend_flops) / n_launch
+        ach = flops / (avg_ms * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": name, "achieved": round(ach, 3), "peak": round(VALU_PEAK_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "visited_pairs_per_launch": visits // n_launch,
+                "blended_pairs_per_launch": counts["blended"] // n_launch,
+                "flops_per_launch": flops, "frac_of_packed_peak": round(ach / VALU_PACKED_PEAK_TFLOPS, 4)}
     dom = max(("blend_bwd", "blend_fwd"), key=lambda k: per_step.get(k, 0.0))
-    evals = counts["bwd"] if dom == "blend_bwd" else counts["fwd"]
-    ops = BWD_OPS_PER_EVAL if dom == "blend_bwd" else FWD_OPS_PER_EVAL
-    n_launch = launches[dom]
-    avg_ms = per_step[dom] / n_launch
-    ach = evals / n_launch * ops / (avg_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "traffic": None,
-            "avg_launch_ms": round(avg_ms, 4), "evals_per_launch": evals // n_launch,
-            "ops_per_eval": ops, "note": "T lane-ops/s (FMA = 1 op), non-packed FP32 issue peak"}
+    roof = blend_roof(dom)
+    other = blend_roof("blend_fwd" if dom == "blend_bwd" else "blend_bwd")
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -207,7 +320,12 @@ def main():
                     "bwd": round(counts["bwd"] * args.steps / dt / 1e9, 3)},
         "kernel_ms_per_step": {k: round(v, 3) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
+        "roofline_other_blend": other,
     }
+    if args.serve_rates:
+        del grads, targets
+        torch.cuda.empty_cache()
+        out["serve"] = serve_bench([float(r) for r in args.serve_rates.split(",")], args.serve_requests)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_pixels)

@@ -241,7 +241,8 @@ veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32
  * Forward and backward blending  (Eq. 1 and its adjoint)
  * ---------------------------------------------------------------------------------- */
 
-/* veg_render_fwd -- per pixel, front-to-back compositing of the tile's list (Eq. 1):
+/* veg_render_fwd -- per pixel, front-to-back compositing of the tile's list (Eq. 1)
+ * (the background colour is the one given to veg_project, kept in the frame descriptors):
  * sigma = 1/2 d^T conic d, d = pixel centre - projected centre; a = A exp(-sigma);
  * pairs with a < alpha_min are skipped; alpha = min(alpha_clamp, a); C += c alpha T;
  * T *= 1 - alpha; the pixel stops after the Gaussian that takes T below t_min.
@@ -249,9 +250,13 @@ veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32
  *   t_final  device [n_frames,H,W] out: final transmittance
  *   n_last   device [n_frames,H,W] out: index into the key list of the last blended
  *            entry, -1 if none (needed by veg_render_bwd)
+ *   n_contrib device [n_frames,H,W] out, or NULL: number of Gaussians blended (not
+ *            skipped) into the pixel
+ * t_final and n_last may be NULL when no backward pass follows.
  * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
 veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts,
-                          float* image, float* t_final, int32_t* n_last, veg_stream_t stream);
+                          float* image, float* t_final, int32_t* n_last, int32_t* n_contrib,
+                          veg_stream_t stream);
 
 /* veg_render_bwd -- adjoint of veg_render_fwd (section "Rendering of VEGs": gradients
  * computed manually through the rasterizer).  Walks each tile's list backwards from
@@ -317,18 +322,27 @@ veg_status veg_debug_math(int32_t op, const float* in_x, const float* in_y, floa
 
 typedef struct veg_server veg_server;
 
+/* Server configuration.  Each of the n_streams batch slots gets static device buffers
+ * carved from `arena` for a batch of up to max_batch requests, max_pairs (frame,
+ * Gaussian) pairs and max_entries key-list entries; veg_serve_arena_bytes gives the size
+ * needed.  Requests of any model, camera, TF and resolution (<= max_width x max_height)
+ * share a batch; requests whose options other than bg differ go to different batches. */
 typedef struct {
   void* arena;               /* device memory the server sub-allocates (caller-owned) */
   size_t arena_bytes;
-  size_t budget_bytes;       /* admission budget for in-flight request memory (<= arena) */
+  size_t budget_bytes;       /* admission budget for in-flight request working memory */
   int32_t max_batch;         /* requests per batch (1..64) */
-  int32_t n_streams;         /* concurrent batches (1..8) */
-  int32_t use_graphs;        /* 1: replay captured hipGraphs per batch slot */
-  int32_t max_width, max_height;   /* largest request resolution */
+  int32_t n_streams;         /* concurrent batch slots (1..8) */
+  int32_t use_graphs;        /* 1: each slot replays one captured hipGraph per batch */
+  int32_t max_width, max_height;   /* largest request resolution (<= VEG_MAX_DIM) */
+  int32_t max_tf_k;          /* largest transfer-function table (2..4096 points) */
   int64_t max_gaussians;     /* largest resident model */
-  int64_t max_entries;       /* key-list capacity per batch (entries) */
+  int64_t max_pairs;         /* (frame, Gaussian) pairs per batch; 0 = max_batch * max_gaussians */
+  int64_t max_entries;       /* key-list capacity per batch (entries, < 2^31) */
 } veg_serve_config;
 
+/* One render request.  The camera and options are copied and the TF table (host memory)
+ * is copied at submit; out_image / out_t_final are written when the request completes. */
 typedef struct {
   int32_t model_id;
   veg_camera camera;
@@ -340,17 +354,19 @@ typedef struct {
 } veg_request;
 
 typedef struct {
-  int64_t submitted, completed, rejected, batches, retries;
+  int64_t submitted, completed, failed, rejected, batches, retries;
   double mean_batch;
-  double p50_ms, p99_ms;         /* submit -> completion observed by the scheduler */
+  double p50_ms, p99_ms, max_ms; /* submit -> completion observed by the scheduler */
   double throughput_rps;         /* completed / (last completion - first submit) */
   double mpix_per_s;
-  double gpu_busy_frac;          /* fraction of wall time with >= 1 batch in flight */
-  int64_t peak_bytes;
+  double gpu_busy_frac;          /* fraction of that interval with >= 1 batch in flight */
+  int64_t peak_bytes;            /* peak admitted working-memory estimate */
 } veg_serve_stats;
 
 enum { VEG_REQ_QUEUED = 0, VEG_REQ_RUNNING = 1, VEG_REQ_DONE = 2, VEG_REQ_FAILED = 3 };
 
+/* Device bytes the server needs in `arena` for this configuration (0 if invalid). */
+size_t veg_serve_arena_bytes(const veg_serve_config* cfg);
 /* Creates a server; a scheduler thread admits queued requests while their estimated
  * memory fits budget - in_use, packs them into batches of up to max_batch requests of
  * any model, camera, TF and resolution, and runs each batch (projection, binning,
@@ -366,7 +382,8 @@ veg_status veg_serve_submit(veg_server* s, const veg_request* r, uint64_t* req_i
 /* State of a request (VEG_REQ_*); VEG_ERR_NOT_FOUND for an unknown id. */
 veg_status veg_serve_poll(veg_server* s, uint64_t req_id, int32_t* state);
 /* Waits until the request is done or failed (timeout_ms < 0: forever).  VEG_OK when its
- * image is complete, VEG_ERR_TIMEOUT, or the request's failure status. */
+ * image is complete, VEG_ERR_TIMEOUT, or the request's failure status.  A request that
+ * has been waited on to completion is released: its id is unknown afterwards. */
 veg_status veg_serve_wait(veg_server* s, uint64_t req_id, int32_t timeout_ms);
 /* Latency/throughput statistics over the requests completed since the last reset. */
 veg_status veg_serve_stats_get(veg_server* s, veg_serve_stats* out);

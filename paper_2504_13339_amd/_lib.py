@@ -62,7 +62,7 @@ class veg_grads(Structure):
 class veg_serve_config(Structure):
     _fields_ = [("arena", c_void_p), ("arena_bytes", c_size_t), ("budget_bytes", c_size_t), ("max_batch", c_int32),
                 ("n_streams", c_int32), ("use_graphs", c_int32), ("max_width", c_int32), ("max_height", c_int32),
-                ("max_gaussians", c_int64), ("max_entries", c_int64)]
+                ("max_tf_k", c_int32), ("max_gaussians", c_int64), ("max_pairs", c_int64), ("max_entries", c_int64)]
 
 
 class veg_request(Structure):
@@ -71,10 +71,10 @@ class veg_request(Structure):
 
 
 class veg_serve_stats(Structure):
-    _fields_ = [("submitted", c_int64), ("completed", c_int64), ("rejected", c_int64), ("batches", c_int64),
-                ("retries", c_int64), ("mean_batch", c_double), ("p50_ms", c_double), ("p99_ms", c_double),
-                ("throughput_rps", c_double), ("mpix_per_s", c_double), ("gpu_busy_frac", c_double),
-                ("peak_bytes", c_int64)]
+    _fields_ = [("submitted", c_int64), ("completed", c_int64), ("failed", c_int64), ("rejected", c_int64),
+                ("batches", c_int64), ("retries", c_int64), ("mean_batch", c_double), ("p50_ms", c_double),
+                ("p99_ms", c_double), ("max_ms", c_double), ("throughput_rps", c_double), ("mpix_per_s", c_double),
+                ("gpu_busy_frac", c_double), ("peak_bytes", c_int64)]
 
 
 P = POINTER
@@ -89,13 +89,15 @@ _SIGS = {
     "veg_bin_count": (c_int, [P(veg_proj), c_void_p, c_size_t, P(c_int64), c_void_p]),
     "veg_bin_sort": (c_int, [P(veg_proj), c_void_p, c_size_t, P(veg_bins), c_void_p]),
     "veg_bin_overflow": (c_int, [c_void_p, c_size_t, P(c_int64), P(c_int32), c_void_p]),
-    "veg_render_fwd": (c_int, [P(veg_proj), P(veg_bins), P(veg_opts), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "veg_render_fwd": (c_int, [P(veg_proj), P(veg_bins), P(veg_opts), c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p]),
     "veg_render_bwd": (c_int, [P(veg_proj), P(veg_bins), P(veg_opts), c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p]),
     "veg_project_bwd": (c_int, [P(veg_gaussians), P(veg_proj), P(veg_opts), c_void_p, P(veg_grads), c_void_p]),
     "veg_l1_loss": (c_int, [c_void_p, c_void_p, c_int64, c_float, c_void_p, c_void_p, c_void_p]),
     "veg_fill_u32": (c_int, [c_void_p, c_int64, c_uint32, c_void_p]),
     "veg_debug_math": (c_int, [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
+    "veg_serve_arena_bytes": (c_size_t, [P(veg_serve_config)]),
     "veg_serve_create": (c_int, [P(veg_serve_config), P(c_void_p)]),
     "veg_serve_add_model": (c_int, [c_void_p, P(veg_gaussians), P(c_int32)]),
     "veg_serve_submit": (c_int, [c_void_p, P(veg_request), P(c_uint64)]),

@@ -101,6 +101,8 @@ size_t pairs_of(const veg_proj* p) { return (size_t)p->n_frames * (size_t)p->n; 
 
 }  // namespace
 
+void veg::set_last_error(const char* msg) { g_err = msg ? msg : ""; }
+
 extern "C" {
 
 const char* veg_status_str(int s) {
@@ -279,7 +281,7 @@ veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32
 }
 
 veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts, float* image,
-                          float* t_final, int32_t* n_last, veg_stream_t stream) {
+                          float* t_final, int32_t* n_last, int32_t* n_contrib, veg_stream_t stream) {
   g_err.clear();
   veg_status s = check_projected(proj);
   if (s != VEG_OK) return s;
@@ -290,7 +292,7 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
   if (s != VEG_OK) return s;
   VEG_CHECK_HIP(launch_blend_fwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
                                  kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, image, t_final, n_last,
-                                 (hipStream_t)stream),
+                                 n_contrib, (hipStream_t)stream),
                 "veg_render_fwd");
   return VEG_OK;
 }

@@ -141,10 +141,12 @@ __global__ __launch_bounds__(1024) void scan_partials_kernel(uint64_t* partials,
 
 // Downsweep of the compaction: kept pair i goes to (dkey, dval)[pos] = (depth[i], i).
 __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __restrict__ count,
-                                                           const uint32_t* __restrict__ depth, uint32_t n,
+                                                           const uint32_t* __restrict__ depth,
+                                                           const uint32_t* __restrict__ n_ptr, uint32_t n_cap,
                                                            const uint64_t* __restrict__ partials, int G,
                                                            uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval) {
   __shared__ uint32_t s_tmp[kWaves];
+  const uint32_t n = read_count(n_ptr, n_cap);
   uint32_t begin, end;
   segment_of(n, G, blockIdx.x, begin, end);
   uint64_t base = partials[blockIdx.x];
@@ -175,7 +177,11 @@ __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __res
 }
 
 // Downsweep of the entry-offset scan fused with emission: the j-th depth-sorted kept pair p
-// writes (global tile, p) for every tile of its rectangle (row-major), starting at its offset.
+// owns count[p] consecutive output slots starting at its offset and fills them with
+// (global tile, p), its rectangle's tiles in row-major order.  Each tile of items first
+// lays out the items' offsets and rectangles in LDS; then the block's threads write the
+// tile's contiguous output slots in order (coalesced), each slot finding its item by binary
+// search over the offsets, so one Gaussian covering many tiles does not serialise a lane.
 __global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restrict__ descs,
                                                         const float4* __restrict__ rec,
                                                         const uint32_t* __restrict__ count,
@@ -185,44 +191,72 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restr
                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                         uint32_t capacity) {
   __shared__ uint32_t s_tmp[kWaves];
+  __shared__ uint32_t s_off[kTileItems];    // exclusive slot offset of each item in the tile
+  __shared__ uint32_t s_pair[kTileItems];
+  __shared__ uint32_t s_base[kTileItems];   // global tile id of the rectangle's first tile
+  __shared__ uint32_t s_shape[kTileItems];  // rectangle width | tiles_x << 16
   const uint32_t n = read_count(v_ptr, v_cap);
   uint32_t begin, end;
   segment_of(n, G, blockIdx.x, begin, end);
   uint64_t base = partials[blockIdx.x];
+  const uint32_t i0 = threadIdx.x * kIpt;
   for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
-    const uint32_t j0 = t0 + threadIdx.x * kIpt;
-    uint32_t pr[kIpt], cn[kIpt];
+    uint32_t cn[kIpt];
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kIpt; ++k) {
-      const uint32_t j = j0 + k;
-      pr[k] = j < end ? sorted_vals[j] : 0u;
-      cn[k] = j < end ? count[pr[k]] : 0u;
+      const uint32_t j = t0 + i0 + k;
+      const uint32_t p = j < end ? sorted_vals[j] : 0u;
+      cn[k] = j < end ? count[p] : 0u;
+      uint32_t b = 0, shape = 1;
+      if (cn[k] > 0u) {
+        const float4 r2 = rec[3 * (size_t)p + 2];
+        const uint32_t a = __float_as_uint(r2.y), c = __float_as_uint(r2.z);
+        const FrameDesc& d = descs[__float_as_uint(r2.w)];
+        const uint32_t x0 = a & 0xffffu, y0 = a >> 16, x1 = c & 0xffffu;
+        b = d.tile_base + y0 * (uint32_t)d.tiles_x + x0;
+        shape = (x1 - x0 + 1u) | ((uint32_t)d.tiles_x << 16);
+      }
+      s_pair[i0 + k] = p;
+      s_base[i0 + k] = b;
+      s_shape[i0 + k] = shape;
       s += cn[k];
     }
     uint32_t tot;
-    const uint32_t off = block_excl_scan(s, s_tmp, &tot);
-    uint64_t pos = base + off;
+    uint32_t off = block_excl_scan(s, s_tmp, &tot);
 #pragma unroll
     for (int k = 0; k < kIpt; ++k) {
-      if (cn[k] == 0u) continue;
-      const float4 r2 = rec[3 * (size_t)pr[k] + 2];
-      const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
-      const uint32_t f = __float_as_uint(r2.w);
-      const FrameDesc& d = descs[f];
-      const uint32_t x0 = a & 0xffffu, y0 = a >> 16, x1 = b & 0xffffu, y1 = b >> 16;
-      const uint32_t tb = d.tile_base, tx_n = (uint32_t)d.tiles_x;
-      for (uint32_t ty = y0; ty <= y1; ++ty) {
-        for (uint32_t tx = x0; tx <= x1; ++tx) {
-          if (pos < capacity) {
-            keys[pos] = tb + ty * tx_n + tx;
-            vals[pos] = pr[k];
-          }
-          ++pos;
+      s_off[i0 + k] = off;
+      off += cn[k];
+    }
+    __syncthreads();
+    for (uint32_t slot = threadIdx.x; slot < tot; slot += kThreads) {
+      // largest item index i with s_off[i] <= slot (it has a nonzero count)
+      uint32_t lo = 0, len = kTileItems;
+      while (len > 0) {
+        const uint32_t half = len >> 1;
+        if (s_off[lo + half] <= slot) {
+          lo += half + 1;
+          len -= half + 1;
+        } else {
+          len = half;
         }
+      }
+      const uint32_t i = lo - 1;
+      const uint32_t local = slot - s_off[i];
+      const uint32_t shape = s_shape[i];
+      const uint32_t w = shape & 0xffffu, txn = shape >> 16;
+      uint32_t q = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)w));
+      if (q * w > local) --q;
+      else if ((q + 1u) * w <= local) ++q;
+      const uint64_t pos = base + slot;
+      if (pos < capacity) {
+        keys[pos] = s_base[i] + q * txn + (local - q * w);
+        vals[pos] = s_pair[i];
       }
     }
     base += tot;
+    __syncthreads();
   }
 }
 
@@ -465,18 +499,19 @@ void carve_bin_ws(void* ws, int64_t pairs, BinWs* out) {
 }
 
 hipError_t launch_bin_count(const uint32_t* count, const uint32_t* depth, uint32_t n_pairs, const BinWs& ws,
-                            hipStream_t stream) {
+                            hipStream_t stream, const uint32_t* n_pairs_dev) {
   uint64_t* partials = (uint64_t*)ws.partials;
   uint64_t* ptmp = (uint64_t*)ws.partials_tmp;
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, stream, ws.counters, (int64_t)64, 0u);
   // 1. compaction of kept pairs
   const int Gv = scan_blocks(n_pairs);
   ScanSrc vis{count, nullptr, nullptr};
-  hipLaunchKernelGGL(scan_reduce_kernel<kVis>, dim3(Gv), dim3(kThreads), 0, stream, vis, nullptr, n_pairs, ptmp, Gv);
+  hipLaunchKernelGGL(scan_reduce_kernel<kVis>, dim3(Gv), dim3(kThreads), 0, stream, vis, n_pairs_dev, n_pairs, ptmp,
+                     Gv);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, ptmp, Gv, ws.counters + 8,
                      ws.counters + 0);
-  hipLaunchKernelGGL(compact_kernel, dim3(Gv), dim3(kThreads), 0, stream, count, depth, n_pairs, ptmp, Gv,
-                     ws.dkeyA, ws.dvalA);
+  hipLaunchKernelGGL(compact_kernel, dim3(Gv), dim3(kThreads), 0, stream, count, depth, n_pairs_dev, n_pairs, ptmp,
+                     Gv, ws.dkeyA, ws.dvalA);
   // 2. front-to-back order: 31 depth-key bits (camera z > 0)
   hipError_t e = radix_sort(ws.dkeyA, ws.dvalA, ws.dkeyB, ws.dvalB, ws.counters + 0, n_pairs, 31, ws.hist, ptmp,
                             stream);

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
                                                        const uint2* __restrict__ ranges, float* __restrict__ image,
-                                                       float* __restrict__ tfinal, int32_t* __restrict__ nlast) {
+                                                       float* __restrict__ tfinal, int32_t* __restrict__ nlast,
+                                                       int32_t* __restrict__ ncontrib) {
   const FrameDesc& d = descs[blockIdx.y];
   const int tile = blockIdx.x;
   if (tile >= d.tiles_x * d.tiles_y) return;
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   __shared__ float s_b[kBatch];      // B
 
   float T[4], C[4][3];
-  int last[4];
+  int last[4], cnt[4];
   bool done[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
     T[r] = 1.0f;
     C[r][0] = C[r][1] = C[r][2] = 0.0f;
     last[r] = -1;
+    cnt[r] = 0;
     done[r] = !(px < d.W && py < d.H);
   }
   const float l2min = o.log2_alpha_min;
@@ -111,6 +113,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
           C[r][2] = fmaf(w, s_b[k], C[r][2]);
           T[r] = fmaf(-alpha, T[r], T[r]);
           last[r] = (int)(base + k);
+          ++cnt[r];
           if (T[r] < o.t_min) done[r] = true;
         }
       }
@@ -122,16 +125,18 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   float* img = own ? d.out_image : image + (size_t)blockIdx.y * 3 * HW;
   float* tf = own ? d.out_tfinal : (tfinal ? tfinal + (size_t)blockIdx.y * HW : nullptr);
   int32_t* nl = own ? d.out_nlast : (nlast ? nlast + (size_t)blockIdx.y * HW : nullptr);
+  int32_t* nc = own ? nullptr : (ncontrib ? ncontrib + (size_t)blockIdx.y * HW : nullptr);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int py = ty * kTile + row0 + r;
     if (px < d.W && py < d.H) {
       const size_t pi = (size_t)py * d.W + px;
-      img[pi] = C[r][0] + T[r] * o.bg0;
-      img[HW + pi] = C[r][1] + T[r] * o.bg1;
-      img[2 * HW + pi] = C[r][2] + T[r] * o.bg2;
+      img[pi] = C[r][0] + T[r] * d.bg[0];
+      img[HW + pi] = C[r][1] + T[r] * d.bg[1];
+      img[2 * HW + pi] = C[r][2] + T[r] * d.bg[2];
       if (tf) tf[pi] = T[r];
       if (nl) nl[pi] = last[r];
+      if (nc) nc[pi] = cnt[r];
     }
   }
 }
@@ -182,9 +187,9 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
     gr[r][0] = in ? dip[pi] : 0.0f;
     gr[r][1] = in ? dip[HW + pi] : 0.0f;
     gr[r][2] = in ? dip[2 * HW + pi] : 0.0f;
-    S[r][0] = o.bg0;
-    S[r][1] = o.bg1;
-    S[r][2] = o.bg2;
+    S[r][0] = d.bg[0];
+    S[r][1] = d.bg[1];
+    S[r][2] = d.bg[2];
     jmax = max(jmax, last[r]);
   }
   jmax = min(wave_max_i32(jmax), (int)rg.y - 1);   // n_last lies inside this tile's range
@@ -268,10 +273,10 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
 
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o, const float4* rec,
                             const uint32_t* vals, const uint32_t* ranges, float* image, float* tfinal, int32_t* nlast,
-                            hipStream_t stream) {
+                            int32_t* ncontrib, hipStream_t stream) {
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(blend_fwd_kernel, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
-                     (const uint2*)ranges, image, tfinal, nlast);
+                     (const uint2*)ranges, image, tfinal, nlast, ncontrib);
   return hipGetLastError();
 }
 

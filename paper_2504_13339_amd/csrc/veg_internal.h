@@ -92,6 +92,9 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+// Thread-local message returned by veg_last_error (defined with the C entry points).
+void set_last_error(const char* msg);
+
 // ---------------------------------------------------------------------------------------
 // Host-side launchers (one translation unit each)
 // ---------------------------------------------------------------------------------------
@@ -126,8 +129,10 @@ constexpr int kMaxSortBlocks = 2048;
 size_t bin_ws_bytes(int64_t pairs);
 void carve_bin_ws(void* ws, int64_t pairs, BinWs* out);
 
+// n_pairs bounds the pair count; when n_pairs_dev is non-null the actual count is read
+// from device memory (capacity mode, used by the server's captured graphs).
 hipError_t launch_bin_count(const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,
-                            const BinWs& ws, hipStream_t stream);
+                            const BinWs& ws, hipStream_t stream, const uint32_t* n_pairs_dev = nullptr);
 hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* rec,
                            const uint32_t* count, uint32_t n_pairs, uint32_t total_tiles,
                            const BinWs& ws, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
@@ -136,7 +141,8 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
 
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
-                            float* image, float* tfinal, int32_t* nlast, hipStream_t stream);
+                            float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
+                            hipStream_t stream);
 hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             const float* tfinal, const int32_t* nlast, const float* dimage,

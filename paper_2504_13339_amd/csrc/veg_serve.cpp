@@ -1,13 +1,677 @@
-// Serving entry points (continuous batching).  Filled in by the serving scheduler.
+// Continuous-batching render server.
+//
+// Resident models stay in device memory (caller-owned SoA).  A scheduler thread keeps a
+// FIFO of submitted requests; whenever a batch slot is free it takes requests from the
+// head of the queue while they fit the slot (requests, pairs, estimated key-list entries,
+// resolution) and the HBM admission budget, writes one frame descriptor per request
+// (model pointers, camera, TF table, output image) through pinned staging memory, and
+// launches projection -> binning -> sorting -> blending for the whole batch on the slot's
+// stream, optionally as one replay of a hipGraph captured for that slot.  Kernels take
+// every size from the device descriptors, so a single capture serves batches of any
+// composition.  Slots run concurrently, so requests that arrive while batches are on the
+// GPU are admitted as soon as a slot and budget free up.  Completion is observed through
+// the slot's event; a batch whose key list overflowed the slot is re-run request by
+// request.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "veg_internal.h"
 
-extern "C" {
-veg_status veg_serve_create(const veg_serve_config*, veg_server**) { return VEG_ERR_INVALID_ARG; }
-veg_status veg_serve_add_model(veg_server*, const veg_gaussians*, int32_t*) { return VEG_ERR_INVALID_ARG; }
-veg_status veg_serve_submit(veg_server*, const veg_request*, uint64_t*) { return VEG_ERR_INVALID_ARG; }
-veg_status veg_serve_poll(veg_server*, uint64_t, int32_t*) { return VEG_ERR_INVALID_ARG; }
-veg_status veg_serve_wait(veg_server*, uint64_t, int32_t) { return VEG_ERR_INVALID_ARG; }
-veg_status veg_serve_stats_get(veg_server*, veg_serve_stats*) { return VEG_ERR_INVALID_ARG; }
-veg_status veg_serve_stats_reset(veg_server*) { return VEG_ERR_INVALID_ARG; }
-veg_status veg_serve_destroy(veg_server*) { return VEG_ERR_INVALID_ARG; }
+namespace veg {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double now_s() { return std::chrono::duration<double>(Clock::now().time_since_epoch()).count(); }
+
+struct BatchHeader {
+  uint32_t n_pairs;
+  uint32_t n_frames;
+  uint32_t pad[62];   // keeps the descriptors 256-byte aligned after the header
+};
+static_assert(sizeof(BatchHeader) == 256, "header size");
+
+struct Req {
+  uint64_t id = 0;
+  veg_request r{};
+  std::vector<float> tf;
+  int32_t state = VEG_REQ_QUEUED;
+  veg_status status = VEG_OK;
+  double t_submit = 0, t_done = 0;
+  int64_t n = 0;
+  int64_t est_entries = 0;
+  int64_t est_bytes = 0;
+  bool solo = false;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  // device (carved from the arena)
+  BatchHeader* d_header = nullptr;
+  FrameDesc* d_descs = nullptr;
+  float* d_luts = nullptr;
+  float4* rec = nullptr;
+  uint32_t* count = nullptr;
+  uint32_t* depth = nullptr;
+  void* ws = nullptr;
+  BinWs bws{};
+  uint32_t *keys = nullptr, *vals = nullptr, *keys_alt = nullptr, *vals_alt = nullptr, *ranges = nullptr;
+  // pinned host staging
+  unsigned char* h_stage = nullptr;   // header + descriptors
+  float* h_luts = nullptr;
+  uint32_t* h_counters = nullptr;
+  // graph
+  hipGraphExec_t exec = nullptr;
+  bool has_graph = false;
+  KOpts graph_opts{};
+  // state
+  bool busy = false;
+  std::vector<uint64_t> reqs;
+  double t_launch = 0;
+  int64_t bytes = 0;
+  int64_t est_entries = 0;
+};
+
+bool same_opts(const veg_opts& a, const veg_opts& b) {
+  return a.alpha_clamp == b.alpha_clamp && a.alpha_min == b.alpha_min && a.t_min == b.t_min &&
+         a.lowpass == b.lowpass && a.near_z == b.near_z && a.guard == b.guard;
 }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t header, descs, luts, rec, count, depth, ws, keys, ranges, total;
+};
+
+}  // namespace
+}  // namespace veg
+
+using namespace veg;
+
+struct veg_server {
+  veg_serve_config cfg{};
+  int device = 0;
+  int64_t pairs_cap = 0, entries_cap = 0;
+  int max_tiles_frame = 0;
+  uint32_t total_tiles_cap = 0;
+  std::mutex mu;
+  std::condition_variable cv;        // scheduler wake-up
+  std::condition_variable cv_done;   // request completion
+  std::vector<veg_gaussians> models;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::deque<uint64_t> queue;
+  std::vector<Slot> slots;
+  std::thread sched;
+  bool stop = false;
+  uint64_t next_id = 1;
+  int64_t in_use = 0, peak = 0;
+  double e_scale = 1.0;   // learned multiplier on the entry-count prior
+  std::string err;
+  // statistics
+  std::vector<double> lat_ms;
+  int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, batches = 0, retries = 0;
+  double sum_batch = 0, pix_done = 0, first_submit = -1, last_done = -1;
+  double busy_acc = 0, busy_since = -1;
+  int inflight = 0;
+};
+
+namespace {
+
+veg_status sfail(veg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  set_last_error(buf);
+  return s;
+}
+
+int64_t pairs_cap_of(const veg_serve_config& c) {
+  return c.max_pairs > 0 ? c.max_pairs : (int64_t)c.max_batch * c.max_gaussians;
+}
+
+int tiles_of(int w, int h) { return ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile); }
+
+Layout slot_layout(const veg_serve_config& c) {
+  Layout L{};
+  const int64_t P = pairs_cap_of(c);
+  const int tiles = c.max_batch * tiles_of(c.max_width, c.max_height);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.header = take(sizeof(BatchHeader));
+  L.descs = take((size_t)c.max_batch * sizeof(FrameDesc));
+  L.luts = take((size_t)c.max_batch * c.max_tf_k * 4 * sizeof(float));
+  L.rec = take((size_t)P * 12 * sizeof(float));
+  L.count = take((size_t)P * 4);
+  L.depth = take((size_t)P * 4);
+  L.ws = take(bin_ws_bytes(P));
+  L.keys = take((size_t)c.max_entries * 4 * 4);
+  L.ranges = take((size_t)tiles * 8);
+  L.total = off;
+  return L;
+}
+
+veg_status check_cfg(const veg_serve_config* c) {
+  if (!c) return sfail(VEG_ERR_INVALID_ARG, "config is NULL");
+  if (c->max_batch < 1 || c->max_batch > 64) return sfail(VEG_ERR_INVALID_ARG, "max_batch must be 1..64");
+  if (c->n_streams < 1 || c->n_streams > 8) return sfail(VEG_ERR_INVALID_ARG, "n_streams must be 1..8");
+  if (c->max_width < 1 || c->max_height < 1 || c->max_width > VEG_MAX_DIM || c->max_height > VEG_MAX_DIM)
+    return sfail(VEG_ERR_INVALID_ARG, "max_width/max_height out of range");
+  if (c->max_tf_k < 2 || c->max_tf_k > 4096) return sfail(VEG_ERR_INVALID_ARG, "max_tf_k must be 2..4096");
+  if (c->max_gaussians < 1 || c->max_gaussians >= ((int64_t)1 << 31))
+    return sfail(VEG_ERR_INVALID_ARG, "max_gaussians out of range");
+  const int64_t P = pairs_cap_of(*c);
+  if (P < c->max_gaussians || P >= ((int64_t)1 << 31)) return sfail(VEG_ERR_INVALID_ARG, "max_pairs out of range");
+  if (c->max_entries < 1 || c->max_entries >= ((int64_t)1 << 31))
+    return sfail(VEG_ERR_INVALID_ARG, "max_entries out of range");
+  if ((int64_t)c->max_batch * tiles_of(c->max_width, c->max_height) >= ((int64_t)1 << 31))
+    return sfail(VEG_ERR_INVALID_ARG, "too many tiles per batch");
+  return VEG_OK;
+}
+
+KOpts kopts_of(const veg_opts& o) {
+  KOpts k;
+  k.alpha_clamp = o.alpha_clamp;
+  k.alpha_min = o.alpha_min;
+  k.t_min = o.t_min;
+  k.lowpass = o.lowpass;
+  k.near_z = o.near_z;
+  k.guard = o.guard;
+  k.log2_alpha_min = std::log2(o.alpha_min);
+  k.bg0 = k.bg1 = k.bg2 = 0.0f;   // the background is per request, in the frame descriptors
+  return k;
+}
+
+// Entry-count prior for one request: about (1 + extent/16)^2 tiles per Gaussian, with the
+// extent taken proportional to the image height; scaled by the learned e_scale.
+int64_t entry_prior(int64_t n, int W, int H) {
+  const double f = std::max(1.0, (double)std::max(W, H) / 1024.0);
+  return (int64_t)std::ceil((double)n * 6.0 * f * f) + 1024;
+}
+
+int64_t req_bytes(int64_t n, int64_t entries, int W, int H) {
+  return n * (48 + 8 + 16) + entries * 16 + (int64_t)tiles_of(W, H) * 8 + (int64_t)W * H * 4;
+}
+
+// Enqueues the whole pipeline for one batch on the slot's stream (also used for capture).
+hipError_t run_pipeline(veg_server* s, Slot& sl, const KOpts& ko) {
+  const veg_serve_config& c = s->cfg;
+  hipError_t e = launch_project(sl.d_descs, c.max_batch, (int)c.max_gaussians, ko, sl.rec, sl.count, sl.depth, false,
+                                sl.stream);
+  if (e != hipSuccess) return e;
+  e = launch_bin_count(sl.count, sl.depth, (uint32_t)s->pairs_cap, sl.bws, sl.stream, &sl.d_header->n_pairs);
+  if (e != hipSuccess) return e;
+  e = launch_bin_sort(sl.d_descs, c.max_batch, sl.rec, sl.count, (uint32_t)s->pairs_cap, s->total_tiles_cap, sl.bws,
+                      sl.keys, sl.vals, sl.keys_alt, sl.vals_alt, sl.ranges, (uint32_t)s->entries_cap, sl.stream);
+  if (e != hipSuccess) return e;
+  return launch_blend_fwd(sl.d_descs, c.max_batch, s->max_tiles_frame, ko, sl.rec, sl.vals, sl.ranges, nullptr,
+                          nullptr, nullptr, nullptr, sl.stream);
+}
+
+// Called with the lock held: writes the batch's descriptors and launches it.
+veg_status launch_batch(veg_server* s, Slot& sl, const std::vector<uint64_t>& ids) {
+  const veg_serve_config& c = s->cfg;
+  BatchHeader* hh = reinterpret_cast<BatchHeader*>(sl.h_stage);
+  FrameDesc* hd = reinterpret_cast<FrameDesc*>(sl.h_stage + sizeof(BatchHeader));
+  std::memset(sl.h_stage, 0, sizeof(BatchHeader) + (size_t)c.max_batch * sizeof(FrameDesc));
+  uint32_t pair_base = 0, tile_base = 0;
+  const Req& first = s->reqs[ids[0]];
+  for (size_t f = 0; f < ids.size(); ++f) {
+    Req& q = s->reqs[ids[f]];
+    const veg_gaussians& g = s->models[q.r.model_id];
+    FrameDesc& d = hd[f];
+    d.means = g.means;
+    d.log_scales = g.log_scales;
+    d.quats = g.quats;
+    d.scalars = g.scalars;
+    d.weights = g.weights;
+    d.lut = sl.d_luts + (size_t)f * c.max_tf_k * 4;
+    d.out_image = q.r.out_image;
+    d.out_tfinal = q.r.out_t_final;
+    d.out_nlast = nullptr;
+    d.K = q.r.tf_k;
+    d.n = (int32_t)g.n;
+    d.W = q.r.camera.width;
+    d.H = q.r.camera.height;
+    d.tiles_x = (d.W + kTile - 1) / kTile;
+    d.tiles_y = (d.H + kTile - 1) / kTile;
+    d.pair_base = pair_base;
+    d.tile_base = tile_base;
+    std::memcpy(d.view, q.r.camera.view, sizeof(d.view));
+    d.fx = q.r.camera.fx;
+    d.fy = q.r.camera.fy;
+    d.cx = q.r.camera.cx;
+    d.cy = q.r.camera.cy;
+    d.bg[0] = q.r.opts.bg[0];
+    d.bg[1] = q.r.opts.bg[1];
+    d.bg[2] = q.r.opts.bg[2];
+    std::memcpy(sl.h_luts + (size_t)f * c.max_tf_k * 4, q.tf.data(), q.tf.size() * sizeof(float));
+    pair_base += (uint32_t)g.n;
+    tile_base += (uint32_t)(d.tiles_x * d.tiles_y);
+    q.state = VEG_REQ_RUNNING;
+  }
+  hh->n_pairs = pair_base;
+  hh->n_frames = (uint32_t)ids.size();
+  const KOpts ko = kopts_of(first.r.opts);
+  hipError_t e = hipMemcpyAsync(sl.d_header, sl.h_stage, sizeof(BatchHeader) + (size_t)c.max_batch * sizeof(FrameDesc),
+                                hipMemcpyHostToDevice, sl.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sl.d_luts, sl.h_luts, ids.size() * (size_t)c.max_tf_k * 4 * sizeof(float),
+                       hipMemcpyHostToDevice, sl.stream);
+  if (e == hipSuccess) {
+    if (c.use_graphs) {
+      if (sl.has_graph && std::memcmp(&sl.graph_opts, &ko, sizeof(KOpts)) != 0) {
+        (void)hipGraphExecDestroy(sl.exec);
+        sl.exec = nullptr;
+        sl.has_graph = false;
+      }
+      if (!sl.has_graph) {
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          hipError_t e2 = run_pipeline(s, sl, ko);
+          e = hipStreamEndCapture(sl.stream, &graph);
+          if (e == hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e == hipSuccess) {
+          sl.has_graph = true;
+          sl.graph_opts = ko;
+        }
+      }
+      if (e == hipSuccess) e = hipGraphLaunch(sl.exec, sl.stream);
+    } else {
+      e = run_pipeline(s, sl, ko);
+    }
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sl.h_counters, sl.bws.counters, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, sl.stream);
+  if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+  if (e != hipSuccess) {
+    s->err = std::string("launch: ") + hipGetErrorString(e);
+    return VEG_ERR_HIP;
+  }
+  return VEG_OK;
+}
+
+void finish_request(veg_server* s, Req& q, veg_status st, double t) {
+  q.state = st == VEG_OK ? VEG_REQ_DONE : VEG_REQ_FAILED;
+  q.status = st;
+  q.t_done = t;
+  if (st == VEG_OK) {
+    s->completed++;
+    s->lat_ms.push_back((t - q.t_submit) * 1e3);
+    s->pix_done += (double)q.r.camera.width * q.r.camera.height;
+    s->last_done = t;
+  } else {
+    s->failed++;
+  }
+}
+
+// Called with the lock held.
+void reap(veg_server* s, Slot& sl, double t) {
+  const uint64_t E = (uint64_t)sl.h_counters[1] | ((uint64_t)sl.h_counters[2] << 32);
+  const bool overflow = sl.h_counters[3] != 0;
+  if (overflow) {
+    // re-run each request of the batch alone (at the front of the queue, in order)
+    if (sl.reqs.size() > 1) {
+      s->retries += (int64_t)sl.reqs.size();
+      for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) {
+        Req& q = s->reqs[*it];
+        q.solo = true;
+        q.state = VEG_REQ_QUEUED;
+        s->queue.push_front(*it);
+      }
+    } else {
+      finish_request(s, s->reqs[sl.reqs[0]], VEG_ERR_CAPACITY, t);
+    }
+    // learn a larger multiplier so the next batches are packed more conservatively
+    if (sl.est_entries > 0) s->e_scale = std::max(s->e_scale, 1.25 * (double)E / (double)sl.est_entries);
+  } else {
+    for (uint64_t id : sl.reqs) finish_request(s, s->reqs[id], VEG_OK, t);
+    if (sl.est_entries > 0) {
+      // observed / prior; jump up at once, decay slowly, keep a 25% margin
+      const double ratio = (double)E / (double)sl.est_entries;
+      s->e_scale = std::max(1.25 * ratio, 0.95 * s->e_scale + 0.05 * 1.25 * ratio);
+    }
+  }
+  s->in_use -= sl.bytes;
+  sl.busy = false;
+  sl.reqs.clear();
+  s->inflight--;
+  if (s->inflight == 0 && s->busy_since >= 0) {
+    s->busy_acc += t - s->busy_since;
+    s->busy_since = -1;
+  }
+  s->cv_done.notify_all();
+}
+
+// Forms a batch from the head of the queue for a free slot; returns false if none fits.
+bool try_launch(veg_server* s, Slot& sl) {
+  if (s->queue.empty()) return false;
+  const veg_serve_config& c = s->cfg;
+  std::vector<uint64_t> ids;
+  int64_t pairs = 0, entries = 0, bytes = 0;
+  const veg_opts* o0 = nullptr;
+  while (!s->queue.empty() && (int)ids.size() < c.max_batch) {
+    Req& q = s->reqs[s->queue.front()];
+    const int64_t e = (int64_t)std::ceil((double)q.est_entries * s->e_scale);
+    const bool fits = pairs + q.n <= s->pairs_cap && entries + e <= s->entries_cap &&
+                      s->in_use + bytes + q.est_bytes <= (int64_t)c.budget_bytes &&
+                      (o0 == nullptr || same_opts(*o0, q.r.opts));
+    if (!ids.empty() && (!fits || q.solo)) break;
+    if (ids.empty() && !fits && s->in_use > 0) break;   // wait for memory to free up
+    ids.push_back(q.id);
+    pairs += q.n;
+    entries += e;
+    bytes += q.est_bytes;
+    o0 = &q.r.opts;
+    s->queue.pop_front();
+    if (q.solo) break;
+  }
+  if (ids.empty()) return false;
+  sl.busy = true;
+  sl.reqs = ids;
+  sl.bytes = bytes;
+  sl.est_entries = 0;
+  for (uint64_t id : ids) sl.est_entries += s->reqs[id].est_entries;
+  s->in_use += bytes;
+  s->peak = std::max(s->peak, s->in_use);
+  s->batches++;
+  s->sum_batch += (double)ids.size();
+  const double t = now_s();
+  if (s->inflight == 0) s->busy_since = t;
+  s->inflight++;
+  sl.t_launch = t;
+  if (launch_batch(s, sl, ids) != VEG_OK) {
+    for (uint64_t id : ids) finish_request(s, s->reqs[id], VEG_ERR_HIP, t);
+    (void)hipStreamSynchronize(sl.stream);
+    sl.busy = false;
+    sl.reqs.clear();
+    s->in_use -= bytes;
+    s->inflight--;
+    if (s->inflight == 0 && s->busy_since >= 0) {
+      s->busy_acc += t - s->busy_since;
+      s->busy_since = -1;
+    }
+    s->cv_done.notify_all();
+  }
+  return true;
+}
+
+void scheduler(veg_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    const double t = now_s();
+    for (Slot& sl : s->slots)
+      if (sl.busy && hipEventQuery(sl.done) == hipSuccess) reap(s, sl, t);
+    bool launched = true;
+    while (launched) {
+      launched = false;
+      for (Slot& sl : s->slots)
+        if (!sl.busy && try_launch(s, sl)) launched = true;
+    }
+    if (s->stop && s->inflight == 0) break;
+    if (s->inflight > 0) {
+      s->cv.wait_for(lk, std::chrono::microseconds(20));
+    } else {
+      s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+    }
+  }
+  // drain: anything still queued fails
+  const double t = now_s();
+  while (!s->queue.empty()) {
+    finish_request(s, s->reqs[s->queue.front()], VEG_ERR_SHUTDOWN, t);
+    s->queue.pop_front();
+  }
+  s->cv_done.notify_all();
+}
+
+void free_slots(veg_server* s) {
+  for (Slot& sl : s->slots) {
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.h_stage) (void)hipHostFree(sl.h_stage);
+    if (sl.h_luts) (void)hipHostFree(sl.h_luts);
+    if (sl.h_counters) (void)hipHostFree(sl.h_counters);
+  }
+  s->slots.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t veg_serve_arena_bytes(const veg_serve_config* cfg) {
+  if (check_cfg(cfg) != VEG_OK) return 0;
+  return slot_layout(*cfg).total * (size_t)cfg->n_streams + 256;
+}
+
+veg_status veg_serve_create(const veg_serve_config* cfg, veg_server** out) {
+  set_last_error("");
+  veg_status st = check_cfg(cfg);
+  if (st != VEG_OK) return st;
+  if (!out || !cfg->arena) return sfail(VEG_ERR_INVALID_ARG, "NULL arena or output");
+  const Layout L = slot_layout(*cfg);
+  if (cfg->arena_bytes < L.total * (size_t)cfg->n_streams + 256)
+    return sfail(VEG_ERR_INVALID_ARG, "arena too small: need %zu bytes", L.total * (size_t)cfg->n_streams + 256);
+  veg_server* s = new veg_server();
+  s->cfg = *cfg;
+  if (s->cfg.budget_bytes == 0) s->cfg.budget_bytes = cfg->arena_bytes;
+  (void)hipGetDevice(&s->device);
+  s->pairs_cap = pairs_cap_of(*cfg);
+  s->entries_cap = cfg->max_entries;
+  s->max_tiles_frame = tiles_of(cfg->max_width, cfg->max_height);
+  s->total_tiles_cap = (uint32_t)(cfg->max_batch * s->max_tiles_frame);
+  s->slots.resize(cfg->n_streams);
+  unsigned char* base = (unsigned char*)(((uintptr_t)cfg->arena + 255) & ~(uintptr_t)255);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < cfg->n_streams && e == hipSuccess; ++k) {
+    Slot& sl = s->slots[k];
+    unsigned char* b = base + (size_t)k * L.total;
+    sl.d_header = (BatchHeader*)(b + L.header);
+    sl.d_descs = (FrameDesc*)(b + L.header + sizeof(BatchHeader));
+    sl.d_luts = (float*)(b + L.luts);
+    sl.rec = (float4*)(b + L.rec);
+    sl.count = (uint32_t*)(b + L.count);
+    sl.depth = (uint32_t*)(b + L.depth);
+    sl.ws = b + L.ws;
+    carve_bin_ws(sl.ws, s->pairs_cap, &sl.bws);
+    uint32_t* kb = (uint32_t*)(b + L.keys);
+    sl.keys = kb;
+    sl.vals = kb + cfg->max_entries;
+    sl.keys_alt = kb + 2 * cfg->max_entries;
+    sl.vals_alt = kb + 3 * cfg->max_entries;
+    sl.ranges = (uint32_t*)(b + L.ranges);
+    e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&sl.h_stage, sizeof(BatchHeader) + (size_t)cfg->max_batch * sizeof(FrameDesc), 0);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&sl.h_luts, (size_t)cfg->max_batch * cfg->max_tf_k * 4 * sizeof(float), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_counters, 64, 0);
+  }
+  if (e != hipSuccess) {
+    free_slots(s);
+    delete s;
+    return sfail(VEG_ERR_HIP, "serve_create: %s", hipGetErrorString(e));
+  }
+  s->sched = std::thread(scheduler, s);
+  *out = s;
+  return VEG_OK;
+}
+
+veg_status veg_serve_add_model(veg_server* s, const veg_gaussians* g, int32_t* model_id) {
+  set_last_error("");
+  if (!s || !g || !model_id) return sfail(VEG_ERR_INVALID_ARG, "NULL argument");
+  if (g->n < 1 || g->n > s->cfg.max_gaussians) return sfail(VEG_ERR_INVALID_ARG, "model size out of range");
+  if (!g->means || !g->log_scales || !g->quats || !g->scalars)
+    return sfail(VEG_ERR_INVALID_ARG, "NULL model array");
+  if (reinterpret_cast<uintptr_t>(g->quats) & 15u) return sfail(VEG_ERR_INVALID_ARG, "quats must be 16-byte aligned");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->models.push_back(*g);
+  *model_id = (int32_t)s->models.size() - 1;
+  return VEG_OK;
+}
+
+veg_status veg_serve_submit(veg_server* s, const veg_request* r, uint64_t* req_id) {
+  set_last_error("");
+  if (!s || !r || !req_id) return sfail(VEG_ERR_INVALID_ARG, "NULL argument");
+  const veg_camera& c = r->camera;
+  if (c.width < 1 || c.height < 1 || c.width > s->cfg.max_width || c.height > s->cfg.max_height)
+    return sfail(VEG_ERR_INVALID_ARG, "resolution outside the server's limits");
+  if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+    return sfail(VEG_ERR_INVALID_ARG, "need fx, fy > 0 and finite cx, cy");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(c.view[k])) return sfail(VEG_ERR_INVALID_ARG, "non-finite view matrix");
+  if (!r->tf_rgba || r->tf_k < 2 || r->tf_k > s->cfg.max_tf_k) return sfail(VEG_ERR_INVALID_ARG, "bad TF table");
+  if (!r->out_image) return sfail(VEG_ERR_INVALID_ARG, "NULL out_image");
+  const veg_opts& o = r->opts;
+  if (!(o.alpha_min > 0.0f) || !(o.alpha_clamp > o.alpha_min) || !(o.alpha_clamp <= 1.0f) || !(o.t_min >= 0.0f) ||
+      !(o.t_min < 1.0f) || !(o.lowpass >= 0.0f) || !(o.near_z > 0.0f) || !(o.guard > 0.0f))
+    return sfail(VEG_ERR_INVALID_ARG, "bad options");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return sfail(VEG_ERR_SHUTDOWN, "server is shutting down");
+  if (r->model_id < 0 || r->model_id >= (int32_t)s->models.size()) return sfail(VEG_ERR_NOT_FOUND, "unknown model");
+  Req q;
+  q.id = s->next_id++;
+  q.r = *r;
+  q.tf.assign(r->tf_rgba, r->tf_rgba + (size_t)r->tf_k * 4);
+  q.r.tf_rgba = nullptr;
+  q.n = s->models[r->model_id].n;
+  q.est_entries = entry_prior(q.n, c.width, c.height);
+  q.est_bytes = req_bytes(q.n, q.est_entries, c.width, c.height);
+  q.t_submit = now_s();
+  if (q.n > s->pairs_cap || q.est_bytes > (int64_t)s->cfg.budget_bytes) {
+    s->rejected++;
+    return sfail(VEG_ERR_OUT_OF_BUDGET, "request can never fit (pairs %lld, est. bytes %lld, budget %zu)",
+                 (long long)q.n, (long long)q.est_bytes, s->cfg.budget_bytes);
+  }
+  s->submitted++;
+  if (s->first_submit < 0) s->first_submit = q.t_submit;
+  *req_id = q.id;
+  s->queue.push_back(q.id);
+  s->reqs.emplace(q.id, std::move(q));
+  s->cv.notify_all();
+  return VEG_OK;
+}
+
+veg_status veg_serve_poll(veg_server* s, uint64_t req_id, int32_t* state) {
+  set_last_error("");
+  if (!s || !state) return sfail(VEG_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(req_id);
+  if (it == s->reqs.end()) return sfail(VEG_ERR_NOT_FOUND, "unknown request");
+  *state = it->second.state;
+  return VEG_OK;
+}
+
+veg_status veg_serve_wait(veg_server* s, uint64_t req_id, int32_t timeout_ms) {
+  set_last_error("");
+  if (!s) return sfail(VEG_ERR_INVALID_ARG, "NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(req_id);
+  if (it == s->reqs.end()) return sfail(VEG_ERR_NOT_FOUND, "unknown request");
+  auto finished = [&] {
+    const int32_t st = s->reqs[req_id].state;
+    return st == VEG_REQ_DONE || st == VEG_REQ_FAILED;
+  };
+  if (timeout_ms < 0) {
+    s->cv_done.wait(lk, finished);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), finished)) {
+    return sfail(VEG_ERR_TIMEOUT, "request %llu not finished", (unsigned long long)req_id);
+  }
+  const veg_status st = s->reqs[req_id].status;
+  s->reqs.erase(req_id);   // a finished request is released once it has been waited on
+  if (st != VEG_OK) return sfail(st, "request %llu failed: %s", (unsigned long long)req_id, s->err.c_str());
+  return VEG_OK;
+}
+
+veg_status veg_serve_stats_get(veg_server* s, veg_serve_stats* out) {
+  set_last_error("");
+  if (!s || !out) return sfail(VEG_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->failed = s->failed;
+  out->rejected = s->rejected;
+  out->batches = s->batches;
+  out->retries = s->retries;
+  out->mean_batch = s->batches ? s->sum_batch / (double)s->batches : 0.0;
+  if (!s->lat_ms.empty()) {
+    std::vector<double> v = s->lat_ms;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+      const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::ceil(p * (double)v.size()) - 1);
+      return v[i];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    out->max_ms = v.back();
+  }
+  const double span = (s->last_done > s->first_submit && s->first_submit >= 0) ? s->last_done - s->first_submit : 0;
+  if (span > 0) {
+    out->throughput_rps = (double)s->completed / span;
+    out->mpix_per_s = s->pix_done / span / 1e6;
+    double busy = s->busy_acc;
+    if (s->busy_since >= 0) busy += now_s() - s->busy_since;
+    out->gpu_busy_frac = std::min(1.0, busy / span);
+  }
+  out->peak_bytes = s->peak;
+  return VEG_OK;
+}
+
+veg_status veg_serve_stats_reset(veg_server* s) {
+  if (!s) return sfail(VEG_ERR_INVALID_ARG, "NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->lat_ms.clear();
+  s->submitted = s->completed = s->failed = s->rejected = s->batches = s->retries = 0;
+  s->sum_batch = s->pix_done = 0;
+  s->first_submit = s->last_done = -1;
+  s->busy_acc = 0;
+  s->busy_since = s->inflight > 0 ? now_s() : -1;
+  s->peak = s->in_use;
+  // forget finished requests
+  for (auto it = s->reqs.begin(); it != s->reqs.end();) {
+    if (it->second.state == VEG_REQ_DONE || it->second.state == VEG_REQ_FAILED) it = s->reqs.erase(it);
+    else ++it;
+  }
+  return VEG_OK;
+}
+
+veg_status veg_serve_destroy(veg_server* s) {
+  if (!s) return sfail(VEG_ERR_INVALID_ARG, "NULL server");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->sched.joinable()) s->sched.join();
+  for (Slot& sl : s->slots)
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+  free_slots(s);
+  delete s;
+  return VEG_OK;
+}
+
+}  // extern "C"

@@ -23,6 +23,7 @@ class FwdState:
     n_last: torch.Tensor
     n_entries: int
     opts: object
+    n_contrib: Optional[torch.Tensor] = None
 
 
 class _NoTimer:
@@ -67,7 +68,7 @@ class EventTimer:
 
 
 def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=None, stream=None,
-           capacity: Optional[int] = None, timer=NO_TIMER) -> FwdState:
+           capacity: Optional[int] = None, timer=NO_TIMER, want_contrib: bool = False) -> FwdState:
     """Forward render of len(cams) frames (one model, one image size).
 
     With ``capacity`` None the key-list length is read back (one stream synchronisation)
@@ -93,9 +94,10 @@ def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=Non
     image = torch.empty((F, 3, H, W), dtype=torch.float32, device=dev)
     t_final = torch.empty((F, H, W), dtype=torch.float32, device=dev)
     n_last = torch.empty((F, H, W), dtype=torch.int32, device=dev)
+    n_contrib = torch.empty((F, H, W), dtype=torch.int32, device=dev) if want_contrib else None
     with timer("blend_fwd"):
-        V.veg_render_fwd(proj, bins, o, image, t_final, n_last, stream=stream)
-    return FwdState(proj, bins, ws, image, t_final, n_last, E, o)
+        V.veg_render_fwd(proj, bins, o, image, t_final, n_last, n_contrib, stream=stream)
+    return FwdState(proj, bins, ws, image, t_final, n_last, E, o, n_contrib)
 
 
 @dataclass
@@ -177,7 +179,7 @@ class StepResult:
 def train_step_l1(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], frames: Sequence[tuple],
                   targets: torch.Tensor, grads: Grads, group: int, opts=None, stream=None,
                   loss_acc: Optional[torch.Tensor] = None, read_loss: bool = True, timer=NO_TIMER,
-                  on_group=None) -> StepResult:
+                  on_group=None, want_contrib: bool = False) -> StepResult:
     """One multi-view x multi-TF training step with L1 loss (mean over all frames).
 
     Frames are processed in groups of ``group``: each group is projected, binned, blended,
@@ -195,7 +197,8 @@ def train_step_l1(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], f
     entries = []
     for f0 in range(0, F, group):
         fr = frames[f0:f0 + group]
-        st = render(g, [cams[c] for c, _ in fr], [tfs[t] for _, t in fr], o, stream=stream, timer=timer)
+        st = render(g, [cams[c] for c, _ in fr], [tfs[t] for _, t in fr], o, stream=stream, timer=timer,
+                    want_contrib=want_contrib)
         entries.append(st.n_entries)
         d_image = torch.empty_like(st.image)
         with timer("l1_loss"):

@@ -186,10 +186,11 @@ def veg_bin_overflow(ws: torch.Tensor, stream=None):
 
 
 def veg_render_fwd(proj: Proj, bins: Bins, opts, image: torch.Tensor, t_final: Optional[torch.Tensor],
-                   n_last: Optional[torch.Tensor], stream=None):
+                   n_last: Optional[torch.Tensor], n_contrib: Optional[torch.Tensor] = None, stream=None):
     o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
     check(load().veg_render_fwd(ctypes.byref(proj.struct), ctypes.byref(bins.struct), ctypes.byref(o), _ptr(image),
-                                _ptr(t_final), _ptr(n_last), stream_handle(stream)), "veg_render_fwd")
+                                _ptr(t_final), _ptr(n_last), _ptr(n_contrib), stream_handle(stream)),
+          "veg_render_fwd")
 
 
 def veg_render_bwd(proj: Proj, bins: Bins, opts, t_final: torch.Tensor, n_last: torch.Tensor, d_image: torch.Tensor,

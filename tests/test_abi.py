@@ -52,3 +52,21 @@ def test_host_side_argument_errors_without_gpu():
     assert b"count" in lib.veg_last_error()
     assert lib.veg_fill_u32(None, 5, 0, None) == 1
     assert lib.veg_status_str(6) == b"HIP error"
+
+
+def test_serve_config_validation_on_host():
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    cfg = _lib.veg_serve_config()
+    cfg.max_batch, cfg.n_streams, cfg.max_width, cfg.max_height, cfg.max_tf_k = 8, 2, 1920, 1080, 256
+    cfg.max_gaussians, cfg.max_entries = 3_000_000, 100_000_000
+    need = lib.veg_serve_arena_bytes(ctypes.byref(cfg))
+    # per slot: records + counts + bin workspace for 24M pairs and 4 key arrays of 100M entries
+    assert 2 * (24_000_000 * 56 + 100_000_000 * 16) < need < 2 * (24_000_000 * 80 + 100_000_000 * 16) + (1 << 26)
+    cfg.max_batch = 0
+    assert lib.veg_serve_arena_bytes(ctypes.byref(cfg)) == 0
+    cfg.max_batch = 8
+    h = ctypes.c_void_p()
+    assert lib.veg_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == 1      # NULL arena
+    assert b"arena" in lib.veg_last_error()
