@@ -47,6 +47,9 @@ __device__ __forceinline__ float exponent(float base, float q1dx, float q2, floa
   return fmaf(-dy, fmaf(q2, dy, q1dx), base);
 }
 
+// One wave per tile.  A pixel is finished exactly when its T < t_min (blend-then-stop),
+// so T itself is the "still active" flag; pixels outside the image start with T = 0.
+template <bool kCount>
 __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -67,21 +70,22 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   __shared__ float4 s_col[kBatch];   // q2, l2A, R, G
   __shared__ float s_b[kBatch];      // B
 
-  float T[4], C[4][3];
+  const float tmin = o.t_min;
+  float T[4], C[4][3], pyl[4];
   int last[4], cnt[4];
-  bool done[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int py = ty * kTile + row0 + r;
-    T[r] = 1.0f;
+    T[r] = (px < d.W && py < d.H) ? 1.0f : 0.0f;
     C[r][0] = C[r][1] = C[r][2] = 0.0f;
     last[r] = -1;
     cnt[r] = 0;
-    done[r] = !(px < d.W && py < d.H);
+    pyl[r] = (float)(row0 + r) + 0.5f;
   }
   const float l2min = o.log2_alpha_min;
+  const float aclamp = o.alpha_clamp;
   for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
-    if (__all(done[0] && done[1] && done[2] && done[3])) break;
+    if (__all(T[0] < tmin && T[1] < tmin && T[2] < tmin && T[3] < tmin)) break;
     const uint32_t j = base + lane;
     if (j < rg.y) {
       const uint32_t p = vals[j];
@@ -97,24 +101,22 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
     for (int k = 0; k < n; ++k) {
       const float4 g = s_geo[k];
       const float4 c = s_col[k];
+      const float cb = s_b[k];
       const float dx = pxl - g.x;
       const float eb = exponent_base(g.z, c.y, dx);
       const float q1dx = g.w * dx;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float dy = ((float)(row0 + r) + 0.5f) - g.y;
-        const float e = exponent(eb, q1dx, c.x, dy);
-        if (!done[r] && e >= l2min) {
-          const float a = __builtin_amdgcn_exp2f(e);
-          const float alpha = fminf(a, o.alpha_clamp);
+        const float e = exponent(eb, q1dx, c.x, pyl[r] - g.y);
+        if (T[r] >= tmin && e >= l2min) {
+          const float alpha = fminf(__builtin_amdgcn_exp2f(e), aclamp);
           const float w = alpha * T[r];
           C[r][0] = fmaf(w, c.z, C[r][0]);
           C[r][1] = fmaf(w, c.w, C[r][1]);
-          C[r][2] = fmaf(w, s_b[k], C[r][2]);
+          C[r][2] = fmaf(w, cb, C[r][2]);
           T[r] = fmaf(-alpha, T[r], T[r]);
           last[r] = (int)(base + k);
-          ++cnt[r];
-          if (T[r] < o.t_min) done[r] = true;
+          if (kCount) ++cnt[r];
         }
       }
     }
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
       img[2 * HW + pi] = C[r][2] + T[r] * d.bg[2];
       if (tf) tf[pi] = T[r];
       if (nl) nl[pi] = last[r];
-      if (nc) nc[pi] = cnt[r];
+      if (kCount && nc) nc[pi] = cnt[r];
     }
   }
 }
@@ -146,6 +148,27 @@ __device__ __forceinline__ int wave_max_i32(int v) {
   return v;
 }
 
+// Sum over each 16-lane row of the wave, in place for all nine accumulators at once
+// (independent DPP chains interleaved, so no hazard stalls); the row total lands in lane 15
+// of the row.
+__device__ __forceinline__ void row_sums(float (&a)[9]) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) a[c] += dpp_shift_f<0x111, 0xf>(a[c]);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) a[c] += dpp_shift_f<0x112, 0xf>(a[c]);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) a[c] += dpp_shift_f<0x114, 0xf>(a[c]);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) a[c] += dpp_shift_f<0x118, 0xf>(a[c]);
+}
+
+// Backward: the same tile walk in reverse.  Per pixel and blended entry it accumulates
+// dL/dR,G,B, sum dsigma and the first and second moments of (dx, dy) weighted by dsigma;
+// the conic is applied once per entry when the batch is flushed:
+//   dL/dconic = (1/2 S_xx, S_xy, 1/2 S_yy),  dL/dmu' = -(a S_x + b S_y, b S_x + c S_y),
+//   dL/dA = -S_d / A   with S_d = sum dsigma and dsigma = dL/dsigma = -dL/dalpha * a.
+// Lanes reduce within their 16-lane row (DPP); the four row leaders add into a per-entry
+// LDS accumulator; each 64-entry batch ends with one vector atomic per component.
 __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -170,11 +193,12 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   const float* dip = dimage + (size_t)blockIdx.y * 3 * HW;
 
   __shared__ float4 s_geo[kBatch];   // mx, my, q0, q1
-  __shared__ float4 s_q[kBatch];     // q2, l2A, 1/A, pair id (bits)
+  __shared__ float4 s_q[kBatch];     // q2, l2A, R, G
   __shared__ float4 s_con[kBatch];   // conic a, b, c, B
-  __shared__ float2 s_rg[kBatch];    // R, G
+  __shared__ float2 s_pa[kBatch];    // pair id (bits), 1/A
+  __shared__ float s_acc[kBatch][9];
 
-  float T[4], S[4][3], gr[4][3];
+  float T[4], S[4][3], gr[4][3], pyl[4];
   int last[4];
   int jmax = -1;
 #pragma unroll
@@ -190,12 +214,14 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
     S[r][0] = d.bg[0];
     S[r][1] = d.bg[1];
     S[r][2] = d.bg[2];
+    pyl[r] = (float)(row0 + r) + 0.5f;
     jmax = max(jmax, last[r]);
   }
   jmax = min(wave_max_i32(jmax), (int)rg.y - 1);   // n_last lies inside this tile's range
   if (jmax < (int)rg.x) return;
   const float l2min = o.log2_alpha_min;
   const float aclamp = o.alpha_clamp;
+  for (int c = 0; c < 9; ++c) s_acc[lane][c] = 0.0f;
   for (int hi = jmax + 1; hi > (int)rg.x; hi -= kBatch) {
     const int lo = max((int)rg.x, hi - kBatch);
     const int j = lo + lane;
@@ -205,28 +231,28 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
       const Staged s = stage(r0, r1, r2, tx, ty);
       s_geo[lane] = make_float4(s.mx, s.my, s.q0, s.q1);
-      s_q[lane] = make_float4(s.q2, s.l2A, 1.0f / r1.y, __uint_as_float(p));
+      s_q[lane] = make_float4(s.q2, s.l2A, r1.z, r1.w);
       s_con[lane] = make_float4(r0.z, r0.w, r1.x, r2.x);
-      s_rg[lane] = make_float2(r1.z, r1.w);
+      s_pa[lane] = make_float2(__uint_as_float(p), 1.0f / r1.y);
     }
     __syncthreads();
     for (int k = hi - 1 - lo; k >= 0; --k) {
       const int jj = lo + k;
       const float4 g = s_geo[k];
       const float4 q = s_q[k];
-      const float4 cn = s_con[k];
-      const float2 rgc = s_rg[k];
-      const float rgbv[3] = {rgc.x, rgc.y, cn.w};
+      const float cbv = s_con[k].w;
+      const float rgbv[3] = {q.z, q.w, cbv};
       const float dx = pxl - g.x;
       const float eb = exponent_base(g.z, q.y, dx);
       const float q1dx = g.w * dx;
+      // acc: 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 R, 6 G, 7 B, 8 S_d
       float acc[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
       bool contrib = false;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float dy = ((float)(row0 + r) + 0.5f) - g.y;
+        const float dy = pyl[r] - g.y;
         const float e = exponent(eb, q1dx, q.x, dy);
         if (jj <= last[r] && e >= l2min) {
           contrib = true;
@@ -243,27 +269,50 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
             dalpha = fmaf(gr[r][ch], diff, dalpha);
             S[r][ch] = fmaf(alpha, diff, S[r][ch]);
           }
-          dalpha *= Tk;
           T[r] = Tk;
-          if (!clamped) {
-            const float dsig = -dalpha * a;          // dL/dsigma
-            acc[8] = fmaf(dalpha * a, q.z, acc[8]);  // dL/dA = dL/dalpha * exp(-sigma)
-            acc[2] = fmaf(0.5f * dx * dx, dsig, acc[2]);
-            acc[3] = fmaf(dx * dy, dsig, acc[3]);
-            acc[4] = fmaf(0.5f * dy * dy, dsig, acc[4]);
-            acc[0] = fmaf(-dsig, fmaf(cn.x, dx, cn.y * dy), acc[0]);
-            acc[1] = fmaf(-dsig, fmaf(cn.y, dx, cn.z * dy), acc[1]);
-          }
+          const float dsig = clamped ? 0.0f : -(dalpha * Tk) * a;   // dL/dsigma
+          const float u = dsig * dx, v = dsig * dy;
+          acc[0] += u;
+          acc[1] += v;
+          acc[2] = fmaf(u, dx, acc[2]);
+          acc[3] = fmaf(u, dy, acc[3]);
+          acc[4] = fmaf(v, dy, acc[4]);
+          acc[8] += dsig;
         }
       }
       if (__any(contrib)) {
-        const uint32_t p = __float_as_uint(q.w);
+        row_sums(acc);
+        if ((lane & 15) == 15) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const float v = wave_sum_to_lane63(acc[c]);
-          if (lane == 63 && v != 0.0f) unsafeAtomicAdd(g2d + (size_t)c * n_pairs + p, v);
+          for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[k][c], acc[c]);
         }
       }
+    }
+    __syncthreads();
+    // flush: lane l owns entry lo + l of this batch
+    if (lane < hi - lo) {
+      float a9[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        a9[c] = s_acc[lane][c];
+        s_acc[lane][c] = 0.0f;
+      }
+      const float4 cn = s_con[lane];
+      const float2 pa = s_pa[lane];
+      const size_t p = __float_as_uint(pa.x);
+      float out[9];
+      out[0] = -(cn.x * a9[0] + cn.y * a9[1]);
+      out[1] = -(cn.y * a9[0] + cn.z * a9[1]);
+      out[2] = 0.5f * a9[2];
+      out[3] = a9[3];
+      out[4] = 0.5f * a9[4];
+      out[5] = a9[5];
+      out[6] = a9[6];
+      out[7] = a9[7];
+      out[8] = -a9[8] * pa.y;
+#pragma unroll
+      for (int c = 0; c < 9; ++c)
+        if (out[c] != 0.0f) unsafeAtomicAdd(g2d + (size_t)c * n_pairs + p, out[c]);
     }
     __syncthreads();
   }
@@ -275,8 +324,12 @@ hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int max_tiles,
                             const uint32_t* vals, const uint32_t* ranges, float* image, float* tfinal, int32_t* nlast,
                             int32_t* ncontrib, hipStream_t stream) {
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(blend_fwd_kernel, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
-                     (const uint2*)ranges, image, tfinal, nlast, ncontrib);
+  if (ncontrib)
+    hipLaunchKernelGGL(blend_fwd_kernel<true>, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
+                       (const uint2*)ranges, image, tfinal, nlast, ncontrib);
+  else
+    hipLaunchKernelGGL(blend_fwd_kernel<false>, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
+                       (const uint2*)ranges, image, tfinal, nlast, ncontrib);
   return hipGetLastError();
 }
 
