@@ -230,7 +230,7 @@ veg_status veg_bin_count(const veg_proj* proj, void* ws, size_t ws_bytes, int64_
   carve_bin_ws(ws, (int64_t)pairs, &w);
   hipStream_t st = (hipStream_t)stream;
   if (pairs > 0) {
-    VEG_CHECK_HIP(launch_bin_count(proj->count, proj->depth, (uint32_t)pairs, w, st), "veg_bin_count");
+    VEG_CHECK_HIP(launch_bin_count((const float4*)proj->rec, proj->count, proj->depth, (uint32_t)pairs, w, st), "veg_bin_count");
   } else {
     VEG_CHECK_HIP(launch_fill_u32(w.counters, 64, 0u, st), "veg_bin_count");
   }

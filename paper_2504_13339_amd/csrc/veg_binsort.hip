@@ -19,10 +19,15 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kIpt = 8;                      // items per thread per tile
 constexpr int kTileItems = kThreads * kIpt;  // 2048
 
+constexpr int kSortIpt = 16;                       // radix sort: items per thread per tile
+constexpr int kSortTile = kThreads * kSortIpt;     // 4096
+constexpr int kChunk = 2048;                       // emission: output slots per chunk
+
 // Block b's contiguous segment of [0, n) when n is split over G blocks in whole tiles.
+template <int TILE = kTileItems>
 __device__ __forceinline__ void segment_of(uint32_t n, int G, int b, uint32_t& begin, uint32_t& end) {
   uint64_t per = ((uint64_t)n + (uint64_t)G - 1) / (uint64_t)G;
-  per = (per + kTileItems - 1) / kTileItems * kTileItems;
+  per = (per + TILE - 1) / TILE * TILE;
   const uint64_t bg = (uint64_t)b * per;
   begin = (uint32_t)(bg < n ? bg : n);
   const uint64_t en = bg + per;
@@ -62,7 +67,7 @@ __device__ __forceinline__ uint32_t block_reduce(uint32_t v, uint32_t* s_tmp) {
 // ------------------------------------------------------------------------------ scans
 // Three item kinds share the reduce-then-scan machinery:
 //   kVis : item i of the pairs, value = count[i] > 0   (compaction of kept pairs)
-//   kCnt : item j of the depth-sorted kept pairs, value = count[vals[j]]   (entry offsets)
+//   kCnt : item j of the depth-sorted kept pairs, value = its tile count   (entry offsets)
 //   kRaw : value = data[i]   (radix histogram scan)
 enum ScanKind { kVis = 0, kCnt = 1, kRaw = 2 };
 
@@ -75,7 +80,7 @@ struct ScanSrc {
 template <int KIND>
 __device__ __forceinline__ uint32_t item_value(const ScanSrc& s, uint32_t i) {
   if (KIND == kVis) return s.count[i] > 0u ? 1u : 0u;
-  if (KIND == kCnt) return s.count[s.vals[i]];
+  if (KIND == kCnt) return s.data[i];
   return s.data[i];
 }
 
@@ -176,16 +181,44 @@ __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __res
   }
 }
 
+// After the depth sort: one gather per kept pair, in front-to-back order, of what the
+// count scan and the emission need (pair id, tile rectangle, frame) and of its tile count,
+// so both later passes read sequentially.
+__global__ __launch_bounds__(kThreads) void gather_items_kernel(const float4* __restrict__ rec,
+                                                                const uint32_t* __restrict__ sorted_vals,
+                                                                const uint32_t* __restrict__ v_ptr, uint32_t v_cap,
+                                                                uint4* __restrict__ items,
+                                                                uint32_t* __restrict__ counts) {
+  const uint32_t n = read_count(v_ptr, v_cap);
+  for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < n; j += gridDim.x * kThreads) {
+    const uint32_t p = sorted_vals[j];
+    const float4 r2 = rec[3 * (size_t)p + 2];
+    const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
+    items[j] = make_uint4(p, a, b, __float_as_uint(r2.w));
+    counts[j] = ((b & 0xffffu) - (a & 0xffffu) + 1u) * ((b >> 16) - (a >> 16) + 1u);
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
+  v = max(v, dpp_shift<0x111, 0xf>(v));
+  v = max(v, dpp_shift<0x112, 0xf>(v));
+  v = max(v, dpp_shift<0x114, 0xf>(v));
+  v = max(v, dpp_shift<0x118, 0xf>(v));
+  v = max(v, dpp_shift<0x142, 0xa>(v));
+  v = max(v, dpp_shift<0x143, 0xc>(v));
+  return v;
+}
+
 // Downsweep of the entry-offset scan fused with emission: the j-th depth-sorted kept pair p
-// owns count[p] consecutive output slots starting at its offset and fills them with
-// (global tile, p), its rectangle's tiles in row-major order.  Each tile of items first
-// lays out the items' offsets and rectangles in LDS; then the block's threads write the
-// tile's contiguous output slots in order (coalesced), each slot finding its item by binary
-// search over the offsets, so one Gaussian covering many tiles does not serialise a lane.
+// owns count consecutive output slots starting at its offset and fills them with
+// (global tile, p), its rectangle's tiles in row-major order.  A tile of items lays out
+// offsets and rectangles in LDS; its output slots are then produced in chunks of 2048:
+// every item starting inside the chunk marks its first slot, a block-wide prefix maximum
+// turns the marks into the owner of every slot, and the threads write consecutive slots
+// (coalesced), so one Gaussian covering many tiles does not serialise a lane.
 __global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restrict__ descs,
-                                                        const float4* __restrict__ rec,
-                                                        const uint32_t* __restrict__ count,
-                                                        const uint32_t* __restrict__ sorted_vals,
+                                                        const uint4* __restrict__ items,
+                                                        const uint32_t* __restrict__ counts,
                                                         const uint32_t* __restrict__ v_ptr, uint32_t v_cap,
                                                         const uint64_t* __restrict__ partials, int G,
                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
@@ -195,25 +228,27 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restr
   __shared__ uint32_t s_pair[kTileItems];
   __shared__ uint32_t s_base[kTileItems];   // global tile id of the rectangle's first tile
   __shared__ uint32_t s_shape[kTileItems];  // rectangle width | tiles_x << 16
+  __shared__ uint32_t s_own[kChunk];        // 1 + owning item of each slot of the chunk
   const uint32_t n = read_count(v_ptr, v_cap);
   uint32_t begin, end;
   segment_of(n, G, blockIdx.x, begin, end);
   uint64_t base = partials[blockIdx.x];
-  const uint32_t i0 = threadIdx.x * kIpt;
+  const uint32_t t = threadIdx.x;
+  const uint32_t i0 = t * kIpt;
+  const int lane = t & 63, w = t >> 6;
   for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
     uint32_t cn[kIpt];
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kIpt; ++k) {
       const uint32_t j = t0 + i0 + k;
-      const uint32_t p = j < end ? sorted_vals[j] : 0u;
-      cn[k] = j < end ? count[p] : 0u;
-      uint32_t b = 0, shape = 1;
+      cn[k] = j < end ? counts[j] : 0u;
+      uint32_t b = 0, shape = 1, p = 0;
       if (cn[k] > 0u) {
-        const float4 r2 = rec[3 * (size_t)p + 2];
-        const uint32_t a = __float_as_uint(r2.y), c = __float_as_uint(r2.z);
-        const FrameDesc& d = descs[__float_as_uint(r2.w)];
-        const uint32_t x0 = a & 0xffffu, y0 = a >> 16, x1 = c & 0xffffu;
+        const uint4 it = items[j];
+        p = it.x;
+        const FrameDesc& d = descs[it.w];
+        const uint32_t x0 = it.y & 0xffffu, y0 = it.y >> 16, x1 = it.z & 0xffffu;
         b = d.tile_base + y0 * (uint32_t)d.tiles_x + x0;
         shape = (x1 - x0 + 1u) | ((uint32_t)d.tiles_x << 16);
       }
@@ -224,36 +259,58 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restr
     }
     uint32_t tot;
     uint32_t off = block_excl_scan(s, s_tmp, &tot);
+    uint32_t offs[kIpt];
 #pragma unroll
     for (int k = 0; k < kIpt; ++k) {
+      offs[k] = off;
       s_off[i0 + k] = off;
       off += cn[k];
     }
-    __syncthreads();
-    for (uint32_t slot = threadIdx.x; slot < tot; slot += kThreads) {
-      // largest item index i with s_off[i] <= slot (it has a nonzero count)
-      uint32_t lo = 0, len = kTileItems;
-      while (len > 0) {
-        const uint32_t half = len >> 1;
-        if (s_off[lo + half] <= slot) {
-          lo += half + 1;
-          len -= half + 1;
-        } else {
-          len = half;
+    uint32_t carry = 0;   // 1 + owner of the slot before the chunk
+    for (uint32_t c0 = 0; c0 < tot; c0 += kChunk) {
+#pragma unroll
+      for (int k = 0; k < kChunk / kThreads; ++k) s_own[t * (kChunk / kThreads) + k] = 0u;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kIpt; ++k)
+        if (cn[k] > 0u && offs[k] >= c0 && offs[k] - c0 < (uint32_t)kChunk) s_own[offs[k] - c0] = i0 + k + 1u;
+      __syncthreads();
+      // block-wide inclusive prefix maximum of s_own (8 slots per thread)
+      uint32_t v[kChunk / kThreads], m = 0;
+#pragma unroll
+      for (int k = 0; k < kChunk / kThreads; ++k) {
+        m = max(m, s_own[t * (kChunk / kThreads) + k]);
+        v[k] = m;
+      }
+      const uint32_t wincl = wave_incl_max_u32(m);
+      if (lane == 63) s_tmp[w] = wincl;
+      const uint32_t wexcl = __shfl_up(wincl, 1) * (lane > 0 ? 1u : 0u);
+      __syncthreads();
+      uint32_t pre = carry;
+#pragma unroll
+      for (int k = 0; k < kWaves; ++k)
+        if (k < w) pre = max(pre, s_tmp[k]);
+      pre = max(pre, wexcl);
+#pragma unroll
+      for (int k = 0; k < kChunk / kThreads; ++k) s_own[t * (kChunk / kThreads) + k] = max(pre, v[k]);
+      __syncthreads();
+      const uint32_t nslot = min((uint32_t)kChunk, tot - c0);
+      for (uint32_t sl = t; sl < nslot; sl += kThreads) {
+        const uint32_t i = s_own[sl] - 1u;
+        const uint32_t local = c0 + sl - s_off[i];
+        const uint32_t shape = s_shape[i];
+        const uint32_t wd = shape & 0xffffu, txn = shape >> 16;
+        uint32_t q = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wd));
+        if (q * wd > local) --q;
+        else if ((q + 1u) * wd <= local) ++q;
+        const uint64_t pos = base + c0 + sl;
+        if (pos < capacity) {
+          keys[pos] = s_base[i] + q * txn + (local - q * wd);
+          vals[pos] = s_pair[i];
         }
       }
-      const uint32_t i = lo - 1;
-      const uint32_t local = slot - s_off[i];
-      const uint32_t shape = s_shape[i];
-      const uint32_t w = shape & 0xffffu, txn = shape >> 16;
-      uint32_t q = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)w));
-      if (q * w > local) --q;
-      else if ((q + 1u) * w <= local) ++q;
-      const uint64_t pos = base + slot;
-      if (pos < capacity) {
-        keys[pos] = s_base[i] + q * txn + (local - q * w);
-        vals[pos] = s_pair[i];
-      }
+      carry = s_own[kChunk - 1];
+      __syncthreads();
     }
     base += tot;
     __syncthreads();
@@ -298,8 +355,8 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbit
   return valid ? peers : 0ull;
 }
 
-// Per-block digit histogram of its segment, hist[d * G + b].  Lanes with equal digits are
-// grouped (ballot match) so skewed digits do not serialise on one LDS counter.
+// Per-block digit histogram of its segment, hist[d * G + b], counted with per-wave LDS
+// atomics (a skewed digit serialises one wave's atomics, which stays cheap).
 __global__ __launch_bounds__(kThreads) void rs_upsweep_kernel(const uint32_t* __restrict__ keys,
                                                               const uint32_t* n_ptr, uint32_t n_cap, int shift,
                                                               int nbits, uint32_t* __restrict__ hist, int G) {
@@ -308,23 +365,26 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep_kernel(const uint32_t* __
   __syncthreads();
   const uint32_t n = read_count(n_ptr, n_cap);
   uint32_t begin, end;
-  segment_of(n, G, blockIdx.x, begin, end);
+  segment_of<kSortTile>(n, G, blockIdx.x, begin, end);
   const int w = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
-  const uint64_t lt = lanemask_lt();
-  for (uint32_t i0 = begin; i0 < end; i0 += kThreads) {
-    const uint32_t i = i0 + threadIdx.x;
-    const bool valid = i < end;
-    const uint32_t d = valid ? (keys[i] >> shift) & mask : 0u;
-    const uint64_t peers = match_digit(d, valid, nbits);
-    if (valid && (peers & lt) == 0ull) atomicAdd(&s_h[w][d], (uint32_t)__popcll(peers));
+  // segments start at multiples of kSortTile, so the 4-key vector loads are aligned
+  const uint32_t nvec = (end - begin) / 4;
+  for (uint32_t v = threadIdx.x; v < nvec; v += kThreads) {
+    const uint4 k4 = *reinterpret_cast<const uint4*>(keys + begin + 4 * v);
+    atomicAdd(&s_h[w][(k4.x >> shift) & mask], 1u);
+    atomicAdd(&s_h[w][(k4.y >> shift) & mask], 1u);
+    atomicAdd(&s_h[w][(k4.z >> shift) & mask], 1u);
+    atomicAdd(&s_h[w][(k4.w >> shift) & mask], 1u);
   }
+  const uint32_t tail = begin + 4 * nvec + threadIdx.x;
+  if (tail < end) atomicAdd(&s_h[w][(keys[tail] >> shift) & mask], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kThreads) {
-    uint32_t s = 0;
+    uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) s += s_h[k][d];
-    hist[(size_t)d * G + blockIdx.x] = s;
+    for (int k = 0; k < kWaves; ++k) c += s_h[k][d];
+    hist[(size_t)d * G + blockIdx.x] = c;
   }
 }
 
@@ -338,24 +398,24 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
   __shared__ uint32_t s_cnt[kWaves][kRadix];
   __shared__ uint32_t s_off[kRadix];
   __shared__ uint32_t s_glob[kRadix];
-  __shared__ uint32_t s_keys[kTileItems];
-  __shared__ uint32_t s_vals[kTileItems];
+  __shared__ uint32_t s_keys[kSortTile];
+  __shared__ uint32_t s_vals[kSortTile];
   __shared__ uint32_t s_tmp[kWaves];
   const uint32_t n = read_count(n_ptr, n_cap);
   uint32_t begin, end;
-  segment_of(n, G, blockIdx.x, begin, end);
+  segment_of<kSortTile>(n, G, blockIdx.x, begin, end);
   if (begin >= end) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
   const uint64_t lt = lanemask_lt();
   s_glob[t] = hist[(size_t)t * G + blockIdx.x];
-  for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
+  for (uint32_t t0 = begin; t0 < end; t0 += kSortTile) {
     for (int k = t; k < kWaves * kRadix; k += kThreads) (&s_cnt[0][0])[k] = 0u;
     __syncthreads();
-    uint32_t key[kIpt], val[kIpt], rank[kIpt];
+    uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
 #pragma unroll
-    for (int r = 0; r < kIpt; ++r) {
-      const uint32_t i = t0 + (uint32_t)(w * (kTileItems / kWaves) + r * 64 + lane);
+    for (int r = 0; r < kSortIpt; ++r) {
+      const uint32_t i = t0 + (uint32_t)(w * (kSortTile / kWaves) + r * 64 + lane);
       const bool valid = i < end;
       key[r] = valid ? kin[i] : 0u;
       val[r] = valid ? vin[i] : 0u;
@@ -384,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kIpt; ++r) {
+    for (int r = 0; r < kSortIpt; ++r) {
       if (rank[r] != 0xffffffffu) {
         const uint32_t d = (key[r] >> shift) & mask;
         const uint32_t pos = s_cnt[w][d] + rank[r];
@@ -393,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
       }
     }
     __syncthreads();
-    const uint32_t nt = min((uint32_t)kTileItems, end - t0);
+    const uint32_t nt = min((uint32_t)kSortTile, end - t0);
     for (uint32_t i = t; i < nt; i += kThreads) {
       const uint32_t k2 = s_keys[i];
       const uint32_t d = (k2 >> shift) & mask;
@@ -415,14 +475,32 @@ __global__ void finalize_kernel(uint32_t* counters, uint32_t capacity) {
   counters[4] = e > (uint64_t)capacity ? capacity : (uint32_t)e;   // entries actually written
 }
 
+// Per-tile [start, end) from the boundaries of the sorted keys; each thread takes 4
+// consecutive keys (one vector load) and compares with its neighbours.
 __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ e_ptr, uint32_t capacity,
                                                           uint32_t* __restrict__ ranges) {
   const uint32_t E = read_count(e_ptr, capacity);
-  for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < E; j += gridDim.x * kThreads) {
-    const uint32_t k = keys[j];
-    if (j == 0 || keys[j - 1] != k) ranges[2 * (size_t)k] = j;
-    if (j + 1 == E || keys[j + 1] != k) ranges[2 * (size_t)k + 1] = j + 1;
+  const uint32_t nq = (E + 3) / 4;
+  for (uint32_t q = blockIdx.x * kThreads + threadIdx.x; q < nq; q += gridDim.x * kThreads) {
+    const uint32_t j0 = 4 * q;
+    uint32_t k[6];
+    k[0] = j0 > 0 ? keys[j0 - 1] : 0xffffffffu;
+    if (j0 + 3 < E) {
+      const uint4 v = *reinterpret_cast<const uint4*>(keys + j0);
+      k[1] = v.x; k[2] = v.y; k[3] = v.z; k[4] = v.w;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) k[1 + i] = j0 + i < E ? keys[j0 + i] : 0xffffffffu;
+    }
+    k[5] = j0 + 4 < E ? keys[j0 + 4] : 0xffffffffu;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t j = j0 + i;
+      if (j >= E) break;
+      if (k[i] != k[i + 1]) ranges[2 * (size_t)k[i + 1]] = j;
+      if (k[i + 2] != k[i + 1] || j + 1 == E) ranges[2 * (size_t)k[i + 1] + 1] = j + 1;
+    }
   }
 }
 
@@ -439,7 +517,7 @@ int blocks_for(int64_t n, int items_per_block, int max_blocks) {
 }
 
 int scan_blocks(int64_t n) { return blocks_for(n, 2 * kTileItems, kMaxScanBlocks); }
-int sort_blocks(int64_t n) { return blocks_for(n, 2 * kTileItems, kMaxSortBlocks); }
+int sort_blocks(int64_t n) { return blocks_for(n, 2 * kSortTile, kMaxSortBlocks); }
 
 // LSD radix sort of (key, val) over bits [0, bits): ping-pongs between (k0,v0) and (k1,v1);
 // the result ends in (k0,v0) when the number of passes is even, else in (k1,v1).
@@ -471,11 +549,12 @@ size_t bin_ws_bytes(int64_t pairs) {
   const size_t p = (size_t)(pairs > 0 ? pairs : 1);
   size_t b = 0;
   b += 4 * p * sizeof(uint32_t);                       // depth-sort ping-pong
+  b += p * 16;                                         // depth-sorted item records
   b += kMaxScanBlocks * sizeof(uint64_t);              // scan partials (entry offsets)
   b += kMaxScanBlocks * sizeof(uint64_t);              // scan partials (scratch)
   b += (size_t)kRadix * kMaxSortBlocks * sizeof(uint32_t);  // radix histograms
   b += 64 * sizeof(uint32_t);                          // counters
-  return b + 9 * 256;                                  // alignment slack
+  return b + 10 * 256;                                 // alignment slack
 }
 
 void carve_bin_ws(void* ws, int64_t pairs, BinWs* out) {
@@ -495,11 +574,12 @@ void carve_bin_ws(void* ws, int64_t pairs, BinWs* out) {
   out->dvalA = (uint32_t*)take(p * 4);
   out->dkeyB = (uint32_t*)take(p * 4);
   out->dvalB = (uint32_t*)take(p * 4);
+  out->items = (uint32_t*)take(p * 16);
   out->depth_sorted_vals = out->dvalA;
 }
 
-hipError_t launch_bin_count(const uint32_t* count, const uint32_t* depth, uint32_t n_pairs, const BinWs& ws,
-                            hipStream_t stream, const uint32_t* n_pairs_dev) {
+hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,
+                            const BinWs& ws, hipStream_t stream, const uint32_t* n_pairs_dev) {
   uint64_t* partials = (uint64_t*)ws.partials;
   uint64_t* ptmp = (uint64_t*)ws.partials_tmp;
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, stream, ws.counters, (int64_t)64, 0u);
@@ -517,9 +597,12 @@ hipError_t launch_bin_count(const uint32_t* count, const uint32_t* depth, uint32
                             stream);
   if (e != hipSuccess) return e;
   // 4 passes: the sorted list is back in (dkeyA, dvalA)
-  // 3. entry offsets in that order; block offsets stay in `partials` for the emission
+  // 3. item records and tile counts in that order (counts reuse dkeyB)
+  hipLaunchKernelGGL(gather_items_kernel, dim3(blocks_for(n_pairs, kThreads * 4, 8192)), dim3(kThreads), 0, stream,
+                     (const float4*)rec, ws.dvalA, ws.counters + 0, n_pairs, (uint4*)ws.items, ws.dkeyB);
+  // 4. entry offsets in that order; block offsets stay in `partials` for the emission
   const int Gc = scan_blocks(n_pairs);
-  ScanSrc cnt{count, ws.dvalA, nullptr};
+  ScanSrc cnt{nullptr, nullptr, ws.dkeyB};
   hipLaunchKernelGGL(scan_reduce_kernel<kCnt>, dim3(Gc), dim3(kThreads), 0, stream, cnt, ws.counters + 0, n_pairs,
                      partials, Gc);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, partials, Gc, ws.counters + 1, nullptr);
@@ -548,7 +631,7 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
   uint32_t* ov = (passes % 2) ? vals : vals_alt;
   const int Gc = scan_blocks(n_pairs);
   if (capacity > 0) {
-    hipLaunchKernelGGL(emit_kernel, dim3(Gc), dim3(kThreads), 0, stream, descs, rec, count, ws.dvalA,
+    hipLaunchKernelGGL(emit_kernel, dim3(Gc), dim3(kThreads), 0, stream, descs, (const uint4*)ws.items, ws.dkeyB,
                        ws.counters + 0, n_pairs, partials, Gc, ek, ev, capacity);
     if (passes > 0) {
       hipError_t e = radix_sort(ek, ev, ok, ov, ws.counters + 4, capacity, bits, ws.hist, ptmp, stream);

@@ -151,15 +151,21 @@ __device__ __forceinline__ int wave_max_i32(int v) {
 // Sum over each 16-lane row of the wave, in place for all nine accumulators at once
 // (independent DPP chains interleaved, so no hazard stalls); the row total lands in lane 15
 // of the row.
+template <int CTRL>
+__device__ __forceinline__ float row_shr_zero(float v) {
+  // row_shr with bound_ctrl: lanes shifted in from outside the row read 0
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
 __device__ __forceinline__ void row_sums(float (&a)[9]) {
 #pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] += dpp_shift_f<0x111, 0xf>(a[c]);
+  for (int c = 0; c < 9; ++c) a[c] += row_shr_zero<0x111>(a[c]);
 #pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] += dpp_shift_f<0x112, 0xf>(a[c]);
+  for (int c = 0; c < 9; ++c) a[c] += row_shr_zero<0x112>(a[c]);
 #pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] += dpp_shift_f<0x114, 0xf>(a[c]);
+  for (int c = 0; c < 9; ++c) a[c] += row_shr_zero<0x114>(a[c]);
 #pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] += dpp_shift_f<0x118, 0xf>(a[c]);
+  for (int c = 0; c < 9; ++c) a[c] += row_shr_zero<0x118>(a[c]);
 }
 
 // Backward: the same tile walk in reverse.  Per pixel and blended entry it accumulates
@@ -280,11 +286,20 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
           acc[8] += dsig;
         }
       }
-      if (__any(contrib)) {
-        row_sums(acc);
-        if ((lane & 15) == 15) {
+      const uint64_t who = __ballot(contrib);
+      if (who != 0ull) {
+        if (__popcll(who) <= 4) {
+          // few contributing lanes: add their partial sums directly (<= 4-way LDS atomics)
+          if (contrib) {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[k][c], acc[c]);
+            for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[k][c], acc[c]);
+          }
+        } else {
+          row_sums(acc);
+          if ((lane & 15) == 15) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[k][c], acc[c]);
+          }
         }
       }
     }

@@ -117,6 +117,7 @@ struct BinWs {
   uint32_t* dvalA;
   uint32_t* dkeyB;
   uint32_t* dvalB;
+  uint32_t* items;          // [pairs] uint4: depth-sorted (pair, rect01, rect23, frame)
   uint32_t* partials;       // [kMaxScanBlocks] uint64: entry-offset scan, kept from count to sort
   uint32_t* partials_tmp;   // [kMaxScanBlocks] uint64: scratch for the other scans
   uint32_t* hist;       // [kRadix * kMaxSortBlocks]
@@ -131,7 +132,7 @@ void carve_bin_ws(void* ws, int64_t pairs, BinWs* out);
 
 // n_pairs bounds the pair count; when n_pairs_dev is non-null the actual count is read
 // from device memory (capacity mode, used by the server's captured graphs).
-hipError_t launch_bin_count(const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,
+hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,
                             const BinWs& ws, hipStream_t stream, const uint32_t* n_pairs_dev = nullptr);
 hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* rec,
                            const uint32_t* count, uint32_t n_pairs, uint32_t total_tiles,

@@ -215,7 +215,7 @@ hipError_t run_pipeline(veg_server* s, Slot& sl, const KOpts& ko) {
   hipError_t e = launch_project(sl.d_descs, c.max_batch, (int)c.max_gaussians, ko, sl.rec, sl.count, sl.depth, false,
                                 sl.stream);
   if (e != hipSuccess) return e;
-  e = launch_bin_count(sl.count, sl.depth, (uint32_t)s->pairs_cap, sl.bws, sl.stream, &sl.d_header->n_pairs);
+  e = launch_bin_count(sl.rec, sl.count, sl.depth, (uint32_t)s->pairs_cap, sl.bws, sl.stream, &sl.d_header->n_pairs);
   if (e != hipSuccess) return e;
   e = launch_bin_sort(sl.d_descs, c.max_batch, sl.rec, sl.count, (uint32_t)s->pairs_cap, s->total_tiles_cap, sl.bws,
                       sl.keys, sl.vals, sl.keys_alt, sl.vals_alt, sl.ranges, (uint32_t)s->entries_cap, sl.stream);

@@ -62,8 +62,8 @@ def test_serve_config_validation_on_host():
     cfg.max_batch, cfg.n_streams, cfg.max_width, cfg.max_height, cfg.max_tf_k = 8, 2, 1920, 1080, 256
     cfg.max_gaussians, cfg.max_entries = 3_000_000, 100_000_000
     need = lib.veg_serve_arena_bytes(ctypes.byref(cfg))
-    # per slot: records + counts + bin workspace for 24M pairs and 4 key arrays of 100M entries
-    assert 2 * (24_000_000 * 56 + 100_000_000 * 16) < need < 2 * (24_000_000 * 80 + 100_000_000 * 16) + (1 << 26)
+    # per slot: 88 B per pair (48 record, 8 count/depth, 32 bin workspace) + 16 B per key-list entry
+    assert 2 * (24_000_000 * 88 + 100_000_000 * 16) <= need < 2 * (24_000_000 * 96 + 100_000_000 * 16) + (1 << 26)
     cfg.max_batch = 0
     assert lib.veg_serve_arena_bytes(ctypes.byref(cfg)) == 0
     cfg.max_batch = 8

@@ -1,0 +1,117 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times
+(groups of 16 frames of 1024x1024 over 1M Gaussians; 2048x2048 over 4M Gaussians).
+
+The oracle cannot brute-force whole frames at these sizes, so the checks are: sampled
+pixels (float64 brute force over all Gaussians), sampled tiles' key lists (bit-exact
+against the float32 footprint mirror), properties of the whole key list that hold at any
+size (sorted, every kept pair appears exactly count times, ranges partition the list), and
+the gradient of a loss restricted to sampled pixels.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import compare_image, image_pixels, luts_to_dev, rel_err, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _group(w, frames):
+    from paper_2504_13339_amd import render as R
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    st = R.render(g, [w.cameras[c] for c, _ in frames], [luts[t] for _, t in frames], w.opts)
+    torch.cuda.synchronize()
+    return g, luts, st
+
+
+def _check_whole_list(st, n, n_frames):
+    E = st.n_entries
+    keys = st.bins.keys[:E].cpu().numpy().view(np.uint32).astype(np.int64)
+    vals = st.bins.vals[:E].cpu().numpy().view(np.uint32).astype(np.int64)
+    assert (np.diff(keys) >= 0).all()
+    count = st.proj.count.cpu().numpy().view(np.uint32)[: n * n_frames].astype(np.int64)
+    assert np.array_equal(np.bincount(vals, minlength=n * n_frames), count)
+    rg = st.bins.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
+    nz = rg[:, 1] > rg[:, 0]
+    assert (rg[nz, 1] - rg[nz, 0]).sum() == E
+    assert (rg[nz, 0][1:] == rg[nz, 1][:-1]).all()          # contiguous, in tile order
+    return keys, vals, rg
+
+
+def _check_sampled_tiles(w, st, frames, keys, vals, rg, n_tiles, seed):
+    """Tile lists of sampled tiles (including the fullest) equal the mirror's."""
+    n = w.gaussians.n
+    rng = np.random.default_rng(seed)
+    tx_n = (w.width + 15) // 16
+    per_frame = tx_n * ((w.height + 15) // 16)
+    for f in (0, len(frames) - 1):
+        ci, ti = frames[f]
+        fp = oracle.footprint_f32(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts)
+        lens = rg[f * per_frame:(f + 1) * per_frame, 1] - rg[f * per_frame:(f + 1) * per_frame, 0]
+        pick = list(rng.integers(0, per_frame, n_tiles)) + [int(np.argmax(lens))]
+        for t in pick:
+            ty, tx = divmod(int(t), tx_n)
+            cover = (fp.count > 0) & (fp.rect[:, 0] <= tx) & (fp.rect[:, 2] >= tx) & \
+                    (fp.rect[:, 1] <= ty) & (fp.rect[:, 3] >= ty)
+            idx = np.nonzero(cover)[0]
+            ref = idx[np.lexsort((idx, fp.depth_bits[idx]))] + f * n
+            s, e = rg[f * per_frame + t]
+            got = vals[s:e] if e > s else np.zeros(0, np.int64)
+            assert np.array_equal(got, ref), (f, t)
+
+
+def test_train_workload_group_of_16_frames():
+    w = synth.workload(2)
+    frames = w.frames[:16]
+    g, luts, st = _group(w, frames)
+    keys, vals, rg = _check_whole_list(st, w.gaussians.n, len(frames))
+    _check_sampled_tiles(w, st, frames, keys, vals, rg, 6, 1)
+    rng = synth.rng_for(2, 77)
+    for f in (0, 9):
+        ci, ti = frames[f]
+        px = synth.sample_pixels(rng, w.width, w.height, 192)
+        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
+        gpu = image_pixels(st.image[f])[px[:, 1] * w.width + px[:, 0]]
+        compare_image(gpu, res)
+
+
+def test_train_workload_sampled_pixel_gradient():
+    """dL/dparams for L = sum over 48 sampled pixels of d . image (frame 3 of the group)."""
+    from paper_2504_13339_amd import render as R
+    w = synth.workload(2)
+    frames = w.frames[:16]
+    g, luts, st = _group(w, frames)
+    f = 3
+    ci, ti = frames[f]
+    rng = synth.rng_for(2, 78)
+    px = synth.sample_pixels(rng, w.width, w.height, 48)
+    d = rng.standard_normal((48, 3))
+    res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
+    d[res.flag_grad] = 0.0
+    d_np = np.zeros((len(frames), 3, w.height, w.width), np.float32)
+    for ch in range(3):   # accumulate, so a pixel sampled twice counts twice as in the oracle
+        np.add.at(d_np[f, ch], (px[:, 1], px[:, 0]), d[:, ch].astype(np.float32))
+    d_img = torch.as_tensor(d_np)
+    grads = R.Grads.zeros(g)
+    R.render_backward(g, st, d_img.cuda(), grads)
+    torch.cuda.synchronize()
+    ref = oracle.gradients(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, d, pixels=px)
+    for name in ("d_means", "d_log_scales", "d_quats", "d_scalars"):
+        assert rel_err(getattr(grads, name).cpu().numpy(), getattr(ref, name)) <= 1e-3, name
+
+
+def test_stress_workload_2048px_4M():
+    w = synth.workload(4)
+    frames = [w.frames[0], w.frames[77]]
+    g, luts, st = _group(w, frames)
+    keys, vals, rg = _check_whole_list(st, w.gaussians.n, len(frames))
+    _check_sampled_tiles(w, st, frames, keys, vals, rg, 3, 2)
+    rng = synth.rng_for(4, 79)
+    for f, (ci, ti) in enumerate(frames):
+        px = synth.sample_pixels(rng, w.width, w.height, 96)
+        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
+        gpu = image_pixels(st.image[f])[px[:, 1] * w.width + px[:, 0]]
+        compare_image(gpu, res)
