@@ -1,7 +1,9 @@
 // Front-to-back blending (paper, Eq. 1) and its adjoint.
 //
-// One 64-lane wave per 16x16 tile; lane l owns the four pixels of column l & 15, rows
-// 4*(l >> 4) .. +3, so the x-offset work of an entry is shared by its four pixels.  The
+// One 64-lane wave per 16x16 tile; lane l owns pixel (l & 7, l >> 3) of each 8x8 quadrant,
+// and the wave takes the quadrants one after another, so the lanes active for an entry in
+// one step are a compact 8x8 block: a small footprint wakes up only the quadrants it
+// touches, the others are skipped whole (empty execution mask).  The
 // tile's list is staged through LDS in batches of 64 entries: each lane fetches one
 // record, turns it into tile-local, log2-scaled form, and the wave then walks the batch
 // with every lane reading the same LDS slot (a broadcast).  A pixel stops after the
@@ -62,25 +64,25 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
   const uint2 rg = ranges[d.tile_base + tile];
   const int lane = threadIdx.x;
-  const int col = lane & 15, row0 = (lane >> 4) * 4;
-  const int px = tx * kTile + col;
-  const float pxl = (float)col + 0.5f;
+  const int qx = lane & 7, qy = lane >> 3;
+  // tile-local pixel centres: quadrant r sits at (8 (r & 1), 8 (r >> 1))
+  const float pxl0 = (float)qx + 0.5f, pxl1 = (float)(qx + 8) + 0.5f;
+  const float pyl0 = (float)qy + 0.5f, pyl1 = (float)(qy + 8) + 0.5f;
 
   __shared__ float4 s_geo[kBatch];   // mx, my, q0, q1
   __shared__ float4 s_col[kBatch];   // q2, l2A, R, G
   __shared__ float s_b[kBatch];      // B
 
   const float tmin = o.t_min;
-  float T[4], C[4][3], pyl[4];
+  float T[4], C[4][3];
   int last[4], cnt[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int py = ty * kTile + row0 + r;
+    const int px = tx * kTile + qx + 8 * (r & 1), py = ty * kTile + qy + 8 * (r >> 1);
     T[r] = (px < d.W && py < d.H) ? 1.0f : 0.0f;
     C[r][0] = C[r][1] = C[r][2] = 0.0f;
     last[r] = -1;
     cnt[r] = 0;
-    pyl[r] = (float)(row0 + r) + 0.5f;
   }
   const float l2min = o.log2_alpha_min;
   const float aclamp = o.alpha_clamp;
@@ -102,12 +104,13 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
       const float4 g = s_geo[k];
       const float4 c = s_col[k];
       const float cb = s_b[k];
-      const float dx = pxl - g.x;
-      const float eb = exponent_base(g.z, c.y, dx);
-      const float q1dx = g.w * dx;
+      const float dx0 = pxl0 - g.x, dx1 = pxl1 - g.x;
+      const float eb0 = exponent_base(g.z, c.y, dx0), eb1 = exponent_base(g.z, c.y, dx1);
+      const float q1dx0 = g.w * dx0, q1dx1 = g.w * dx1;
+      const float dy0 = pyl0 - g.y, dy1 = pyl1 - g.y;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float e = exponent(eb, q1dx, c.x, pyl[r] - g.y);
+        const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, c.x, (r >> 1) ? dy1 : dy0);
         if (T[r] >= tmin && e >= l2min) {
           const float alpha = fminf(__builtin_amdgcn_exp2f(e), aclamp);
           const float w = alpha * T[r];
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   int32_t* nc = own ? nullptr : (ncontrib ? ncontrib + (size_t)blockIdx.y * HW : nullptr);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int py = ty * kTile + row0 + r;
+    const int px = tx * kTile + qx + 8 * (r & 1), py = ty * kTile + qy + 8 * (r >> 1);
     if (px < d.W && py < d.H) {
       const size_t pi = (size_t)py * d.W + px;
       img[pi] = C[r][0] + T[r] * d.bg[0];
@@ -190,9 +193,9 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   const uint2 rg = ranges[d.tile_base + tile];
   if (rg.y <= rg.x) return;
   const int lane = threadIdx.x;
-  const int col = lane & 15, row0 = (lane >> 4) * 4;
-  const int px = tx * kTile + col;
-  const float pxl = (float)col + 0.5f;
+  const int qx = lane & 7, qy = lane >> 3;
+  const float pxl0 = (float)qx + 0.5f, pxl1 = (float)(qx + 8) + 0.5f;
+  const float pyl0 = (float)qy + 0.5f, pyl1 = (float)(qy + 8) + 0.5f;
   const size_t HW = (size_t)d.W * d.H;
   const float* tfp = tfinal + (size_t)blockIdx.y * HW;
   const int32_t* nlp = nlast + (size_t)blockIdx.y * HW;
@@ -204,12 +207,12 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   __shared__ float2 s_pa[kBatch];    // pair id (bits), 1/A
   __shared__ float s_acc[kBatch][9];
 
-  float T[4], S[4][3], gr[4][3], pyl[4];
+  float T[4], S[4][3], gr[4][3];
   int last[4];
   int jmax = -1;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int py = ty * kTile + row0 + r;
+    const int px = tx * kTile + qx + 8 * (r & 1), py = ty * kTile + qy + 8 * (r >> 1);
     const bool in = px < d.W && py < d.H;
     const size_t pi = (size_t)py * d.W + px;
     T[r] = in ? tfp[pi] : 1.0f;
@@ -220,7 +223,6 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
     S[r][0] = d.bg[0];
     S[r][1] = d.bg[1];
     S[r][2] = d.bg[2];
-    pyl[r] = (float)(row0 + r) + 0.5f;
     jmax = max(jmax, last[r]);
   }
   jmax = min(wave_max_i32(jmax), (int)rg.y - 1);   // n_last lies inside this tile's range
@@ -248,9 +250,10 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       const float4 q = s_q[k];
       const float cbv = s_con[k].w;
       const float rgbv[3] = {q.z, q.w, cbv};
-      const float dx = pxl - g.x;
-      const float eb = exponent_base(g.z, q.y, dx);
-      const float q1dx = g.w * dx;
+      const float dx0 = pxl0 - g.x, dx1 = pxl1 - g.x;
+      const float eb0 = exponent_base(g.z, q.y, dx0), eb1 = exponent_base(g.z, q.y, dx1);
+      const float q1dx0 = g.w * dx0, q1dx1 = g.w * dx1;
+      const float dy0 = pyl0 - g.y, dy1 = pyl1 - g.y;
       // acc: 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 R, 6 G, 7 B, 8 S_d
       float acc[9];
 #pragma unroll
@@ -258,8 +261,8 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       bool contrib = false;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float dy = pyl[r] - g.y;
-        const float e = exponent(eb, q1dx, q.x, dy);
+        const float dx = (r & 1) ? dx1 : dx0, dy = (r >> 1) ? dy1 : dy0;
+        const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, q.x, dy);
         if (jj <= last[r] && e >= l2min) {
           contrib = true;
           const float a = __builtin_amdgcn_exp2f(e);
