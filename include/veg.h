@@ -264,7 +264,8 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
  * the gradient w.r.t. the screen-space quantities.
  *   t_final, n_last  device, as written by veg_render_fwd for the same proj/bins
  *   d_image          device [n_frames,3,H,W] dL/dimage
- *   g2d              device [9][n_frames*n] float, ACCUMULATED: per pair
+ *   g2d              device [n_frames*n][9] float (pair-major: a pair's nine values are
+ *                    contiguous), ACCUMULATED: per pair
  *                    d mx, d my, d conic a, d conic b, d conic c, d R, d G, d B, d A,
  *                    where conic b enters sigma as 1/2 (a dx^2 + 2 b dx dy + c dy^2)
  * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */

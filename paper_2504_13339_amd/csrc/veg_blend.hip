@@ -177,7 +177,8 @@ __device__ __forceinline__ void row_sums(float (&a)[9]) {
 //   dL/dconic = (1/2 S_xx, S_xy, 1/2 S_yy),  dL/dmu' = -(a S_x + b S_y, b S_x + c S_y),
 //   dL/dA = -S_d / A   with S_d = sum dsigma and dsigma = dL/dsigma = -dL/dalpha * a.
 // Lanes reduce within their 16-lane row (DPP); the four row leaders add into a per-entry
-// LDS accumulator; each 64-entry batch ends with one vector atomic per component.
+// LDS accumulator; each 64-entry batch ends with nine vector atomics into the pair-major
+// gradient records.
 __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -307,30 +308,31 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       }
     }
     __syncthreads();
-    // flush: lane l owns entry lo + l of this batch
-    if (lane < hi - lo) {
-      float a9[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        a9[c] = s_acc[lane][c];
-        s_acc[lane][c] = 0.0f;
-      }
+    // flush.  Lane l first turns entry l's sums into screen-space gradients (in place);
+    // then the 64 x 9 values go out in nine rounds over consecutive (entry, component)
+    // slots, so the lanes of one atomic instruction cover about seven entries' contiguous
+    // nine-float records (a few cache lines) instead of 64 scattered words.
+    const int nb = hi - lo;
+    if (lane < nb) {
       const float4 cn = s_con[lane];
-      const float2 pa = s_pa[lane];
-      const size_t p = __float_as_uint(pa.x);
-      float out[9];
-      out[0] = -(cn.x * a9[0] + cn.y * a9[1]);
-      out[1] = -(cn.y * a9[0] + cn.z * a9[1]);
-      out[2] = 0.5f * a9[2];
-      out[3] = a9[3];
-      out[4] = 0.5f * a9[4];
-      out[5] = a9[5];
-      out[6] = a9[6];
-      out[7] = a9[7];
-      out[8] = -a9[8] * pa.y;
+      const float sx = s_acc[lane][0], sy = s_acc[lane][1];
+      s_acc[lane][0] = -(cn.x * sx + cn.y * sy);
+      s_acc[lane][1] = -(cn.y * sx + cn.z * sy);
+      s_acc[lane][2] = 0.5f * s_acc[lane][2];
+      s_acc[lane][4] = 0.5f * s_acc[lane][4];
+      s_acc[lane][8] = -s_acc[lane][8] * s_pa[lane].y;
+    }
+    __syncthreads();
+    float* flat = &s_acc[0][0];
 #pragma unroll
-      for (int c = 0; c < 9; ++c)
-        if (out[c] != 0.0f) unsafeAtomicAdd(g2d + (size_t)c * n_pairs + p, out[c]);
+    for (int t = 0; t < 9; ++t) {
+      const int idx = t * kBatch + lane;
+      const int e = idx / 9, c = idx - 9 * e;
+      if (e < nb) {
+        const float v = flat[idx];
+        flat[idx] = 0.0f;
+        if (v != 0.0f) unsafeAtomicAdd(g2d + (size_t)__float_as_uint(s_pa[e].x) * 9 + c, v);
+      }
     }
     __syncthreads();
   }

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __res
     float gg[9];
     bool any = false;
     for (int c = 0; c < 9; ++c) {
-      gg[c] = g2d[(size_t)c * n_pairs + pid];
+      gg[c] = g2d[pid * 9 + c];
       any |= (gg[c] != 0.0f);
     }
     if (!any) continue;

@@ -290,7 +290,7 @@ def test_backward_c0_matches_oracle_adjoint():
     d = np.random.default_rng(21).standard_normal((64 * 64, 3))
     st, grads, g2d, ref = _grads_case(w, d)
     n = w.gaussians.n
-    g2 = g2d.cpu().numpy().reshape(9, -1)[:, :n]
+    g2 = g2d.cpu().numpy().reshape(-1, 9)[:n].T
     assert rel_err(g2[0:2].T, ref.d_mean2d) <= 1e-3
     assert rel_err(g2[2:5].T, ref.d_conic) <= 1e-3
     assert rel_err(g2[5:8].T, ref.d_rgb) <= 1e-3
