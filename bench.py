@@ -288,7 +288,7 @@ def main():
     for k in range(args.steps):
         for f0 in range(0, F, args.group):
             fr = w.frames[f0:f0 + args.group]
-            st = R.render(g, [w.cameras[c] for c, _ in fr], [luts[t] for _, t in fr], w.opts)
+            st = R.render(g, [w.cameras[c] for c, _ in fr], [luts[t] for _, t in fr], w.opts, hits=False)
             del st
     torch.cuda.synchronize()
     fwd_mpix = F * H * W * args.steps / (time.perf_counter() - t1) / 1e6

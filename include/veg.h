@@ -197,7 +197,13 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
  *   keys, vals          device [capacity] uint32 (final sorted list)
  *   keys_alt, vals_alt  device [capacity] uint32 (ping-pong buffers)
  *   ranges              device [2 * total_tiles] uint32
- *   capacity            entries the buffers hold (<= 2^31 - 1) */
+ *   capacity            entries the buffers hold (<= 2^31 - 1)
+ *   hits, hit_words     optional (NULL, 0): device [hit_words] uint64, hit_words >=
+ *                       veg_bin_hit_words(capacity, total_tiles).  When given,
+ *                       veg_render_fwd records for every entry whether it was blended into
+ *                       at least one pixel of its tile, and veg_render_bwd, called with the
+ *                       same bins after that forward call, visits only those entries (the
+ *                       others contribute nothing to any gradient). */
 typedef struct {
   uint32_t* keys;
   uint32_t* vals;
@@ -205,7 +211,13 @@ typedef struct {
   uint32_t* vals_alt;
   uint32_t* ranges;
   int64_t capacity;
+  uint64_t* hits;
+  int64_t hit_words;
 } veg_bins;
+
+/* Words of veg_bins.hits for a list of `capacity` entries over `total_tiles` tiles
+ * (one bit per entry, each tile's bits starting in a word of its own). */
+int64_t veg_bin_hit_words(int64_t capacity, int64_t total_tiles);
 
 /* Scratch for veg_bin_count / veg_bin_sort of `n_pairs` pairs and `capacity` entries. */
 size_t veg_bin_workspace_bytes(int64_t n_pairs, int64_t capacity);

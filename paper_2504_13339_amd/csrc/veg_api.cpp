@@ -280,6 +280,20 @@ veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32
   return VEG_OK;
 }
 
+int64_t veg_bin_hit_words(int64_t capacity, int64_t total_tiles) {
+  if (capacity < 0 || total_tiles < 0) return 0;
+  return capacity / 64 + total_tiles + 2;
+}
+
+// The hit bits are optional; when present the buffer must hold every tile's words.
+static veg_status check_hits(const veg_proj* proj, const veg_bins* bins, const char* what) {
+  if (!bins->hits) return VEG_OK;
+  const int64_t tiles = (int64_t)proj->n_frames * proj->tiles_x * proj->tiles_y;
+  if (bins->hit_words < veg_bin_hit_words(bins->capacity, tiles))
+    return fail(VEG_ERR_INVALID_ARG, "%s: hit_words < veg_bin_hit_words(capacity, tiles)", what);
+  return VEG_OK;
+}
+
 veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts, float* image,
                           float* t_final, int32_t* n_last, int32_t* n_contrib, veg_stream_t stream) {
   g_err.clear();
@@ -287,12 +301,14 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
   if (s != VEG_OK) return s;
   if (!bins || !bins->ranges || !image) return fail(VEG_ERR_INVALID_ARG, "render_fwd: NULL argument");
   if (proj->n > 0 && bins->capacity > 0 && !bins->vals) return fail(VEG_ERR_INVALID_ARG, "render_fwd: NULL vals");
+  s = check_hits(proj, bins, "render_fwd");
+  if (s != VEG_OK) return s;
   veg_opts o;
   s = resolve_opts(opts, &o);
   if (s != VEG_OK) return s;
   VEG_CHECK_HIP(launch_blend_fwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
                                  kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, image, t_final, n_last,
-                                 n_contrib, (hipStream_t)stream),
+                                 n_contrib, bins->hits, (hipStream_t)stream),
                 "veg_render_fwd");
   return VEG_OK;
 }
@@ -304,12 +320,14 @@ veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_
   if (s != VEG_OK) return s;
   if (!bins || !bins->ranges || !t_final || !n_last || !d_image || (proj->n > 0 && !g2d))
     return fail(VEG_ERR_INVALID_ARG, "render_bwd: NULL argument");
+  s = check_hits(proj, bins, "render_bwd");
+  if (s != VEG_OK) return s;
   veg_opts o;
   s = resolve_opts(opts, &o);
   if (s != VEG_OK) return s;
   VEG_CHECK_HIP(launch_blend_bwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
                                  kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, t_final, n_last,
-                                 d_image, g2d, (uint32_t)pairs_of(proj), (hipStream_t)stream),
+                                 d_image, g2d, (uint32_t)pairs_of(proj), bins->hits, (hipStream_t)stream),
                 "veg_render_bwd");
   return VEG_OK;
 }

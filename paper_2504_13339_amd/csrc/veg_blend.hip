@@ -49,15 +49,38 @@ __device__ __forceinline__ float exponent(float base, float q1dx, float q2, floa
   return fmaf(-dy, fmaf(q2, dy, q1dx), base);
 }
 
+// Word of the per-entry hit bits that holds entry rg.x + 64 b of global tile gt: tile gt's
+// words start at floor(rg.x / 64) + gt, which keeps the tiles' words disjoint and needs
+// floor(E / 64) + tiles + 1 words for E entries.
+__device__ __forceinline__ size_t hit_word(uint32_t start, uint32_t gt, uint32_t b) {
+  return (size_t)(start >> 6) + gt + b;
+}
+
+// OR over the wave; the result is complete in lane 63.
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);   // row_shr:4
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);   // row_shr:8
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
+  return ((uint64_t)wave_or_u32((uint32_t)(v >> 32)) << 32) | wave_or_u32((uint32_t)v);
+}
+
 // One wave per tile.  A pixel is finished exactly when its T < t_min (blend-then-stop),
 // so T itself is the "still active" flag; pixels outside the image start with T = 0.
-template <bool kCount>
+// With kHits, bit k of word b records whether entry rg.x + 64 b + k was blended into any
+// pixel of the tile (the backward pass skips the others).
+template <bool kCount, bool kHits>
 __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
                                                        const uint2* __restrict__ ranges, float* __restrict__ image,
                                                        float* __restrict__ tfinal, int32_t* __restrict__ nlast,
-                                                       int32_t* __restrict__ ncontrib) {
+                                                       int32_t* __restrict__ ncontrib, uint64_t* __restrict__ hits) {
   const FrameDesc& d = descs[blockIdx.y];
   const int tile = blockIdx.x;
   if (tile >= d.tiles_x * d.tiles_y) return;
@@ -100,7 +123,9 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
     }
     __syncthreads();
     const int n = (int)min((uint32_t)kBatch, rg.y - base);
-    for (int k = 0; k < n; ++k) {
+    uint64_t lh = 0;   // bit k: this lane blended entry base + k
+    uint64_t bk = 1;
+    for (int k = 0; k < n; ++k, bk <<= 1) {
       const float4 g = s_geo[k];
       const float4 c = s_col[k];
       const float cb = s_b[k];
@@ -112,6 +137,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
       for (int r = 0; r < 4; ++r) {
         const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, c.x, (r >> 1) ? dy1 : dy0);
         if (T[r] >= tmin && e >= l2min) {
+          if (kHits) lh |= bk;
           const float alpha = fminf(__builtin_amdgcn_exp2f(e), aclamp);
           const float w = alpha * T[r];
           C[r][0] = fmaf(w, c.z, C[r][0]);
@@ -122,6 +148,10 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
           if (kCount) ++cnt[r];
         }
       }
+    }
+    if (kHits) {
+      const uint64_t word = wave_or_u64(lh);
+      if (lane == 63) hits[hit_word(rg.x, d.tile_base + tile, (base - rg.x) >> 6)] = word;
     }
     __syncthreads();
   }
@@ -186,7 +216,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
                                                        const float* __restrict__ tfinal,
                                                        const int32_t* __restrict__ nlast,
                                                        const float* __restrict__ dimage, float* __restrict__ g2d,
-                                                       uint32_t n_pairs) {
+                                                       uint32_t n_pairs, const uint64_t* __restrict__ hits) {
   const FrameDesc& d = descs[blockIdx.y];
   const int tile = blockIdx.x;
   if (tile >= d.tiles_x * d.tiles_y) return;
@@ -245,7 +275,20 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       s_pa[lane] = make_float2(__uint_as_float(p), 1.0f / r1.y);
     }
     __syncthreads();
-    for (int k = hi - 1 - lo; k >= 0; --k) {
+    // entries of this batch to visit, highest first: all, or those the forward pass blended
+    const int nb = hi - lo;
+    uint64_t todo = ~0ull >> (64 - nb);
+    if (hits) {
+      const uint32_t off = (uint32_t)lo - rg.x;
+      const size_t w0 = hit_word(rg.x, d.tile_base + tile, off >> 6);
+      const uint32_t sh = off & 63u;
+      uint64_t v = hits[w0] >> sh;
+      if (sh != 0 && sh + (uint32_t)nb > 64u) v |= hits[w0 + 1] << (64u - sh);
+      todo &= v;
+    }
+    while (todo != 0ull) {
+      const int k = 63 - __builtin_clzll(todo);
+      todo &= ~(1ull << k);
       const int jj = lo + k;
       const float4 g = s_geo[k];
       const float4 q = s_q[k];
@@ -312,7 +355,6 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
     // then the 64 x 9 values go out in nine rounds over consecutive (entry, component)
     // slots, so the lanes of one atomic instruction cover about seven entries' contiguous
     // nine-float records (a few cache lines) instead of 64 scattered words.
-    const int nb = hi - lo;
     if (lane < nb) {
       const float4 cn = s_con[lane];
       const float sx = s_acc[lane][0], sy = s_acc[lane][1];
@@ -324,7 +366,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
     }
     __syncthreads();
     float* flat = &s_acc[0][0];
-#pragma unroll
+#pragma unroll 1   // unrolled, the rounds' loads are hoisted and the kernel needs ~40 more VGPRs
     for (int t = 0; t < 9; ++t) {
       const int idx = t * kBatch + lane;
       const int e = idx / 9, c = idx - 9 * e;
@@ -342,23 +384,32 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
 
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o, const float4* rec,
                             const uint32_t* vals, const uint32_t* ranges, float* image, float* tfinal, int32_t* nlast,
-                            int32_t* ncontrib, hipStream_t stream) {
+                            int32_t* ncontrib, uint64_t* hits, hipStream_t stream) {
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
-  if (ncontrib)
-    hipLaunchKernelGGL(blend_fwd_kernel<true>, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
-                       (const uint2*)ranges, image, tfinal, nlast, ncontrib);
+  const dim3 grid(max_tiles, n_frames), block(64);
+  const uint2* rg = (const uint2*)ranges;
+  if (ncontrib && hits)
+    hipLaunchKernelGGL((blend_fwd_kernel<true, true>), grid, block, 0, stream, descs, o, rec, vals, rg, image, tfinal,
+                       nlast, ncontrib, hits);
+  else if (ncontrib)
+    hipLaunchKernelGGL((blend_fwd_kernel<true, false>), grid, block, 0, stream, descs, o, rec, vals, rg, image, tfinal,
+                       nlast, ncontrib, hits);
+  else if (hits)
+    hipLaunchKernelGGL((blend_fwd_kernel<false, true>), grid, block, 0, stream, descs, o, rec, vals, rg, image, tfinal,
+                       nlast, ncontrib, hits);
   else
-    hipLaunchKernelGGL(blend_fwd_kernel<false>, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
-                       (const uint2*)ranges, image, tfinal, nlast, ncontrib);
+    hipLaunchKernelGGL((blend_fwd_kernel<false, false>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
+                       tfinal, nlast, ncontrib, hits);
   return hipGetLastError();
 }
 
 hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o, const float4* rec,
                             const uint32_t* vals, const uint32_t* ranges, const float* tfinal, const int32_t* nlast,
-                            const float* dimage, float* g2d, uint32_t n_pairs, hipStream_t stream) {
+                            const float* dimage, float* g2d, uint32_t n_pairs, const uint64_t* hits,
+                            hipStream_t stream) {
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(blend_bwd_kernel, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
-                     (const uint2*)ranges, tfinal, nlast, dimage, g2d, n_pairs);
+                     (const uint2*)ranges, tfinal, nlast, dimage, g2d, n_pairs, hits);
   return hipGetLastError();
 }
 

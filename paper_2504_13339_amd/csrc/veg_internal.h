@@ -143,11 +143,11 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
-                            hipStream_t stream);
+                            uint64_t* hits, hipStream_t stream);
 hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             const float* tfinal, const int32_t* nlast, const float* dimage,
-                            float* g2d, uint32_t n_pairs, hipStream_t stream);
+                            float* g2d, uint32_t n_pairs, const uint64_t* hits, hipStream_t stream);
 
 hipError_t launch_l1(const float* image, const float* target, int64_t count, float scale,
                      double* loss, float* dimage, hipStream_t stream);

@@ -68,12 +68,15 @@ class EventTimer:
 
 
 def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=None, stream=None,
-           capacity: Optional[int] = None, timer=NO_TIMER, want_contrib: bool = False) -> FwdState:
+           capacity: Optional[int] = None, timer=NO_TIMER, want_contrib: bool = False,
+           hits: bool = True) -> FwdState:
     """Forward render of len(cams) frames (one model, one image size).
 
     With ``capacity`` None the key-list length is read back (one stream synchronisation)
     and the buffers are sized exactly; otherwise ``capacity`` entries are allocated, no
-    synchronisation happens, and an overflow must be checked with ``veg_bin_overflow``."""
+    synchronisation happens, and an overflow must be checked with ``veg_bin_overflow``.
+    ``hits`` records which entries were blended anywhere, for a following backward pass
+    (set it False for forward-only rendering)."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
     dev = g.means.device
     proj = V.alloc_proj(g.n, len(cams), device=dev)
@@ -87,7 +90,7 @@ def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=Non
         cap = E
     else:
         E, cap = -1, int(capacity)
-    bins = V.alloc_bins(proj, cap, device=dev)
+    bins = V.alloc_bins(proj, cap, device=dev, hits=hits)
     with timer("bin_sort"):
         V.veg_bin_sort(proj, ws, bins, stream=stream)
     F, H, W = len(cams), int(proj.struct.height), int(proj.struct.width)

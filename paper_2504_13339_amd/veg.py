@@ -18,7 +18,7 @@ from ._lib import check, load
 __all__ = [
     "Gaussians", "Proj", "Bins", "default_opts", "make_opts", "veg_project", "veg_bin_count", "veg_bin_sort",
     "veg_bin_overflow", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
-    "veg_debug_math", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
+    "veg_debug_math", "veg_bin_hit_words", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
 ]
 
 
@@ -154,21 +154,33 @@ class Bins:
     keys_alt: torch.Tensor
     vals_alt: torch.Tensor
     ranges: torch.Tensor
+    hits: Optional[torch.Tensor] = None
 
     @property
     def capacity(self) -> int:
         return int(self.struct.capacity)
 
 
-def alloc_bins(proj: Proj, capacity: int, device="cuda") -> Bins:
+def veg_bin_hit_words(capacity: int, total_tiles: int) -> int:
+    return int(load().veg_bin_hit_words(int(capacity), int(total_tiles)))
+
+
+def alloc_bins(proj: Proj, capacity: int, device="cuda", hits: bool = True) -> Bins:
+    """Key-list buffers for ``capacity`` entries; with ``hits`` also the per-entry hit bits
+    that let the backward pass skip entries the forward pass blended nowhere."""
     cap = max(1, int(capacity))
     k = torch.empty(cap, dtype=torch.int32, device=device)
     v = torch.empty(cap, dtype=torch.int32, device=device)
     ka = torch.empty(cap, dtype=torch.int32, device=device)
     va = torch.empty(cap, dtype=torch.int32, device=device)
     r = torch.empty(max(1, 2 * int(proj.struct.total_tiles)), dtype=torch.int32, device=device)
-    st = _lib.veg_bins(_ptr(k), _ptr(v), _ptr(ka), _ptr(va), _ptr(r), int(capacity))
-    return Bins(st, k, v, ka, va, r)
+    h = None
+    if hits:
+        nw = veg_bin_hit_words(capacity, proj.struct.total_tiles)
+        h = torch.empty(max(1, nw), dtype=torch.int64, device=device)
+    st = _lib.veg_bins(_ptr(k), _ptr(v), _ptr(ka), _ptr(va), _ptr(r), int(capacity),
+                       _ptr(h) if h is not None else None, int(h.numel()) if h is not None else 0)
+    return Bins(st, k, v, ka, va, r, h)
 
 
 def veg_bin_sort(proj: Proj, ws: torch.Tensor, bins: Bins, stream=None) -> Bins:

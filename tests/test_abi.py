@@ -70,3 +70,21 @@ def test_serve_config_validation_on_host():
     h = ctypes.c_void_p()
     assert lib.veg_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == 1      # NULL arena
     assert b"arena" in lib.veg_last_error()
+
+
+def test_hit_bits_buffer_is_validated_on_host():
+    """A hit-bit buffer smaller than veg_bin_hit_words(capacity, tiles) is rejected before any
+    launch (the pointers below are never dereferenced)."""
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    assert lib.veg_bin_hit_words(64, 1) == 64 // 64 + 1 + 2
+    assert lib.veg_bin_hit_words(1000, 4096 * 16) == 1000 // 64 + 4096 * 16 + 2
+    fake = ctypes.c_void_p(0x10000)
+    p = _lib.veg_proj(1, 1, 16, 16, 1, 1, 1, fake, fake, fake, fake)
+    b = _lib.veg_bins(fake, fake, fake, fake, fake, 64, fake, 3)
+    img = ctypes.c_void_p(0x20000)
+    assert lib.veg_render_fwd(ctypes.byref(p), ctypes.byref(b), None, img, None, None, None, None) == 1
+    assert b"hit_words" in lib.veg_last_error()
+    assert lib.veg_render_bwd(ctypes.byref(p), ctypes.byref(b), None, img, img, img, img, None) == 1
+    assert b"hit_words" in lib.veg_last_error()

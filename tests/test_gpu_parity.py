@@ -301,6 +301,43 @@ def test_backward_c0_matches_oracle_adjoint():
     assert rel_err(grads.d_scalars.cpu().numpy(), ref.d_scalars) <= 1e-3
 
 
+def test_backward_skipping_unblended_entries_changes_nothing():
+    """The forward pass's per-entry hit bits only let the backward pass skip entries that
+    blend into no pixel of their tile: gradients with and without them agree (up to the
+    order of float atomics across tiles), and entries are in fact skipped."""
+    V, R = hip()
+    w = synth.workload(1, n_override=60000, res_override=256)
+    g = to_dev(w.gaussians)
+    cams = [w.cameras[c] for c, _ in w.frames[:3]]
+    luts = luts_to_dev(w.tfs)
+    tfs = [luts[t] for _, t in w.frames[:3]]
+    d_img = torch.randn((3, 3, 256, 256), generator=torch.Generator().manual_seed(5)).cuda()
+    out = []
+    for hits in (True, False):
+        st = R.render(g, cams, tfs, OPTS, hits=hits)
+        grads = R.Grads.zeros(g)
+        g2d = R.render_backward(g, st, d_img, grads)
+        torch.cuda.synchronize()
+        out.append((st, grads, g2d))
+    (sa, ga, g2a), (sb, gb, g2b) = out
+    assert torch.equal(sa.image, sb.image) and torch.equal(sa.n_last, sb.n_last)
+    assert rel_err(g2a.cpu().numpy(), g2b.cpu().numpy()) <= 1e-5
+    for name in ("d_means", "d_log_scales", "d_quats", "d_scalars"):
+        assert rel_err(getattr(ga, name).cpu().numpy(), getattr(gb, name).cpu().numpy()) <= 1e-5, name
+    # bits of the entries up to each tile's last blended one (the batches the forward pass
+    # processed): some set, some clear
+    rg = sa.bins.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
+    words = sa.bins.hits.cpu().numpy().view(np.uint64)
+    jm = sa.n_last.cpu().numpy().reshape(3, 16, 16, 16, 16).max(axis=(2, 4)).reshape(-1).astype(np.int64)
+    n_set = n_all = 0
+    for t in np.nonzero((rg[:, 1] > rg[:, 0]) & (jm >= rg[:, 0]))[0].tolist():
+        s0 = int(rg[t, 0])
+        for j in range(s0, min(int(jm[t]), int(rg[t, 1]) - 1) + 1):
+            n_all += 1
+            n_set += (int(words[(s0 >> 6) + t + (j - s0) // 64]) >> ((j - s0) % 64)) & 1
+    assert 0 < n_set < n_all
+
+
 def test_backward_with_weights_dense_scene():
     w = synth.workload(0, n_override=3000)
     w.gaussians.weights = synth.rng_for(0, 4).uniform(0.3, 1.0, w.gaussians.n).astype(np.float32)
