@@ -47,6 +47,34 @@ VALU_PACKED_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "train-1M-1024px-16x3_hbm_traffic.md")
+BLEND_SOURCES = ("paper_2504_13339_amd/csrc/veg_blend.hip", "paper_2504_13339_amd/csrc/veg_internal.h")
+PROFILE_KERNEL = {"blend_bwd": "blend_bwd_kernel", "blend_fwd": "void blend_fwd_kernel<false, true>"}
+
+
+def profiled_traffic(name):
+    """HBM bytes per launch of a blend kernel from the committed counter summary (FETCH_SIZE
+    and WRITE_SIZE passes calibrated on a plain copy), or None when the blend sources have
+    changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for p in BLEND_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    m = re.search(r"sha256\(veg_blend\.hip \+ veg_internal\.h\): ([0-9a-f]{64})", text)
+    if not m or m.group(1) != h.hexdigest():
+        return None
+    row = re.search(r"^\| `" + re.escape(PROFILE_KERNEL[name]) + r"` \|([^\n]*)$", text, flags=re.M)
+    if not row:
+        return None
+    return float(row.group(1).split("|")[-2])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -302,7 +330,8 @@ def main():
         flops = (visits * FLOPS_VISIT + counts["blended"] * blend_flops) / n_launch
         ach = flops / (avg_ms * 1e-3) / 1e12
         return {"bound": "alu", "kernel": name, "achieved": round(ach, 3), "peak": round(VALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4), "traffic": profiled_traffic(name),
+                "traffic_unit": "HBM bytes per launch",
                 "avg_launch_ms": round(avg_ms, 4), "visited_pairs_per_launch": visits // n_launch,
                 "blended_pairs_per_launch": counts["blended"] // n_launch,
                 "flops_per_launch": flops, "frac_of_packed_peak": round(ach / VALU_PACKED_PEAK_TFLOPS, 4)}
