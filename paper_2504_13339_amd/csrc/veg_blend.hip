@@ -181,24 +181,35 @@ __device__ __forceinline__ int wave_max_i32(int v) {
   return v;
 }
 
-// Sum over each 16-lane row of the wave, in place for all nine accumulators at once
-// (independent DPP chains interleaved, so no hazard stalls); the row total lands in lane 15
-// of the row.
+// Lane permutation within 16-lane rows (every source lane is valid, so bound_ctrl only
+// lets the compiler fold the move into the consuming add).
 template <int CTRL>
-__device__ __forceinline__ float row_shr_zero(float v) {
-  // row_shr with bound_ctrl: lanes shifted in from outside the row read 0
+__device__ __forceinline__ float dpp_perm(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 
-__device__ __forceinline__ void row_sums(float (&a)[9]) {
+// Two entries' nine per-lane partial sums (a, b) summed over each 16-lane row by a
+// reduce-scatter butterfly: at every step a lane keeps half of the values it carries and
+// adds its partner's copy of that half (partners: lane ^ 8 by row rotation, the mirror
+// inside each half-row, then ^ 2 and ^ 1 inside quads).  Afterwards, within each half-row
+// (the lower half carries entry a, the upper half entry b), the lane with i = lane & 7
+// holds component ((i & 4) ? 5 : 0) + ((i & 2) ? 3 : 0) + (i & 1) in w0 (not i = 7) and,
+// when i & 3 == 0, component (i & 4) ? 7 : 2 in w1.
+__device__ __forceinline__ void row_reduce_pair(const float (&a)[9], const float (&b)[9], int lane, float& w0,
+                                                float& w1) {
+  const bool l1 = (lane & 8) == 0, l2 = (lane & 4) == 0, l3 = (lane & 2) == 0, l4 = (lane & 1) == 0;
+  float r[9];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] += row_shr_zero<0x111>(a[c]);
+  for (int c = 0; c < 9; ++c) r[c] = (l1 ? a[c] : b[c]) + dpp_perm<0x128>(l1 ? b[c] : a[c]);   // row_ror:8
+  float s[5];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] += row_shr_zero<0x112>(a[c]);
-#pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] += row_shr_zero<0x114>(a[c]);
-#pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] += row_shr_zero<0x118>(a[c]);
+  for (int c = 0; c < 4; ++c) s[c] = (l2 ? r[c] : r[c + 5]) + dpp_perm<0x141>(l2 ? r[c + 5] : r[c]);   // half mirror
+  s[4] = r[4] + dpp_perm<0x141>(r[4]);
+  const float u0 = (l3 ? s[0] : s[3]) + dpp_perm<0x4e>(l3 ? s[3] : s[0]);   // quad_perm 2,3,0,1
+  const float u1 = (l3 ? s[1] : s[4]) + dpp_perm<0x4e>(l3 ? s[4] : s[1]);
+  const float u2 = s[2] + dpp_perm<0x4e>(s[2]);
+  w0 = (l4 ? u0 : u1) + dpp_perm<0xb1>(l4 ? u1 : u0);   // quad_perm 1,0,3,2
+  w1 = u2 + dpp_perm<0xb1>(u2);
 }
 
 // Backward: the same tile walk in reverse.  Per pixel and blended entry it accumulates
@@ -206,9 +217,10 @@ __device__ __forceinline__ void row_sums(float (&a)[9]) {
 // the conic is applied once per entry when the batch is flushed:
 //   dL/dconic = (1/2 S_xx, S_xy, 1/2 S_yy),  dL/dmu' = -(a S_x + b S_y, b S_x + c S_y),
 //   dL/dA = -S_d / A   with S_d = sum dsigma and dsigma = dL/dsigma = -dL/dalpha * a.
-// Lanes reduce within their 16-lane row (DPP); the four row leaders add into a per-entry
-// LDS accumulator; each 64-entry batch ends with nine vector atomics into the pair-major
-// gradient records.
+// Entries are taken in pairs: a reduce-scatter butterfly over each 16-lane row sums both
+// entries' nine values at once and every lane adds its share into a per-entry LDS
+// accumulator (at most four lanes per address); each 64-entry batch ends with nine vector
+// atomics into the pair-major gradient records.
 __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -261,6 +273,12 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   const float l2min = o.log2_alpha_min;
   const float aclamp = o.alpha_clamp;
   for (int c = 0; c < 9; ++c) s_acc[lane][c] = 0.0f;
+  // lanes' share of a pair's butterfly result: which component of which entry, if any
+  const int bi = lane & 7;
+  const int comp0 = ((bi & 4) ? 5 : 0) + ((bi & 2) ? 3 : 0) + (bi & 1);
+  const bool own0 = bi != 7;
+  const int comp1 = (bi & 4) ? 7 : 2;
+  const bool own1 = (bi & 3) == 0;
   for (int hi = jmax + 1; hi > (int)rg.x; hi -= kBatch) {
     const int lo = max((int)rg.x, hi - kBatch);
     const int j = lo + lane;
@@ -286,9 +304,8 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       if (sh != 0 && sh + (uint32_t)nb > 64u) v |= hits[w0 + 1] << (64u - sh);
       todo &= v;
     }
-    while (todo != 0ull) {
-      const int k = 63 - __builtin_clzll(todo);
-      todo &= ~(1ull << k);
+    // adjoint of entry k of the staged batch for this lane's four pixels (updates T, S)
+    auto entry_adjoint = [&](const int k, float (&acc)[9], bool& contrib) {
       const int jj = lo + k;
       const float4 g = s_geo[k];
       const float4 q = s_q[k];
@@ -298,11 +315,6 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       const float eb0 = exponent_base(g.z, q.y, dx0), eb1 = exponent_base(g.z, q.y, dx1);
       const float q1dx0 = g.w * dx0, q1dx1 = g.w * dx1;
       const float dy0 = pyl0 - g.y, dy1 = pyl1 - g.y;
-      // acc: 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 R, 6 G, 7 B, 8 S_d
-      float acc[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
-      bool contrib = false;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float dx = (r & 1) ? dx1 : dx0, dy = (r >> 1) ? dy1 : dy0;
@@ -333,21 +345,39 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
           acc[8] += dsig;
         }
       }
-      const uint64_t who = __ballot(contrib);
-      if (who != 0ull) {
-        if (__popcll(who) <= 4) {
-          // few contributing lanes: add their partial sums directly (<= 4-way LDS atomics)
-          if (contrib) {
+    };
+    // entries go in pairs (A, then the next lower B) so that one butterfly reduces both
+    while (todo != 0ull) {
+      const int ka = 63 - __builtin_clzll(todo);
+      todo &= ~(1ull << ka);
+      const bool has_b = todo != 0ull;
+      const int kb = has_b ? 63 - __builtin_clzll(todo) : ka;
+      if (has_b) todo &= ~(1ull << kb);
+      // acc: 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 R, 6 G, 7 B, 8 S_d
+      float acc_a[9], acc_b[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[k][c], acc[c]);
-          }
-        } else {
-          row_sums(acc);
-          if ((lane & 15) == 15) {
+      for (int c = 0; c < 9; ++c) acc_a[c] = acc_b[c] = 0.0f;
+      bool con_a = false, con_b = false;
+      entry_adjoint(ka, acc_a, con_a);
+      if (has_b) entry_adjoint(kb, acc_b, con_b);
+      const uint64_t who = __ballot(con_a || con_b);
+      if (who == 0ull) continue;
+      if (__popcll(who) <= 4) {
+        // few contributing lanes: add their partial sums directly (<= 4-way LDS atomics)
+        if (con_a) {
 #pragma unroll
-            for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[k][c], acc[c]);
-          }
+          for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[ka][c], acc_a[c]);
         }
+        if (con_b) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[kb][c], acc_b[c]);
+        }
+      } else {
+        float w0, w1;
+        row_reduce_pair(acc_a, acc_b, lane, w0, w1);
+        const int ke = (lane & 8) ? kb : ka;
+        if (own0) atomicAdd(&s_acc[ke][comp0], w0);
+        if (own1) atomicAdd(&s_acc[ke][comp1], w1);
       }
     }
     __syncthreads();
