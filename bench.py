@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--views", type=int, default=None)
     ap.add_argument("--tfs", type=int, default=None)
     ap.add_argument("--res", type=int, default=None)
-    ap.add_argument("--cpu-pixels", type=int, default=48)
+    ap.add_argument("--cpu-pixels", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s); '' to skip")
     ap.add_argument("--serve-requests", type=int, default=400)
