@@ -212,15 +212,25 @@ __device__ __forceinline__ void row_reduce_pair(const float (&a)[9], const float
   w1 = u2 + dpp_perm<0xb1>(u2);
 }
 
+// Sum of a value over the four 16-lane rows of the wave, in every lane: swap the halves of
+// the wave, then adjacent rows.
+__device__ __forceinline__ float sum_rows(float v) {
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  const float x = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // Backward: the same tile walk in reverse.  Per pixel and blended entry it accumulates
 // dL/dR,G,B, sum dsigma and the first and second moments of (dx, dy) weighted by dsigma;
 // the conic is applied once per entry when the batch is flushed:
 //   dL/dconic = (1/2 S_xx, S_xy, 1/2 S_yy),  dL/dmu' = -(a S_x + b S_y, b S_x + c S_y),
 //   dL/dA = -S_d / A   with S_d = sum dsigma and dsigma = dL/dsigma = -dL/dalpha * a.
 // Entries are taken in pairs: a reduce-scatter butterfly over each 16-lane row sums both
-// entries' nine values at once and every lane adds its share into a per-entry LDS
-// accumulator (at most four lanes per address); each 64-entry batch ends with nine vector
-// atomics into the pair-major gradient records.
+// entries' nine values at once, two lane swaps add up the four rows, and the first row
+// stores the entries' totals into a per-entry LDS slot (plain stores: an entry is reduced
+// once per tile); each 64-entry batch ends with nine vector atomics into the pair-major
+// gradient records.
 __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -360,24 +370,17 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       bool con_a = false, con_b = false;
       entry_adjoint(ka, acc_a, con_a);
       if (has_b) entry_adjoint(kb, acc_b, con_b);
-      const uint64_t who = __ballot(con_a || con_b);
-      if (who == 0ull) continue;
-      if (__popcll(who) <= 4) {
-        // few contributing lanes: add their partial sums directly (<= 4-way LDS atomics)
-        if (con_a) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[ka][c], acc_a[c]);
-        }
-        if (con_b) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) atomicAdd(&s_acc[kb][c], acc_b[c]);
-        }
-      } else {
-        float w0, w1;
-        row_reduce_pair(acc_a, acc_b, lane, w0, w1);
+      if (__ballot(con_a || con_b) == 0ull) continue;
+      float w0, w1;
+      row_reduce_pair(acc_a, acc_b, lane, w0, w1);
+      // sum the four rows' results; every processed entry is reduced exactly once per tile,
+      // so row 0 stores its totals (no atomics)
+      w0 = sum_rows(w0);
+      w1 = sum_rows(w1);
+      if (lane < (has_b ? 16 : 8)) {   // without a B entry the upper half carries zeros for A's slots
         const int ke = (lane & 8) ? kb : ka;
-        if (own0) atomicAdd(&s_acc[ke][comp0], w0);
-        if (own1) atomicAdd(&s_acc[ke][comp1], w1);
+        if (own0) s_acc[ke][comp0] = w0;
+        if (own1) s_acc[ke][comp1] = w1;
       }
     }
     __syncthreads();
