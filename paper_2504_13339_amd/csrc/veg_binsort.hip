@@ -209,38 +209,70 @@ __device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
   return v;
 }
 
-// Downsweep of the entry-offset scan fused with emission: the j-th depth-sorted kept pair p
-// owns count consecutive output slots starting at its offset and fills them with
-// (global tile, p), its rectangle's tiles in row-major order.  A tile of items lays out
-// offsets and rectangles in LDS; its output slots are then produced in chunks of 2048:
-// every item starting inside the chunk marks its first slot, a block-wide prefix maximum
-// turns the marks into the owner of every slot, and the threads write consecutive slots
-// (coalesced), so one Gaussian covering many tiles does not serialise a lane.
-__global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restrict__ descs,
-                                                        const uint4* __restrict__ items,
-                                                        const uint32_t* __restrict__ counts,
-                                                        const uint32_t* __restrict__ v_ptr, uint32_t v_cap,
-                                                        const uint64_t* __restrict__ partials, int G,
-                                                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                        uint32_t capacity) {
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbits) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return valid ? peers : 0ull;
+}
+
+constexpr int kEmitItems = 1024;   // items per LDS tile of the emission
+constexpr int kEIpt = kEmitItems / kThreads;
+
+// Emission fused with the first digit pass of the tile sort.  The j-th depth-sorted kept
+// pair p owns `count` consecutive output slots starting at its offset, holding (global tile,
+// p) for its rectangle's tiles in row-major order.  A block walks its items in tiles of
+// 1024 (offsets and rectangles in LDS) and their slots in chunks of 2048: every item
+// starting inside the chunk marks its first slot and a block-wide prefix maximum turns the
+// marks into the owner of every slot.  kPhase 0 counts the low `nbits` bits of the slots'
+// tile ids into the block's digit histogram (hist[d * G + b]); kPhase 1, after that
+// histogram has been scanned, regenerates the same slots, ranks each chunk by digit
+// (stable: slot order) and writes the entries straight to their place after the pass, so
+// the unsorted list is never stored.  Slots at or beyond `capacity` are dropped (overflow).
+template <int kPhase>
+__global__ __launch_bounds__(kThreads) void emit_radix_kernel(const FrameDesc* __restrict__ descs,
+                                                              const uint4* __restrict__ items,
+                                                              const uint32_t* __restrict__ counts,
+                                                              const uint32_t* __restrict__ v_ptr, uint32_t v_cap,
+                                                              const uint64_t* __restrict__ partials, int G,
+                                                              uint32_t capacity, int nbits,
+                                                              uint32_t* __restrict__ hist,
+                                                              uint32_t* __restrict__ keys,
+                                                              uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_tmp[kWaves];
-  __shared__ uint32_t s_off[kTileItems];    // exclusive slot offset of each item in the tile
-  __shared__ uint32_t s_pair[kTileItems];
-  __shared__ uint32_t s_base[kTileItems];   // global tile id of the rectangle's first tile
-  __shared__ uint32_t s_shape[kTileItems];  // rectangle width | tiles_x << 16
-  __shared__ uint32_t s_own[kChunk];        // 1 + owning item of each slot of the chunk
+  __shared__ uint32_t s_off[kEmitItems];    // exclusive slot offset of each item in the tile
+  __shared__ uint32_t s_pair[kEmitItems];
+  __shared__ uint32_t s_base[kEmitItems];   // global tile id of the rectangle's first tile
+  __shared__ uint32_t s_shape[kEmitItems];  // rectangle width | tiles_x << 16
+  __shared__ uint32_t s_own[kChunk];        // 1 + owning item of each slot; then sorted keys
+  __shared__ uint32_t s_sval[kChunk];       // sorted values (phase 1)
+  __shared__ uint32_t s_cnt[kWaves][kRadix];
+  __shared__ uint32_t s_doff[kRadix];       // chunk-local start of each digit (phase 1)
+  __shared__ uint32_t s_glob[kRadix];       // running global start of each digit (phase 1)
   const uint32_t n = read_count(v_ptr, v_cap);
   uint32_t begin, end;
   segment_of(n, G, blockIdx.x, begin, end);
   uint64_t base = partials[blockIdx.x];
   const uint32_t t = threadIdx.x;
-  const uint32_t i0 = t * kIpt;
   const int lane = t & 63, w = t >> 6;
-  for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
-    uint32_t cn[kIpt];
-    uint32_t s = 0;
+  const uint32_t mask = (1u << nbits) - 1u;
+  const uint64_t lt = lanemask_lt();
+  if (kPhase == 0) {
 #pragma unroll
-    for (int k = 0; k < kIpt; ++k) {
+    for (int k = 0; k < kWaves; ++k) s_cnt[k][t] = 0u;
+  } else {
+    s_glob[t] = hist[(size_t)t * G + blockIdx.x];
+  }
+  __syncthreads();
+  const uint32_t i0 = t * kEIpt;
+  for (uint32_t t0 = begin; t0 < end; t0 += kEmitItems) {
+    uint32_t cn[kEIpt];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kEIpt; ++k) {
       const uint32_t j = t0 + i0 + k;
       cn[k] = j < end ? counts[j] : 0u;
       uint32_t b = 0, shape = 1, p = 0;
@@ -255,13 +287,13 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restr
       s_pair[i0 + k] = p;
       s_base[i0 + k] = b;
       s_shape[i0 + k] = shape;
-      s += cn[k];
+      sum += cn[k];
     }
     uint32_t tot;
-    uint32_t off = block_excl_scan(s, s_tmp, &tot);
-    uint32_t offs[kIpt];
+    uint32_t off = block_excl_scan(sum, s_tmp, &tot);
+    uint32_t offs[kEIpt];
 #pragma unroll
-    for (int k = 0; k < kIpt; ++k) {
+    for (int k = 0; k < kEIpt; ++k) {
       offs[k] = off;
       s_off[i0 + k] = off;
       off += cn[k];
@@ -272,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restr
       for (int k = 0; k < kChunk / kThreads; ++k) s_own[t * (kChunk / kThreads) + k] = 0u;
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < kIpt; ++k)
+      for (int k = 0; k < kEIpt; ++k)
         if (cn[k] > 0u && offs[k] >= c0 && offs[k] - c0 < (uint32_t)kChunk) s_own[offs[k] - c0] = i0 + k + 1u;
       __syncthreads();
       // block-wide inclusive prefix maximum of s_own (8 slots per thread)
@@ -294,26 +326,99 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(const FrameDesc* __restr
 #pragma unroll
       for (int k = 0; k < kChunk / kThreads; ++k) s_own[t * (kChunk / kThreads) + k] = max(pre, v[k]);
       __syncthreads();
+      carry = s_own[kChunk - 1];
+      // the chunk's slots below capacity; thread slots in wave-major order for a stable rank
       const uint32_t nslot = min((uint32_t)kChunk, tot - c0);
-      for (uint32_t sl = t; sl < nslot; sl += kThreads) {
-        const uint32_t i = s_own[sl] - 1u;
-        const uint32_t local = c0 + sl - s_off[i];
-        const uint32_t shape = s_shape[i];
-        const uint32_t wd = shape & 0xffffu, txn = shape >> 16;
-        uint32_t q = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wd));
-        if (q * wd > local) --q;
-        else if ((q + 1u) * wd <= local) ++q;
-        const uint64_t pos = base + c0 + sl;
-        if (pos < capacity) {
-          keys[pos] = s_base[i] + q * txn + (local - q * wd);
-          vals[pos] = s_pair[i];
+      const uint64_t g0 = base + c0;
+      const uint32_t nvalid = g0 >= capacity ? 0u : (uint32_t)min((uint64_t)nslot, (uint64_t)capacity - g0);
+      constexpr int kR = kChunk / kThreads;   // 8 slots per thread
+      uint32_t key[kR], val[kR];
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        const uint32_t sl = (uint32_t)(w * (kChunk / kWaves) + r * 64 + lane);
+        key[r] = 0u;
+        val[r] = 0u;
+        if (sl < nvalid) {
+          const uint32_t i = s_own[sl] - 1u;
+          const uint32_t local = c0 + sl - s_off[i];
+          const uint32_t shape = s_shape[i];
+          const uint32_t wd = shape & 0xffffu, txn = shape >> 16;
+          uint32_t q = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wd));
+          if (q * wd > local) --q;
+          else if ((q + 1u) * wd <= local) ++q;
+          key[r] = s_base[i] + q * txn + (local - q * wd);
+          val[r] = s_pair[i];
         }
       }
-      carry = s_own[kChunk - 1];
-      __syncthreads();
+      if (kPhase == 0) {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          const uint32_t sl = (uint32_t)(w * (kChunk / kWaves) + r * 64 + lane);
+          if (sl < nvalid) atomicAdd(&s_cnt[w][key[r] & mask], 1u);
+        }
+        __syncthreads();   // s_own is rewritten by the next chunk
+      } else {
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) s_cnt[k][t] = 0u;
+        __syncthreads();   // also: every thread has read its owners and the carry
+        uint32_t rank[kR];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          const uint32_t sl = (uint32_t)(w * (kChunk / kWaves) + r * 64 + lane);
+          const bool valid = sl < nvalid;
+          const uint32_t d = key[r] & mask;
+          const uint64_t peers = match_digit(d, valid, nbits);
+          const uint32_t below = (uint32_t)__popcll(peers & lt);
+          const uint32_t old = valid ? s_cnt[w][d] : 0u;
+          if (valid && below == 0u) s_cnt[w][d] = old + (uint32_t)__popcll(peers);
+          rank[r] = valid ? old + below : 0xffffffffu;
+        }
+        __syncthreads();
+        uint32_t c[kWaves], dtot = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+          c[k] = s_cnt[k][t];
+          dtot += c[k];
+        }
+        uint32_t dummy;
+        const uint32_t excl = block_excl_scan(dtot, s_tmp, &dummy);
+        s_doff[t] = excl;
+        uint32_t run = excl;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+          s_cnt[k][t] = run;
+          run += c[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+          if (rank[r] != 0xffffffffu) {
+            const uint32_t pos = s_cnt[w][key[r] & mask] + rank[r];
+            s_own[pos] = key[r];
+            s_sval[pos] = val[r];
+          }
+        }
+        __syncthreads();
+        for (uint32_t i = t; i < nvalid; i += kThreads) {
+          const uint32_t k2 = s_own[i];
+          const uint32_t d = k2 & mask;
+          const uint32_t g = s_glob[d] + (i - s_doff[d]);
+          keys[g] = k2;
+          vals[g] = s_sval[i];
+        }
+        __syncthreads();
+        s_glob[t] += dtot;
+        __syncthreads();
+      }
     }
     base += tot;
     __syncthreads();
+  }
+  if (kPhase == 0) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) c += s_cnt[k][t];
+    hist[(size_t)t * G + blockIdx.x] = c;
   }
 }
 
@@ -344,16 +449,6 @@ __global__ __launch_bounds__(kThreads) void hist_scan_down_kernel(uint32_t* __re
 }
 
 // ------------------------------------------------------------------------------ radix sort
-
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbits) {
-  uint64_t peers = __ballot(valid);
-  for (int b = 0; b < nbits; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t m = __ballot(bit);
-    peers &= bit ? m : ~m;
-  }
-  return valid ? peers : 0ull;
-}
 
 // Per-block digit histogram of its segment, hist[d * G + b], counted with per-wave LDS
 // atomics (a skewed digit serialises one wave's atomics, which stays cheap).
@@ -519,13 +614,13 @@ int blocks_for(int64_t n, int items_per_block, int max_blocks) {
 int scan_blocks(int64_t n) { return blocks_for(n, 2 * kTileItems, kMaxScanBlocks); }
 int sort_blocks(int64_t n) { return blocks_for(n, 2 * kSortTile, kMaxSortBlocks); }
 
-// LSD radix sort of (key, val) over bits [0, bits): ping-pongs between (k0,v0) and (k1,v1);
-// the result ends in (k0,v0) when the number of passes is even, else in (k1,v1).
+// LSD radix sort of (key, val) over bits [first_bit, bits): ping-pongs between (k0,v0) and
+// (k1,v1); the result ends in (k0,v0) when the number of passes is even, else in (k1,v1).
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_ptr, uint32_t n_cap,
-                      int bits, uint32_t* hist, uint64_t* partials, hipStream_t stream) {
+                      int bits, uint32_t* hist, uint64_t* partials, hipStream_t stream, int first_bit = 0) {
   const int G = sort_blocks(n_cap);
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
-  for (int shift = 0; shift < bits; shift += kRadixBits) {
+  for (int shift = first_bit; shift < bits; shift += kRadixBits) {
     const int nb = min(kRadixBits, bits - shift);
     hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, n_ptr, n_cap, shift, nb, hist, G);
     // exclusive scan of the digit-major histogram (kRadix * G values)
@@ -552,7 +647,7 @@ size_t bin_ws_bytes(int64_t pairs) {
   b += p * 16;                                         // depth-sorted item records
   b += kMaxScanBlocks * sizeof(uint64_t);              // scan partials (entry offsets)
   b += kMaxScanBlocks * sizeof(uint64_t);              // scan partials (scratch)
-  b += (size_t)kRadix * kMaxSortBlocks * sizeof(uint32_t);  // radix histograms
+  b += (size_t)kRadix * kMaxHistBlocks * sizeof(uint32_t);  // radix histograms
   b += 64 * sizeof(uint32_t);                          // counters
   return b + 10 * 256;                                 // alignment slack
 }
@@ -569,7 +664,7 @@ void carve_bin_ws(void* ws, int64_t pairs, BinWs* out) {
   out->counters = (uint32_t*)take(64 * 4);
   out->partials = (uint32_t*)take(kMaxScanBlocks * 8);
   out->partials_tmp = (uint32_t*)take(kMaxScanBlocks * 8);
-  out->hist = (uint32_t*)take((size_t)kRadix * kMaxSortBlocks * 4);
+  out->hist = (uint32_t*)take((size_t)kRadix * kMaxHistBlocks * 4);
   out->dkeyA = (uint32_t*)take(p * 4);
   out->dvalA = (uint32_t*)take(p * 4);
   out->dkeyB = (uint32_t*)take(p * 4);
@@ -624,17 +719,27 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
   uint64_t* ptmp = (uint64_t*)ws.partials_tmp;
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1), 0, stream, ws.counters, capacity);
   const int bits = tile_bits(total_tiles);
-  const int passes = (bits + kRadixBits - 1) / kRadixBits;
-  uint32_t* ek = (passes % 2) ? keys_alt : keys;
-  uint32_t* ev = (passes % 2) ? vals_alt : vals;
-  uint32_t* ok = (passes % 2) ? keys : keys_alt;
-  uint32_t* ov = (passes % 2) ? vals : vals_alt;
+  const int nb0 = bits < kRadixBits ? bits : kRadixBits;   // bits of the fused first pass
+  const int passes = 1 + (bits > nb0 ? (bits - nb0 + kRadixBits - 1) / kRadixBits : 0);
+  // the fused pass writes (ek, ev); each later pass flips buffers; the result ends in keys
+  uint32_t* ek = (passes % 2) ? keys : keys_alt;
+  uint32_t* ev = (passes % 2) ? vals : vals_alt;
+  uint32_t* ok = (passes % 2) ? keys_alt : keys;
+  uint32_t* ov = (passes % 2) ? vals_alt : vals;
   const int Gc = scan_blocks(n_pairs);
   if (capacity > 0) {
-    hipLaunchKernelGGL(emit_kernel, dim3(Gc), dim3(kThreads), 0, stream, descs, (const uint4*)ws.items, ws.dkeyB,
-                       ws.counters + 0, n_pairs, partials, Gc, ek, ev, capacity);
-    if (passes > 0) {
-      hipError_t e = radix_sort(ek, ev, ok, ov, ws.counters + 4, capacity, bits, ws.hist, ptmp, stream);
+    hipLaunchKernelGGL(emit_radix_kernel<0>, dim3(Gc), dim3(kThreads), 0, stream, descs, (const uint4*)ws.items,
+                       ws.dkeyB, ws.counters + 0, n_pairs, partials, Gc, capacity, nb0, ws.hist, nullptr, nullptr);
+    const uint32_t hn = (uint32_t)(kRadix * Gc);
+    const int Gs = scan_blocks(hn);
+    ScanSrc src{nullptr, nullptr, ws.hist};
+    hipLaunchKernelGGL(scan_reduce_kernel<kRaw>, dim3(Gs), dim3(kThreads), 0, stream, src, nullptr, hn, ptmp, Gs);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, ptmp, Gs, nullptr, nullptr);
+    hipLaunchKernelGGL(hist_scan_down_kernel, dim3(Gs), dim3(kThreads), 0, stream, ws.hist, hn, ptmp, Gs);
+    hipLaunchKernelGGL(emit_radix_kernel<1>, dim3(Gc), dim3(kThreads), 0, stream, descs, (const uint4*)ws.items,
+                       ws.dkeyB, ws.counters + 0, n_pairs, partials, Gc, capacity, nb0, ws.hist, ek, ev);
+    if (passes > 1) {
+      hipError_t e = radix_sort(ek, ev, ok, ov, ws.counters + 4, capacity, bits, ws.hist, ptmp, stream, nb0);
       if (e != hipSuccess) return e;
     }
   }

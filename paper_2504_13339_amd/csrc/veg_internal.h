@@ -120,13 +120,14 @@ struct BinWs {
   uint32_t* items;          // [pairs] uint4: depth-sorted (pair, rect01, rect23, frame)
   uint32_t* partials;       // [kMaxScanBlocks] uint64: entry-offset scan, kept from count to sort
   uint32_t* partials_tmp;   // [kMaxScanBlocks] uint64: scratch for the other scans
-  uint32_t* hist;       // [kRadix * kMaxSortBlocks]
+  uint32_t* hist;       // [kRadix * kMaxHistBlocks]
   uint32_t* counters;   // [0] kept pairs V, [1..2] entries E (uint64), [3] overflow flag,
                         // [4] entries written min(E, capacity), [8..9] V (uint64)
   uint32_t* depth_sorted_vals;  // points at whichever of dvalA/dvalB holds the sorted result
 };
 constexpr int kMaxScanBlocks = 4096;
 constexpr int kMaxSortBlocks = 2048;
+constexpr int kMaxHistBlocks = kMaxScanBlocks > kMaxSortBlocks ? kMaxScanBlocks : kMaxSortBlocks;
 size_t bin_ws_bytes(int64_t pairs);
 void carve_bin_ws(void* ws, int64_t pairs, BinWs* out);
 
