@@ -11,6 +11,9 @@ The 3D covariance R S S^T R^T is projected to a 2D screen covariance with Zwicke
 linearisation; each pixel evaluates the 2D Gaussian at its centre and composites the
 Gaussians front to back, C = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j).  Tiling and
 sorting only make this faster, so the oracle computes the definition by brute force.
+Optionally each Gaussian also carries Blinn-Phong lighting attributes (normal, ambient,
+diffuse and specular coefficients, shininess; Eq. 2-3), which turn C(v) into the shaded
+colour under a headlight before compositing.
 
 Three parts:
 
@@ -30,7 +33,9 @@ Three parts:
   autograd in float64 on the CPU.
 
 Readings where the paper is silent (tile size, thresholds, footprint rule, low-pass,
-guard band, near plane, stop semantics, knot derivative) follow the renderer options:
+guard band, near plane, stop semantics, knot derivative, light direction) follow the
+renderer options and the headlight of the paper's evaluation (light and view direction =
+the unit vector from the camera centre to the Gaussian):
 alpha clamp 0.99, skip alpha < 1/255, stop once T < 1e-4 after blending the Gaussian that
 crossed it, low-pass 0.3 px^2, guard 1.3, near 0.2.
 """
@@ -168,8 +173,15 @@ def footprint_f32(g, cam, lut, opts) -> Footprint:
         mx = float(fx) * xn + float(cx)
         my = float(fy) * yn + float(cy)
 
+        sh = getattr(g, "shading", None)
         finite = _finite_rows(g.means, g.log_scales, g.quats, g.scalars[:, None],
                               None if g.weights is None else g.weights[:, None])
+        if sh is not None:
+            finite = finite & _finite_rows(sh.normals, sh.k_ambient[:, None], sh.k_diffuse[:, None],
+                                           sh.k_specular[:, None], sh.shininess[:, None])
+            nn = np.asarray(sh.normals, np.float32)
+            nrm2 = ((nn[:, 0] * nn[:, 0] + nn[:, 1] * nn[:, 1]) + nn[:, 2] * nn[:, 2])
+            finite = finite & (nrm2 >= QNORM2_MIN)
         # transfer function
         K = lut.shape[0]
         v = g.scalars.astype(np.float32)
@@ -337,7 +349,7 @@ def _t64(a):
     return torch.as_tensor(np.asarray(a, np.float64))
 
 
-def project_f64(means, log_scales, quats, scalars, weights, cam, lut, opts) -> OracleProjection:
+def project_f64(means, log_scales, quats, scalars, weights, cam, lut, opts, shading=None) -> OracleProjection:
     """Per-Gaussian quantities in float64 (torch, differentiable).
 
     TF first (paper: colour and opacity from the transfer function before rasterizing;
@@ -345,6 +357,12 @@ def project_f64(means, log_scales, quats, scalars, weights, cam, lut, opts) -> O
     Sigma = R S S^T R^T, then Zwicker's EWA projection Sigma' = J W Sigma W^T J^T + lowpass I
     with J the Jacobian of the pinhole map at the camera-space centre (its x/z, y/z clamped
     to the guard band), conic = Sigma'^-1.
+
+    ``shading`` = (normals, k_ambient, k_diffuse, k_specular, shininess) applies the
+    Blinn-Phong colour of Eq. 2-3 with a headlight: light and view direction both the unit
+    vector l from the camera centre to the Gaussian, so the half vector is l and, with
+    s = |n^ . l| (n^ the normalised normal),
+        c = C(v) (k_a + k_d s) + k_s s^beta (white),  the specular term 0 when s = 0.
     """
     means, log_scales, quats, scalars = map(_t64, (means, log_scales, quats, scalars))
     weights = None if weights is None else _t64(weights)
@@ -365,6 +383,16 @@ def project_f64(means, log_scales, quats, scalars, weights, cam, lut, opts) -> O
     rgba = lut[i] * (1 - fr) + lut[i + 1] * fr
     rgb = rgba[:, :3]
     A = rgba[:, 3] if weights is None else rgba[:, 3] * weights
+    if shading is not None:
+        nrm, k_a, k_d, k_s, beta = map(_t64, shading)
+        campos = -(Wr.T @ b)                                # camera centre: W campos + b = 0
+        dvec = means - campos
+        ldir = dvec / torch.sqrt((dvec * dvec).sum(-1))[:, None]
+        nhat = nrm / torch.sqrt((nrm * nrm).sum(-1))[:, None]
+        sabs = (nhat * ldir).sum(-1).abs()
+        pos = sabs > 0
+        spec = torch.where(pos, k_s * torch.where(pos, sabs, torch.ones_like(sabs)) ** beta, torch.zeros_like(sabs))
+        rgb = rgb * (k_a + k_d * sabs)[:, None] + spec[:, None]
 
     qn2 = (quats * quats).sum(-1)
     qhat = quats / torch.sqrt(qn2)[:, None]
@@ -393,6 +421,9 @@ def project_f64(means, log_scales, quats, scalars, weights, cam, lut, opts) -> O
         ok = fin(means) & fin(log_scales) & fin(quats) & torch.isfinite(scalars)
         if weights is not None:
             ok &= torch.isfinite(weights)
+        if shading is not None:
+            ok &= fin(nrm) & torch.isfinite(k_a) & torch.isfinite(k_d) & torch.isfinite(k_s) & torch.isfinite(beta)
+            ok &= (nrm * nrm).sum(-1) >= float(QNORM2_MIN)
         amin = float(np.float32(opts["alpha_min"]))
         ok &= (tz > float(np.float32(opts["near_z"]))) & (A >= amin) & (qn2 >= float(QNORM2_MIN)) & (det > 0)
         ok &= torch.isfinite(conic).all(1) & torch.isfinite(mean2d).all(1)
@@ -501,10 +532,16 @@ def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray,
                        flag_grad=np.concatenate(gflags), slack=np.concatenate(slacks))
 
 
+def _shading_arrays(g):
+    sh = getattr(g, "shading", None)
+    return None if sh is None else (sh.normals, sh.k_ambient, sh.k_diffuse, sh.k_specular, sh.shininess)
+
+
 def render_image(g, cam, lut, opts, pixels=None, bg=None, t_min=None, **kw):
     """Convenience: O1 depth order + O2 for one frame.  Returns (PixelResult, proj, order, fp)."""
     fp = footprint_f32(g, cam, lut, opts)
-    proj = project_f64(g.means, g.log_scales, g.quats, g.scalars, g.weights, cam, lut, opts)
+    proj = project_f64(g.means, g.log_scales, g.quats, g.scalars, g.weights, cam, lut, opts,
+                       shading=_shading_arrays(g))
     order = depth_order(fp, proj.kept)
     if pixels is None:
         ys, xs = np.mgrid[0:cam.height, 0:cam.width]
@@ -531,6 +568,12 @@ class OracleGrads:
     d_rgb: np.ndarray
     d_A: np.ndarray
     loss: float
+    # lighting attributes (None for an unshaded model)
+    d_normals: Optional[np.ndarray] = None
+    d_k_ambient: Optional[np.ndarray] = None
+    d_k_diffuse: Optional[np.ndarray] = None
+    d_k_specular: Optional[np.ndarray] = None
+    d_shininess: Optional[np.ndarray] = None
 
 
 def gradients(g, cam, lut, opts, d_color, pixels=None, bg=None, batch: int = 0) -> OracleGrads:
@@ -543,7 +586,9 @@ def gradients(g, cam, lut, opts, d_color, pixels=None, bg=None, batch: int = 0) 
     leaves = [torch.tensor(np.asarray(x, np.float64), requires_grad=True)
               for x in (g.means, g.log_scales, g.quats, g.scalars)]
     w = None if g.weights is None else torch.tensor(np.asarray(g.weights, np.float64), requires_grad=True)
-    proj = project_f64(*leaves, w, cam, lut, opts)
+    sh_arr = _shading_arrays(g)
+    sh = None if sh_arr is None else [torch.tensor(np.asarray(x, np.float64), requires_grad=True) for x in sh_arr]
+    proj = project_f64(*leaves, w, cam, lut, opts, shading=sh)
     inter = [proj.mean2d, proj.conic, proj.rgb, proj.A]
     for t in inter:
         t.retain_grad()
@@ -567,4 +612,7 @@ def gradients(g, cam, lut, opts, d_color, pixels=None, bg=None, batch: int = 0) 
     return OracleGrads(d_means=gnp(leaves[0]), d_log_scales=gnp(leaves[1]), d_quats=gnp(leaves[2]),
                        d_scalars=gnp(leaves[3]), d_weights=None if w is None else gnp(w),
                        d_mean2d=gnp(proj.mean2d), d_conic=gnp(proj.conic), d_rgb=gnp(proj.rgb),
-                       d_A=gnp(proj.A), loss=total)
+                       d_A=gnp(proj.A), loss=total,
+                       **({} if sh is None else dict(d_normals=gnp(sh[0]), d_k_ambient=gnp(sh[1]),
+                                                     d_k_diffuse=gnp(sh[2]), d_k_specular=gnp(sh[3]),
+                                                     d_shininess=gnp(sh[4]))))

@@ -23,7 +23,7 @@ import numpy as np
 SEED_BASE = 0x2504_13339
 
 __all__ = [
-    "SEED_BASE", "Gaussians", "Camera", "rng_for", "uniform_gaussians", "shell_gaussians",
+    "SEED_BASE", "Gaussians", "Shading", "random_shading", "Camera", "rng_for", "uniform_gaussians", "shell_gaussians",
     "clustered_gaussians", "random_tf", "identity_tf", "constant_tf", "fibonacci_directions",
     "random_direction", "look_at_camera", "perturbed_copy", "sample_pixels", "Workload",
     "workload", "serve_trace", "DEFAULT_OPTS",
@@ -41,12 +41,32 @@ def rng_for(config_index: int, sub: int = 0) -> np.random.Generator:
 
 
 @dataclass
+class Shading:
+    """Per-Gaussian lighting attributes (section "The VEG Representation", Blinn-Phong):
+    normal, ambient / diffuse / specular coefficients and shininess, already activated."""
+    normals: np.ndarray      # [n,3] float32, any length > 0
+    k_ambient: np.ndarray    # [n]
+    k_diffuse: np.ndarray    # [n]
+    k_specular: np.ndarray   # [n]
+    shininess: np.ndarray    # [n] > 0
+
+    def subset(self, idx) -> "Shading":
+        return Shading(self.normals[idx].copy(), self.k_ambient[idx].copy(), self.k_diffuse[idx].copy(),
+                       self.k_specular[idx].copy(), self.shininess[idx].copy())
+
+    def astype(self, dt) -> "Shading":
+        return Shading(*(np.asarray(a, dt) for a in (self.normals, self.k_ambient, self.k_diffuse,
+                                                      self.k_specular, self.shininess)))
+
+
+@dataclass
 class Gaussians:
     means: np.ndarray        # [n,3] float32
     log_scales: np.ndarray   # [n,3] float32
     quats: np.ndarray        # [n,4] float32, (w,x,y,z)
     scalars: np.ndarray      # [n]   float32 in [0,1]
     weights: Optional[np.ndarray] = None  # [n] float32 or None (== 1)
+    shading: Optional[Shading] = None     # lighting attributes or None (TF colour only)
 
     @property
     def n(self) -> int:
@@ -55,7 +75,20 @@ class Gaussians:
     def subset(self, idx) -> "Gaussians":
         return Gaussians(self.means[idx].copy(), self.log_scales[idx].copy(),
                          self.quats[idx].copy(), self.scalars[idx].copy(),
-                         None if self.weights is None else self.weights[idx].copy())
+                         None if self.weights is None else self.weights[idx].copy(),
+                         None if self.shading is None else self.shading.subset(idx))
+
+
+def random_shading(rng, n, k_ambient=(0.1, 0.4), k_diffuse=(0.4, 0.9), k_specular=(0.0, 0.5),
+                   shininess=(2.0, 64.0)) -> Shading:
+    """Random lighting attributes: normals from an isotropic normal distribution (unit
+    after normalisation), coefficients uniform in the given ranges, shininess log-uniform."""
+    nrm = rng.standard_normal((n, 3)).astype(np.float32)
+    ka = rng.uniform(*k_ambient, n).astype(np.float32)
+    kd = rng.uniform(*k_diffuse, n).astype(np.float32)
+    ks = rng.uniform(*k_specular, n).astype(np.float32)
+    beta = np.exp(rng.uniform(math.log(shininess[0]), math.log(shininess[1]), n)).astype(np.float32)
+    return Shading(nrm, ka, kd, ks, beta)
 
 
 @dataclass
@@ -184,7 +217,8 @@ def perturbed_copy(rng, g: Gaussians, mean_sigma=0.01, scalar_sigma=0.05) -> Gau
     means = (g.means + rng.normal(0.0, mean_sigma, g.means.shape)).astype(np.float32)
     v = np.clip(g.scalars + rng.normal(0.0, scalar_sigma, g.scalars.shape), 0.0, 1.0).astype(np.float32)
     return Gaussians(means, g.log_scales.copy(), g.quats.copy(), v,
-                     None if g.weights is None else g.weights.copy())
+                     None if g.weights is None else g.weights.copy(),
+                     None if g.shading is None else g.shading.subset(slice(None)))
 
 
 def sample_pixels(rng, width, height, n, centre_frac=0.5) -> np.ndarray:

@@ -433,9 +433,12 @@ def _loss_f64(g, cam, lut, d):
     """Loss with float64 parameters (FD needs perturbations below float32 resolution).
     The depth order and cull decisions of the unperturbed float32 inputs are kept."""
     g32 = synth.Gaussians(g.means.astype(np.float32), g.log_scales.astype(np.float32), g.quats.astype(np.float32),
-                          g.scalars.astype(np.float32), None if g.weights is None else g.weights.astype(np.float32))
+                          g.scalars.astype(np.float32), None if g.weights is None else g.weights.astype(np.float32),
+                          None if g.shading is None else g.shading.astype(np.float32))
     fp = oracle.footprint_f32(g32, cam, lut, OPTS)
-    proj = oracle.project_f64(g.means, g.log_scales, g.quats, g.scalars, g.weights, cam, lut, OPTS)
+    sh = None if g.shading is None else (g.shading.normals, g.shading.k_ambient, g.shading.k_diffuse,
+                                         g.shading.k_specular, g.shading.shininess)
+    proj = oracle.project_f64(g.means, g.log_scales, g.quats, g.scalars, g.weights, cam, lut, OPTS, shading=sh)
     order = oracle.depth_order(fp, proj.kept)
     ys, xs = np.mgrid[0:cam.height, 0:cam.width]
     px = np.stack([xs.reshape(-1), ys.reshape(-1)], 1)
@@ -447,3 +450,91 @@ def test_flagged_fraction_is_small_on_the_small_workload():
     w = synth.workload(0)
     res, *_ = oracle.render_image(w.gaussians, w.cameras[0], w.tfs[0], OPTS)
     assert res.flag.mean() <= 1e-2
+
+
+# ----------------------------------------------------------------------------- lighting
+
+def _shading(n, normals=None, ka=0.2, kd=0.6, ks=0.3, beta=3.0):
+    nrm = np.tile(np.array([[0, 0, 1]], np.float32), (n, 1)) if normals is None else np.asarray(normals, np.float32)
+    full = lambda x: np.full(n, x, np.float32)
+    return synth.Shading(nrm, full(ka), full(kd), full(ks), full(beta))
+
+
+def _proj_rgb(g, cam, lut):
+    sh = None if g.shading is None else (g.shading.normals, g.shading.k_ambient, g.shading.k_diffuse,
+                                         g.shading.k_specular, g.shading.shininess)
+    p = oracle.project_f64(g.means, g.log_scales, g.quats, g.scalars, g.weights, cam, lut, OPTS, shading=sh)
+    return p.rgb.detach().numpy()
+
+
+def test_shading_with_only_ambient_light_is_the_tf_colour():
+    rng = np.random.default_rng(31)
+    g = synth.uniform_gaussians(rng, 50, 0.02, 0.1, box=0.5)
+    cam = synth.look_at_camera(synth.random_direction(rng), 3.0, 48, 48)
+    lut = synth.random_tf(rng)
+    plain = _proj_rgb(g, cam, lut)
+    g.shading = _shading(g.n, normals=rng.standard_normal((g.n, 3)), ka=1.0, kd=0.0, ks=0.0, beta=5.0)
+    assert np.array_equal(_proj_rgb(g, cam, lut), plain)
+
+
+def test_shading_headlight_closed_forms():
+    """Camera on the z axis looking at the origin (its centre at (0, 0, -3)), identity TF at
+    v = 1 so that C(v) = 1 exactly: with k_a = 1/4, k_d = 1/2, k_s = 3/8 and beta = 3, Eq. 2-3
+    give c = 1/4 + s/2 + 3/8 s^3 with s = |n . l| for the unit direction l from the camera:
+    9/8 at s = 1, 35/64 at s = 1/2, 1/4 at s = 0 (no specular term)."""
+    cam = _axis_camera(3.0)
+    lut = synth.identity_tf(256)
+    c60, s60 = math.cos(math.radians(60.0)), math.sin(math.radians(60.0))
+    normals = [[0, 0, 1], [0, 0, -2], [s60, 0, c60], [0, -s60, -c60], [1, 0, 0], [0, 3, 0]]
+    n = len(normals)
+    g = _gaussians([[0, 0, 0]] * n, [[0.05] * 3] * n, [1.0] * n)
+    g.shading = _shading(n, normals=normals, ka=0.25, kd=0.5, ks=0.375, beta=3.0)
+    rgb = _proj_rgb(g, cam, lut)
+    want = [9 / 8, 9 / 8, 35 / 64, 35 / 64, 1 / 4, 1 / 4]
+    for i, w in enumerate(want):
+        assert np.allclose(rgb[i], w, atol=1e-7, rtol=0), (i, rgb[i], w)
+    # off-axis centre: the light direction is the centre's own direction from the camera
+    mu = np.array([[0.6, -0.4, 0.5]])
+    towards_camera = np.array([0.0, 0.0, -3.0]) - mu
+    g2 = _gaussians(mu, [[0.05] * 3], [1.0])
+    g2.shading = _shading(1, normals=towards_camera, ka=0.25, kd=0.5, ks=0.375, beta=3.0)
+    assert np.allclose(_proj_rgb(g2, cam, lut)[0], 9 / 8, atol=1e-6)
+
+
+def test_shading_gradients_match_central_finite_differences():
+    rng = np.random.default_rng(32)
+    n = 10
+    g = synth.uniform_gaussians(rng, n, 0.08, 0.25, box=0.5)
+    g.shading = synth.random_shading(rng, n, shininess=(1.5, 8.0))
+    cam = synth.look_at_camera(synth.random_direction(rng), 3.0, 32, 32)
+    lut = synth.random_tf(rng)
+    lut[:, 3] = np.clip(lut[:, 3] + 0.3, 0, 0.8)
+    d = rng.standard_normal((32 * 32, 3))
+    gr = oracle.gradients(g, cam, lut, OPTS, d)
+    res, *_ = oracle.render_image(g, cam, lut, OPTS)
+    assert not res.flag.any() and not res.flag_grad.any()
+
+    def fd(field, idx):
+        sub, name = field.split(".") if "." in field else (None, field)
+        x0 = float((getattr(g.shading, name) if sub else getattr(g, name))[idx])
+        h = 1e-6 * max(1.0, abs(x0))
+        out = []
+        for sgn in (1, -1):
+            gg = synth.Gaussians(g.means.astype(np.float64), g.log_scales.astype(np.float64),
+                                 g.quats.astype(np.float64), g.scalars.astype(np.float64), None,
+                                 g.shading.astype(np.float64))
+            arr = getattr(gg.shading, name) if sub else getattr(gg, name)
+            arr[idx] = x0 + sgn * h
+            out.append(_loss_f64(gg, cam, lut, d))
+        return (out[0] - out[1]) / (2 * h)
+
+    fields = [("shading.normals", gr.d_normals), ("shading.k_ambient", gr.d_k_ambient),
+              ("shading.k_diffuse", gr.d_k_diffuse), ("shading.k_specular", gr.d_k_specular),
+              ("shading.shininess", gr.d_shininess), ("means", gr.d_means), ("scalars", gr.d_scalars)]
+    for field, grad in fields:
+        flat = [np.unravel_index(k, grad.shape) for k in range(grad.size)]
+        scale = np.abs(grad).max()
+        assert scale > 0, field
+        for idx in flat[:: max(1, len(flat) // 12)]:
+            num = fd(field, idx)
+            assert abs(num - grad[idx]) <= 1e-6 * scale + 1e-9, (field, idx, num, grad[idx])
