@@ -75,14 +75,22 @@ int veg_version(void);
  * ---------------------------------------------------------------------------------- */
 
 /* A VEG model, device SoA (section "The VEG Representation": centre mu, scaling S,
- * rotation R, scalar value v, weight w).  Lighting attributes are not part of this ABI.
+ * rotation R, scalar value v, weight w, and the lighting attributes of its Blinn-Phong
+ * model, Eq. 2-3).
  *   means      [n,3]  world-space centres
  *   log_scales [n,3]  log of the three axis scales (S = diag(exp(log_scales)))
  *   quats      [n,4]  rotation as an unnormalised quaternion (w,x,y,z); normalised inside
  *   scalars    [n]    scalar value, already activated (the paper stores it through a
  *                     sigmoid; apply it before the call); used clamped to [0,1]
  *   weights    [n]    trainable opacity weight, already activated, or NULL meaning 1
- * Gaussians with any non-finite input are culled, never an error. */
+ * Lighting (all five NULL: the colour is the transfer function's C(v); all five non-NULL:
+ * the Blinn-Phong colour of Eq. 2-3 under a headlight, light and view direction both the
+ * unit vector l from the camera centre to the Gaussian, so that with s = |n^ . l|
+ *   c = C(v) (k_ambient + k_diffuse s) + k_specular s^shininess (white; 0 when s = 0)):
+ *   normals    [n,3]  normal, any non-zero length (normalised inside)
+ *   k_ambient, k_diffuse, k_specular, shininess  [n]  already activated, shininess > 0
+ * Gaussians with any non-finite input, or a zero quaternion or normal, are culled, never an
+ * error. */
 typedef struct {
   int64_t n;
   const float* means;
@@ -90,6 +98,11 @@ typedef struct {
   const float* quats;
   const float* scalars;
   const float* weights;
+  const float* normals;
+  const float* k_ambient;
+  const float* k_diffuse;
+  const float* k_specular;
+  const float* shininess;
 } veg_gaussians;
 
 /* Pinhole camera (host struct).  view = world->camera 3x4 row-major [R|t]; camera axes
@@ -286,20 +299,29 @@ veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_
                           float* g2d, veg_stream_t stream);
 
 /* Parameter gradients, device, ACCUMULATED (+=).  d_weights may be NULL (then not
- * computed); it must be non-NULL only when the model has weights. */
+ * computed); it must be non-NULL only when the model has weights.  The five lighting
+ * gradients are all NULL (not computed) or all non-NULL, the latter only for a model with
+ * lighting attributes. */
 typedef struct {
   float* d_means;       /* [n,3] */
   float* d_log_scales;  /* [n,3] */
   float* d_quats;       /* [n,4] */
   float* d_scalars;     /* [n]   */
   float* d_weights;     /* [n] or NULL */
+  float* d_normals;     /* [n,3] or NULL */
+  float* d_k_ambient;   /* [n] or NULL */
+  float* d_k_diffuse;   /* [n] or NULL */
+  float* d_k_specular;  /* [n] or NULL */
+  float* d_shininess;   /* [n] or NULL */
 } veg_grads;
 
 /* veg_project_bwd -- chains g2d through the conic inverse, the EWA projection, the
  * covariance R S S^T R^T, the quaternion normalisation, exp of the log-scales, the
- * projected centre, and the transfer function's piecewise-linear segments (slope of the
- * segment to the right of a control point; zero outside [0,1]) to the model parameters,
- * summed over the frames of `proj`.
+ * projected centre, the lighting of Eq. 2-3 (when the model has it: normal normalisation,
+ * the light direction's dependence on the centre, coefficients, shininess; the derivative
+ * of |n^ . l| is taken as 0 where it vanishes) and the transfer function's piecewise-linear
+ * segments (slope of the segment to the right of a control point; zero outside [0,1]) to
+ * the model parameters, summed over the frames of `proj`.
  * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
 veg_status veg_project_bwd(const veg_gaussians* g, const veg_proj* proj, const veg_opts* opts,
                            const float* g2d, const veg_grads* grads, veg_stream_t stream);

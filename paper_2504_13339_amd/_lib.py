@@ -26,7 +26,8 @@ class VegError(RuntimeError):
 
 class veg_gaussians(Structure):
     _fields_ = [("n", c_int64), ("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p),
-                ("scalars", c_void_p), ("weights", c_void_p)]
+                ("scalars", c_void_p), ("weights", c_void_p), ("normals", c_void_p), ("k_ambient", c_void_p),
+                ("k_diffuse", c_void_p), ("k_specular", c_void_p), ("shininess", c_void_p)]
 
 
 class veg_camera(Structure):
@@ -56,7 +57,8 @@ class veg_bins(Structure):
 
 class veg_grads(Structure):
     _fields_ = [("d_means", c_void_p), ("d_log_scales", c_void_p), ("d_quats", c_void_p), ("d_scalars", c_void_p),
-                ("d_weights", c_void_p)]
+                ("d_weights", c_void_p), ("d_normals", c_void_p), ("d_k_ambient", c_void_p),
+                ("d_k_diffuse", c_void_p), ("d_k_specular", c_void_p), ("d_shininess", c_void_p)]
 
 
 class veg_serve_config(Structure):

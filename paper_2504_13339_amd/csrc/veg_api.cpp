@@ -94,6 +94,10 @@ veg_status check_gaussians(const veg_gaussians* g) {
     return fail(VEG_ERR_INVALID_ARG, "gaussians: NULL parameter array");
   if (g->quats && (reinterpret_cast<uintptr_t>(g->quats) & 15u))
     return fail(VEG_ERR_INVALID_ARG, "gaussians: quats must be 16-byte aligned");
+  const int lit = (g->normals != nullptr) + (g->k_ambient != nullptr) + (g->k_diffuse != nullptr) +
+                  (g->k_specular != nullptr) + (g->shininess != nullptr);
+  if (lit != 0 && lit != 5)
+    return fail(VEG_ERR_INVALID_ARG, "gaussians: lighting attributes must be all NULL or all given");
   return VEG_OK;
 }
 
@@ -177,6 +181,7 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
     d.quats = g->quats;
     d.scalars = g->scalars;
     d.weights = g->weights;
+    set_lighting(d, *g, cams[f]);
     d.lut = tfs[f].rgba;
     d.K = tfs[f].k;
     d.n = (int32_t)g->n;
@@ -345,12 +350,20 @@ veg_status veg_project_bwd(const veg_gaussians* g, const veg_proj* proj, const v
     return fail(VEG_ERR_INVALID_ARG, "project_bwd: NULL gradient buffer");
   if (grads->d_weights && !g->weights)
     return fail(VEG_ERR_INVALID_ARG, "project_bwd: d_weights given but the model has no weights");
+  {
+    const int lg = (grads->d_normals != nullptr) + (grads->d_k_ambient != nullptr) +
+                   (grads->d_k_diffuse != nullptr) + (grads->d_k_specular != nullptr) +
+                   (grads->d_shininess != nullptr);
+    if (lg != 0 && lg != 5)
+      return fail(VEG_ERR_INVALID_ARG, "project_bwd: lighting gradients must be all NULL or all given");
+    if (lg == 5 && !g->normals)
+      return fail(VEG_ERR_INVALID_ARG, "project_bwd: lighting gradients given but the model has no lighting");
+  }
   veg_opts o;
   s = resolve_opts(opts, &o);
   if (s != VEG_OK) return s;
   VEG_CHECK_HIP(launch_project_bwd((const FrameDesc*)proj->frames, proj->n_frames, (int)g->n, kopts(&o), g2d,
-                                   (uint32_t)pairs_of(proj), grads->d_means, grads->d_log_scales, grads->d_quats,
-                                   grads->d_scalars, grads->d_weights, (hipStream_t)stream),
+                                   (uint32_t)pairs_of(proj), *grads, (hipStream_t)stream),
                 "veg_project_bwd");
   return VEG_OK;
 }

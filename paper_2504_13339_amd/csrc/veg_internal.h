@@ -21,6 +21,11 @@ struct alignas(16) FrameDesc {
   const float* quats;
   const float* scalars;
   const float* weights;      // may be null
+  const float* normals;      // lighting attributes; all null for TF colour only
+  const float* k_ambient;
+  const float* k_diffuse;
+  const float* k_specular;
+  const float* shininess;
   const float* lut;          // [K,4]
   float* out_image;          // per-frame outputs (server); null in the stateless API
   float* out_tfinal;
@@ -35,9 +40,10 @@ struct alignas(16) FrameDesc {
   float view[12];
   float fx, fy, cx, cy;
   float bg[3];
-  float pad1;
+  float campos[3];           // camera centre in world space (headlight position)
+  float pad1[4];
 };
-static_assert(sizeof(FrameDesc) == 192, "FrameDesc layout");
+static_assert(sizeof(FrameDesc) == 256, "FrameDesc layout");
 
 // Options as the kernels use them (derived once on the host).
 struct KOpts {
@@ -108,8 +114,20 @@ hipError_t launch_project(const FrameDesc* descs, int n_frames, int n_max, const
                           float4* rec, uint32_t* count, uint32_t* depth, bool shared_model,
                           hipStream_t stream);
 hipError_t launch_project_bwd(const FrameDesc* descs, int n_frames, int n, const KOpts& o,
-                              const float* g2d, uint32_t n_pairs, float* d_means, float* d_ls,
-                              float* d_quats, float* d_scalars, float* d_weights, hipStream_t stream);
+                              const float* g2d, uint32_t n_pairs, const veg_grads& grads, hipStream_t stream);
+
+// Lighting attributes of a model and the camera centre (-R^T t of the world->camera
+// transform [R|t]) into a frame descriptor.
+inline void set_lighting(FrameDesc& d, const veg_gaussians& g, const veg_camera& c) {
+  d.normals = g.normals;
+  d.k_ambient = g.k_ambient;
+  d.k_diffuse = g.k_diffuse;
+  d.k_specular = g.k_specular;
+  d.shininess = g.shininess;
+  for (int j = 0; j < 3; ++j)
+    d.campos[j] = (float)(-((double)c.view[j] * c.view[3] + (double)c.view[4 + j] * c.view[7] +
+                            (double)c.view[8 + j] * c.view[11]));
+}
 
 // Binning pipeline (workspace-based).  `pairs` and `capacity` bound the device counts.
 struct BinWs {

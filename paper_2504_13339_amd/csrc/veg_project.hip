@@ -80,6 +80,10 @@ struct GParams {
   float qh[4];         // normalised quaternion
   float R[9];          // rotation, row-major
   float s[3];          // scales
+  bool lit;            // lighting attributes present
+  float nn2, ninv;     // |n|^2, 1/|n|
+  float nh[3];         // normalised normal
+  float ka, kd, ks, beta;
 };
 
 __device__ __forceinline__ void load_params(const FrameDesc& d, int i, GParams& g) {
@@ -110,6 +114,46 @@ __device__ __forceinline__ void load_params(const FrameDesc& d, int i, GParams& 
   g.s[0] = exp32(g.ls[0]);
   g.s[1] = exp32(g.ls[1]);
   g.s[2] = exp32(g.ls[2]);
+  g.lit = d.normals != nullptr;
+  if (g.lit) {
+    const float* nr = d.normals + 3 * (size_t)i;
+    const float n0 = nr[0], n1 = nr[1], n2 = nr[2];
+    g.ka = d.k_ambient[i];
+    g.kd = d.k_diffuse[i];
+    g.ks = d.k_specular[i];
+    g.beta = d.shininess[i];
+    g.finite = g.finite && __builtin_isfinite(n0) && __builtin_isfinite(n1) && __builtin_isfinite(n2) &&
+               __builtin_isfinite(g.ka) && __builtin_isfinite(g.kd) && __builtin_isfinite(g.ks) &&
+               __builtin_isfinite(g.beta);
+    g.nn2 = (n0 * n0 + n1 * n1) + n2 * n2;
+    g.ninv = 1.0f / sqrtf(g.nn2);
+    g.nh[0] = n0 * g.ninv;
+    g.nh[1] = n1 * g.ninv;
+    g.nh[2] = n2 * g.ninv;
+  } else {
+    g.nn2 = 1.0f;
+  }
+}
+
+// Blinn-Phong colour of Eq. 2-3 under a headlight: light and view direction are both the
+// unit vector l from the camera centre to the Gaussian, so the half vector is l and, with
+// u = n^ . l and s = |u|, c = C (k_a + k_d s) + k_s s^beta (white; 0 when s = 0).
+struct Lit {
+  float l[3], dinv;   // unit light direction, 1 / |mu - campos|
+  float u, s, f, sb;  // n^ . l, |u|, k_a + k_d s, s^beta
+};
+
+__device__ __forceinline__ void shade(const FrameDesc& d, const GParams& g, const float C[3], float rgb[3], Lit& L) {
+  const float dx = g.mu[0] - d.campos[0], dy = g.mu[1] - d.campos[1], dz = g.mu[2] - d.campos[2];
+  L.dinv = 1.0f / sqrtf((dx * dx + dy * dy) + dz * dz);
+  L.l[0] = dx * L.dinv;
+  L.l[1] = dy * L.dinv;
+  L.l[2] = dz * L.dinv;
+  L.u = (g.nh[0] * L.l[0] + g.nh[1] * L.l[1]) + g.nh[2] * L.l[2];
+  L.s = fabsf(L.u);
+  L.f = g.ka + g.kd * L.s;
+  L.sb = L.s > 1e-30f ? exp32(g.beta * log32(L.s)) : 0.0f;
+  for (int c = 0; c < 3; ++c) rgb[c] = C[c] * L.f + g.ks * L.sb;
 }
 
 struct TfSample {
@@ -207,17 +251,19 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
   const float* cur = nullptr;
   const float* cur_v = nullptr;
   const float* cur_w = nullptr;
+  const float* cur_n = nullptr;
   for (int f = f0; f < f1; ++f) {
     const FrameDesc& d = descs[f];
     if (i >= d.n) continue;
-    if (d.means != cur || d.scalars != cur_v || d.weights != cur_w) {
+    if (d.means != cur || d.scalars != cur_v || d.weights != cur_w || d.normals != cur_n) {
       load_params(d, i, g);
       cur = d.means;
       cur_v = d.scalars;
       cur_w = d.weights;
+      cur_n = d.normals;
     }
     const uint32_t pid = d.pair_base + (uint32_t)i;
-    bool keep = g.finite && g.n2 >= 1e-24f;
+    bool keep = g.finite && g.n2 >= 1e-24f && g.nn2 >= 1e-24f;
     TfSample tf;
     tf_lookup(d, keep ? g.v : 0.0f, tf);
     const float A = tf.O * g.w;
@@ -251,10 +297,15 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
     const float c0 = p.S11 / p.det, c1 = -p.S01 / p.det, c2 = p.S00 / p.det;
     const float mxr = (float)(p.mx - 16.0 * (double)x0);
     const float myr = (float)(p.my - 16.0 * (double)y0);
+    float rgb[3] = {tf.rgb[0], tf.rgb[1], tf.rgb[2]};
+    if (g.lit) {
+      Lit L;
+      shade(d, g, tf.rgb, rgb, L);
+    }
     float4* r = rec + 3 * (size_t)pid;
     r[0] = make_float4(mxr, myr, c0, c1);
-    r[1] = make_float4(c2, A, tf.rgb[0], tf.rgb[1]);
-    r[2] = make_float4(tf.rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
+    r[1] = make_float4(c2, A, rgb[0], rgb[1]);
+    r[2] = make_float4(rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
                        __uint_as_float((uint32_t)f));
   }
 }
@@ -263,17 +314,15 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
 // model), accumulate in registers, add once to the parameter gradients.
 __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __restrict__ descs, int n_frames,
                                                           int n, KOpts o, const float* __restrict__ g2d,
-                                                          uint32_t n_pairs, float* __restrict__ d_means,
-                                                          float* __restrict__ d_ls, float* __restrict__ d_quats,
-                                                          float* __restrict__ d_scalars,
-                                                          float* __restrict__ d_weights) {
+                                                          uint32_t n_pairs, veg_grads gr) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   GParams g;
   load_params(descs[0], i, g);
-  if (!g.finite || !(g.n2 >= 1e-24f)) return;
+  if (!g.finite || !(g.n2 >= 1e-24f) || !(g.nn2 >= 1e-24f)) return;
   float dmu[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ds[3] = {0, 0, 0};
   float dv = 0.0f, dw = 0.0f;
+  float dn[3] = {0, 0, 0}, dka = 0.0f, dkd = 0.0f, dks = 0.0f, dbeta = 0.0f;
   for (int f = 0; f < n_frames; ++f) {
     const FrameDesc& d = descs[f];
     const size_t pid = (size_t)d.pair_base + (size_t)i;
@@ -290,8 +339,38 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __res
     tf_lookup(d, g.v, tf);
     const float dmx = gg[0], dmy = gg[1], dc0 = gg[2], dc1 = gg[3], dc2 = gg[4];
     const float dA = gg[8];
-    // transfer function: A = O w, rgb = C(v)
-    dv += (dA * g.w) * tf.slope[3] + gg[5] * tf.slope[0] + gg[6] * tf.slope[1] + gg[7] * tf.slope[2];
+    // lighting: rgb = C (k_a + k_d s) + k_s s^beta, s = |n^ . l|, l = (mu - campos) / |.|
+    float dC[3] = {gg[5], gg[6], gg[7]};
+    if (g.lit) {
+      float rgb[3];
+      Lit L;
+      shade(d, g, tf.rgb, rgb, L);
+      const float P = (gg[5] * tf.rgb[0] + gg[6] * tf.rgb[1]) + gg[7] * tf.rgb[2];
+      const float D = (gg[5] + gg[6]) + gg[7];
+      for (int c = 0; c < 3; ++c) dC[c] = gg[5 + c] * L.f;
+      dka += P;
+      dkd += P * L.s;
+      float dsv = g.kd * P;
+      if (L.sb > 0.0f) {
+        dks += D * L.sb;
+        dbeta += D * g.ks * L.sb * log32(L.s);
+        dsv += D * g.ks * g.beta * L.sb / L.s;
+      }
+      const float du = L.u > 0.0f ? dsv : (L.u < 0.0f ? -dsv : 0.0f);
+      float dnh[3], dl[3];
+      for (int k = 0; k < 3; ++k) {
+        dnh[k] = du * L.l[k];
+        dl[k] = du * g.nh[k];
+      }
+      const float dotn = (dnh[0] * g.nh[0] + dnh[1] * g.nh[1]) + dnh[2] * g.nh[2];
+      const float dotl = (dl[0] * L.l[0] + dl[1] * L.l[1]) + dl[2] * L.l[2];
+      for (int k = 0; k < 3; ++k) {
+        dn[k] += (dnh[k] - g.nh[k] * dotn) * g.ninv;
+        dmu[k] += (dl[k] - L.l[k] * dotl) * L.dinv;
+      }
+    }
+    // transfer function: A = O w, C = C(v)
+    dv += (dA * g.w) * tf.slope[3] + dC[0] * tf.slope[0] + dC[1] * tf.slope[1] + dC[2] * tf.slope[2];
     dw += dA * tf.O;
     // projected centre
     const float tz = p.depth;
@@ -361,12 +440,19 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __res
            2 * x * dR[6] + 2 * y * dR[7];
   const float dot = dqh[0] * w + dqh[1] * x + dqh[2] * y + dqh[3] * z;
   for (int k = 0; k < 3; ++k) {
-    d_means[3 * (size_t)i + k] += dmu[k];
-    d_ls[3 * (size_t)i + k] += ds[k] * g.s[k];
+    gr.d_means[3 * (size_t)i + k] += dmu[k];
+    gr.d_log_scales[3 * (size_t)i + k] += ds[k] * g.s[k];
   }
-  for (int k = 0; k < 4; ++k) d_quats[4 * (size_t)i + k] += (dqh[k] - g.qh[k] * dot) * g.inv;
-  d_scalars[i] += dv;
-  if (d_weights) d_weights[i] += dw;
+  for (int k = 0; k < 4; ++k) gr.d_quats[4 * (size_t)i + k] += (dqh[k] - g.qh[k] * dot) * g.inv;
+  gr.d_scalars[i] += dv;
+  if (gr.d_weights) gr.d_weights[i] += dw;
+  if (gr.d_normals) {
+    for (int k = 0; k < 3; ++k) gr.d_normals[3 * (size_t)i + k] += dn[k];
+    gr.d_k_ambient[i] += dka;
+    gr.d_k_diffuse[i] += dkd;
+    gr.d_k_specular[i] += dks;
+    gr.d_shininess[i] += dbeta;
+  }
 }
 
 __global__ void debug_math_kernel(int op, const float* x, const float* y, float* out, int64_t n) {
@@ -413,11 +499,10 @@ hipError_t launch_project(const FrameDesc* descs, int n_frames, int n_max, const
 }
 
 hipError_t launch_project_bwd(const FrameDesc* descs, int n_frames, int n, const KOpts& o, const float* g2d,
-                              uint32_t n_pairs, float* d_means, float* d_ls, float* d_quats, float* d_scalars,
-                              float* d_weights, hipStream_t stream) {
+                              uint32_t n_pairs, const veg_grads& grads, hipStream_t stream) {
   if (n <= 0 || n_frames <= 0) return hipSuccess;
   hipLaunchKernelGGL(project_bwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, descs, n_frames, n, o, g2d,
-                     n_pairs, d_means, d_ls, d_quats, d_scalars, d_weights);
+                     n_pairs, grads);
   return hipGetLastError();
 }
 

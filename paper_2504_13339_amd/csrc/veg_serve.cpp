@@ -241,6 +241,7 @@ veg_status launch_batch(veg_server* s, Slot& sl, const std::vector<uint64_t>& id
     d.quats = g.quats;
     d.scalars = g.scalars;
     d.weights = g.weights;
+    set_lighting(d, g, q.r.camera);
     d.lut = sl.d_luts + (size_t)f * c.max_tf_k * 4;
     d.out_image = q.r.out_image;
     d.out_tfinal = q.r.out_t_final;

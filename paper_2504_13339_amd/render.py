@@ -110,6 +110,11 @@ class Grads:
     d_quats: torch.Tensor
     d_scalars: torch.Tensor
     d_weights: Optional[torch.Tensor] = None
+    d_normals: Optional[torch.Tensor] = None
+    d_k_ambient: Optional[torch.Tensor] = None
+    d_k_diffuse: Optional[torch.Tensor] = None
+    d_k_specular: Optional[torch.Tensor] = None
+    d_shininess: Optional[torch.Tensor] = None
 
     @staticmethod
     def zeros(g: V.Gaussians, stream=None) -> "Grads":
@@ -118,10 +123,19 @@ class Grads:
             V.veg_fill_u32(t, 0, stream=stream)
             return t
         n = g.n
-        return Grads(z((n, 3)), z((n, 3)), z((n, 4)), z((n,)), z((n,)) if g.weights is not None else None)
+        lit = {} if not g.lit else dict(d_normals=z((n, 3)), d_k_ambient=z((n,)), d_k_diffuse=z((n,)),
+                                        d_k_specular=z((n,)), d_shininess=z((n,)))
+        return Grads(z((n, 3)), z((n, 3)), z((n, 4)), z((n,)), z((n,)) if g.weights is not None else None, **lit)
+
+    @property
+    def lighting(self):
+        if self.d_normals is None:
+            return None
+        return (self.d_normals, self.d_k_ambient, self.d_k_diffuse, self.d_k_specular, self.d_shininess)
 
     def zero_(self, stream=None):
-        for t in (self.d_means, self.d_log_scales, self.d_quats, self.d_scalars, self.d_weights):
+        for t in (self.d_means, self.d_log_scales, self.d_quats, self.d_scalars, self.d_weights) + \
+                (self.lighting or ()):
             if t is not None:
                 V.veg_fill_u32(t, 0, stream=stream)
 
@@ -142,35 +156,41 @@ def render_backward(g: V.Gaussians, st: FwdState, d_image: torch.Tensor, grads: 
         V.veg_render_bwd(st.proj, st.bins, st.opts, st.t_final, st.n_last, d_image.contiguous(), g2d, stream=stream)
     with timer("project_bwd"):
         V.veg_project_bwd(g, st.proj, st.opts, g2d, grads.d_means, grads.d_log_scales, grads.d_quats,
-                          grads.d_scalars, grads.d_weights, stream=stream)
+                          grads.d_scalars, grads.d_weights, stream=stream, d_lighting=grads.lighting)
     return g2d
 
 
 class VEGRender(torch.autograd.Function):
-    """image[F,3,H,W] = render(means, log_scales, quats, scalars, weights; cams, tfs).
+    """image[F,3,H,W] = render(means, log_scales, quats, scalars, weights[, lighting]; cams, tfs).
 
-    ``scalars`` and ``weights`` are the activated values (apply the sigmoid before)."""
+    ``scalars``, ``weights`` and the lighting coefficients are the activated values (apply
+    the sigmoid or other activation before).  ``lighting`` is None or the tuple (normals,
+    k_ambient, k_diffuse, k_specular, shininess)."""
 
     @staticmethod
-    def forward(ctx, means, log_scales, quats, scalars, weights, cams, tfs, opts):
-        g = V.Gaussians(means.detach().contiguous(), log_scales.detach().contiguous(), quats.detach().contiguous(),
-                        scalars.detach().contiguous(), None if weights is None else weights.detach().contiguous())
+    def forward(ctx, means, log_scales, quats, scalars, weights, cams, tfs, opts, *lighting):
+        def c(t):
+            return None if t is None else t.detach().contiguous()
+        lit = dict(zip(V.LIGHTING, (c(t) for t in lighting))) if lighting else {}
+        g = V.Gaussians(c(means), c(log_scales), c(quats), c(scalars), c(weights), **lit)
         st = render(g, cams, tfs, opts)
         ctx.g = g
         ctx.st = st
         ctx.has_w = weights is not None
+        ctx.n_lit = len(lighting)
         return st.image
 
     @staticmethod
     def backward(ctx, d_image):
         grads = Grads.zeros(ctx.g)
         render_backward(ctx.g, ctx.st, d_image.contiguous(), grads)
+        lit = grads.lighting if ctx.n_lit else ()
         return (grads.d_means, grads.d_log_scales, grads.d_quats, grads.d_scalars,
-                grads.d_weights if ctx.has_w else None, None, None, None)
+                grads.d_weights if ctx.has_w else None, None, None, None) + tuple(lit)
 
 
-def render_autograd(means, log_scales, quats, scalars, weights, cams, tfs, opts=None):
-    return VEGRender.apply(means, log_scales, quats, scalars, weights, cams, tfs, opts)
+def render_autograd(means, log_scales, quats, scalars, weights, cams, tfs, opts=None, lighting=None):
+    return VEGRender.apply(means, log_scales, quats, scalars, weights, cams, tfs, opts, *(lighting or ()))
 
 
 @dataclass

@@ -37,32 +37,48 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr())
 
 
+LIGHTING = ("normals", "k_ambient", "k_diffuse", "k_specular", "shininess")
+
+
 @dataclass
 class Gaussians:
-    """Device SoA model: means [n,3], log_scales [n,3], quats [n,4], scalars [n], weights [n] or None."""
+    """Device SoA model: means [n,3], log_scales [n,3], quats [n,4], scalars [n], weights [n]
+    or None, and optionally the lighting attributes normals [n,3], k_ambient, k_diffuse,
+    k_specular, shininess [n] (all or none)."""
     means: torch.Tensor
     log_scales: torch.Tensor
     quats: torch.Tensor
     scalars: torch.Tensor
     weights: Optional[torch.Tensor] = None
+    normals: Optional[torch.Tensor] = None
+    k_ambient: Optional[torch.Tensor] = None
+    k_diffuse: Optional[torch.Tensor] = None
+    k_specular: Optional[torch.Tensor] = None
+    shininess: Optional[torch.Tensor] = None
 
     @property
     def n(self) -> int:
         return int(self.means.shape[0])
 
+    @property
+    def lit(self) -> bool:
+        return self.normals is not None
+
     def struct(self) -> _lib.veg_gaussians:
-        for name in ("means", "log_scales", "quats", "scalars", "weights"):
+        for name in ("means", "log_scales", "quats", "scalars", "weights") + LIGHTING:
             t = getattr(self, name)
             if t is not None and t.dtype != torch.float32:
                 raise ValueError(f"{name} must be float32")
         return _lib.veg_gaussians(self.n, _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats),
-                                  _ptr(self.scalars), _ptr(self.weights))
+                                  _ptr(self.scalars), _ptr(self.weights), *(_ptr(getattr(self, k)) for k in LIGHTING))
 
     @staticmethod
     def from_numpy(g, device="cuda") -> "Gaussians":
         def t(a):
             return None if a is None else torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
-        return Gaussians(t(g.means), t(g.log_scales), t(g.quats), t(g.scalars), t(getattr(g, "weights", None)))
+        sh = getattr(g, "shading", None)
+        lit = {} if sh is None else {k: t(getattr(sh, k)) for k in LIGHTING}
+        return Gaussians(t(g.means), t(g.log_scales), t(g.quats), t(g.scalars), t(getattr(g, "weights", None)), **lit)
 
 
 def default_opts() -> _lib.veg_opts:
@@ -213,10 +229,13 @@ def veg_render_bwd(proj: Proj, bins: Bins, opts, t_final: torch.Tensor, n_last: 
 
 
 def veg_project_bwd(g: Gaussians, proj: Proj, opts, g2d: torch.Tensor, d_means, d_log_scales, d_quats, d_scalars,
-                    d_weights=None, stream=None):
+                    d_weights=None, stream=None, d_lighting=None):
+    """``d_lighting``: None or (d_normals, d_k_ambient, d_k_diffuse, d_k_specular, d_shininess)."""
     o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
     gs = g.struct()
-    gr = _lib.veg_grads(_ptr(d_means), _ptr(d_log_scales), _ptr(d_quats), _ptr(d_scalars), _ptr(d_weights))
+    lg = (None,) * 5 if d_lighting is None else tuple(d_lighting)
+    gr = _lib.veg_grads(_ptr(d_means), _ptr(d_log_scales), _ptr(d_quats), _ptr(d_scalars), _ptr(d_weights),
+                        *(_ptr(t) for t in lg))
     check(load().veg_project_bwd(ctypes.byref(gs), ctypes.byref(proj.struct), ctypes.byref(o), _ptr(g2d),
                                  ctypes.byref(gr), stream_handle(stream)), "veg_project_bwd")
 
