@@ -171,6 +171,7 @@ def serve_bench(rates, n_per_rate, max_batch=8, n_streams=3, use_graphs=True):
                 "max_batch": max_batch, "streams": n_streams, "graphs": bool(use_graphs), "rates": {}}
     srv = Server(max_gaussians=max(m.n for m in models), max_entries=64_000_000, max_batch=max_batch,
                  n_streams=n_streams, use_graphs=use_graphs, max_width=1920, max_height=1080, max_tf_k=256)
+    results["arena_gb"] = round(srv.arena_bytes / 1e9, 2)
     mids = [srv.add_model(m) for m in models]
     ring = {}
 
@@ -236,14 +237,16 @@ def serve_bench(rates, n_per_rate, max_batch=8, n_streams=3, use_graphs=True):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--group", type=int, default=16, help="frames per recompute group")
     ap.add_argument("--n", type=int, default=None, help="override Gaussian count (testing only)")
     ap.add_argument("--views", type=int, default=None)
     ap.add_argument("--tfs", type=int, default=None)
     ap.add_argument("--res", type=int, default=None)
     ap.add_argument("--cpu-pixels", type=int, default=640)
+    ap.add_argument("--lit-steps", type=int, default=5,
+                    help="timed steps of the same workload with lighting attributes (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s); '' to skip")
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -264,6 +267,7 @@ def main():
               "(frames would be split across GPUs with one gradient all-reduce; not built)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2504_13339_amd import render as R
 
@@ -297,10 +301,14 @@ def main():
     timer = R.EventTimer()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for k in range(args.steps):
+        ts = time.perf_counter()
         res = R.train_step_l1(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, loss_acc=loss_acc,
-                              timer=timer)
-        log(f"bench: step {k} loss {res.loss:.6f}")
+                              timer=timer)   # reading the loss ends the step on the host
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        if k % 10 == 0 or k == args.steps - 1:
+            log(f"bench: step {k} loss {res.loss:.6f}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
@@ -320,6 +328,24 @@ def main():
             del st
     torch.cuda.synchronize()
     fwd_mpix = F * H * W * args.steps / (time.perf_counter() - t1) / 1e6
+
+    # the same training step with Blinn-Phong lighting attributes on every Gaussian
+    lit_mpix = None
+    if args.lit_steps > 0:
+        import synth
+        from paper_2504_13339_amd import veg as V
+        sh = synth.random_shading(synth.rng_for(2, 90), w.gaussians.n)
+        gl = V.Gaussians(g.means, g.log_scales, g.quats, g.scalars, g.weights,
+                         **{k: torch.as_tensor(getattr(sh, k)).cuda() for k in V.LIGHTING})
+        grads_l = R.Grads.zeros(gl)
+        R.train_step_l1(gl, w.cameras, luts, w.frames, targets, grads_l, args.group, w.opts, loss_acc=loss_acc)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for k in range(args.lit_steps):
+            R.train_step_l1(gl, w.cameras, luts, w.frames, targets, grads_l, args.group, w.opts, loss_acc=loss_acc)
+        torch.cuda.synchronize()
+        lit_mpix = F * H * W * args.lit_steps / (time.perf_counter() - t2) / 1e6
+        del grads_l, gl
 
     # roofline of the dominant kernel (blend forward or backward: VALU-bound)
     def blend_roof(name):
@@ -341,10 +367,12 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "step_ms_p10_p50_p90": [round(float(x), 3) for x in np.percentile(step_ms, [10, 50, 90])],
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "gaussians": w.gaussians.n, "frames": F, "width": W, "height": H,
                    "group": args.group},
         "fwd_mpix_s": round(fwd_mpix, 2),
+        "lit_mpix_s": None if lit_mpix is None else round(lit_mpix, 2),
         "geval_s": {"fwd": round(counts["fwd"] * args.steps / dt / 1e9, 3),
                     "bwd": round(counts["bwd"] * args.steps / dt / 1e9, 3)},
         "kernel_ms_per_step": {k: round(v, 3) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
