@@ -31,6 +31,10 @@ Three parts:
   decide differently).
 * O3 ``gradients`` -- the gradient of a linear functional of O2's image, by torch
   autograd in float64 on the CPU.
+* The training-loop neighbours of section "Training": ``ssim_map`` / ``ssim_loss`` (the
+  SSIM term of the image loss, Gaussian 11-tap window, float64, gradient by autograd),
+  ``adam_step`` (the optimizer update) and ``densify_stats`` (per-Gaussian accumulated
+  screen-space gradient norm and visibility count that drive densification).
 
 Readings where the paper is silent (tile size, thresholds, footprint rule, low-pass,
 guard band, near plane, stop semantics, knot derivative, light direction) follow the
@@ -51,7 +55,8 @@ import torch
 __all__ = [
     "TILE", "QNORM2_MIN", "exp32", "log32", "footprint_f32", "key_list", "project_f64",
     "render_pixels", "render_image", "gradients", "quat_to_rot_f64", "OracleProjection",
-    "depth_order", "frame_pairs",
+    "depth_order", "frame_pairs", "ssim_window_1d", "ssim_map", "ssim_loss", "adam_step", "densify_stats",
+    "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA",
 ]
 
 TILE = 16
@@ -616,3 +621,81 @@ def gradients(g, cam, lut, opts, d_color, pixels=None, bg=None, batch: int = 0) 
                        **({} if sh is None else dict(d_normals=gnp(sh[0]), d_k_ambient=gnp(sh[1]),
                                                      d_k_diffuse=gnp(sh[2]), d_k_specular=gnp(sh[3]),
                                                      d_shininess=gnp(sh[4]))))
+
+
+# ---------------------------------------------------------------------------------------
+# Training-loop neighbours (section "Training"): SSIM loss, Adam, densification statistics
+# ---------------------------------------------------------------------------------------
+
+SSIM_WINDOW = 11
+SSIM_SIGMA = 1.5
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window_1d(size: int = SSIM_WINDOW, sigma: float = SSIM_SIGMA) -> np.ndarray:
+    """Normalised 1D Gaussian taps of the SSIM window (Wang et al.; the 2D window is the
+    outer product)."""
+    x = np.arange(size, dtype=np.float64) - (size - 1) / 2.0
+    g = np.exp(-(x * x) / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def ssim_map(img, ref):
+    """Per-pixel SSIM of two images [P, H, W] (P independent planes, e.g. frames x
+    channels), float64 torch: local means, variances and covariance under the Gaussian
+    window, zero outside the image ("same" size),
+        S = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2)),
+    C1 = 0.01^2, C2 = 0.03^2 (data range 1)."""
+    x = img if torch.is_tensor(img) else torch.as_tensor(np.asarray(img, np.float64))
+    y = ref if torch.is_tensor(ref) else torch.as_tensor(np.asarray(ref, np.float64))
+    x = x.to(torch.float64)[:, None]
+    y = y.to(torch.float64)[:, None]
+    g = torch.as_tensor(ssim_window_1d())
+    w2 = (g[:, None] * g[None, :])[None, None]
+    pad = SSIM_WINDOW // 2
+
+    def blur(t):
+        return torch.nn.functional.conv2d(t, w2, padding=pad)
+    mx, my = blur(x), blur(y)
+    sxx = blur(x * x) - mx * mx
+    syy = blur(y * y) - my * my
+    sxy = blur(x * y) - mx * my
+    s = ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+    return s[:, 0]
+
+
+def ssim_loss(img, ref, weight: float):
+    """weight * sum over planes and pixels of (1 - SSIM) and its gradient w.r.t. img
+    (float64 autograd).  Returns (loss, d_img as numpy)."""
+    x = torch.tensor(np.asarray(img, np.float64), requires_grad=True)
+    L = weight * (1.0 - ssim_map(x, ref)).sum()
+    L.backward()
+    return float(L.detach()), x.grad.numpy().copy()
+
+
+def adam_step(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15):
+    """One Adam update (Kingma & Ba) in float64, in place on copies; ``step`` counts from 1:
+        m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
+        p <- p - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+    Returns (p, m, v)."""
+    p = np.asarray(p, np.float64).copy()
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
+    mh = m / (1 - beta1 ** step)
+    vh = v / (1 - beta2 ** step)
+    p -= lr * mh / (np.sqrt(vh) + eps)
+    return p, m, v
+
+
+def densify_stats(g2d_frames, kept_frames):
+    """Densification statistics over a group of frames (the adaptive density control of the
+    3DGS-style training the paper follows): per Gaussian, the sum over the frames in which
+    it was kept of the norm of the gradient w.r.t. its projected centre, and the number of
+    those frames.  g2d_frames: [F, n, 9] screen-space gradients (d mx, d my first);
+    kept_frames: [F, n] bool."""
+    g = np.asarray(g2d_frames, np.float64)
+    k = np.asarray(kept_frames, bool)
+    norm = np.sqrt(g[..., 0] ** 2 + g[..., 1] ** 2)
+    return (norm * k).sum(0), k.sum(0).astype(np.int64)

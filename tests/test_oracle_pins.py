@@ -538,3 +538,89 @@ def test_shading_gradients_match_central_finite_differences():
         for idx in flat[:: max(1, len(flat) // 12)]:
             num = fd(field, idx)
             assert abs(num - grad[idx]) <= 1e-6 * scale + 1e-9, (field, idx, num, grad[idx])
+
+
+# ----------------------------------------------------------------------------- training-loop neighbours
+
+def test_ssim_of_an_image_with_itself_is_one_and_has_zero_gradient():
+    rng = np.random.default_rng(50)
+    x = rng.uniform(0, 1, (3, 20, 24))
+    s = oracle.ssim_map(x, x).numpy()
+    assert np.abs(s - 1.0).max() < 1e-12
+    loss, grad = oracle.ssim_loss(x, x, 0.7)
+    assert abs(loss) < 1e-10 and np.abs(grad).max() < 1e-10
+
+
+def test_ssim_of_constant_images_in_the_interior():
+    """Away from the border (5 px) the windowed mean of a constant image a is a and both
+    variances and the covariance vanish, so SSIM = (2ab + C1) / (a^2 + b^2 + C1)."""
+    a, b = 0.3, 0.7
+    s = oracle.ssim_map(np.full((1, 16, 18), a), np.full((1, 16, 18), b)).numpy()[0]
+    want = (2 * a * b + oracle.SSIM_C1) / (a * a + b * b + oracle.SSIM_C1)
+    assert np.abs(s[5:-5, 5:-5] - want).max() < 1e-12
+    assert np.abs(s[0, 0] - want) > 1e-3          # zero padding shows at the border
+
+
+def test_ssim_map_matches_a_brute_force_window_sum():
+    rng = np.random.default_rng(51)
+    x, y = rng.uniform(0, 1, (1, 9, 8)), rng.uniform(0, 1, (1, 9, 8))
+    g = oracle.ssim_window_1d()
+    assert abs(g.sum() - 1.0) < 1e-15
+    H, W = x.shape[1:]
+    ref = np.zeros((H, W))
+    for i in range(H):
+        for j in range(W):
+            acc = np.zeros(5)
+            for u in range(11):
+                for v in range(11):
+                    ii, jj = i + u - 5, j + v - 5
+                    if 0 <= ii < H and 0 <= jj < W:
+                        wgt = g[u] * g[v]
+                        a, b = x[0, ii, jj], y[0, ii, jj]
+                        acc += wgt * np.array([a, b, a * a, b * b, a * b])
+            mx, my, ex2, ey2, exy = acc
+            sx, sy, sxy = ex2 - mx * mx, ey2 - my * my, exy - mx * my
+            ref[i, j] = ((2 * mx * my + 1e-4) * (2 * sxy + 9e-4)) / ((mx * mx + my * my + 1e-4) * (sx + sy + 9e-4))
+    assert np.abs(oracle.ssim_map(x, y).numpy()[0] - ref).max() < 1e-12
+
+
+def test_ssim_loss_gradient_matches_central_differences():
+    rng = np.random.default_rng(52)
+    x, y = rng.uniform(0.1, 0.9, (2, 12, 13)), rng.uniform(0.1, 0.9, (2, 12, 13))
+    loss, grad = oracle.ssim_loss(x, y, 0.25)
+    for idx in [(0, 0, 0), (0, 6, 7), (1, 11, 12), (1, 3, 9), (0, 11, 0)]:
+        h = 1e-6
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        num = (oracle.ssim_loss(xp, y, 0.25)[0] - oracle.ssim_loss(xm, y, 0.25)[0]) / (2 * h)
+        assert abs(num - grad[idx]) <= 1e-7 * max(1.0, abs(grad[idx])), (idx, num, grad[idx])
+
+
+def test_adam_closed_forms():
+    """Bias correction makes the first update lr * g / (|g| + eps) for any beta; with a
+    constant gradient m^ = g and v^ = g^2 at every step, so each step moves by the same
+    amount; with beta1 = beta2 = 0 Adam is sign descent."""
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    p0 = np.array([1.0, 2.0, 3.0, 4.0])
+    lr, eps = 0.01, 1e-15
+    p1, m, v = oracle.adam_step(p0, g, np.zeros(4), np.zeros(4), 1, lr, eps=eps)
+    assert np.allclose(p1, p0 - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+    p = p0
+    m = v = np.zeros(4)
+    for t in range(1, 6):
+        p, m, v = oracle.adam_step(p, g, m, v, t, lr, eps=eps)
+    assert np.allclose(p, p0 - 5 * lr * np.sign(g), rtol=0, atol=1e-12)
+    q, _, _ = oracle.adam_step(p0, g, np.ones(4), np.ones(4), 7, lr, beta1=0.0, beta2=0.0, eps=eps)
+    assert np.allclose(q, p0 - lr * np.sign(g), rtol=0, atol=1e-12)
+
+
+def test_densify_stats_of_a_constructed_gradient():
+    g2d = np.zeros((2, 3, 9))
+    g2d[0, 0, :2] = (3.0, 4.0)
+    g2d[1, 0, :2] = (-6.0, 8.0)
+    g2d[0, 1, :2] = (1.0, 0.0)
+    g2d[1, 2, :2] = (5.0, 12.0)
+    kept = np.array([[True, True, False], [True, False, False]])
+    acc, cnt = oracle.densify_stats(g2d, kept)
+    assert np.allclose(acc, [15.0, 1.0, 0.0]) and list(cnt) == [2, 1, 0]
