@@ -331,7 +331,7 @@ veg_status veg_project_bwd(const veg_gaussians* g, const veg_proj* proj, const v
  * ---------------------------------------------------------------------------------- */
 
 /* veg_l1_loss -- the L1 part of the training loss (section "Training": (1-lambda) L1 +
- * lambda SSIM; SSIM is not in this ABI):
+ * lambda SSIM; the SSIM part is veg_ssim_loss):
  *   loss   += scale * sum |image - target|            (device double, ACCUMULATED)
  *   d_image =  scale * sign(image - target)           (device float, overwritten;
  *                                                      sign(0) = 0)
@@ -339,6 +339,39 @@ veg_status veg_project_bwd(const veg_gaussians* g, const veg_proj* proj, const v
  * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
 veg_status veg_l1_loss(const float* image, const float* target, int64_t count, float scale,
                        double* loss, float* d_image, veg_stream_t stream);
+
+/* veg_ssim_loss -- the SSIM part of the training loss (section "Training"; SSIM of Wang et
+ * al. with the usual 11-tap Gaussian window, sigma 1.5, zeros outside the image,
+ * C1 = 0.01^2, C2 = 0.03^2 for a data range of 1):
+ *   loss    += weight * sum over planes and pixels of (1 - SSIM)   (device double)
+ *   d_image += weight * d/dimage of that sum                       (device float, ADDED,
+ *              so that it follows veg_l1_loss, which overwrites d_image)
+ *   image, target  device [n_planes, height, width] float (e.g. frames x colour channels)
+ *   ws, ws_bytes   device scratch >= veg_ssim_workspace_bytes(n_planes, width, height)
+ * Errors: VEG_ERR_INVALID_ARG (sizes, NULLs, n_planes > 65535, small workspace), VEG_ERR_HIP. */
+size_t veg_ssim_workspace_bytes(int64_t n_planes, int32_t width, int32_t height);
+veg_status veg_ssim_loss(const float* image, const float* target, int64_t n_planes, int32_t width,
+                         int32_t height, float weight, double* loss, float* d_image, void* ws,
+                         size_t ws_bytes, veg_stream_t stream);
+
+/* veg_adam_step -- one Adam update of a parameter array (the optimizer of section
+ * "Training"; Kingma & Ba):  m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
+ *   param <- param - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ *   param, m, v  device [count] float, updated in place; grad device [count] float
+ *   step         1 for the first update
+ * Errors: VEG_ERR_INVALID_ARG (NULLs, count < 0, step < 1, lr or betas out of range), VEG_ERR_HIP. */
+veg_status veg_adam_step(float* param, const float* grad, float* m, float* v, int64_t count, float lr,
+                         float beta1, float beta2, float eps, int32_t step, veg_stream_t stream);
+
+/* veg_densify_stats -- statistics for the adaptive density control (section "Training":
+ * gradients drive densification and pruning): for every Gaussian, over the frames of
+ * `proj` in which it was kept, the norm of dL/d(projected centre) in pixels taken from
+ * g2d, and the number of such frames.
+ *   grad_accum  device [n] float, ADDED
+ *   vis_count   device [n] int32, ADDED
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+veg_status veg_densify_stats(const veg_proj* proj, const float* g2d, float* grad_accum, int32_t* vis_count,
+                             veg_stream_t stream);
 
 /* Fills `count` 32-bit words at device pointer `dst` with `value` (a kernel, so it is
  * safe inside captured graphs). */

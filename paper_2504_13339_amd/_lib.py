@@ -99,6 +99,12 @@ _SIGS = {
     "veg_project_bwd": (c_int, [P(veg_gaussians), P(veg_proj), P(veg_opts), c_void_p, P(veg_grads), c_void_p]),
     "veg_l1_loss": (c_int, [c_void_p, c_void_p, c_int64, c_float, c_void_p, c_void_p, c_void_p]),
     "veg_fill_u32": (c_int, [c_void_p, c_int64, c_uint32, c_void_p]),
+    "veg_ssim_workspace_bytes": (c_size_t, [c_int64, c_int32, c_int32]),
+    "veg_ssim_loss": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_float, c_void_p, c_void_p, c_void_p,
+                              c_size_t, c_void_p]),
+    "veg_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_float, c_float, c_float, c_float,
+                              c_int32, c_void_p]),
+    "veg_densify_stats": (c_int, [P(veg_proj), c_void_p, c_void_p, c_void_p, c_void_p]),
     "veg_debug_math": (c_int, [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     "veg_serve_arena_bytes": (c_size_t, [P(veg_serve_config)]),
     "veg_serve_create": (c_int, [P(veg_serve_config), P(c_void_p)]),

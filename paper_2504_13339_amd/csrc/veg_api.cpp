@@ -378,6 +378,54 @@ veg_status veg_l1_loss(const float* image, const float* target, int64_t count, f
   return VEG_OK;
 }
 
+size_t veg_ssim_workspace_bytes(int64_t n_planes, int32_t width, int32_t height) {
+  if (n_planes < 0 || width < 0 || height < 0) return 0;
+  return 3 * sizeof(float) * (size_t)n_planes * (size_t)width * (size_t)height;
+}
+
+veg_status veg_ssim_loss(const float* image, const float* target, int64_t n_planes, int32_t width, int32_t height,
+                         float weight, double* loss, float* d_image, void* ws, size_t ws_bytes, veg_stream_t stream) {
+  g_err.clear();
+  if (n_planes < 0 || width < 0 || height < 0 || width > VEG_MAX_DIM || height > VEG_MAX_DIM || n_planes > 65535)
+    return fail(VEG_ERR_INVALID_ARG, "ssim_loss: sizes out of range");
+  if (n_planes == 0 || width == 0 || height == 0) return VEG_OK;
+  if (!image || !target || !loss || !d_image || !ws) return fail(VEG_ERR_INVALID_ARG, "ssim_loss: NULL argument");
+  if (ws_bytes < veg_ssim_workspace_bytes(n_planes, width, height))
+    return fail(VEG_ERR_INVALID_ARG, "ssim_loss: workspace smaller than veg_ssim_workspace_bytes");
+  if (!std::isfinite(weight)) return fail(VEG_ERR_INVALID_ARG, "ssim_loss: weight must be finite");
+  VEG_CHECK_HIP(launch_ssim(image, target, n_planes, width, height, weight, loss, d_image, (float*)ws,
+                            (hipStream_t)stream),
+                "veg_ssim_loss");
+  return VEG_OK;
+}
+
+veg_status veg_adam_step(float* param, const float* grad, float* m, float* v, int64_t count, float lr, float beta1,
+                         float beta2, float eps, int32_t step, veg_stream_t stream) {
+  g_err.clear();
+  if (count < 0 || step < 1) return fail(VEG_ERR_INVALID_ARG, "adam_step: count < 0 or step < 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f) || !std::isfinite(lr))
+    return fail(VEG_ERR_INVALID_ARG, "adam_step: need 0 <= beta < 1, eps >= 0, finite lr");
+  if (count == 0) return VEG_OK;
+  if (!param || !grad || !m || !v) return fail(VEG_ERR_INVALID_ARG, "adam_step: NULL argument");
+  const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  VEG_CHECK_HIP(launch_adam(param, grad, m, v, count, lr, beta1, beta2, eps, bc1, bc2, (hipStream_t)stream),
+                "veg_adam_step");
+  return VEG_OK;
+}
+
+veg_status veg_densify_stats(const veg_proj* proj, const float* g2d, float* grad_accum, int32_t* vis_count,
+                             veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  if (proj->n > 0 && (!g2d || !grad_accum || !vis_count)) return fail(VEG_ERR_INVALID_ARG, "densify_stats: NULL");
+  VEG_CHECK_HIP(launch_densify_stats((const FrameDesc*)proj->frames, proj->n_frames, (int)proj->n, proj->count, g2d,
+                                     grad_accum, vis_count, (hipStream_t)stream),
+                "veg_densify_stats");
+  return VEG_OK;
+}
+
 veg_status veg_fill_u32(void* dst, int64_t count, uint32_t value, veg_stream_t stream) {
   g_err.clear();
   if (count < 0 || (count > 0 && !dst)) return fail(VEG_ERR_INVALID_ARG, "fill: bad arguments");

@@ -1,0 +1,220 @@
+// Training-loop neighbours of the renderer (paper, section "Training"): the SSIM term of
+// the image loss (1 - lambda) L1 + lambda SSIM, the Adam update of the parameters, and the
+// per-Gaussian statistics that drive densification.
+#include "veg_internal.h"
+
+#include <cmath>
+
+#pragma clang fp contract(off)
+
+namespace veg {
+namespace {
+
+// SSIM window: 11 taps, Gaussian with sigma 1.5, normalised (the 2D window is the outer
+// product, so both passes use the same taps).  Constants for a data range of 1.
+constexpr int kWin = 11, kHalf = 5;
+constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
+constexpr int kTx = 32, kTy = 16;                       // output tile
+constexpr int kIx = kTx + 2 * kHalf, kIy = kTy + 2 * kHalf;   // input tile with halo
+
+struct Win {
+  float w[kWin];
+};
+
+// Input tile of one plane with zeros outside the image.
+__device__ __forceinline__ void load_tile(const float* __restrict__ src, int W, int H, int x0, int y0, float* dst) {
+  for (int k = threadIdx.x; k < kIx * kIy; k += blockDim.x) {
+    const int lx = k % kIx, ly = k / kIx;
+    const int gx = x0 - kHalf + lx, gy = y0 - kHalf + ly;
+    dst[k] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? src[(size_t)gy * W + gx] : 0.0f;
+  }
+}
+
+// Per tile: windowed means of x, y, x^2, y^2, x y (horizontal then vertical pass through
+// LDS), the SSIM map S and its partial derivatives with respect to mu_x, E[x^2] and E[x y]
+// at every pixel:
+//   N = (2 mu_x mu_y + C1)(2 s_xy + C2) = A1 A2,  D = (mu_x^2 + mu_y^2 + C1)(s_x + s_y + C2) = B1 B2,
+//   dS/dmu_x = (2 mu_y (A2 - A1) - 2 mu_x S (B2 - B1)) / D,  dS/dE[x^2] = -S B1 / D,
+//   dS/dE[xy] = 2 A1 / D.
+// The three maps are stored multiplied by dL/dS = -weight for the backward pass.
+__global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                       int W, int H, float weight, double* __restrict__ loss,
+                                                       float* __restrict__ dmaps, size_t plane_stride, Win win) {
+  __shared__ float s_x[kIx * kIy], s_y[kIx * kIy];
+  __shared__ float s_h[5][kIy * kTx];
+  __shared__ double s_part[4];
+  const int x0 = blockIdx.x * kTx, y0 = blockIdx.y * kTy;
+  const size_t plane = blockIdx.z;
+  const float* xs = img + plane * (size_t)W * H;
+  const float* ys = tgt + plane * (size_t)W * H;
+  load_tile(xs, W, H, x0, y0, s_x);
+  load_tile(ys, W, H, x0, y0, s_y);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kIy * kTx; k += blockDim.x) {
+    const int ox = k % kTx, ly = k / kTx;
+    float a[5] = {0, 0, 0, 0, 0};
+    for (int t = 0; t < kWin; ++t) {
+      const float wv = win.w[t];
+      const float xv = s_x[ly * kIx + ox + t], yv = s_y[ly * kIx + ox + t];
+      a[0] += wv * xv;
+      a[1] += wv * yv;
+      a[2] += wv * (xv * xv);
+      a[3] += wv * (yv * yv);
+      a[4] += wv * (xv * yv);
+    }
+    for (int c = 0; c < 5; ++c) s_h[c][k] = a[c];
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int k = threadIdx.x; k < kTx * kTy; k += blockDim.x) {
+    const int ox = k % kTx, oy = k / kTx;
+    const int gx = x0 + ox, gy = y0 + oy;
+    if (gx >= W || gy >= H) continue;
+    float m[5] = {0, 0, 0, 0, 0};
+    for (int t = 0; t < kWin; ++t) {
+      const float wv = win.w[t];
+      for (int c = 0; c < 5; ++c) m[c] += wv * s_h[c][(oy + t) * kTx + ox];
+    }
+    const float mx = m[0], my = m[1];
+    const float sx = m[2] - mx * mx, sy = m[3] - my * my, sxy = m[4] - mx * my;
+    const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * sxy + kC2;
+    const float B1 = mx * mx + my * my + kC1, B2 = sx + sy + kC2;
+    const float D = B1 * B2;
+    const float S = (A1 * A2) / D;
+    part += (double)(1.0f - S);
+    const float dmu = (2.0f * my * (A2 - A1) - 2.0f * mx * S * (B2 - B1)) / D;
+    const float dex2 = -S * B1 / D;
+    const float dexy = 2.0f * A1 / D;
+    const size_t pi = plane * (size_t)W * H + (size_t)gy * W + gx;
+    dmaps[pi] = -weight * dmu;
+    dmaps[plane_stride + pi] = -weight * dex2;
+    dmaps[2 * plane_stride + pi] = -weight * dexy;
+  }
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+    if (t != 0.0) unsafeAtomicAdd(loss, t * (double)weight);
+  }
+}
+
+// Adjoint: dL/dx = G * D_mu + 2 x (G * D_x2) + y (G * D_xy), the window applied to the maps
+// with zeros outside the image (the adjoint of the zero-padded forward window); added to
+// d_image.
+__global__ __launch_bounds__(256) void ssim_bwd_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                       int W, int H, const float* __restrict__ dmaps,
+                                                       size_t plane_stride, float* __restrict__ dimg, Win win) {
+  __shared__ float s_m[3][kIx * kIy];
+  __shared__ float s_h[3][kIy * kTx];
+  const int x0 = blockIdx.x * kTx, y0 = blockIdx.y * kTy;
+  const size_t plane = blockIdx.z;
+  for (int c = 0; c < 3; ++c) load_tile(dmaps + c * plane_stride + plane * (size_t)W * H, W, H, x0, y0, s_m[c]);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kIy * kTx; k += blockDim.x) {
+    const int ox = k % kTx, ly = k / kTx;
+    float a[3] = {0, 0, 0};
+    for (int t = 0; t < kWin; ++t) {
+      const float wv = win.w[t];
+      for (int c = 0; c < 3; ++c) a[c] += wv * s_m[c][ly * kIx + ox + t];
+    }
+    for (int c = 0; c < 3; ++c) s_h[c][k] = a[c];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kTx * kTy; k += blockDim.x) {
+    const int ox = k % kTx, oy = k / kTx;
+    const int gx = x0 + ox, gy = y0 + oy;
+    if (gx >= W || gy >= H) continue;
+    float m[3] = {0, 0, 0};
+    for (int t = 0; t < kWin; ++t) {
+      const float wv = win.w[t];
+      for (int c = 0; c < 3; ++c) m[c] += wv * s_h[c][(oy + t) * kTx + ox];
+    }
+    const size_t pi = plane * (size_t)W * H + (size_t)gy * W + gx;
+    dimg[pi] += (m[0] + 2.0f * img[pi] * m[1]) + tgt[pi] * m[2];
+  }
+}
+
+// Adam (Kingma & Ba): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+// p <- p - lr (m / bc1) / (sqrt(v / bc2) + eps) with bc = 1 - beta^t from the host.
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                                                   float b1, float b2, float eps, float bc1, float bc2) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+// Densification statistics: for every Gaussian, over the frames in which it was kept, the
+// norm of the gradient w.r.t. its projected centre and the count of such frames (added).
+__global__ __launch_bounds__(256) void densify_stats_kernel(const FrameDesc* __restrict__ descs, int n_frames, int n,
+                                                            const uint32_t* __restrict__ count,
+                                                            const float* __restrict__ g2d, float* __restrict__ acc,
+                                                            int32_t* __restrict__ vis) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float a = 0.0f;
+  int c = 0;
+  for (int f = 0; f < n_frames; ++f) {
+    const size_t pid = (size_t)descs[f].pair_base + (size_t)i;
+    if (count[pid] == 0u) continue;
+    const float gx = g2d[pid * 9 + 0], gy = g2d[pid * 9 + 1];
+    a += sqrtf(gx * gx + gy * gy);
+    ++c;
+  }
+  acc[i] += a;
+  vis[i] += c;
+}
+
+}  // namespace
+
+// The window taps: exp(-x^2 / (2 sigma^2)) at x = -5..5, sigma 1.5, divided by their sum.
+static Win ssim_window() {
+  Win w;
+  double s = 0.0, g[kWin];
+  for (int t = 0; t < kWin; ++t) {
+    const double x = (double)(t - kHalf);
+    g[t] = std::exp(-(x * x) / (2.0 * 1.5 * 1.5));
+    s += g[t];
+  }
+  for (int t = 0; t < kWin; ++t) w.w[t] = (float)(g[t] / s);
+  return w;
+}
+
+hipError_t launch_ssim(const float* image, const float* target, int64_t n_planes, int W, int H, float weight,
+                       double* loss, float* d_image, float* dmaps, hipStream_t stream) {
+  if (n_planes <= 0 || W <= 0 || H <= 0) return hipSuccess;
+  const size_t plane_stride = (size_t)n_planes * W * H;
+  const dim3 grid((W + kTx - 1) / kTx, (H + kTy - 1) / kTy, (unsigned)n_planes);
+  const Win win = ssim_window();
+  hipLaunchKernelGGL(ssim_fwd_kernel, grid, dim3(256), 0, stream, image, target, W, H, weight, loss, dmaps,
+                     plane_stride, win);
+  hipLaunchKernelGGL(ssim_bwd_kernel, grid, dim3(256), 0, stream, image, target, W, H, dmaps, plane_stride, d_image,
+                     win);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65535) blocks = 65535;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, g, m, v, n, lr, b1, b2, eps, bc1,
+                     bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float* g2d,
+                                float* acc, int32_t* vis, hipStream_t stream) {
+  if (n <= 0 || n_frames <= 0) return hipSuccess;
+  hipLaunchKernelGGL(densify_stats_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, descs, n_frames, n, count,
+                     g2d, acc, vis);
+  return hipGetLastError();
+}
+
+}  // namespace veg

@@ -199,36 +199,92 @@ class StepResult:
     n_entries: List[int]
 
 
-def train_step_l1(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], frames: Sequence[tuple],
-                  targets: torch.Tensor, grads: Grads, group: int, opts=None, stream=None,
-                  loss_acc: Optional[torch.Tensor] = None, read_loss: bool = True, timer=NO_TIMER,
-                  on_group=None, want_contrib: bool = False) -> StepResult:
-    """One multi-view x multi-TF training step with L1 loss (mean over all frames).
+@dataclass
+class DensifyStats:
+    """Per-Gaussian accumulators for densification and pruning: the summed norm of
+    dL/d(projected centre) over the frames where the Gaussian was kept, and that count."""
+    grad_accum: torch.Tensor
+    vis_count: torch.Tensor
+
+    @staticmethod
+    def zeros(n: int, device="cuda", stream=None) -> "DensifyStats":
+        a = torch.empty(max(1, n), dtype=torch.float32, device=device)
+        c = torch.empty(max(1, n), dtype=torch.int32, device=device)
+        V.veg_fill_u32(a, 0, stream=stream)
+        V.veg_fill_u32(c, 0, stream=stream)
+        return DensifyStats(a, c)
+
+
+def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], frames: Sequence[tuple],
+               targets: torch.Tensor, grads: Grads, group: int, opts=None, ssim_lambda: float = 0.0, stream=None,
+               loss_acc: Optional[torch.Tensor] = None, read_loss: bool = True, timer=NO_TIMER, on_group=None,
+               want_contrib: bool = False, densify: Optional[DensifyStats] = None) -> StepResult:
+    """One multi-view x multi-TF training step with the image loss
+    (1 - lambda) mean|image - target| + lambda mean(1 - SSIM), means over all frames,
+    channels and pixels.
 
     Frames are processed in groups of ``group``: each group is projected, binned, blended,
     differentiated and its key lists are released before the next group starts, so only
     one group's per-pixel state is alive (forward recomputation per group instead of
-    storing all frames' lists).  The L1 mean is separable over frames, so the accumulated
-    gradient equals the full-step gradient."""
+    storing all frames' lists).  Both loss terms are separable over frames (SSIM's window
+    stays inside one image plane), so the accumulated gradient equals the full-step
+    gradient.  With ``densify`` the densification statistics of every group are added."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
+    if not 0.0 <= ssim_lambda <= 1.0:
+        raise ValueError("ssim_lambda must lie in [0, 1]")
     F = len(frames)
     H, W = int(targets.shape[-2]), int(targets.shape[-1])
-    scale = 1.0 / float(F * 3 * H * W)
+    M = float(F * 3 * H * W)
     if loss_acc is None:
         loss_acc = torch.empty(1, dtype=torch.float64, device=g.means.device)
     V.veg_fill_u32(loss_acc, 0, stream=stream)
     entries = []
+    ssim_ws = None
     for f0 in range(0, F, group):
         fr = frames[f0:f0 + group]
         st = render(g, [cams[c] for c, _ in fr], [tfs[t] for _, t in fr], o, stream=stream, timer=timer,
                     want_contrib=want_contrib)
         entries.append(st.n_entries)
         d_image = torch.empty_like(st.image)
+        tgt = targets[f0:f0 + len(fr)].contiguous()
         with timer("l1_loss"):
-            V.veg_l1_loss(st.image, targets[f0:f0 + len(fr)].contiguous(), scale, loss_acc, d_image, stream=stream)
-        render_backward(g, st, d_image, grads, stream=stream, timer=timer)
+            V.veg_l1_loss(st.image, tgt, (1.0 - ssim_lambda) / M, loss_acc, d_image, stream=stream)
+        if ssim_lambda > 0.0:
+            with timer("ssim_loss"):
+                ssim_ws = V.veg_ssim_loss(st.image, tgt, ssim_lambda / M, loss_acc, d_image, ws=ssim_ws,
+                                          stream=stream)
+        g2d = render_backward(g, st, d_image, grads, stream=stream, timer=timer)
+        if densify is not None:
+            with timer("densify_stats"):
+                V.veg_densify_stats(st.proj, g2d, densify.grad_accum, densify.vis_count, stream=stream)
         if on_group is not None:
             on_group(f0, st)
-        del st, d_image
+        del st, d_image, g2d
     loss = float(loss_acc.item()) if read_loss else float("nan")
     return StepResult(loss, entries)
+
+
+def train_step_l1(*args, **kw) -> StepResult:
+    """The training step with the L1 term alone (lambda = 0)."""
+    kw["ssim_lambda"] = 0.0
+    return train_step(*args, **kw)
+
+
+class Adam:
+    """Adam over float32 parameter tensors, each with its own learning rate; one
+    veg_adam_step launch per tensor (moments held here, zero-initialised)."""
+
+    def __init__(self, params: Sequence[tuple], betas=(0.9, 0.999), eps: float = 1e-15, stream=None):
+        self.params = [(p, float(lr)) for p, lr in params]
+        self.betas, self.eps, self.t = betas, float(eps), 0
+        self.m = [torch.empty_like(p) for p, _ in self.params]
+        self.v = [torch.empty_like(p) for p, _ in self.params]
+        for t in self.m + self.v:
+            V.veg_fill_u32(t, 0, stream=stream)
+
+    def step(self, grads: Sequence[torch.Tensor], stream=None):
+        if len(grads) != len(self.params):
+            raise ValueError("one gradient per parameter tensor")
+        self.t += 1
+        for (p, lr), gr, m, v in zip(self.params, grads, self.m, self.v):
+            V.veg_adam_step(p, gr, m, v, lr, self.t, self.betas[0], self.betas[1], self.eps, stream=stream)

@@ -19,6 +19,7 @@ __all__ = [
     "Gaussians", "Proj", "Bins", "default_opts", "make_opts", "veg_project", "veg_bin_count", "veg_bin_sort",
     "veg_bin_overflow", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
     "veg_debug_math", "veg_bin_hit_words", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
+    "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_adam_step", "veg_densify_stats",
 ]
 
 
@@ -246,6 +247,48 @@ def veg_l1_loss(image: torch.Tensor, target: torch.Tensor, scale: float, loss: t
         raise ValueError("loss accumulator must be float64")
     check(load().veg_l1_loss(_ptr(image), _ptr(target), image.numel(), float(scale), _ptr(loss), _ptr(d_image),
                              stream_handle(stream)), "veg_l1_loss")
+
+
+def veg_ssim_workspace_bytes(n_planes: int, width: int, height: int) -> int:
+    return int(load().veg_ssim_workspace_bytes(n_planes, width, height))
+
+
+def veg_ssim_loss(image: torch.Tensor, target: torch.Tensor, weight: float, loss: torch.Tensor,
+                  d_image: torch.Tensor, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Adds weight * sum(1 - SSIM) over the planes of ``image`` (any leading shape, the last
+    two dimensions H, W) to ``loss`` and its gradient to ``d_image``.  Returns the workspace
+    (allocated here when ``ws`` is None or too small)."""
+    if loss.dtype != torch.float64:
+        raise ValueError("loss accumulator must be float64")
+    if image.shape != target.shape or image.shape != d_image.shape or image.dim() < 2:
+        raise ValueError("image, target and d_image must share one shape [..., H, W]")
+    H, W = int(image.shape[-2]), int(image.shape[-1])
+    planes = image.numel() // max(1, H * W)
+    need = veg_ssim_workspace_bytes(planes, W, H)
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(max(need, 4), dtype=torch.uint8, device=image.device)
+    check(load().veg_ssim_loss(_ptr(image), _ptr(target), planes, W, H, float(weight), _ptr(loss), _ptr(d_image),
+                               _ptr(ws), ws.numel() * ws.element_size(), stream_handle(stream)), "veg_ssim_loss")
+    return ws
+
+
+def veg_adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float, step: int,
+                  beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, stream=None):
+    for t in (param, grad, m, v):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != param.numel():
+            raise ValueError("adam: param, grad, m, v must be contiguous float32 of one size")
+    check(load().veg_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), float(lr), float(beta1),
+                               float(beta2), float(eps), int(step), stream_handle(stream)), "veg_adam_step")
+
+
+def veg_densify_stats(proj: "Proj", g2d: torch.Tensor, grad_accum: torch.Tensor, vis_count: torch.Tensor,
+                      stream=None):
+    if grad_accum.dtype != torch.float32 or vis_count.dtype != torch.int32:
+        raise ValueError("grad_accum must be float32 and vis_count int32")
+    if grad_accum.numel() < int(proj.struct.n) or vis_count.numel() < int(proj.struct.n):
+        raise ValueError("grad_accum / vis_count smaller than the number of Gaussians")
+    check(load().veg_densify_stats(ctypes.byref(proj.struct), _ptr(g2d), _ptr(grad_accum), _ptr(vis_count),
+                                   stream_handle(stream)), "veg_densify_stats")
 
 
 def veg_fill_u32(t: torch.Tensor, value: int = 0, stream=None):
