@@ -247,6 +247,8 @@ def main():
     ap.add_argument("--cpu-pixels", type=int, default=640)
     ap.add_argument("--lit-steps", type=int, default=5,
                     help="timed steps of the same workload with lighting attributes (0 to skip)")
+    ap.add_argument("--full-steps", type=int, default=5,
+                    help="timed whole training iterations: L1 + SSIM loss, densification statistics, Adam (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s); '' to skip")
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -347,6 +349,39 @@ def main():
         lit_mpix = F * H * W * args.lit_steps / (time.perf_counter() - t2) / 1e6
         del grads_l, gl
 
+    # a whole training iteration: the (1 - 0.2) L1 + 0.2 (1 - SSIM) loss, densification
+    # statistics and the Adam update of every parameter tensor (this changes the model, so
+    # it runs after the other measurements that use it)
+    full = None
+    if args.full_steps > 0:
+        dens = R.DensifyStats.zeros(w.gaussians.n)
+        lrs = [(g.means, 1.6e-4), (g.log_scales, 5e-3), (g.quats, 1e-3), (g.scalars, 2.5e-4)]
+        if g.weights is not None:
+            lrs.append((g.weights, 2.5e-2))
+        opt = R.Adam(lrs)
+
+        def full_iter(timer=R.NO_TIMER):
+            grads.zero_()
+            r = R.train_step(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, ssim_lambda=0.2,
+                             loss_acc=loss_acc, densify=dens, timer=timer, read_loss=False)
+            with timer("adam"):
+                opt.step([grads.d_means, grads.d_log_scales, grads.d_quats, grads.d_scalars] +
+                         ([grads.d_weights] if g.weights is not None else []))
+            return r
+        full_iter()
+        torch.cuda.synchronize()
+        ftimer = R.EventTimer()
+        t3 = time.perf_counter()
+        for k in range(args.full_steps):
+            full_iter(ftimer)
+        torch.cuda.synchronize()
+        fdt = time.perf_counter() - t3
+        ft = {k: round(sum(v) / args.full_steps, 3) for k, v in ftimer.totals_ms().items()
+              if k in ("l1_loss", "ssim_loss", "densify_stats", "adam")}
+        full = {"mpix_s": round(F * H * W * args.full_steps / fdt / 1e6, 2),
+                "ms_per_step": round(fdt * 1e3 / args.full_steps, 3), "ssim_lambda": 0.2, "kernel_ms_per_step": ft}
+        del dens, opt
+
     # roofline of the dominant kernel (blend forward or backward: VALU-bound)
     def blend_roof(name):
         visits = counts["bwd"] if name == "blend_bwd" else counts["fwd"]
@@ -373,6 +408,7 @@ def main():
                    "group": args.group},
         "fwd_mpix_s": round(fwd_mpix, 2),
         "lit_mpix_s": None if lit_mpix is None else round(lit_mpix, 2),
+        "full_iteration": full,
         "geval_s": {"fwd": round(counts["fwd"] * args.steps / dt / 1e9, 3),
                     "bwd": round(counts["bwd"] * args.steps / dt / 1e9, 3)},
         "kernel_ms_per_step": {k: round(v, 3) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
