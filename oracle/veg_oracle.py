@@ -31,6 +31,10 @@ Three parts:
   decide differently).
 * O3 ``gradients`` -- the gradient of a linear functional of O2's image, by torch
   autograd in float64 on the CPU.
+* ``footprint_shared_f32`` -- the key list of frames that share a camera (several transfer
+  functions over one view, as in opacity-guided training): the footprint at the largest
+  opacity over the frames' tables, which contains each frame's own footprint.  The images
+  and gradients of such frames are still O2 / O3 per frame.
 * The training-loop neighbours of section "Training": ``ssim_map`` / ``ssim_loss`` (the
   SSIM term of the image loss, Gaussian 11-tap window, float64, gradient by autograd),
   ``adam_step`` (the optimizer update) and ``densify_stats`` (per-Gaussian accumulated
@@ -53,7 +57,7 @@ import numpy as np
 import torch
 
 __all__ = [
-    "TILE", "QNORM2_MIN", "exp32", "log32", "footprint_f32", "key_list", "project_f64",
+    "TILE", "QNORM2_MIN", "exp32", "log32", "footprint_f32", "footprint_shared_f32", "key_list", "project_f64",
     "render_pixels", "render_image", "gradients", "quat_to_rot_f64", "OracleProjection",
     "depth_order", "frame_pairs", "ssim_window_1d", "ssim_map", "ssim_loss", "adam_step", "densify_stats",
     "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA",
@@ -132,6 +136,7 @@ class Footprint:
     my: np.ndarray
     ex: np.ndarray          # [n] float32 half extents of the alpha >= alpha_min ellipse
     ey: np.ndarray
+    A: Optional[np.ndarray] = None   # [n] float32 peak opacity O(v) w (before the cull)
 
 
 def _finite_rows(*arrs):
@@ -264,7 +269,29 @@ def footprint_f32(g, cam, lut, opts) -> Footprint:
     rect[kk, 3] = yhi[kk].astype(np.int64) // TILE
     count = np.where(kk, (rect[:, 2] - rect[:, 0] + 1).astype(np.int64) * (rect[:, 3] - rect[:, 1] + 1), 0)
     return Footprint(keep=keep, depth=depth, depth_bits=depth.view(np.uint32).copy(), rect=rect,
-                     count=count, mx=mx, my=my, ex=ex, ey=ey)
+                     count=count, mx=mx, my=my, ex=ex, ey=ey, A=np.asarray(A, np.float32))
+
+
+def footprint_shared_f32(g, cam, luts, opts) -> Footprint:
+    """Footprint of one camera whose frames (one per table in ``luts``) share a key list.
+
+    Everything in ``footprint_f32`` except A is independent of the transfer function, and
+    the ellipse where A exp(-sigma) >= alpha_min grows with A, so the frames' footprints
+    are all contained in the footprint at the largest A over the tables.  The shared list
+    is built from exactly that footprint: per Gaussian, the fields of the table with the
+    largest A (non-finite A never wins; ties give identical fields).  A Gaussian is in the
+    list when that table keeps it.  Each frame then skips, pixel by pixel, the entries its
+    own A puts below alpha_min, so every frame's image is the one of its own footprint."""
+    fps = [footprint_f32(g, cam, lut, opts) for lut in luts]
+    with np.errstate(invalid="ignore"):
+        a = np.stack([np.where(np.isfinite(fp.A), fp.A, -np.inf) for fp in fps])
+    k = np.argmax(a, axis=0)
+    idx = np.arange(k.shape[0])
+
+    def pick(name):
+        return np.stack([getattr(fp, name) for fp in fps])[k, idx]
+    return Footprint(keep=pick("keep"), depth=fps[0].depth, depth_bits=fps[0].depth_bits, rect=pick("rect"),
+                     count=pick("count"), mx=fps[0].mx, my=fps[0].my, ex=pick("ex"), ey=pick("ey"), A=pick("A"))
 
 
 def tiles_of(cam):

@@ -26,7 +26,7 @@ __all__ = [
     "SEED_BASE", "Gaussians", "Shading", "random_shading", "Camera", "rng_for", "uniform_gaussians", "shell_gaussians",
     "clustered_gaussians", "random_tf", "identity_tf", "constant_tf", "fibonacci_directions",
     "random_direction", "look_at_camera", "perturbed_copy", "sample_pixels", "Workload",
-    "workload", "serve_trace", "DEFAULT_OPTS",
+    "workload", "serve_trace", "DEFAULT_OPTS", "tent_opacity", "sequential_rgb", "tent_tfs",
 ]
 
 # Renderer options used by every workload (alpha clamp, skip threshold, stop threshold
@@ -163,6 +163,38 @@ def random_tf(rng, k=256, n_peaks=3) -> np.ndarray:
     return np.concatenate([rgb, op[:, None]], axis=1).astype(np.float32)
 
 
+def tent_opacity(x, n_steps: int, step: int) -> np.ndarray:
+    """Opacity map ``step`` of the opacity-guided training family (section "Training"): the
+    scalar range [0,1] is cut into ``n_steps`` equal steps; map j is a tent centred in step
+    j, c = (j + 1/2) / n_steps, falling off linearly with slope n_steps:
+    O_j(x) = max(0, 1 - n_steps |x - c|).  Peak 1 (the paper does not state the height).
+    Neighbouring tents overlap by half, so the maps sum to 1 on [c_0, c_{n-1}]."""
+    x = np.asarray(x, np.float64)
+    c = (step + 0.5) / n_steps
+    return np.maximum(0.0, 1.0 - n_steps * np.abs(x - c))
+
+
+def sequential_rgb(x) -> np.ndarray:
+    """A sequential (non-diverging) colour map, dark blue through teal and green to yellow,
+    piecewise linear in RGB through five knots.  The paper trains with one sequential
+    colour map and reports that the colour mapping matters little as long as it is not
+    diverging; this one is this project's own."""
+    x = np.asarray(x, np.float64)
+    knots = np.array([0.0, 0.25, 0.5, 0.75, 1.0])
+    cols = np.array([[0.10, 0.05, 0.35], [0.15, 0.30, 0.55], [0.10, 0.55, 0.55], [0.40, 0.75, 0.30],
+                     [0.98, 0.90, 0.15]])
+    return np.stack([np.interp(x, knots, cols[:, ch]) for ch in range(3)], axis=-1)
+
+
+def tent_tfs(n_steps: int, k: int = 256) -> List[np.ndarray]:
+    """The ``n_steps`` [k,4] float32 tables of the opacity-guided family: colour from
+    ``sequential_rgb``, opacity from ``tent_opacity``, both sampled at x_j = j / (k-1)."""
+    x = np.arange(k, dtype=np.float64) / (k - 1)
+    rgb = sequential_rgb(x)
+    return [np.concatenate([rgb, tent_opacity(x, n_steps, j)[:, None]], axis=1).astype(np.float32)
+            for j in range(n_steps)]
+
+
 def identity_tf(k=256) -> np.ndarray:
     x = (np.arange(k, dtype=np.float64) / (k - 1)).astype(np.float32)
     return np.stack([x, x, x, x], axis=1).copy()
@@ -258,8 +290,9 @@ def _frames(n_views, n_tfs):
 
 def workload(index: int, n_override: Optional[int] = None, views_override: Optional[int] = None,
              tfs_override: Optional[int] = None, res_override: Optional[int] = None) -> Workload:
-    """The five synthetic workloads (index 0..4).  Overrides shrink a workload for tests
-    while keeping its structure (same generator, same seed)."""
+    """The synthetic workloads: 0..4 (3 is the serving trace) and 5, the opacity-guided
+    training family.  Overrides shrink a workload for tests while keeping its structure
+    (same generator, same seed)."""
     rng = rng_for(index)
     if index == 0:
         n = n_override or 1000
@@ -296,7 +329,18 @@ def workload(index: int, n_override: Optional[int] = None, views_override: Optio
         tgt = perturbed_copy(rng_for(index, 1), g)
         return Workload("stress-4M-2048px-32x4", g, cams, tfs, _frames(nv, nt), target_gaussians=tgt,
                         description="4M Gaussians (50% uniform, 50% shells), 32 views x 4 TFs, 2048x2048")
-    raise ValueError("workload index must be 0, 1, 2 or 4 (3 is the serving trace: serve_trace())")
+    if index == 5:
+        # opacity-guided training: every view rendered with the whole tent family (10 steps,
+        # the paper's default), 500k Gaussians (the paper's initial count), 800x800
+        n = n_override or 500_000
+        g = clustered_gaussians(rng, n, 0.7, 0.002, 0.03)
+        nv, nt, res = views_override or 8, tfs_override or 10, res_override or 800
+        cams = [look_at_camera(d, 3.0, res, res) for d in fibonacci_directions(nv)]
+        tfs = tent_tfs(nt)
+        tgt = perturbed_copy(rng_for(index, 1), g)
+        return Workload("opacity-guided-500k-800px-8x10", g, cams, tfs, _frames(nv, nt), target_gaussians=tgt,
+                        description="500k shell-clustered Gaussians, 8 views x 10 tent opacity maps, 800x800, fwd+bwd")
+    raise ValueError("workload index must be 0, 1, 2, 4 or 5 (3 is the serving trace: serve_trace())")
 
 
 @dataclass

@@ -624,3 +624,82 @@ def test_densify_stats_of_a_constructed_gradient():
     kept = np.array([[True, True, False], [True, False, False]])
     acc, cnt = oracle.densify_stats(g2d, kept)
     assert np.allclose(acc, [15.0, 1.0, 0.0]) and list(cnt) == [2, 1, 0]
+
+
+# ---------------------------------------------------------------------------------------
+# Opacity-guided training family and the key list shared by a view's transfer functions
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n_steps", [5, 10, 20])
+def test_tent_opacity_maps_follow_the_stated_rule(n_steps):
+    """Section "Training": one map per step of the scalar range, centred in its step, linear
+    drop-off with slope equal to the number of steps; together they weight the range
+    equally (partition of unity between the first and last centres)."""
+    x = np.linspace(0, 1, 20001)
+    maps = np.stack([synth.tent_opacity(x, n_steps, j) for j in range(n_steps)])
+    assert maps.min() >= 0 and maps.max() <= 1
+    for j in range(n_steps):
+        c = (j + 0.5) / n_steps
+        assert synth.tent_opacity(c, n_steps, j) == 1.0
+        h = 0.25 / n_steps
+        slope = (synth.tent_opacity(c - h, n_steps, j) - synth.tent_opacity(c - 2 * h, n_steps, j)) / h
+        assert abs(slope - n_steps) <= 1e-9 * n_steps
+        far = np.abs(x - c) >= 1.0 / n_steps
+        assert np.all(maps[j][far] == 0)
+    inner = (x >= 0.5 / n_steps) & (x <= 1 - 0.5 / n_steps)
+    assert np.allclose(maps.sum(0)[inner], 1.0, atol=1e-12)
+    lut = synth.tent_tfs(n_steps)
+    assert len(lut) == n_steps and lut[0].shape == (256, 4)
+    assert np.allclose(lut[3][:, 3], synth.tent_opacity(np.arange(256) / 255, n_steps, 3), atol=1e-7)
+
+
+def _shared_case(n=1000, res=64):
+    w = synth.workload(0, n_override=n, res_override=res)
+    luts = [synth.random_tf(synth.rng_for(0, 70 + k)) for k in range(3)] + synth.tent_tfs(10)[2:5]
+    return w.gaussians, w.cameras[0], luts
+
+
+def test_shared_footprint_contains_every_frames_footprint():
+    g, cam, luts = _shared_case()
+    union = oracle.footprint_shared_f32(g, cam, luts, OPTS)
+    fps = [oracle.footprint_f32(g, cam, lut, OPTS) for lut in luts]
+    assert np.array_equal(union.keep, np.any([fp.keep for fp in fps], axis=0))
+    for fp in fps:
+        k = fp.keep
+        assert np.all(union.rect[k, 0] <= fp.rect[k, 0]) and np.all(union.rect[k, 1] <= fp.rect[k, 1])
+        assert np.all(union.rect[k, 2] >= fp.rect[k, 2]) and np.all(union.rect[k, 3] >= fp.rect[k, 3])
+        assert np.all(union.count >= fp.count)
+    assert np.array_equal(union.depth_bits, fps[0].depth_bits)
+    # with one table the shared footprint is that table's own, field for field
+    one = oracle.footprint_shared_f32(g, cam, luts[:1], OPTS)
+    for name in ("keep", "rect", "count", "ex", "ey"):
+        assert np.array_equal(getattr(one, name), getattr(fps[0], name)), name
+    # some Gaussians are kept by some tables only, so the shared list is a strict union
+    some = np.any([fp.keep for fp in fps], axis=0) & ~np.all([fp.keep for fp in fps], axis=0)
+    assert some.sum() > 50
+
+
+def test_shared_footprint_is_lossless_for_every_table():
+    """Every pixel where any table's float64 alpha reaches alpha_min lies in the shared
+    rectangle (pixel enumeration, as for a single table)."""
+    g, cam, luts = _shared_case()
+    union = oracle.footprint_shared_f32(g, cam, luts, OPTS)
+    ys, xs = np.mgrid[0:64, 0:64]
+    pxc, pyc = xs.reshape(-1) + 0.5, ys.reshape(-1) + 0.5
+    amin = float(np.float32(1 / 255))
+    checked = 0
+    for lut in luts:
+        proj = oracle.project_f64(g.means, g.log_scales, g.quats, g.scalars, None, cam, lut, OPTS)
+        mu, con, A = (proj.mean2d.detach().numpy(), proj.conic.detach().numpy(), proj.A.detach().numpy())
+        for i in np.nonzero(proj.kept)[0]:
+            dx, dy = pxc - mu[i, 0], pyc - mu[i, 1]
+            a = A[i] * np.exp(-0.5 * (con[i, 0] * dx * dx + 2 * con[i, 1] * dx * dy + con[i, 2] * dy * dy))
+            hit = a >= amin * (1 + 1e-5)
+            if not hit.any():
+                continue
+            assert union.keep[i]
+            tx, ty = xs.reshape(-1)[hit] // 16, ys.reshape(-1)[hit] // 16
+            x0, y0, x1, y1 = union.rect[i]
+            assert tx.min() >= x0 and tx.max() <= x1 and ty.min() >= y0 and ty.max() <= y1
+            checked += 1
+    assert checked > 300
