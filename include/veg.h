@@ -164,6 +164,8 @@ typedef struct {
   float* rec;
   uint32_t* count;
   uint32_t* depth;
+  int32_t tfs_per_view;  /* out: frames sharing one key list (1 from veg_project; 0 is
+                            read as 1) */
 } veg_proj;
 
 size_t veg_frames_bytes(int32_t n_frames);
@@ -200,6 +202,28 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
                        const veg_tf* tfs, const veg_opts* opts, veg_proj* proj,
                        veg_stream_t stream);
 
+/* veg_project_views -- veg_project for views rendered with several transfer functions
+ * each (opacity-guided training renders every camera with a family of opacity maps,
+ * section "Training"): n_views cameras x tfs_per_view tables, frame f = v * tfs_per_view + k
+ * uses cams[v] and tfs[f].  Geometry does not depend on the table, so the frames of a view
+ * share one key list: the first frame's pairs carry the footprint at the largest A over
+ * the view's tables (it contains every frame's own footprint), the other frames' counts are
+ * 0.  Every frame's record holds the shared geometry (centre relative to the shared
+ * rectangle) with its own A and colour, A = 0 where the frame's own footprint culls the
+ * Gaussian (A below alpha_min or no pixel centre covered), so each frame keeps exactly the
+ * Gaussians veg_project would keep for it.  The blend passes then give each frame the
+ * image and gradients of its own footprint (each frame skips pixel by pixel what its A
+ * puts below alpha_min); only the float32 rounding of the centre offset may differ from
+ * veg_project's.
+ *   n_views * tfs_per_view = proj->n_frames <= VEG_MAX_FRAMES; cams host [n_views];
+ *   tfs host [n_views * tfs_per_view].  Sets proj->tfs_per_view.
+ *   veg_bins.hits (optional) must then hold tfs_per_view * veg_bin_hit_words(capacity,
+ *   total_tiles) words: one block of hit bits per frame slot.
+ * Errors: as veg_project, and tfs_per_view outside 1..VEG_MAX_FRAMES. */
+veg_status veg_project_views(const veg_gaussians* g, int32_t n_views, int32_t tfs_per_view,
+                             const veg_camera* cams, const veg_tf* tfs, const veg_opts* opts,
+                             veg_proj* proj, veg_stream_t stream);
+
 /* ----------------------------------------------------------------------------------
  * Binning and sorting  (the tile-based rasterizer's key list)
  * ---------------------------------------------------------------------------------- */
@@ -212,7 +236,7 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
  *   ranges              device [2 * total_tiles] uint32
  *   capacity            entries the buffers hold (<= 2^31 - 1)
  *   hits, hit_words     optional (NULL, 0): device [hit_words] uint64, hit_words >=
- *                       veg_bin_hit_words(capacity, total_tiles).  When given,
+ *                       tfs_per_view * veg_bin_hit_words(capacity, total_tiles).  When given,
  *                       veg_render_fwd records for every entry whether it was blended into
  *                       at least one pixel of its tile, and veg_render_bwd, called with the
  *                       same bins after that forward call, visits only those entries (the

@@ -280,8 +280,9 @@ def footprint_shared_f32(g, cam, luts, opts) -> Footprint:
     are all contained in the footprint at the largest A over the tables.  The shared list
     is built from exactly that footprint: per Gaussian, the fields of the table with the
     largest A (non-finite A never wins; ties give identical fields).  A Gaussian is in the
-    list when that table keeps it.  Each frame then skips, pixel by pixel, the entries its
-    own A puts below alpha_min, so every frame's image is the one of its own footprint."""
+    list when that table keeps it.  A frame blends only the Gaussians its own footprint
+    keeps, and skips pixel by pixel what its own A puts below alpha_min, so every frame's
+    image is the one of its own footprint."""
     fps = [footprint_f32(g, cam, lut, opts) for lut in luts]
     with np.errstate(invalid="ignore"):
         a = np.stack([np.where(np.isfinite(fp.A), fp.A, -np.inf) for fp in fps])

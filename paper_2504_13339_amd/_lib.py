@@ -47,7 +47,7 @@ class veg_opts(Structure):
 class veg_proj(Structure):
     _fields_ = [("n", c_int64), ("n_frames", c_int32), ("width", c_int32), ("height", c_int32),
                 ("tiles_x", c_int32), ("tiles_y", c_int32), ("total_tiles", c_int64), ("frames", c_void_p),
-                ("rec", c_void_p), ("count", c_void_p), ("depth", c_void_p)]
+                ("rec", c_void_p), ("count", c_void_p), ("depth", c_void_p), ("tfs_per_view", c_int32)]
 
 
 class veg_bins(Structure):
@@ -87,6 +87,8 @@ _SIGS = {
     "veg_opts_default": (None, [P(veg_opts)]),
     "veg_frames_bytes": (c_size_t, [c_int32]),
     "veg_project": (c_int, [P(veg_gaussians), c_int32, P(veg_camera), P(veg_tf), P(veg_opts), P(veg_proj), c_void_p]),
+    "veg_project_views": (c_int, [P(veg_gaussians), c_int32, c_int32, P(veg_camera), P(veg_tf), P(veg_opts),
+                                  P(veg_proj), c_void_p]),
     "veg_bin_workspace_bytes": (c_size_t, [c_int64, c_int64]),
     "veg_bin_count": (c_int, [P(veg_proj), c_void_p, c_size_t, P(c_int64), c_void_p]),
     "veg_bin_sort": (c_int, [P(veg_proj), c_void_p, c_size_t, P(veg_bins), c_void_p]),

@@ -141,13 +141,18 @@ void veg_opts_default(veg_opts* o) {
 
 size_t veg_frames_bytes(int32_t n_frames) { return n_frames > 0 ? (size_t)n_frames * sizeof(FrameDesc) : 0; }
 
-veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camera* cams, const veg_tf* tfs,
-                       const veg_opts* opts, veg_proj* proj, veg_stream_t stream) {
+// Frames f = v * per_view + k: camera cams[v], table tfs[f]; the frames of a view share the
+// key list of its first frame (per_view = 1: every frame has its own).
+static veg_status project_impl(const veg_gaussians* g, int32_t n_views, int32_t per_view, const veg_camera* cams,
+                               const veg_tf* tfs, const veg_opts* opts, veg_proj* proj, veg_stream_t stream) {
   g_err.clear();
   veg_status s = check_gaussians(g);
   if (s != VEG_OK) return s;
   if (!cams || !tfs) return fail(VEG_ERR_INVALID_ARG, "cams/tfs is NULL");
-  if (n_frames < 1 || n_frames > VEG_MAX_FRAMES) return fail(VEG_ERR_INVALID_ARG, "n_frames out of range");
+  if (per_view < 1 || per_view > VEG_MAX_FRAMES) return fail(VEG_ERR_INVALID_ARG, "tfs_per_view out of range");
+  if (n_views < 1 || (int64_t)n_views * per_view > VEG_MAX_FRAMES)
+    return fail(VEG_ERR_INVALID_ARG, "n_frames out of range");
+  const int32_t n_frames = n_views * per_view;
   s = check_proj(proj);
   if (s != VEG_OK) return s;
   if (proj->n != g->n || proj->n_frames != n_frames)
@@ -157,7 +162,7 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
   if (s != VEG_OK) return s;
   const int W = cams[0].width, H = cams[0].height;
   for (int f = 0; f < n_frames; ++f) {
-    const veg_camera& c = cams[f];
+    const veg_camera& c = cams[f / per_view];
     if (c.width != W || c.height != H) return fail(VEG_ERR_INVALID_ARG, "frame %d: all frames need one size", f);
     if (c.width < 1 || c.height < 1 || c.width > VEG_MAX_DIM || c.height > VEG_MAX_DIM)
       return fail(VEG_ERR_INVALID_ARG, "frame %d: width/height out of range", f);
@@ -181,7 +186,8 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
     d.quats = g->quats;
     d.scalars = g->scalars;
     d.weights = g->weights;
-    set_lighting(d, *g, cams[f]);
+    const veg_camera& cam = cams[f / per_view];
+    set_lighting(d, *g, cam);
     d.lut = tfs[f].rgba;
     d.K = tfs[f].k;
     d.n = (int32_t)g->n;
@@ -192,11 +198,14 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
     d.pair_base = (uint32_t)((int64_t)f * g->n);
     d.tile_base = (uint32_t)((int64_t)f * tiles_x * tiles_y);
     d.pix_base = (uint32_t)((int64_t)f * W * H);
-    std::memcpy(d.view, cams[f].view, sizeof(d.view));
-    d.fx = cams[f].fx;
-    d.fy = cams[f].fy;
-    d.cx = cams[f].cx;
-    d.cy = cams[f].cy;
+    d.list_frame = (uint32_t)(f - f % per_view);
+    d.slot = f % per_view;
+    d.n_share = d.slot == 0 ? per_view : 0;
+    std::memcpy(d.view, cam.view, sizeof(d.view));
+    d.fx = cam.fx;
+    d.fy = cam.fy;
+    d.cx = cam.cx;
+    d.cy = cam.cy;
     d.bg[0] = o.bg[0];
     d.bg[1] = o.bg[1];
     d.bg[2] = o.bg[2];
@@ -213,11 +222,22 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
   proj->tiles_x = tiles_x;
   proj->tiles_y = tiles_y;
   proj->total_tiles = total_tiles;
+  proj->tfs_per_view = per_view;
   if (g->n > 0)
     VEG_CHECK_HIP(launch_project((const FrameDesc*)proj->frames, n_frames, (int)g->n, kopts(&o), (float4*)proj->rec,
                                  proj->count, proj->depth, true, st),
                   "veg_project");
   return VEG_OK;
+}
+
+veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camera* cams, const veg_tf* tfs,
+                       const veg_opts* opts, veg_proj* proj, veg_stream_t stream) {
+  return project_impl(g, n_frames, 1, cams, tfs, opts, proj, stream);
+}
+
+veg_status veg_project_views(const veg_gaussians* g, int32_t n_views, int32_t tfs_per_view, const veg_camera* cams,
+                             const veg_tf* tfs, const veg_opts* opts, veg_proj* proj, veg_stream_t stream) {
+  return project_impl(g, n_views, tfs_per_view, cams, tfs, opts, proj, stream);
 }
 
 size_t veg_bin_workspace_bytes(int64_t n_pairs, int64_t capacity) {
@@ -290,12 +310,22 @@ int64_t veg_bin_hit_words(int64_t capacity, int64_t total_tiles) {
   return capacity / 64 + total_tiles + 2;
 }
 
-// The hit bits are optional; when present the buffer must hold every tile's words.
+// Frames per shared key list (0 in a struct not filled by veg_project_views means 1).
+static int per_view_of(const veg_proj* proj) { return proj->tfs_per_view > 1 ? proj->tfs_per_view : 1; }
+
+// Words of one frame slot's hit bits.
+static uint64_t hit_stride_of(const veg_proj* proj, const veg_bins* bins) {
+  return (uint64_t)veg_bin_hit_words(bins->capacity, (int64_t)proj->n_frames * proj->tiles_x * proj->tiles_y);
+}
+
+// The hit bits are optional; when present the buffer must hold every tile's words for each
+// frame that shares a list.
 static veg_status check_hits(const veg_proj* proj, const veg_bins* bins, const char* what) {
+  if (proj->n_frames % per_view_of(proj) != 0)
+    return fail(VEG_ERR_INVALID_ARG, "%s: n_frames is not a multiple of tfs_per_view", what);
   if (!bins->hits) return VEG_OK;
-  const int64_t tiles = (int64_t)proj->n_frames * proj->tiles_x * proj->tiles_y;
-  if (bins->hit_words < veg_bin_hit_words(bins->capacity, tiles))
-    return fail(VEG_ERR_INVALID_ARG, "%s: hit_words < veg_bin_hit_words(capacity, tiles)", what);
+  if ((uint64_t)bins->hit_words < (uint64_t)per_view_of(proj) * hit_stride_of(proj, bins))
+    return fail(VEG_ERR_INVALID_ARG, "%s: hit_words < tfs_per_view * veg_bin_hit_words(capacity, tiles)", what);
   return VEG_OK;
 }
 
@@ -311,9 +341,10 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
   veg_opts o;
   s = resolve_opts(opts, &o);
   if (s != VEG_OK) return s;
-  VEG_CHECK_HIP(launch_blend_fwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
-                                 kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, image, t_final, n_last,
-                                 n_contrib, bins->hits, (hipStream_t)stream),
+  VEG_CHECK_HIP(launch_blend_fwd((const FrameDesc*)proj->frames, proj->n_frames, per_view_of(proj),
+                                 proj->tiles_x * proj->tiles_y, kopts(&o), (const float4*)proj->rec, bins->vals,
+                                 bins->ranges, image, t_final, n_last, n_contrib, bins->hits,
+                                 hit_stride_of(proj, bins), (hipStream_t)stream),
                 "veg_render_fwd");
   return VEG_OK;
 }
@@ -332,7 +363,8 @@ veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_
   if (s != VEG_OK) return s;
   VEG_CHECK_HIP(launch_blend_bwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
                                  kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, t_final, n_last,
-                                 d_image, g2d, (uint32_t)pairs_of(proj), bins->hits, (hipStream_t)stream),
+                                 d_image, g2d, (uint32_t)pairs_of(proj), bins->hits, hit_stride_of(proj, bins),
+                                 (hipStream_t)stream),
                 "veg_render_bwd");
   return VEG_OK;
 }
@@ -420,7 +452,8 @@ veg_status veg_densify_stats(const veg_proj* proj, const float* g2d, float* grad
   veg_status s = check_projected(proj);
   if (s != VEG_OK) return s;
   if (proj->n > 0 && (!g2d || !grad_accum || !vis_count)) return fail(VEG_ERR_INVALID_ARG, "densify_stats: NULL");
-  VEG_CHECK_HIP(launch_densify_stats((const FrameDesc*)proj->frames, proj->n_frames, (int)proj->n, proj->count, g2d,
+  VEG_CHECK_HIP(launch_densify_stats((const FrameDesc*)proj->frames, proj->n_frames, (int)proj->n, proj->count,
+                                     (const float4*)proj->rec, g2d,
                                      grad_accum, vis_count, (hipStream_t)stream),
                 "veg_densify_stats");
   return VEG_OK;

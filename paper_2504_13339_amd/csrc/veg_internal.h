@@ -36,12 +36,14 @@ struct alignas(16) FrameDesc {
   uint32_t pair_base;        // first pair id of this frame
   uint32_t tile_base;        // first global tile id of this frame
   uint32_t pix_base;         // first pixel of this frame in batched per-pixel buffers
-  uint32_t pad0;
+  uint32_t list_frame;       // frame whose key list this frame blends (itself unless shared)
   float view[12];
   float fx, fy, cx, cy;
   float bg[3];
   float campos[3];           // camera centre in world space (headlight position)
-  float pad1[4];
+  int32_t slot;              // position among the frames sharing the list (0 = owner)
+  int32_t n_share;           // owner: frames sharing its list (>= 1); 0 on the other frames
+  uint32_t pad1[2];
 };
 static_assert(sizeof(FrameDesc) == 256, "FrameDesc layout");
 
@@ -118,6 +120,13 @@ hipError_t launch_project_bwd(const FrameDesc* descs, int n_frames, int n, const
 
 // Lighting attributes of a model and the camera centre (-R^T t of the world->camera
 // transform [R|t]) into a frame descriptor.
+// A frame that owns its key list alone.
+inline void set_own_list(FrameDesc& d, int f) {
+  d.list_frame = (uint32_t)f;
+  d.slot = 0;
+  d.n_share = 1;
+}
+
 inline void set_lighting(FrameDesc& d, const veg_gaussians& g, const veg_camera& c) {
   d.normals = g.normals;
   d.k_ambient = g.k_ambient;
@@ -159,14 +168,18 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
                            uint32_t* vals_alt, uint32_t* ranges, uint32_t capacity,
                            hipStream_t stream);
 
-hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
+// Frames come in views of `per_view` consecutive frames that share the first one's key
+// list (per_view = 1: every frame owns its list).  Hit bits of the frame in slot k start at
+// word k * hit_stride.
+hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
-                            uint64_t* hits, hipStream_t stream);
+                            uint64_t* hits, uint64_t hit_stride, hipStream_t stream);
 hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             const float* tfinal, const int32_t* nlast, const float* dimage,
-                            float* g2d, uint32_t n_pairs, const uint64_t* hits, hipStream_t stream);
+                            float* g2d, uint32_t n_pairs, const uint64_t* hits, uint64_t hit_stride,
+                            hipStream_t stream);
 
 hipError_t launch_l1(const float* image, const float* target, int64_t count, float scale,
                      double* loss, float* dimage, hipStream_t stream);
@@ -175,8 +188,8 @@ hipError_t launch_ssim(const float* image, const float* target, int64_t n_planes
                        double* loss, float* d_image, float* dmaps, hipStream_t stream);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, float bc1, float bc2, hipStream_t stream);
-hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float* g2d,
-                                float* acc, int32_t* vis, hipStream_t stream);
+hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float4* rec,
+                                const float* g2d, float* acc, int32_t* vis, hipStream_t stream);
 hipError_t launch_debug_math(int op, const float* x, const float* y, float* out, int64_t n,
                              hipStream_t stream);
 

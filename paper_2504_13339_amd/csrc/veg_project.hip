@@ -230,6 +230,24 @@ __device__ __forceinline__ void project_one(const FrameDesc& d, const KOpts& o, 
   p.det = p.S00 * p.S11 - p.S01 * p.S01;
 }
 
+// Pixel range of the footprint (the ellipse where A exp(-sigma) >= alpha_min, by the
+// extent contract of veg_project), clipped to the image; false when it holds no pixel.
+__device__ __forceinline__ bool pixel_range(const Proj& p, float A, const KOpts& o, int W, int H, double& xlo,
+                                            double& xhi, double& ylo, double& yhi) {
+  const float tau = 2.0f * log32(A / o.alpha_min);
+  const float ex = sqrtf(tau * p.S00);
+  const float ey = sqrtf(tau * p.S11);
+  xlo = ceil((p.mx - (double)ex) - 0.5);
+  xhi = floor((p.mx + (double)ex) - 0.5);
+  ylo = ceil((p.my - (double)ey) - 0.5);
+  yhi = floor((p.my + (double)ey) - 0.5);
+  xlo = fmax(xlo, 0.0);
+  ylo = fmax(ylo, 0.0);
+  xhi = fmin(xhi, (double)(W - 1));
+  yhi = fmin(yhi, (double)(H - 1));
+  return (xlo <= xhi) && (ylo <= yhi);
+}
+
 struct Blob {
   uint32_t w[kBlobMaxBytes / 4];
 };
@@ -254,7 +272,7 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
   const float* cur_n = nullptr;
   for (int f = f0; f < f1; ++f) {
     const FrameDesc& d = descs[f];
-    if (i >= d.n) continue;
+    if (i >= d.n || d.n_share == 0) continue;   // a frame sharing another's list is projected with it
     if (d.means != cur || d.scalars != cur_v || d.weights != cur_w || d.normals != cur_n) {
       load_params(d, i, g);
       cur = d.means;
@@ -263,10 +281,20 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
       cur_n = d.normals;
     }
     const uint32_t pid = d.pair_base + (uint32_t)i;
+    const int n_share = d.n_share;
     bool keep = g.finite && g.n2 >= 1e-24f && g.nn2 >= 1e-24f;
     TfSample tf;
     tf_lookup(d, keep ? g.v : 0.0f, tf);
-    const float A = tf.O * g.w;
+    // Frames sharing this list: the footprint at the largest A over their tables contains
+    // each frame's own, so it decides the list; only the owner's pair is counted.
+    float A = tf.O * g.w;
+    for (int k = 1; k < n_share; ++k) {
+      const FrameDesc& dk = descs[f + k];
+      count[dk.pair_base + (uint32_t)i] = 0u;
+      TfSample tk;
+      tf_lookup(dk, keep ? g.v : 0.0f, tk);
+      A = fmaxf(A, tk.O * g.w);
+    }
     keep = keep && (A >= o.alpha_min);
     Proj p;
     project_one(d, o, g, p);
@@ -275,18 +303,8 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
       count[pid] = 0u;
       continue;
     }
-    const float tau = 2.0f * log32(A / o.alpha_min);
-    const float ex = sqrtf(tau * p.S00);
-    const float ey = sqrtf(tau * p.S11);
-    double xlo = ceil((p.mx - (double)ex) - 0.5);
-    double xhi = floor((p.mx + (double)ex) - 0.5);
-    double ylo = ceil((p.my - (double)ey) - 0.5);
-    double yhi = floor((p.my + (double)ey) - 0.5);
-    xlo = fmax(xlo, 0.0);
-    ylo = fmax(ylo, 0.0);
-    xhi = fmin(xhi, (double)(d.W - 1));
-    yhi = fmin(yhi, (double)(d.H - 1));
-    if (!(xlo <= xhi) || !(ylo <= yhi)) {
+    double xlo, xhi, ylo, yhi;
+    if (!pixel_range(p, A, o, d.W, d.H, xlo, xhi, ylo, yhi)) {
       count[pid] = 0u;
       continue;
     }
@@ -297,16 +315,31 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
     const float c0 = p.S11 / p.det, c1 = -p.S01 / p.det, c2 = p.S00 / p.det;
     const float mxr = (float)(p.mx - 16.0 * (double)x0);
     const float myr = (float)(p.my - 16.0 * (double)y0);
-    float rgb[3] = {tf.rgb[0], tf.rgb[1], tf.rgb[2]};
-    if (g.lit) {
-      Lit L;
-      shade(d, g, tf.rgb, rgb, L);
+    // one record per frame: the shared geometry with the frame's own A and colour.  A = 0
+    // where the frame's own footprint culls the Gaussian (A below alpha_min, or an ellipse
+    // that covers no pixel centre), so the frame keeps exactly the Gaussians it would keep
+    // on its own list and its blend skips the rest.
+    for (int k = 0; k < n_share; ++k) {
+      const FrameDesc& dk = descs[f + k];
+      TfSample tk = tf;
+      if (k > 0) tf_lookup(dk, g.v, tk);
+      float Ak = tk.O * g.w;
+      if (!(Ak >= o.alpha_min)) Ak = 0.0f;
+      if (n_share > 1 && Ak > 0.0f) {
+        double a0, a1, b0, b1;
+        if (!pixel_range(p, Ak, o, d.W, d.H, a0, a1, b0, b1)) Ak = 0.0f;
+      }
+      float rgb[3] = {tk.rgb[0], tk.rgb[1], tk.rgb[2]};
+      if (g.lit) {
+        Lit L;
+        shade(dk, g, tk.rgb, rgb, L);
+      }
+      float4* r = rec + 3 * (size_t)(dk.pair_base + (uint32_t)i);
+      r[0] = make_float4(mxr, myr, c0, c1);
+      r[1] = make_float4(c2, Ak, rgb[0], rgb[1]);
+      r[2] = make_float4(rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
+                         __uint_as_float((uint32_t)(f + k)));
     }
-    float4* r = rec + 3 * (size_t)pid;
-    r[0] = make_float4(mxr, myr, c0, c1);
-    r[1] = make_float4(c2, A, rgb[0], rgb[1]);
-    r[2] = make_float4(rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
-                       __uint_as_float((uint32_t)f));
   }
 }
 

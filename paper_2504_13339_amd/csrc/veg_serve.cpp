@@ -220,8 +220,8 @@ hipError_t run_pipeline(veg_server* s, Slot& sl, const KOpts& ko) {
   e = launch_bin_sort(sl.d_descs, c.max_batch, sl.rec, sl.count, (uint32_t)s->pairs_cap, s->total_tiles_cap, sl.bws,
                       sl.keys, sl.vals, sl.keys_alt, sl.vals_alt, sl.ranges, (uint32_t)s->entries_cap, sl.stream);
   if (e != hipSuccess) return e;
-  return launch_blend_fwd(sl.d_descs, c.max_batch, s->max_tiles_frame, ko, sl.rec, sl.vals, sl.ranges, nullptr,
-                          nullptr, nullptr, nullptr, nullptr, sl.stream);
+  return launch_blend_fwd(sl.d_descs, c.max_batch, 1, s->max_tiles_frame, ko, sl.rec, sl.vals, sl.ranges, nullptr,
+                          nullptr, nullptr, nullptr, nullptr, 0, sl.stream);
 }
 
 // Called with the lock held: writes the batch's descriptors and launches it.
@@ -254,6 +254,7 @@ veg_status launch_batch(veg_server* s, Slot& sl, const std::vector<uint64_t>& id
     d.tiles_y = (d.H + kTile - 1) / kTile;
     d.pair_base = pair_base;
     d.tile_base = tile_base;
+    set_own_list(d, (int)f);
     std::memcpy(d.view, q.r.camera.view, sizeof(d.view));
     d.fx = q.r.camera.fx;
     d.fy = q.r.camera.fy;

@@ -152,8 +152,12 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const 
 
 // Densification statistics: for every Gaussian, over the frames in which it was kept, the
 // norm of the gradient w.r.t. its projected centre and the count of such frames (added).
+// Kept in a frame: its list holds the Gaussian (count of the list owner's pair) and the
+// frame's own A is not culled (A is 0 in the record otherwise; a frame owning its list
+// alone never stores A = 0 for a counted pair).
 __global__ __launch_bounds__(256) void densify_stats_kernel(const FrameDesc* __restrict__ descs, int n_frames, int n,
                                                             const uint32_t* __restrict__ count,
+                                                            const float4* __restrict__ rec,
                                                             const float* __restrict__ g2d, float* __restrict__ acc,
                                                             int32_t* __restrict__ vis) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -161,8 +165,10 @@ __global__ __launch_bounds__(256) void densify_stats_kernel(const FrameDesc* __r
   float a = 0.0f;
   int c = 0;
   for (int f = 0; f < n_frames; ++f) {
-    const size_t pid = (size_t)descs[f].pair_base + (size_t)i;
-    if (count[pid] == 0u) continue;
+    const FrameDesc& d = descs[f];
+    const size_t pid = (size_t)d.pair_base + (size_t)i;
+    if (count[(size_t)descs[d.list_frame].pair_base + (size_t)i] == 0u) continue;
+    if (!(rec[3 * pid + 1].y > 0.0f)) continue;
     const float gx = g2d[pid * 9 + 0], gy = g2d[pid * 9 + 1];
     a += sqrtf(gx * gx + gy * gy);
     ++c;
@@ -209,11 +215,11 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   return hipGetLastError();
 }
 
-hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float* g2d,
-                                float* acc, int32_t* vis, hipStream_t stream) {
+hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float4* rec,
+                                const float* g2d, float* acc, int32_t* vis, hipStream_t stream) {
   if (n <= 0 || n_frames <= 0) return hipSuccess;
   hipLaunchKernelGGL(densify_stats_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, descs, n_frames, n, count,
-                     g2d, acc, vis);
+                     rec, g2d, acc, vis);
   return hipGetLastError();
 }
 

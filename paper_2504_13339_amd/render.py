@@ -69,20 +69,25 @@ class EventTimer:
 
 def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=None, stream=None,
            capacity: Optional[int] = None, timer=NO_TIMER, want_contrib: bool = False,
-           hits: bool = True) -> FwdState:
-    """Forward render of len(cams) frames (one model, one image size).
+           hits: bool = True, shared: bool = False) -> FwdState:
+    """Forward render of len(tfs) frames (one model, one image size).
 
-    With ``capacity`` None the key-list length is read back (one stream synchronisation)
-    and the buffers are sized exactly; otherwise ``capacity`` entries are allocated, no
-    synchronisation happens, and an overflow must be checked with ``veg_bin_overflow``.
-    ``hits`` records which entries were blended anywhere, for a following backward pass
-    (set it False for forward-only rendering)."""
+    Frame f uses cams[f] and tfs[f]; with ``shared`` there are len(tfs) // len(cams) tables
+    per camera instead, frame v * K + k uses cams[v] and tfs[v * K + k], and a view's frames
+    share one projection and key list.  With ``capacity`` None the key-list length is read
+    back (one stream synchronisation) and the buffers are sized exactly; otherwise
+    ``capacity`` entries are allocated, no synchronisation happens, and an overflow must be
+    checked with ``veg_bin_overflow``.  ``hits`` records which entries were blended
+    anywhere, for a following backward pass (set it False for forward-only rendering)."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
     dev = g.means.device
-    proj = V.alloc_proj(g.n, len(cams), device=dev)
+    proj = V.alloc_proj(g.n, len(tfs), device=dev)
     ws = V.alloc_bin_workspace(proj, device=dev)
     with timer("project"):
-        V.veg_project(g, cams, tfs, o, proj=proj, stream=stream)
+        if shared:
+            V.veg_project_views(g, cams, tfs, o, proj=proj, stream=stream)
+        else:
+            V.veg_project(g, cams, tfs, o, proj=proj, stream=stream)
     with timer("bin_count"):
         V.veg_bin_count(proj, ws, sync=False, stream=stream)
     if capacity is None:
@@ -93,7 +98,7 @@ def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=Non
     bins = V.alloc_bins(proj, cap, device=dev, hits=hits)
     with timer("bin_sort"):
         V.veg_bin_sort(proj, ws, bins, stream=stream)
-    F, H, W = len(cams), int(proj.struct.height), int(proj.struct.width)
+    F, H, W = len(tfs), int(proj.struct.height), int(proj.struct.width)
     image = torch.empty((F, 3, H, W), dtype=torch.float32, device=dev)
     t_final = torch.empty((F, H, W), dtype=torch.float32, device=dev)
     n_last = torch.empty((F, H, W), dtype=torch.int32, device=dev)
@@ -215,10 +220,29 @@ class DensifyStats:
         return DensifyStats(a, c)
 
 
+def views_of(frames: Sequence[tuple]) -> int:
+    """Tables per view when ``frames`` is a view-major product (every camera with the same
+    tables, in the same order), else 0."""
+    if not frames:
+        return 0
+    K = 1
+    while K < len(frames) and frames[K][0] == frames[0][0]:
+        K += 1
+    if len(frames) % K != 0:
+        return 0
+    tabs = [t for _, t in frames[:K]]
+    for v in range(len(frames) // K):
+        blk = frames[v * K:(v + 1) * K]
+        if any(c != blk[0][0] for c, _ in blk) or [t for _, t in blk] != tabs:
+            return 0
+    return K
+
+
 def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], frames: Sequence[tuple],
                targets: torch.Tensor, grads: Grads, group: int, opts=None, ssim_lambda: float = 0.0, stream=None,
                loss_acc: Optional[torch.Tensor] = None, read_loss: bool = True, timer=NO_TIMER, on_group=None,
-               want_contrib: bool = False, densify: Optional[DensifyStats] = None) -> StepResult:
+               want_contrib: bool = False, densify: Optional[DensifyStats] = None,
+               shared: bool = False) -> StepResult:
     """One multi-view x multi-TF training step with the image loss
     (1 - lambda) mean|image - target| + lambda mean(1 - SSIM), means over all frames,
     channels and pixels.
@@ -228,10 +252,21 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
     one group's per-pixel state is alive (forward recomputation per group instead of
     storing all frames' lists).  Both loss terms are separable over frames (SSIM's window
     stays inside one image plane), so the accumulated gradient equals the full-step
-    gradient.  With ``densify`` the densification statistics of every group are added."""
+    gradient.  With ``densify`` the densification statistics of every group are added.
+
+    With ``shared`` the frames must be a view-major product of cameras and tables; a
+    group is then a whole number of views (``group`` rounded down to a multiple of the
+    tables per view, at least one view) and each view's frames share one projection and
+    key list."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
     if not 0.0 <= ssim_lambda <= 1.0:
         raise ValueError("ssim_lambda must lie in [0, 1]")
+    K = 1
+    if shared:
+        K = views_of(frames)
+        if K == 0:
+            raise ValueError("shared views need frames ordered as views x the same tables")
+        group = max(K, group // K * K)
     F = len(frames)
     H, W = int(targets.shape[-2]), int(targets.shape[-1])
     M = float(F * 3 * H * W)
@@ -242,8 +277,9 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
     ssim_ws = None
     for f0 in range(0, F, group):
         fr = frames[f0:f0 + group]
-        st = render(g, [cams[c] for c, _ in fr], [tfs[t] for _, t in fr], o, stream=stream, timer=timer,
-                    want_contrib=want_contrib)
+        view_cams = [cams[c] for c, _ in fr[::K]] if shared else [cams[c] for c, _ in fr]
+        st = render(g, view_cams, [tfs[t] for _, t in fr], o, stream=stream, timer=timer,
+                    want_contrib=want_contrib, shared=shared)
         entries.append(st.n_entries)
         d_image = torch.empty_like(st.image)
         tgt = targets[f0:f0 + len(fr)].contiguous()

@@ -19,7 +19,7 @@ __all__ = [
     "Gaussians", "Proj", "Bins", "default_opts", "make_opts", "veg_project", "veg_bin_count", "veg_bin_sort",
     "veg_bin_overflow", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
     "veg_debug_math", "veg_bin_hit_words", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
-    "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_adam_step", "veg_densify_stats",
+    "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_adam_step", "veg_densify_stats", "veg_project_views",
 ]
 
 
@@ -151,6 +151,26 @@ def veg_project(g: Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=
     return proj
 
 
+def veg_project_views(g: Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=None,
+                      proj: Optional[Proj] = None, stream=None) -> Proj:
+    """Projection of len(cams) views x len(tfs) // len(cams) tables; frame v * K + k uses
+    cams[v] and tfs[v * K + k], and the frames of a view share one key list."""
+    nv = len(cams)
+    if nv < 1 or len(tfs) % nv != 0:
+        raise ValueError("need the same number of tables for every view")
+    K = len(tfs) // nv
+    if proj is None:
+        proj = alloc_proj(g.n, nv * K, device=g.means.device)
+    cam_arr = (_lib.veg_camera * nv)(*[camera_struct(c) for c in cams])
+    tf_arr = (_lib.veg_tf * len(tfs))(*[_lib.veg_tf(_ptr(t), int(t.shape[0])) for t in tfs])
+    proj.keep = list(tfs)
+    o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
+    gs = g.struct()
+    check(load().veg_project_views(ctypes.byref(gs), nv, K, cam_arr, tf_arr, ctypes.byref(o),
+                                   ctypes.byref(proj.struct), stream_handle(stream)), "veg_project_views")
+    return proj
+
+
 def alloc_bin_workspace(proj: Proj, device="cuda") -> torch.Tensor:
     nbytes = load().veg_bin_workspace_bytes(proj.n_pairs, 0)
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
@@ -193,7 +213,7 @@ def alloc_bins(proj: Proj, capacity: int, device="cuda", hits: bool = True) -> B
     r = torch.empty(max(1, 2 * int(proj.struct.total_tiles)), dtype=torch.int32, device=device)
     h = None
     if hits:
-        nw = veg_bin_hit_words(capacity, proj.struct.total_tiles)
+        nw = max(1, int(proj.struct.tfs_per_view)) * veg_bin_hit_words(capacity, proj.struct.total_tiles)
         h = torch.empty(max(1, nw), dtype=torch.int64, device=device)
     st = _lib.veg_bins(_ptr(k), _ptr(v), _ptr(ka), _ptr(va), _ptr(r), int(capacity),
                        _ptr(h) if h is not None else None, int(h.numel()) if h is not None else 0)

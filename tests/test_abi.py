@@ -88,3 +88,29 @@ def test_hit_bits_buffer_is_validated_on_host():
     assert b"hit_words" in lib.veg_last_error()
     assert lib.veg_render_bwd(ctypes.byref(p), ctypes.byref(b), None, img, img, img, img, None) == 1
     assert b"hit_words" in lib.veg_last_error()
+
+
+def test_shared_view_hit_bits_and_frame_grouping_on_host():
+    """With tfs_per_view = K the hit-bit buffer needs K blocks of veg_bin_hit_words, and the
+    frame count must be a multiple of K (checked before any launch)."""
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    img = ctypes.c_void_p(0x20000)
+    stride = lib.veg_bin_hit_words(64, 3)
+    p = _lib.veg_proj(1, 3, 16, 16, 1, 1, 3, fake, fake, fake, fake, 3)
+    b = _lib.veg_bins(fake, fake, fake, fake, fake, 64, fake, 3 * stride - 1)
+    assert lib.veg_render_fwd(ctypes.byref(p), ctypes.byref(b), None, img, None, None, None, None) == 1
+    assert b"tfs_per_view" in lib.veg_last_error()
+    p2 = _lib.veg_proj(1, 4, 16, 16, 1, 1, 4, fake, fake, fake, fake, 3)
+    assert lib.veg_render_bwd(ctypes.byref(p2), ctypes.byref(b), None, img, img, img, img, None) == 1
+    assert b"multiple" in lib.veg_last_error()
+
+
+def test_views_of_detects_view_major_products():
+    from paper_2504_13339_amd import render as R
+    assert R.views_of([(0, 0), (0, 1), (1, 0), (1, 1)]) == 2
+    assert R.views_of([(0, 0), (1, 0)]) == 1
+    assert R.views_of([(0, 0), (0, 1), (1, 1), (1, 0)]) == 0
+    assert R.views_of([(0, 0), (0, 1), (1, 0)]) == 0

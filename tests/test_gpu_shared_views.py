@@ -1,0 +1,154 @@
+"""Views rendered with several transfer functions that share one projection and key list
+(veg_project_views): the list and records bit-exact against the oracle's shared-footprint
+mirror, every frame's image and gradients against the per-frame oracle, and the training
+step against the same step without sharing."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import compare_image, hip, image_pixels, luts_to_dev, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+OPTS = dict(synth.DEFAULT_OPTS)
+
+
+def _case(n=3000, views=2, K=3, res=80, tents=False):
+    w = synth.workload(1, n_override=n, views_override=views, tfs_override=K, res_override=res)
+    if tents:
+        w.tfs = synth.tent_tfs(K)
+    return w
+
+
+def _render_shared(w, contrib=False):
+    V, R = hip()
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    st = R.render(g, w.cameras, [luts[t] for _, t in w.frames], OPTS, shared=True, want_contrib=contrib)
+    torch.cuda.synchronize()
+    return g, luts, st
+
+
+def _rects(r):
+    r01, r23 = r[:, 9].view(np.uint32), r[:, 10].view(np.uint32)
+    return np.stack([r01 & 0xFFFF, r01 >> 16, r23 & 0xFFFF, r23 >> 16], 1).astype(np.int64)
+
+
+@pytest.mark.parametrize("K,tents", [(3, False), (10, True), (1, False)])
+def test_shared_key_list_and_records_bit_exact(K, tents):
+    w = _case(K=K, tents=tents)
+    g, luts, st = _render_shared(w)
+    assert int(st.proj.struct.tfs_per_view) == K
+    n, F = w.gaussians.n, len(w.frames)
+    count = st.proj.count.cpu().numpy().view(np.uint32)[: n * F].astype(np.int64).reshape(F, n)
+    depth = st.proj.depth.cpu().numpy().view(np.uint32)[: n * F].reshape(F, n)
+    rec = st.proj.rec.cpu().numpy()[: n * F * 12].reshape(F, n, 12)
+    fps = []
+    geo = [0, 1, 2, 3, 4, 9, 10]
+    for v, cam in enumerate(w.cameras):
+        un = oracle.footprint_shared_f32(w.gaussians, cam, w.tfs, OPTS)
+        kept = un.count > 0
+        o = v * K
+        assert np.array_equal(count[o], un.count), f"view {v}: shared tile counts differ"
+        assert np.array_equal(depth[o][kept], un.depth_bits[kept])
+        assert np.array_equal(_rects(rec[o][kept]), un.rect[kept])
+        for k in range(K):
+            f = o + k
+            if k > 0:
+                assert not count[f].any(), f"frame {f}: only the list owner is counted"
+            fps.append(un if k == 0 else dataclasses.replace(un, count=np.zeros_like(un.count),
+                                                               keep=np.zeros_like(un.keep)))
+            r = rec[f][kept]
+            assert np.array_equal(np.ascontiguousarray(r[:, geo]).view(np.uint32),
+                                  np.ascontiguousarray(rec[o][kept][:, geo]).view(np.uint32))
+            # the frame's own A where its own footprint keeps the Gaussian, else 0
+            own = oracle.footprint_f32(w.gaussians, cam, w.tfs[k], OPTS)
+            a_ref = np.where(own.keep[kept], own.A[kept], np.float32(0)).astype(np.float32)
+            assert np.array_equal(r[:, 5], a_ref), f"frame {f}: per-frame A"
+            assert np.all(own.keep <= kept)
+            assert np.array_equal(r[:, 11].view(np.uint32), np.full(kept.sum(), f, np.uint32))
+    tiles, depths, pairs, ranges, _ = oracle.key_list(fps, [w.cameras[c] for c, _ in w.frames])
+    E = tiles.shape[0]
+    assert st.n_entries == E
+    assert np.array_equal(st.bins.keys.cpu().numpy().view(np.uint32)[:E].astype(np.int64), tiles)
+    assert np.array_equal(st.bins.vals.cpu().numpy().view(np.uint32)[:E].astype(np.int64), pairs)
+    rg = st.bins.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
+    assert np.array_equal(rg, ranges)
+
+
+@pytest.mark.parametrize("K,tents,views", [(3, False, 2), (10, True, 1), (5, True, 2)])
+def test_shared_images_match_oracle(K, tents, views):
+    """Walks of several frames (3; 3 + 3 + 4 for ten tables; 2 + 3 for five)."""
+    w = _case(n=2000, K=K, tents=tents, res=64, views=views)
+    g, luts, st = _render_shared(w)
+    for f, (ci, ti) in enumerate(w.frames):
+        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], OPTS)
+        compare_image(image_pixels(st.image[f]), res)
+
+
+def test_shared_blend_counts_equal_unshared():
+    """Blended-entry counts per pixel and final transmittance: sharing only changes the
+    centre's rounding, so almost every pixel matches the unshared render exactly."""
+    V, R = hip()
+    w = _case(n=3000, K=4, res=96)
+    g, luts, st = _render_shared(w, contrib=True)
+    ref = R.render(g, [w.cameras[c] for c, _ in w.frames], [luts[t] for _, t in w.frames], OPTS, want_contrib=True)
+    torch.cuda.synchronize()
+    same = (st.n_contrib == ref.n_contrib).float().mean().item()
+    assert same >= 0.999
+    assert (st.image - ref.image).abs().max().item() <= 1e-3
+    assert ((st.image - ref.image).abs() > 1e-5).float().mean().item() <= 1e-3
+
+
+def test_shared_gradients_match_oracle():
+    V, R = hip()
+    w = _case(n=2000, K=3, res=64)
+    g, luts, st = _render_shared(w)
+    F, H, W = len(w.frames), 64, 64
+    rng = np.random.default_rng(91)
+    d_all = np.zeros((F, 3, H, W), np.float32)
+    acc = None
+    for f, (ci, ti) in enumerate(w.frames):
+        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], OPTS)
+        d = rng.standard_normal((H * W, 3)).astype(np.float32).astype(np.float64)
+        d[res.flag | res.flag_grad] = 0.0
+        d_all[f] = d.T.reshape(3, H, W)
+        gr = oracle.gradients(w.gaussians, w.cameras[ci], w.tfs[ti], OPTS, d)
+        cur = {k: getattr(gr, k) for k in ("d_means", "d_log_scales", "d_quats", "d_scalars")}
+        acc = cur if acc is None else {k: acc[k] + cur[k] for k in acc}
+    grads = R.Grads.zeros(g)
+    R.render_backward(g, st, torch.as_tensor(d_all).cuda(), grads)
+    torch.cuda.synchronize()
+    for k, ref in acc.items():
+        assert rel_err(getattr(grads, k).cpu().numpy(), ref) <= 1e-3, k
+
+
+def test_shared_train_step_matches_unshared():
+    """Loss (1 - 0.2) L1 + 0.2 (1 - SSIM) over 3 views x 2 tables in groups of two views;
+    a frame of a shared view keeps exactly the Gaussians its own footprint keeps, so the
+    visibility counts are equal."""
+    V, R = hip()
+    w = _case(n=4000, views=3, K=2, res=80)
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    rng = np.random.default_rng(92)
+    tgt = torch.as_tensor(rng.uniform(0, 1, (len(w.frames), 3, 80, 80)).astype(np.float32)).cuda()
+    out = {}
+    for shared in (False, True):
+        grads = R.Grads.zeros(g)
+        dens = R.DensifyStats.zeros(w.gaussians.n)
+        res = R.train_step(g, w.cameras, luts, w.frames, tgt, grads, 4, OPTS, ssim_lambda=0.2, densify=dens,
+                           shared=shared)
+        torch.cuda.synchronize()
+        out[shared] = (res.loss, {k: getattr(grads, k).cpu().numpy() for k in
+                                  ("d_means", "d_log_scales", "d_quats", "d_scalars")},
+                       dens.vis_count.cpu().numpy())
+    assert abs(out[True][0] - out[False][0]) <= 1e-5 * abs(out[False][0])
+    for k, v in out[True][1].items():
+        assert rel_err(v, out[False][1][k]) <= 1e-3, k
+    assert np.array_equal(out[True][2], out[False][2])
+
