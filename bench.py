@@ -49,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "train-1M-1024px-16x3_hbm_traffic.md")
 BLEND_SOURCES = ("paper_2504_13339_amd/csrc/veg_blend.hip", "paper_2504_13339_amd/csrc/veg_internal.h")
-PROFILE_KERNEL = {"blend_bwd": "blend_bwd_kernel", "blend_fwd": "void blend_fwd_kernel<false, true>"}
+PROFILE_KERNEL = {"blend_bwd": "blend_bwd_kernel", "blend_fwd": "void blend_fwd_kernel<false, true, {shared}>"}
 
 
-def profiled_traffic(name):
+def profiled_traffic(name, shared=True):
     """HBM bytes per launch of a blend kernel from the committed counter summary (FETCH_SIZE
     and WRITE_SIZE passes calibrated on a plain copy), or None when the blend sources have
     changed since it was taken."""
@@ -69,7 +69,8 @@ def profiled_traffic(name):
     m = re.search(r"sha256\(veg_blend\.hip \+ veg_internal\.h\): ([0-9a-f]{64})", text)
     if not m or m.group(1) != h.hexdigest():
         return None
-    row = re.search(r"^\| `" + re.escape(PROFILE_KERNEL[name]) + r"` \|([^\n]*)$", text, flags=re.M)
+    kernel = PROFILE_KERNEL[name].format(shared="true" if shared else "false")
+    row = re.search(r"^\| `" + re.escape(kernel) + r"` \|([^\n]*)$", text, flags=re.M)
     if not row:
         return None
     return float(row.group(1).split("|")[-2])
@@ -240,7 +241,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--group", type=int, default=16, help="frames per recompute group")
+    ap.add_argument("--group", type=int, default=48, help="frames per recompute group")
+    ap.add_argument("--no-shared", dest="shared", action="store_false",
+                    help="give every frame its own projection and key list (veg_project) instead of sharing "
+                         "them between the frames of one camera (veg_project_views)")
     ap.add_argument("--n", type=int, default=None, help="override Gaussian count (testing only)")
     ap.add_argument("--views", type=int, default=None)
     ap.add_argument("--tfs", type=int, default=None)
@@ -283,6 +287,9 @@ def main():
     loss_acc = torch.empty(1, dtype=torch.float64, device="cuda")
     t_min = float(w.opts["t_min"])
 
+    K = R.views_of(w.frames) if args.shared else 1
+    group_frames = max(K, args.group // K * K)
+
     # warm-up; the first warm-up step also counts the visited evaluations per group
     counts = {"fwd": 0, "bwd": 0, "blended": 0}
 
@@ -293,11 +300,16 @@ def main():
         counts["blended"] += c
 
     # the counting pass is an extra (untimed) step that also asks the forward for n_contrib
-    res = R.train_step_l1(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, loss_acc=loss_acc,
-                          on_group=count_group, want_contrib=True)
+    def l1_step(gm, gr, shared=args.shared, **kw):
+        return R.train_step(gm, w.cameras, luts, w.frames, targets, gr, args.group, w.opts, loss_acc=loss_acc,
+                            shared=shared, **kw)
+
+    # Visits are counted on every frame's own list (the algorithm's work); a frame on a
+    # shared list visits the same entries and drops the rest at staging.
+    res = l1_step(g, grads, shared=False, on_group=count_group, want_contrib=True)
     log(f"bench: counting step loss {res.loss:.6f} entries {res.n_entries}")
     for k in range(args.warmup):
-        res = R.train_step_l1(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, loss_acc=loss_acc)
+        res = l1_step(g, grads)
         log(f"bench: warm-up step {k} loss {res.loss:.6f}")
 
     # timed steps
@@ -307,8 +319,7 @@ def main():
     step_ms = []
     for k in range(args.steps):
         ts = time.perf_counter()
-        res = R.train_step_l1(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, loss_acc=loss_acc,
-                              timer=timer)   # reading the loss ends the step on the host
+        res = l1_step(g, grads, timer=timer)   # reading the loss ends the step on the host
         step_ms.append((time.perf_counter() - ts) * 1e3)
         if k % 10 == 0 or k == args.steps - 1:
             log(f"bench: step {k} loss {res.loss:.6f}")
@@ -325,9 +336,10 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for k in range(args.steps):
-        for f0 in range(0, F, args.group):
-            fr = w.frames[f0:f0 + args.group]
-            st = R.render(g, [w.cameras[c] for c, _ in fr], [luts[t] for _, t in fr], w.opts, hits=False)
+        for f0 in range(0, F, group_frames):
+            fr = w.frames[f0:f0 + group_frames]
+            cams = [w.cameras[c] for c, _ in (fr[::K] if args.shared else fr)]
+            st = R.render(g, cams, [luts[t] for _, t in fr], w.opts, hits=False, shared=args.shared)
             del st
     torch.cuda.synchronize()
     fwd_mpix = F * H * W * args.steps / (time.perf_counter() - t1) / 1e6
@@ -341,11 +353,11 @@ def main():
         gl = V.Gaussians(g.means, g.log_scales, g.quats, g.scalars, g.weights,
                          **{k: torch.as_tensor(getattr(sh, k)).cuda() for k in V.LIGHTING})
         grads_l = R.Grads.zeros(gl)
-        R.train_step_l1(gl, w.cameras, luts, w.frames, targets, grads_l, args.group, w.opts, loss_acc=loss_acc)
+        l1_step(gl, grads_l)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         for k in range(args.lit_steps):
-            R.train_step_l1(gl, w.cameras, luts, w.frames, targets, grads_l, args.group, w.opts, loss_acc=loss_acc)
+            l1_step(gl, grads_l)
         torch.cuda.synchronize()
         lit_mpix = F * H * W * args.lit_steps / (time.perf_counter() - t2) / 1e6
         del grads_l, gl
@@ -364,6 +376,7 @@ def main():
         def full_iter(timer=R.NO_TIMER):
             grads.zero_()
             r = R.train_step(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, ssim_lambda=0.2,
+                             shared=args.shared,
                              loss_acc=loss_acc, densify=dens, timer=timer, read_loss=False)
             with timer("adam"):
                 opt.step([grads.d_means, grads.d_log_scales, grads.d_quats, grads.d_scalars] +
@@ -392,7 +405,7 @@ def main():
         flops = (visits * FLOPS_VISIT + counts["blended"] * blend_flops) / n_launch
         ach = flops / (avg_ms * 1e-3) / 1e12
         return {"bound": "alu", "kernel": name, "achieved": round(ach, 3), "peak": round(VALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4), "traffic": profiled_traffic(name),
+                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4), "traffic": profiled_traffic(name, args.shared),
                 "traffic_unit": "HBM bytes per launch",
                 "avg_launch_ms": round(avg_ms, 4), "visited_pairs_per_launch": visits // n_launch,
                 "blended_pairs_per_launch": counts["blended"] // n_launch,
@@ -406,7 +419,7 @@ def main():
         "step_ms_p10_p50_p90": [round(float(x), 3) for x in np.percentile(step_ms, [10, 50, 90])],
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "gaussians": w.gaussians.n, "frames": F, "width": W, "height": H,
-                   "group": args.group},
+                   "group": group_frames, "shared_views": bool(args.shared)},
         "fwd_mpix_s": round(fwd_mpix, 2),
         "lit_mpix_s": None if lit_mpix is None else round(lit_mpix, 2),
         "full_iteration": full,

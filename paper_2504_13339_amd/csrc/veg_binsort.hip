@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void gather_items_kernel(const float4* __
     const uint32_t p = sorted_vals[j];
     const float4 r2 = rec[3 * (size_t)p + 2];
     const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
-    items[j] = make_uint4(p, a, b, __float_as_uint(r2.w));
+    items[j] = make_uint4(p, a, b, __float_as_uint(r2.w) & kFrameMask);
     counts[j] = ((b & 0xffffu) - (a & 0xffffu) + 1u) * ((b >> 16) - (a >> 16) + 1u);
   }
 }

@@ -20,7 +20,6 @@ namespace veg {
 namespace {
 
 constexpr int kBatch = 64;
-constexpr int kMaxWalkFrames = 4;   // frames blended together in one walk of a shared list
 constexpr float kLog2e = 0x1.715476p+0f;
 
 struct Staged {
@@ -76,155 +75,142 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
 // With kHits, bit k of word b records whether entry rg.x + 64 b + k was blended into any
 // pixel of the tile (the backward pass skips the others).
 //
-// kFrames frames that share one key list (one camera, several transfer functions) are
-// blended in the same walk: the entry's staging and the per-pixel quadratic form are
-// computed once, and each frame adds its own log2 A before its own skip test, blend and
-// stop.  Block y is view y; its list belongs to frame y * per_view, and this launch blends
-// frames y * per_view + slot0 + [0, kFrames).  Frame k's record of an entry sits at the
-// list's pair id plus the difference of the two frames' pair bases.
-template <int kFrames, bool kCount, bool kHits>
-__global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restrict__ descs, int per_view, int slot0,
-                                                       KOpts o, const float4* __restrict__ rec,
+// Block y renders frame y over the key list of frame list_frame (itself unless the frame
+// shares its view's list); the frame's record of an entry sits at the list's pair id plus
+// the difference of the two frames' pair bases.  With kShared the staged batch keeps only
+// the entries live for this frame (its own A > 0 and the tile inside its own rectangle,
+// from the record's insets), packed to the front of the batch, so the walk costs what the
+// frame's own list would.
+template <bool kCount, bool kHits, bool kShared>
+__global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
+                                                       const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
                                                        const uint2* __restrict__ ranges, float* __restrict__ image,
                                                        float* __restrict__ tfinal, int32_t* __restrict__ nlast,
                                                        int32_t* __restrict__ ncontrib, uint64_t* __restrict__ hits,
                                                        uint64_t hit_stride) {
-  const int fo = blockIdx.y * per_view;   // list owner
-  const int fb = fo + slot0;              // first frame blended here
-  const FrameDesc& d = descs[fo];
+  const FrameDesc& d = descs[blockIdx.y];
+  const FrameDesc& dl = kShared ? descs[d.list_frame] : d;
   const int tile = blockIdx.x;
   if (tile >= d.tiles_x * d.tiles_y) return;
   const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
-  const uint2 rg = ranges[d.tile_base + tile];
+  const uint2 rg = ranges[dl.tile_base + tile];
+  const uint32_t roff = kShared ? d.pair_base - dl.pair_base : 0u;
+  uint64_t* fhits = kHits ? hits + (kShared ? (uint64_t)d.slot * hit_stride : 0ull) : nullptr;
   const int lane = threadIdx.x;
   const int qx = lane & 7, qy = lane >> 3;
   // tile-local pixel centres: quadrant r sits at (8 (r & 1), 8 (r >> 1))
   const float pxl0 = (float)qx + 0.5f, pxl1 = (float)(qx + 8) + 0.5f;
   const float pyl0 = (float)qy + 0.5f, pyl1 = (float)(qy + 8) + 0.5f;
-  uint32_t roff[kFrames];
-#pragma unroll
-  for (int f = 0; f < kFrames; ++f) roff[f] = descs[fb + f].pair_base - d.pair_base;
 
   __shared__ float4 s_geo[kBatch];   // mx, my, q0, q1
-  __shared__ float4 s_col[kBatch];   // q2, l2A, R, G of the first frame
-  __shared__ float s_b[kBatch];      // B of the first frame
-  __shared__ float4 s_more[kFrames > 1 ? kFrames - 1 : 1][kBatch];   // l2A, R, G, B of the others
+  __shared__ float4 s_col[kBatch];   // q2, l2A, R, G
+  __shared__ float s_b[kBatch];      // B
+  __shared__ int s_k[kShared ? kBatch : 1];   // batch position of a packed entry
 
   const float tmin = o.t_min;
-  float T[kFrames][4], C[kFrames][4][3];
-  int last[kFrames][4], cnt[kFrames][4];
+  float T[4], C[4][3];
+  int last[4], cnt[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int px = tx * kTile + qx + 8 * (r & 1), py = ty * kTile + qy + 8 * (r >> 1);
-#pragma unroll
-    for (int f = 0; f < kFrames; ++f) {
-      T[f][r] = (px < d.W && py < d.H) ? 1.0f : 0.0f;
-      C[f][r][0] = C[f][r][1] = C[f][r][2] = 0.0f;
-      last[f][r] = -1;
-      cnt[f][r] = 0;
-    }
+    T[r] = (px < d.W && py < d.H) ? 1.0f : 0.0f;
+    C[r][0] = C[r][1] = C[r][2] = 0.0f;
+    last[r] = -1;
+    cnt[r] = 0;
   }
   const float l2min = o.log2_alpha_min;
   const float aclamp = o.alpha_clamp;
   for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
-    bool done = true;
-#pragma unroll
-    for (int f = 0; f < kFrames; ++f) done = done && T[f][0] < tmin && T[f][1] < tmin && T[f][2] < tmin && T[f][3] < tmin;
-    if (__all(done)) break;
+    if (__all(T[0] < tmin && T[1] < tmin && T[2] < tmin && T[3] < tmin)) break;
     const uint32_t j = base + lane;
-    if (j < rg.y) {
-      const uint32_t p = vals[j];
-      const float4* rp = rec + 3 * (size_t)(p + roff[0]);
-      const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
-      const Staged s = stage(r0, r1, r2, tx, ty);
-      s_geo[lane] = make_float4(s.mx, s.my, s.q0, s.q1);
-      s_col[lane] = make_float4(s.q2, s.l2A, r1.z, r1.w);
-      s_b[lane] = r2.x;
-#pragma unroll
-      for (int f = 1; f < kFrames; ++f) {
-        const float4* rq = rec + 3 * (size_t)(p + roff[f]);
-        const float4 q1 = rq[1], q2 = rq[2];
-        s_more[f - 1][lane] = make_float4(__log2f(q1.y), q1.z, q1.w, q2.x);
+    int n;
+    if constexpr (kShared) {
+      float4 r0, r1, r2;
+      bool live = j < rg.y;
+      if (live) {
+        const float4* rp = rec + 3 * (size_t)(vals[j] + roff);
+        r0 = rp[0];
+        r1 = rp[1];
+        r2 = rp[2];
+        const uint32_t in = __float_as_uint(r2.w) >> kFrameBits;
+        const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
+        const int x0 = (int)((a & 0xffffu) + (in & 31u)), y0 = (int)((a >> 16) + ((in >> 5) & 31u));
+        const int x1 = (int)((b & 0xffffu) - ((in >> 10) & 31u)), y1 = (int)((b >> 16) - ((in >> 15) & 31u));
+        live = r1.y > 0.0f && tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1;
       }
+      const uint64_t m = __ballot(live);
+      const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      n = __popcll(m);
+      if (live) {
+        const Staged s = stage(r0, r1, r2, tx, ty);
+        s_geo[slot] = make_float4(s.mx, s.my, s.q0, s.q1);
+        s_col[slot] = make_float4(s.q2, s.l2A, r1.z, r1.w);
+        s_b[slot] = r2.x;
+        s_k[slot] = lane;
+      }
+    } else {
+      if (j < rg.y) {
+        const float4* rp = rec + 3 * (size_t)vals[j];
+        const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
+        const Staged s = stage(r0, r1, r2, tx, ty);
+        s_geo[lane] = make_float4(s.mx, s.my, s.q0, s.q1);
+        s_col[lane] = make_float4(s.q2, s.l2A, r1.z, r1.w);
+        s_b[lane] = r2.x;
+      }
+      n = (int)min((uint32_t)kBatch, rg.y - base);
     }
     __syncthreads();
-    const int n = (int)min((uint32_t)kBatch, rg.y - base);
-    uint64_t lh[kFrames];   // bit k: this lane blended entry base + k (per frame)
-#pragma unroll
-    for (int f = 0; f < kFrames; ++f) lh[f] = 0;
+    uint64_t lh = 0;   // bit k: this lane blended entry base + k
     uint64_t bk = 1;
     for (int k = 0; k < n; ++k, bk <<= 1) {
+      const int kk = kShared ? s_k[k] : k;   // position in the batch
       const float4 g = s_geo[k];
       const float4 c = s_col[k];
+      const float cb = s_b[k];
       const float dx0 = pxl0 - g.x, dx1 = pxl1 - g.x;
+      const float eb0 = exponent_base(g.z, c.y, dx0), eb1 = exponent_base(g.z, c.y, dx1);
       const float q1dx0 = g.w * dx0, q1dx1 = g.w * dx1;
       const float dy0 = pyl0 - g.y, dy1 = pyl1 - g.y;
 #pragma unroll
-      for (int f = 0; f < kFrames; ++f) {
-        float l2A, cr, cg, cb;
-        if (f == 0) {
-          l2A = c.y;
-          cr = c.z;
-          cg = c.w;
-          cb = s_b[k];
-        } else {
-          const float4 m = s_more[f > 0 ? f - 1 : 0][k];
-          l2A = m.x;
-          cr = m.y;
-          cg = m.z;
-          cb = m.w;
-        }
-        const float eb0 = exponent_base(g.z, l2A, dx0), eb1 = exponent_base(g.z, l2A, dx1);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, c.x, (r >> 1) ? dy1 : dy0);
-          if (T[f][r] >= tmin && e >= l2min) {
-            if (kHits) lh[f] |= bk;
-            const float alpha = fminf(__builtin_amdgcn_exp2f(e), aclamp);
-            const float w = alpha * T[f][r];
-            C[f][r][0] = fmaf(w, cr, C[f][r][0]);
-            C[f][r][1] = fmaf(w, cg, C[f][r][1]);
-            C[f][r][2] = fmaf(w, cb, C[f][r][2]);
-            T[f][r] = fmaf(-alpha, T[f][r], T[f][r]);
-            last[f][r] = (int)(base + k);
-            if (kCount) ++cnt[f][r];
-          }
+      for (int r = 0; r < 4; ++r) {
+        const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, c.x, (r >> 1) ? dy1 : dy0);
+        if (T[r] >= tmin && e >= l2min) {
+          if (kHits) lh |= kShared ? (1ull << kk) : bk;
+          const float alpha = fminf(__builtin_amdgcn_exp2f(e), aclamp);
+          const float w = alpha * T[r];
+          C[r][0] = fmaf(w, c.z, C[r][0]);
+          C[r][1] = fmaf(w, c.w, C[r][1]);
+          C[r][2] = fmaf(w, cb, C[r][2]);
+          T[r] = fmaf(-alpha, T[r], T[r]);
+          last[r] = (int)base + kk;
+          if (kCount) ++cnt[r];
         }
       }
     }
     if (kHits) {
-#pragma unroll
-      for (int f = 0; f < kFrames; ++f) {
-        const uint64_t word = wave_or_u64(lh[f]);
-        if (lane == 63)
-          hits[(uint64_t)(slot0 + f) * hit_stride + hit_word(rg.x, d.tile_base + tile, (base - rg.x) >> 6)] = word;
-      }
+      const uint64_t word = wave_or_u64(lh);
+      if (lane == 63) fhits[hit_word(rg.x, dl.tile_base + tile, (base - rg.x) >> 6)] = word;
     }
     __syncthreads();
   }
   const size_t HW = (size_t)d.W * d.H;
+  const bool own = d.out_image != nullptr;   // per-frame outputs (server batches)
+  float* img = own ? d.out_image : image + (size_t)blockIdx.y * 3 * HW;
+  float* tf = own ? d.out_tfinal : (tfinal ? tfinal + (size_t)blockIdx.y * HW : nullptr);
+  int32_t* nl = own ? d.out_nlast : (nlast ? nlast + (size_t)blockIdx.y * HW : nullptr);
+  int32_t* nc = own ? nullptr : (ncontrib ? ncontrib + (size_t)blockIdx.y * HW : nullptr);
 #pragma unroll
-  for (int f = 0; f < kFrames; ++f) {
-    const int fr = fb + f;
-    const FrameDesc& df = descs[fr];
-    const bool own = df.out_image != nullptr;   // per-frame outputs (server batches)
-    float* img = own ? df.out_image : image + (size_t)fr * 3 * HW;
-    float* tf = own ? df.out_tfinal : (tfinal ? tfinal + (size_t)fr * HW : nullptr);
-    int32_t* nl = own ? df.out_nlast : (nlast ? nlast + (size_t)fr * HW : nullptr);
-    int32_t* nc = own ? nullptr : (ncontrib ? ncontrib + (size_t)fr * HW : nullptr);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int px = tx * kTile + qx + 8 * (r & 1), py = ty * kTile + qy + 8 * (r >> 1);
-      if (px < d.W && py < d.H) {
-        const size_t pi = (size_t)py * d.W + px;
-        img[pi] = C[f][r][0] + T[f][r] * df.bg[0];
-        img[HW + pi] = C[f][r][1] + T[f][r] * df.bg[1];
-        img[2 * HW + pi] = C[f][r][2] + T[f][r] * df.bg[2];
-        if (tf) tf[pi] = T[f][r];
-        if (nl) nl[pi] = last[f][r];
-        if (kCount && nc) nc[pi] = cnt[f][r];
-      }
+  for (int r = 0; r < 4; ++r) {
+    const int px = tx * kTile + qx + 8 * (r & 1), py = ty * kTile + qy + 8 * (r >> 1);
+    if (px < d.W && py < d.H) {
+      const size_t pi = (size_t)py * d.W + px;
+      img[pi] = C[r][0] + T[r] * d.bg[0];
+      img[HW + pi] = C[r][1] + T[r] * d.bg[1];
+      img[2 * HW + pi] = C[r][2] + T[r] * d.bg[2];
+      if (tf) tf[pi] = T[r];
+      if (nl) nl[pi] = last[r];
+      if (kCount && nc) nc[pi] = cnt[r];
     }
   }
 }
@@ -301,6 +287,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   const uint2 rg = ranges[dl.tile_base + tile];
   if (rg.y <= rg.x) return;
   const uint32_t roff = d.pair_base - dl.pair_base;   // list pair id -> this frame's pair id
+  const bool shared = dl.n_share > 1;
   const uint64_t* fhits = hits ? hits + (uint64_t)d.slot * hit_stride : nullptr;
   const int lane = threadIdx.x;
   const int qx = lane & 7, qy = lane >> 3;
@@ -315,6 +302,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   __shared__ float4 s_q[kBatch];     // q2, l2A, R, G
   __shared__ float4 s_con[kBatch];   // conic a, b, c, B
   __shared__ float2 s_pa[kBatch];    // pair id (bits), 1/A
+  __shared__ int s_pos[kBatch];      // position of a staged entry in its batch
   __shared__ float s_acc[kBatch][9];
 
   float T[4], S[4][3], gr[4][3];
@@ -348,22 +336,11 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   const bool own1 = (bi & 3) == 0;
   for (int hi = jmax + 1; hi > (int)rg.x; hi -= kBatch) {
     const int lo = max((int)rg.x, hi - kBatch);
-    const int j = lo + lane;
-    if (j < hi) {
-      const uint32_t p = vals[j] + roff;
-      const float4* rp = rec + 3 * (size_t)p;
-      const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
-      const Staged s = stage(r0, r1, r2, tx, ty);
-      s_geo[lane] = make_float4(s.mx, s.my, s.q0, s.q1);
-      s_q[lane] = make_float4(s.q2, s.l2A, r1.z, r1.w);
-      s_con[lane] = make_float4(r0.z, r0.w, r1.x, r2.x);
-      // A = 0 marks an entry this frame's table culls (shared lists): never blended, and its
-      // all-zero sums must not become 0 * inf in the flush
-      s_pa[lane] = make_float2(__uint_as_float(p), r1.y > 0.0f ? 1.0f / r1.y : 0.0f);
-    }
-    __syncthreads();
-    // entries of this batch to visit, highest first: all, or those the forward pass blended
     const int nb = hi - lo;
+    const int j = lo + lane;
+    // entries of this batch to visit: those the forward pass blended (hit bits), else all
+    // that are live for this frame.  Only they are staged, packed to the front of the batch
+    // in list order; s_pos keeps each one's position in the batch.
     uint64_t todo = ~0ull >> (64 - nb);
     if (fhits) {
       const uint32_t off = (uint32_t)lo - rg.x;
@@ -373,9 +350,40 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       if (sh != 0 && sh + (uint32_t)nb > 64u) v |= fhits[w0 + 1] << (64u - sh);
       todo &= v;
     }
+    bool mine = (todo >> lane) & 1ull;
+    uint32_t p = 0u;
+    float4 r0, r1, r2;
+    if (mine) {
+      p = vals[j] + roff;
+      const float4* rp = rec + 3 * (size_t)p;
+      r0 = rp[0];
+      r1 = rp[1];
+      r2 = rp[2];
+      if (shared && !fhits) {   // the forward pass's live test for a frame on a shared list
+        const uint32_t in = __float_as_uint(r2.w) >> kFrameBits;
+        const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
+        const int x0 = (int)((a & 0xffffu) + (in & 31u)), y0 = (int)((a >> 16) + ((in >> 5) & 31u));
+        const int x1 = (int)((b & 0xffffu) - ((in >> 10) & 31u)), y1 = (int)((b >> 16) - ((in >> 15) & 31u));
+        mine = r1.y > 0.0f && tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1;
+      }
+    }
+    todo = __ballot(mine);
+    const int cnt = __popcll(todo);
+    if (mine) {
+      const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(todo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)todo, 0u));
+      const Staged s = stage(r0, r1, r2, tx, ty);
+      s_geo[slot] = make_float4(s.mx, s.my, s.q0, s.q1);
+      s_q[slot] = make_float4(s.q2, s.l2A, r1.z, r1.w);
+      s_con[slot] = make_float4(r0.z, r0.w, r1.x, r2.x);
+      // A = 0 marks an entry this frame's footprint culls (shared lists): never blended, and
+      // its all-zero sums must not become 0 * inf in the flush
+      s_pa[slot] = make_float2(__uint_as_float(p), r1.y > 0.0f ? 1.0f / r1.y : 0.0f);
+      s_pos[slot] = lane;
+    }
+    __syncthreads();
     // adjoint of entry k of the staged batch for this lane's four pixels (updates T, S)
     auto entry_adjoint = [&](const int k, float (&acc)[9], bool& contrib) {
-      const int jj = lo + k;
+      const int jj = lo + s_pos[k];
       const float4 g = s_geo[k];
       const float4 q = s_q[k];
       const float cbv = s_con[k].w;
@@ -416,12 +424,9 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       }
     };
     // entries go in pairs (A, then the next lower B) so that one butterfly reduces both
-    while (todo != 0ull) {
-      const int ka = 63 - __builtin_clzll(todo);
-      todo &= ~(1ull << ka);
-      const bool has_b = todo != 0ull;
-      const int kb = has_b ? 63 - __builtin_clzll(todo) : ka;
-      if (has_b) todo &= ~(1ull << kb);
+    for (int ka = cnt - 1; ka >= 0; ka -= 2) {
+      const bool has_b = ka > 0;
+      const int kb = has_b ? ka - 1 : ka;
       // acc: 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 R, 6 G, 7 B, 8 S_d
       float acc_a[9], acc_b[9];
 #pragma unroll
@@ -443,11 +448,11 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       }
     }
     __syncthreads();
-    // flush.  Lane l first turns entry l's sums into screen-space gradients (in place);
-    // then the 64 x 9 values go out in nine rounds over consecutive (entry, component)
-    // slots, so the lanes of one atomic instruction cover about seven entries' contiguous
-    // nine-float records (a few cache lines) instead of 64 scattered words.
-    if (lane < nb) {
+    // flush.  Lane l first turns staged entry l's sums into screen-space gradients (in
+    // place); then the cnt x 9 values go out in rounds of 64 over consecutive (entry,
+    // component) slots, so the lanes of one atomic instruction cover about seven entries'
+    // contiguous nine-float records (a few cache lines) instead of 64 scattered words.
+    if (lane < cnt) {
       const float4 cn = s_con[lane];
       const float sx = s_acc[lane][0], sy = s_acc[lane][1];
       s_acc[lane][0] = -(cn.x * sx + cn.y * sy);
@@ -459,10 +464,10 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
     __syncthreads();
     float* flat = &s_acc[0][0];
 #pragma unroll 1   // unrolled, the rounds' loads are hoisted and the kernel needs ~40 more VGPRs
-    for (int t = 0; t < 9; ++t) {
+    for (int t = 0; t * kBatch < 9 * cnt; ++t) {
       const int idx = t * kBatch + lane;
       const int e = idx / 9, c = idx - 9 * e;
-      if (e < nb) {
+      if (e < cnt) {
         const float v = flat[idx];
         flat[idx] = 0.0f;
         if (v != 0.0f) unsafeAtomicAdd(g2d + (size_t)__float_as_uint(s_pa[e].x) * 9 + c, v);
@@ -476,54 +481,39 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
 
 namespace {
 
-template <int kFrames>
-void launch_fwd_frames(dim3 grid, hipStream_t stream, const FrameDesc* descs, int per_view, int slot0, const KOpts& o,
-                       const float4* rec, const uint32_t* vals, const uint2* rg, float* image, float* tfinal,
-                       int32_t* nlast, int32_t* ncontrib, uint64_t* hits, uint64_t hit_stride) {
+template <bool kShared>
+void launch_fwd(dim3 grid, hipStream_t stream, const FrameDesc* descs, const KOpts& o, const float4* rec,
+                const uint32_t* vals, const uint2* rg, float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
+                uint64_t* hits, uint64_t hit_stride) {
   const dim3 block(64);
   if (ncontrib && hits)
-    hipLaunchKernelGGL((blend_fwd_kernel<kFrames, true, true>), grid, block, 0, stream, descs, per_view, slot0, o, rec,
-                       vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride);
+    hipLaunchKernelGGL((blend_fwd_kernel<true, true, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
+                       tfinal, nlast, ncontrib, hits, hit_stride);
   else if (ncontrib)
-    hipLaunchKernelGGL((blend_fwd_kernel<kFrames, true, false>), grid, block, 0, stream, descs, per_view, slot0, o,
-                       rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride);
+    hipLaunchKernelGGL((blend_fwd_kernel<true, false, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
+                       tfinal, nlast, ncontrib, hits, hit_stride);
   else if (hits)
-    hipLaunchKernelGGL((blend_fwd_kernel<kFrames, false, true>), grid, block, 0, stream, descs, per_view, slot0, o,
-                       rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride);
+    hipLaunchKernelGGL((blend_fwd_kernel<false, true, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
+                       tfinal, nlast, ncontrib, hits, hit_stride);
   else
-    hipLaunchKernelGGL((blend_fwd_kernel<kFrames, false, false>), grid, block, 0, stream, descs, per_view, slot0, o,
-                       rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride);
+    hipLaunchKernelGGL((blend_fwd_kernel<false, false, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg,
+                       image, tfinal, nlast, ncontrib, hits, hit_stride);
 }
 
 }  // namespace
 
-// A view's frames are blended in walks of at most kMaxWalkFrames frames, split as evenly
-// as possible (10 frames: 3 + 3 + 4); every walk re-reads the shared list.
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges, float* image,
                             float* tfinal, int32_t* nlast, int32_t* ncontrib, uint64_t* hits, uint64_t hit_stride,
                             hipStream_t stream) {
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
   if (per_view < 1 || n_frames % per_view != 0) return hipErrorInvalidValue;
-  const int n_views = n_frames / per_view;
-  const dim3 grid(max_tiles, n_views);
+  const dim3 grid(max_tiles, n_frames);
   const uint2* rg = (const uint2*)ranges;
-  const int walks = (per_view + kMaxWalkFrames - 1) / kMaxWalkFrames;
-  int slot = 0;
-  for (int w = 0; w < walks; ++w) {
-    const int nf = (per_view - slot) / (walks - w);
-    switch (nf) {
-      case 1: launch_fwd_frames<1>(grid, stream, descs, per_view, slot, o, rec, vals, rg, image, tfinal, nlast,
-                                   ncontrib, hits, hit_stride); break;
-      case 2: launch_fwd_frames<2>(grid, stream, descs, per_view, slot, o, rec, vals, rg, image, tfinal, nlast,
-                                   ncontrib, hits, hit_stride); break;
-      case 3: launch_fwd_frames<3>(grid, stream, descs, per_view, slot, o, rec, vals, rg, image, tfinal, nlast,
-                                   ncontrib, hits, hit_stride); break;
-      default: launch_fwd_frames<4>(grid, stream, descs, per_view, slot, o, rec, vals, rg, image, tfinal, nlast,
-                                    ncontrib, hits, hit_stride); break;
-    }
-    slot += nf;
-  }
+  if (per_view > 1)
+    launch_fwd<true>(grid, stream, descs, o, rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride);
+  else
+    launch_fwd<false>(grid, stream, descs, o, rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride);
   return hipGetLastError();
 }
 

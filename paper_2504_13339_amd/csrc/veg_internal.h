@@ -9,6 +9,13 @@
 namespace veg {
 
 constexpr int kTile = VEG_TILE;
+
+// The record's last word: frame index in the low kFrameBits bits; above them, for frames
+// that share a key list, the frame's own tile rectangle as four 5-bit insets from the
+// shared rectangle (x0, y0, x1, y1 order; 31 = at least 31 tiles, a conservative bound).
+constexpr uint32_t kFrameBits = 12;
+constexpr uint32_t kFrameMask = (1u << kFrameBits) - 1u;
+static_assert(VEG_MAX_FRAMES <= (1 << kFrameBits), "frame index must fit the record's frame field");
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 

@@ -325,9 +325,19 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
       if (k > 0) tf_lookup(dk, g.v, tk);
       float Ak = tk.O * g.w;
       if (!(Ak >= o.alpha_min)) Ak = 0.0f;
+      uint32_t inset = 0u;   // own tile rectangle inside the shared one
       if (n_share > 1 && Ak > 0.0f) {
         double a0, a1, b0, b1;
-        if (!pixel_range(p, Ak, o, d.W, d.H, a0, a1, b0, b1)) Ak = 0.0f;
+        if (!pixel_range(p, Ak, o, d.W, d.H, a0, a1, b0, b1)) {
+          Ak = 0.0f;
+        } else {
+          const uint32_t ox0 = (uint32_t)a0 / kTile, ox1 = (uint32_t)a1 / kTile;
+          const uint32_t oy0 = (uint32_t)b0 / kTile, oy1 = (uint32_t)b1 / kTile;
+          // each inset clamped to [0, 31]: never claims more than the shared rectangle excludes
+          const uint32_t ix0 = ox0 > x0 ? min(ox0 - x0, 31u) : 0u, iy0 = oy0 > y0 ? min(oy0 - y0, 31u) : 0u;
+          const uint32_t ix1 = x1 > ox1 ? min(x1 - ox1, 31u) : 0u, iy1 = y1 > oy1 ? min(y1 - oy1, 31u) : 0u;
+          inset = ix0 | (iy0 << 5) | (ix1 << 10) | (iy1 << 15);
+        }
       }
       float rgb[3] = {tk.rgb[0], tk.rgb[1], tk.rgb[2]};
       if (g.lit) {
@@ -338,7 +348,7 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
       r[0] = make_float4(mxr, myr, c0, c1);
       r[1] = make_float4(c2, Ak, rgb[0], rgb[1]);
       r[2] = make_float4(rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
-                         __uint_as_float((uint32_t)(f + k)));
+                         __uint_as_float((uint32_t)(f + k) | (inset << kFrameBits)));
     }
   }
 }

@@ -70,7 +70,16 @@ def test_shared_key_list_and_records_bit_exact(K, tents):
             a_ref = np.where(own.keep[kept], own.A[kept], np.float32(0)).astype(np.float32)
             assert np.array_equal(r[:, 5], a_ref), f"frame {f}: per-frame A"
             assert np.all(own.keep <= kept)
-            assert np.array_equal(r[:, 11].view(np.uint32), np.full(kept.sum(), f, np.uint32))
+            word = r[:, 11].view(np.uint32)
+            assert np.array_equal(word & 0xFFF, np.full(kept.sum(), f, np.uint32))
+            # the frame's own tile rectangle as insets from the shared one (0 where culled or
+            # when the view has one table), each clamped to [0, 31]
+            ur, orr = un.rect[kept].astype(np.int64), own.rect[kept].astype(np.int64)
+            ins = np.stack([orr[:, 0] - ur[:, 0], orr[:, 1] - ur[:, 1], ur[:, 2] - orr[:, 2],
+                            ur[:, 3] - orr[:, 3]], 1).clip(0, 31)
+            ins[~own.keep[kept] | (K == 1)] = 0
+            ref = (ins[:, 0] | (ins[:, 1] << 5) | (ins[:, 2] << 10) | (ins[:, 3] << 15)).astype(np.uint32)
+            assert np.array_equal(word >> 12, ref), f"frame {f}: own-rectangle insets"
     tiles, depths, pairs, ranges, _ = oracle.key_list(fps, [w.cameras[c] for c, _ in w.frames])
     E = tiles.shape[0]
     assert st.n_entries == E
@@ -82,7 +91,6 @@ def test_shared_key_list_and_records_bit_exact(K, tents):
 
 @pytest.mark.parametrize("K,tents,views", [(3, False, 2), (10, True, 1), (5, True, 2)])
 def test_shared_images_match_oracle(K, tents, views):
-    """Walks of several frames (3; 3 + 3 + 4 for ten tables; 2 + 3 for five)."""
     w = _case(n=2000, K=K, tents=tents, res=64, views=views)
     g, luts, st = _render_shared(w)
     for f, (ci, ti) in enumerate(w.frames):
@@ -91,8 +99,9 @@ def test_shared_images_match_oracle(K, tents, views):
 
 
 def test_shared_blend_counts_equal_unshared():
-    """Blended-entry counts per pixel and final transmittance: sharing only changes the
-    centre's rounding, so almost every pixel matches the unshared render exactly."""
+    """Blended-entry counts per pixel: a frame on a shared list blends what it blends on its
+    own list; only the centre's rounding differs, so almost every pixel matches the
+    unshared render exactly."""
     V, R = hip()
     w = _case(n=3000, K=4, res=96)
     g, luts, st = _render_shared(w, contrib=True)
@@ -108,7 +117,12 @@ def test_shared_gradients_match_oracle():
     V, R = hip()
     w = _case(n=2000, K=3, res=64)
     g, luts, st = _render_shared(w)
-    F, H, W = len(w.frames), 64, 64
+    _check_backward(w, g, st)
+
+
+def _check_backward(w, g, st):
+    V, R = hip()
+    F, H, W = len(w.frames), w.width, w.height
     rng = np.random.default_rng(91)
     d_all = np.zeros((F, 3, H, W), np.float32)
     acc = None
@@ -125,6 +139,19 @@ def test_shared_gradients_match_oracle():
     torch.cuda.synchronize()
     for k, ref in acc.items():
         assert rel_err(getattr(grads, k).cpu().numpy(), ref) <= 1e-3, k
+
+
+def test_shared_backward_without_hit_bits_matches_oracle():
+    """Without hit bits the backward pass walks the whole shared list and must drop the
+    same entries the forward pass dropped for the frame."""
+    V, R = hip()
+    w = _case(n=2000, K=4, res=64, tents=True)
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    st = R.render(g, w.cameras, [luts[t] for _, t in w.frames], OPTS, shared=True, hits=False)
+    torch.cuda.synchronize()
+    assert st.bins.hits is None
+    _check_backward(w, g, st)
 
 
 def test_shared_train_step_matches_unshared():
