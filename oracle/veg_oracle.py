@@ -31,6 +31,7 @@ Three parts:
   decide differently).
 * O3 ``gradients`` -- the gradient of a linear functional of O2's image, by torch
   autograd in float64 on the CPU.
+* ``vq_decode`` -- attributes stored as codebook indices, expanded into the model arrays.
 * ``footprint_shared_f32`` -- the key list of frames that share a camera (several transfer
   functions over one view, as in opacity-guided training): the footprint at the largest
   opacity over the frames' tables, which contains each frame's own footprint.  The images
@@ -60,7 +61,7 @@ __all__ = [
     "TILE", "QNORM2_MIN", "exp32", "log32", "footprint_f32", "footprint_shared_f32", "key_list", "project_f64",
     "render_pixels", "render_image", "gradients", "quat_to_rot_f64", "OracleProjection",
     "depth_order", "frame_pairs", "ssim_window_1d", "ssim_map", "ssim_loss", "adam_step", "densify_stats",
-    "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA",
+    "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA", "vq_decode",
 ]
 
 TILE = 16
@@ -727,3 +728,25 @@ def densify_stats(g2d_frames, kept_frames):
     k = np.asarray(kept_frames, bool)
     norm = np.sqrt(g[..., 0] ** 2 + g[..., 1] ** 2)
     return (norm * k).sum(0), k.sum(0).astype(np.int64)
+
+
+def vq_decode(idx, book, widths):
+    """Vector-quantised storage of model attributes (the paper compresses trained models by
+    clustering most parameters into a codebook): Gaussian i's attribute vector is row
+    idx[i] of ``book`` [k, dim]; the row is split, in order, into fields of the given
+    widths (e.g. 3 log-scales then 4 quaternion components).  An index outside the codebook
+    gives NaN in every field, which culls the Gaussian.  Returns one float32 array per
+    field, [n, width] (a width-1 field as [n])."""
+    idx = np.asarray(idx).astype(np.int64)
+    book = np.asarray(book, np.float32)
+    k, dim = book.shape
+    assert sum(widths) == dim
+    ok = (idx >= 0) & (idx < k)
+    rows = np.full((idx.shape[0], dim), np.nan, np.float32)
+    rows[ok] = book[idx[ok]]
+    out, c = [], 0
+    for w in widths:
+        f = rows[:, c:c + w]
+        out.append(f[:, 0].copy() if w == 1 else f.copy())
+        c += w
+    return out

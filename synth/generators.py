@@ -26,7 +26,7 @@ __all__ = [
     "SEED_BASE", "Gaussians", "Shading", "random_shading", "Camera", "rng_for", "uniform_gaussians", "shell_gaussians",
     "clustered_gaussians", "random_tf", "identity_tf", "constant_tf", "fibonacci_directions",
     "random_direction", "look_at_camera", "perturbed_copy", "sample_pixels", "Workload",
-    "workload", "serve_trace", "DEFAULT_OPTS", "tent_opacity", "sequential_rgb", "tent_tfs",
+    "workload", "serve_trace", "DEFAULT_OPTS", "tent_opacity", "sequential_rgb", "tent_tfs", "vq_encode",
 ]
 
 # Renderer options used by every workload (alpha clamp, skip threshold, stop threshold
@@ -193,6 +193,37 @@ def tent_tfs(n_steps: int, k: int = 256) -> List[np.ndarray]:
     rgb = sequential_rgb(x)
     return [np.concatenate([rgb, tent_opacity(x, n_steps, j)[:, None]], axis=1).astype(np.float32)
             for j in range(n_steps)]
+
+
+def vq_encode(rng, x, k: int, iters: int = 4, chunk: int = 65536):
+    """Codebook of ``k`` rows for the vectors ``x`` [n, dim] and the index of each vector's
+    nearest row (Euclidean), by a few Lloyd (k-means) iterations from k distinct rows of x
+    (distinct values where x has at least k) drawn with ``rng``.  Stands in for the compression step that produces a stored model;
+    returns (idx uint16 [n], book float32 [k, dim])."""
+    x = np.asarray(x, np.float32)
+    n = x.shape[0]
+    assert 1 <= k <= 65536 and k <= n
+    u = np.unique(x, axis=0)                     # start from distinct rows where there are enough
+    src = u if u.shape[0] >= k else x
+    book = src[rng.choice(src.shape[0], k, replace=False)].astype(np.float64)
+
+    def nearest(b):
+        idx = np.empty(n, np.int64)
+        bb = (b * b).sum(1)
+        for s in range(0, n, chunk):
+            xs = x[s:s + chunk].astype(np.float64)
+            d = bb[None, :] - 2.0 * xs @ b.T
+            idx[s:s + chunk] = np.argmin(d, axis=1)
+        return idx
+    for _ in range(iters):
+        idx = nearest(book)
+        cnt = np.bincount(idx, minlength=k)
+        acc = np.zeros_like(book)
+        np.add.at(acc, idx, x.astype(np.float64))
+        filled = cnt > 0
+        book[filled] = acc[filled] / cnt[filled, None]
+    idx = nearest(book)
+    return idx.astype(np.uint16), book.astype(np.float32)
 
 
 def identity_tf(k=256) -> np.ndarray:

@@ -703,3 +703,47 @@ def test_shared_footprint_is_lossless_for_every_table():
             assert tx.min() >= x0 and tx.max() <= x1 and ty.min() >= y0 and ty.max() <= y1
             checked += 1
     assert checked > 300
+
+
+# ---------------------------------------------------------------------------------------
+# Vector-quantised model storage
+# ---------------------------------------------------------------------------------------
+
+def test_vq_round_trip_recovers_a_model_built_from_codewords():
+    """A model whose rows are codewords encodes to its own indices (nearest row at distance
+    0) and decodes back bit for bit; the fields split the row in order."""
+    rng = np.random.default_rng(3)
+    book = rng.standard_normal((50, 7)).astype(np.float32)
+    idx = rng.integers(0, 50, 2000)
+    x = book[idx]
+    enc, b2 = synth.vq_encode(np.random.default_rng(4), x, 50, iters=3)
+    ls, q = oracle.vq_decode(enc, b2, [3, 4])
+    assert np.array_equal(np.concatenate([ls, q], 1), x)
+    # a codebook of one row decodes every Gaussian to that row; widths of one give [n] arrays
+    a, b, c = oracle.vq_decode(np.zeros(5, np.uint16), np.array([[1.0, 2.0, 3.0]], np.float32), [1, 1, 1])
+    assert a.shape == (5,) and np.all(a == 1) and np.all(b == 2) and np.all(c == 3)
+
+
+def test_vq_out_of_range_index_culls_the_gaussian():
+    g = synth.workload(0, n_override=200).gaussians
+    book = np.concatenate([g.log_scales[:10], g.quats[:10]], 1).astype(np.float32)
+    idx = np.arange(200) % 12                # rows 10 and 11 do not exist
+    ls, q = oracle.vq_decode(idx, book, [3, 4])
+    bad = idx >= 10
+    assert np.all(np.isnan(ls[bad])) and np.all(np.isnan(q[bad])) and np.isfinite(ls[~bad]).all()
+    g2 = synth.Gaussians(g.means, ls, q, g.scalars, g.weights)
+    cam, lut = synth.workload(0).cameras[0], synth.workload(0).tfs[0]
+    fp = oracle.footprint_f32(g2, cam, lut, OPTS)
+    assert not fp.keep[bad].any()
+
+
+def test_vq_encoding_reduces_distortion_with_iterations():
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((3000, 7)).astype(np.float32)
+
+    def distortion(iters):
+        idx, book = synth.vq_encode(np.random.default_rng(6), x, 64, iters=iters)
+        (rows,) = oracle.vq_decode(idx, book, [7])
+        return float(((rows - x) ** 2).sum())
+    d0, d4 = distortion(0), distortion(4)
+    assert d4 < d0
