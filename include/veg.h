@@ -397,6 +397,25 @@ veg_status veg_adam_step(float* param, const float* grad, float* m, float* v, in
 veg_status veg_densify_stats(const veg_proj* proj, const float* g2d, float* grad_accum, int32_t* vis_count,
                              veg_stream_t stream);
 
+/* veg_vq_decode -- expands vector-quantised model attributes into the structure-of-arrays
+ * model (trained models are stored with most parameters clustered into a codebook; the
+ * paper adopts this from the compact-3DGS work it cites): Gaussian i's attribute vector is
+ * row idx[i] of `book`, split in order into the destination fields, e.g. a 7-wide shape
+ * codebook into log_scales [n,3] and quats [n,4].
+ *   idx       device [n] uint16
+ *   book      device [k][dim] float32, row-major; 1 <= k <= 65536, 1 <= dim <= 16
+ *   fields    host [n_fields] (1..8): dst device [n][width] float32 (overwritten),
+ *             width >= 1; the widths sum to dim
+ * An index >= k writes NaN to every field of that Gaussian, which the projection culls
+ * (never a fault, never an error).  Storage of the indices and codebook is the caller's.
+ * Errors: VEG_ERR_INVALID_ARG (sizes, NULL pointers, widths), VEG_ERR_HIP. */
+typedef struct {
+  float* dst;
+  int32_t width;
+} veg_vq_field;
+veg_status veg_vq_decode(const uint16_t* idx, int64_t n, const float* book, int32_t k, int32_t dim,
+                         const veg_vq_field* fields, int32_t n_fields, veg_stream_t stream);
+
 /* Fills `count` 32-bit words at device pointer `dst` with `value` (a kernel, so it is
  * safe inside captured graphs). */
 veg_status veg_fill_u32(void* dst, int64_t count, uint32_t value, veg_stream_t stream);

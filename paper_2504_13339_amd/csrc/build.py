@@ -18,8 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libveg.so")
 
-SOURCES = ["veg_project.hip", "veg_binsort.hip", "veg_blend.hip", "veg_loss.hip", "veg_train.hip", "veg_api.cpp",
-           "veg_serve.cpp"]
+SOURCES = ["veg_project.hip", "veg_binsort.hip", "veg_blend.hip", "veg_loss.hip", "veg_train.hip", "veg_vq.hip",
+           "veg_api.cpp", "veg_serve.cpp"]
 ARCH = os.environ.get("VEG_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", HERE,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -459,6 +459,32 @@ veg_status veg_densify_stats(const veg_proj* proj, const float* g2d, float* grad
   return VEG_OK;
 }
 
+veg_status veg_vq_decode(const uint16_t* idx, int64_t n, const float* book, int32_t k, int32_t dim,
+                         const veg_vq_field* fields, int32_t n_fields, veg_stream_t stream) {
+  g_err.clear();
+  if (n < 0) return fail(VEG_ERR_INVALID_ARG, "vq_decode: n < 0");
+  if (k < 1 || k > 65536 || dim < 1 || dim > 16)
+    return fail(VEG_ERR_INVALID_ARG, "vq_decode: need 1 <= k <= 65536 and 1 <= dim <= 16");
+  if (!fields || n_fields < 1 || n_fields > kVqMaxFields)
+    return fail(VEG_ERR_INVALID_ARG, "vq_decode: need 1..%d fields", kVqMaxFields);
+  VqFields fl;
+  std::memset(&fl, 0, sizeof(fl));
+  int sum = 0;
+  for (int f = 0; f < n_fields; ++f) {
+    if (fields[f].width < 1) return fail(VEG_ERR_INVALID_ARG, "vq_decode: field %d has width < 1", f);
+    if (n > 0 && !fields[f].dst) return fail(VEG_ERR_INVALID_ARG, "vq_decode: field %d dst is NULL", f);
+    fl.dst[f] = fields[f].dst;
+    fl.width[f] = fields[f].width;
+    sum += fields[f].width;
+  }
+  fl.n_fields = n_fields;
+  if (sum != dim) return fail(VEG_ERR_INVALID_ARG, "vq_decode: field widths sum to %d, codebook rows have %d", sum, dim);
+  if (n == 0) return VEG_OK;
+  if (!idx || !book) return fail(VEG_ERR_INVALID_ARG, "vq_decode: NULL idx or book");
+  VEG_CHECK_HIP(launch_vq_decode(idx, n, book, k, dim, fl, (hipStream_t)stream), "veg_vq_decode");
+  return VEG_OK;
+}
+
 veg_status veg_fill_u32(void* dst, int64_t count, uint32_t value, veg_stream_t stream) {
   g_err.clear();
   if (count < 0 || (count > 0 && !dst)) return fail(VEG_ERR_INVALID_ARG, "fill: bad arguments");

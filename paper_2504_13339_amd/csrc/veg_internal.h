@@ -197,6 +197,15 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float eps, float bc1, float bc2, hipStream_t stream);
 hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float4* rec,
                                 const float* g2d, float* acc, int32_t* vis, hipStream_t stream);
+// Destination fields of a codebook decode (kernel argument by value).
+constexpr int kVqMaxFields = 8;
+struct VqFields {
+  float* dst[kVqMaxFields];
+  int32_t width[kVqMaxFields];
+  int32_t n_fields;
+};
+hipError_t launch_vq_decode(const uint16_t* idx, int64_t n, const float* book, int k, int dim, const VqFields& fl,
+                            hipStream_t stream);
 hipError_t launch_debug_math(int op, const float* x, const float* y, float* out, int64_t n,
                              hipStream_t stream);
 

@@ -20,6 +20,7 @@ __all__ = [
     "veg_bin_overflow", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
     "veg_debug_math", "veg_bin_hit_words", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
     "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_adam_step", "veg_densify_stats", "veg_project_views",
+    "veg_vq_decode", "decode_vq_model",
 ]
 
 
@@ -309,6 +310,34 @@ def veg_densify_stats(proj: "Proj", g2d: torch.Tensor, grad_accum: torch.Tensor,
         raise ValueError("grad_accum / vis_count smaller than the number of Gaussians")
     check(load().veg_densify_stats(ctypes.byref(proj.struct), _ptr(g2d), _ptr(grad_accum), _ptr(vis_count),
                                    stream_handle(stream)), "veg_densify_stats")
+
+
+def veg_vq_decode(idx: torch.Tensor, book: torch.Tensor, outs: Sequence[torch.Tensor], stream=None):
+    """Expands codebook indices (device uint16 [n]) into ``outs`` (device float32 [n, w] or
+    [n] for w = 1); the codebook rows [k, dim] are split across them in order."""
+    if idx.dtype != torch.uint16 or book.dtype != torch.float32 or book.dim() != 2:
+        raise ValueError("idx must be uint16 and book float32 [k, dim]")
+    n = idx.numel()
+    fields = []
+    for o in outs:
+        w = 1 if o.dim() == 1 else int(o.shape[1])
+        if o.dtype != torch.float32 or not o.is_contiguous() or o.numel() != n * w:
+            raise ValueError("each output must be a contiguous float32 [n] or [n, w] tensor")
+        fields.append(_lib.veg_vq_field(_ptr(o), w))
+    arr = (_lib.veg_vq_field * len(fields))(*fields)
+    check(load().veg_vq_decode(_ptr(idx), n, _ptr(book.contiguous()), int(book.shape[0]), int(book.shape[1]), arr,
+                               len(fields), stream_handle(stream)), "veg_vq_decode")
+
+
+def decode_vq_model(means: torch.Tensor, scalars: torch.Tensor, shape_idx: torch.Tensor, shape_book: torch.Tensor,
+                    weights: Optional[torch.Tensor] = None, stream=None) -> "Gaussians":
+    """A model stored with its shape (log-scales and quaternion, 7 values) in a codebook,
+    decoded into a Gaussians set (positions, scalars and weights stay per Gaussian)."""
+    n = means.shape[0]
+    ls = torch.empty((n, 3), dtype=torch.float32, device=means.device)
+    q = torch.empty((n, 4), dtype=torch.float32, device=means.device)
+    veg_vq_decode(shape_idx, shape_book, [ls, q], stream=stream)
+    return Gaussians(means, ls, q, scalars, weights)
 
 
 def veg_fill_u32(t: torch.Tensor, value: int = 0, stream=None):

@@ -114,3 +114,16 @@ def test_views_of_detects_view_major_products():
     assert R.views_of([(0, 0), (1, 0)]) == 1
     assert R.views_of([(0, 0), (0, 1), (1, 1), (1, 0)]) == 0
     assert R.views_of([(0, 0), (0, 1), (1, 0)]) == 0
+
+
+def test_vq_decode_arguments_are_checked_on_host():
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    f = (_lib.veg_vq_field * 2)(_lib.veg_vq_field(fake, 3), _lib.veg_vq_field(fake, 3))
+    assert lib.veg_vq_decode(fake, 10, fake, 16, 7, f, 2, None) == 1          # widths 6 != dim 7
+    assert b"sum" in lib.veg_last_error()
+    assert lib.veg_vq_decode(fake, 10, fake, 0, 6, f, 2, None) == 1           # empty codebook
+    assert lib.veg_vq_decode(fake, 10, fake, 16, 6, f, 9, None) == 1          # too many fields
+    assert lib.veg_vq_decode(None, 0, None, 16, 6, f, 2, None) == 0           # nothing to decode
