@@ -115,8 +115,8 @@ def eval_counts(st, t_min):
     tx_n, ty_n = int(proj.struct.tiles_x), int(proj.struct.tiles_y)
     ys = torch.arange(H, device="cuda").view(1, H, 1) // 16
     xs = torch.arange(W, device="cuda").view(1, 1, W) // 16
-    K = max(1, int(proj.struct.tfs_per_view))      # frames sharing a list walk their owner's tiles
-    fs = (torch.arange(F, device="cuda") // K * K).view(F, 1, 1)
+    K = max(1, int(proj.struct.tfs_per_view))      # frames sharing a list walk their view's tiles
+    fs = (torch.arange(F, device="cuda") // K).view(F, 1, 1)
     tile = (fs * (tx_n * ty_n) + ys * tx_n + xs).reshape(-1).long()
     rg = bins.ranges.view(-1, 2).long()
     start = rg[tile, 0]

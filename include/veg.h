@@ -159,7 +159,8 @@ typedef struct {
   int32_t n_frames;     /* in */
   int32_t width, height;             /* out: image size (all frames share it) */
   int32_t tiles_x, tiles_y;          /* out */
-  int64_t total_tiles;               /* out: n_frames * tiles_x * tiles_y */
+  int64_t total_tiles;               /* out: lists * tiles_x * tiles_y, lists = n_frames /
+                                        tfs_per_view (one list per frame from veg_project) */
   void* frames;
   float* rec;
   uint32_t* count;
@@ -208,10 +209,12 @@ veg_status veg_project(const veg_gaussians* g, int32_t n_frames, const veg_camer
  * uses cams[v] and tfs[f].  Geometry does not depend on the table, so the frames of a view
  * share one key list: the first frame's pairs carry the footprint at the largest A over
  * the view's tables (it contains every frame's own footprint), the other frames' counts are
- * 0.  Every frame's record holds the shared geometry (centre relative to the shared
- * rectangle) with its own A and colour, A = 0 where the frame's own footprint culls the
- * Gaussian (A below alpha_min or no pixel centre covered), so each frame keeps exactly the
- * Gaussians veg_project would keep for it.  The blend passes then give each frame the
+ * 0, and tiles are numbered per view (global tile id v * tiles_x * tiles_y + local, so
+ * proj->total_tiles = n_views * tiles_x * tiles_y).  Every frame's record holds the shared
+ * geometry (centre relative to the shared rectangle) with its own A and colour, A = 0
+ * where the frame's own footprint culls the Gaussian (A below alpha_min or no pixel
+ * centre covered), so each frame keeps exactly the Gaussians veg_project would keep for
+ * it.  The blend passes then give each frame the
  * image and gradients of its own footprint (each frame skips pixel by pixel what its A
  * puts below alpha_min); only the float32 rounding of the centre offset may differ from
  * veg_project's.
@@ -229,7 +232,8 @@ veg_status veg_project_views(const veg_gaussians* g, int32_t n_views, int32_t tf
  * ---------------------------------------------------------------------------------- */
 
 /* Sorted key list.  Entry j is (keys[j] = global tile id, vals[j] = pair id); global tile
- * id = f * tiles_x * tiles_y + ty * tiles_x + tx.  Entries are ordered by (tile, depth
+ * id = f * tiles_x * tiles_y + ty * tiles_x + tx (v instead of f for the views of
+ * veg_project_views, whose lists are the views' owners' pairs).  Entries are ordered by (tile, depth
  * key, Gaussian index).  ranges[2t], ranges[2t+1] = [start, end) of tile t (0,0 if empty).
  *   keys, vals          device [capacity] uint32 (final sorted list)
  *   keys_alt, vals_alt  device [capacity] uint32 (ping-pong buffers)

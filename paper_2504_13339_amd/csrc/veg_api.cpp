@@ -82,7 +82,7 @@ veg_status check_projected(const veg_proj* p) {
   veg_status s = check_proj(p);
   if (s != VEG_OK) return s;
   if (p->width < 1 || p->height < 1 || p->tiles_x < 1 || p->tiles_y < 1 ||
-      p->total_tiles != (int64_t)p->n_frames * p->tiles_x * p->tiles_y)
+      p->total_tiles != (int64_t)(p->n_frames / (p->tfs_per_view > 1 ? p->tfs_per_view : 1)) * p->tiles_x * p->tiles_y)
     return fail(VEG_ERR_INVALID_ARG, "proj: not filled by veg_project");
   return VEG_OK;
 }
@@ -175,7 +175,8 @@ static veg_status project_impl(const veg_gaussians* g, int32_t n_views, int32_t 
       return fail(VEG_ERR_INVALID_ARG, "frame %d: TF table must be 16-byte aligned", f);
   }
   const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
-  const int64_t total_tiles = (int64_t)n_frames * tiles_x * tiles_y;
+  // tiles are numbered per list: a view's frames share their owner's tiles
+  const int64_t total_tiles = (int64_t)n_views * tiles_x * tiles_y;
   if (total_tiles >= ((int64_t)1 << 31)) return fail(VEG_ERR_INVALID_ARG, "too many tiles");
   std::vector<FrameDesc> descs(n_frames);
   for (int f = 0; f < n_frames; ++f) {
@@ -196,7 +197,7 @@ static veg_status project_impl(const veg_gaussians* g, int32_t n_views, int32_t 
     d.tiles_x = tiles_x;
     d.tiles_y = tiles_y;
     d.pair_base = (uint32_t)((int64_t)f * g->n);
-    d.tile_base = (uint32_t)((int64_t)f * tiles_x * tiles_y);
+    d.tile_base = (uint32_t)((int64_t)(f / per_view) * tiles_x * tiles_y);
     d.pix_base = (uint32_t)((int64_t)f * W * H);
     d.list_frame = (uint32_t)(f - f % per_view);
     d.slot = f % per_view;
@@ -315,7 +316,7 @@ static int per_view_of(const veg_proj* proj) { return proj->tfs_per_view > 1 ? p
 
 // Words of one frame slot's hit bits.
 static uint64_t hit_stride_of(const veg_proj* proj, const veg_bins* bins) {
-  return (uint64_t)veg_bin_hit_words(bins->capacity, (int64_t)proj->n_frames * proj->tiles_x * proj->tiles_y);
+  return (uint64_t)veg_bin_hit_words(bins->capacity, proj->total_tiles);
 }
 
 // The hit bits are optional; when present the buffer must hold every tile's words for each

@@ -98,12 +98,12 @@ def test_shared_view_hit_bits_and_frame_grouping_on_host():
     lib = _lib.load()
     fake = ctypes.c_void_p(0x10000)
     img = ctypes.c_void_p(0x20000)
-    stride = lib.veg_bin_hit_words(64, 3)
-    p = _lib.veg_proj(1, 3, 16, 16, 1, 1, 3, fake, fake, fake, fake, 3)
+    stride = lib.veg_bin_hit_words(64, 1)           # one list of one tile for the three frames
+    p = _lib.veg_proj(1, 3, 16, 16, 1, 1, 1, fake, fake, fake, fake, 3)
     b = _lib.veg_bins(fake, fake, fake, fake, fake, 64, fake, 3 * stride - 1)
     assert lib.veg_render_fwd(ctypes.byref(p), ctypes.byref(b), None, img, None, None, None, None) == 1
     assert b"tfs_per_view" in lib.veg_last_error()
-    p2 = _lib.veg_proj(1, 4, 16, 16, 1, 1, 4, fake, fake, fake, fake, 3)
+    p2 = _lib.veg_proj(1, 4, 16, 16, 1, 1, 1, fake, fake, fake, fake, 3)
     assert lib.veg_render_bwd(ctypes.byref(p2), ctypes.byref(b), None, img, img, img, img, None) == 1
     assert b"multiple" in lib.veg_last_error()
 

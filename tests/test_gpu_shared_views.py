@@ -80,7 +80,10 @@ def test_shared_key_list_and_records_bit_exact(K, tents):
             ins[~own.keep[kept] | (K == 1)] = 0
             ref = (ins[:, 0] | (ins[:, 1] << 5) | (ins[:, 2] << 10) | (ins[:, 3] << 15)).astype(np.uint32)
             assert np.array_equal(word >> 12, ref), f"frame {f}: own-rectangle insets"
-    tiles, depths, pairs, ranges, _ = oracle.key_list(fps, [w.cameras[c] for c, _ in w.frames])
+    # tiles are numbered per view; the oracle's list over the owners (one per view) gives
+    # pair ids v * n + i, the library's owner pairs are (v K) * n + i
+    tiles, depths, pairs, ranges, _ = oracle.key_list(fps[::K], list(w.cameras))
+    pairs = pairs // n * (K * n) + pairs % n
     E = tiles.shape[0]
     assert st.n_entries == E
     assert np.array_equal(st.bins.keys.cpu().numpy().view(np.uint32)[:E].astype(np.int64), tiles)
