@@ -127,10 +127,10 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
     int n;
     if constexpr (kShared) {
       float4 r0, r1, r2;
+      const float4* rp = nullptr;
       bool live = j < rg.y;
-      if (live) {
-        const float4* rp = rec + 3 * (size_t)(vals[j] + roff);
-        r0 = rp[0];
+      if (live) {   // the live test needs the second and third float4 only
+        rp = rec + 3 * (size_t)(vals[j] + roff);
         r1 = rp[1];
         r2 = rp[2];
         const uint32_t in = __float_as_uint(r2.w) >> kFrameBits;
@@ -143,6 +143,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
       const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
       n = __popcll(m);
       if (live) {
+        r0 = rp[0];
         const Staged s = stage(r0, r1, r2, tx, ty);
         s_geo[slot] = make_float4(s.mx, s.my, s.q0, s.q1);
         s_col[slot] = make_float4(s.q2, s.l2A, r1.z, r1.w);

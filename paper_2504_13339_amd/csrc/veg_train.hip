@@ -14,25 +14,37 @@ namespace {
 // product, so both passes use the same taps).  Constants for a data range of 1.
 constexpr int kWin = 11, kHalf = 5;
 constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
-constexpr int kTx = 32, kTy = 16;                       // output tile
-constexpr int kIx = kTx + 2 * kHalf, kIy = kTy + 2 * kHalf;   // input tile with halo
+// A block produces a 32 x 32 output tile from a 42 x 42 input tile (5-pixel halo, zeros
+// outside the image) staged in LDS.  Horizontal pass: each thread turns 14 staged values of
+// a row into 4 outputs; vertical pass: each thread turns 14 values of a column into 4
+// outputs.  Register blocking cuts LDS reads to about 27 per pixel and quantity set.
+constexpr int kT = 32, kIn = kT + 2 * kHalf, kB = 4;
+constexpr int kPadIn = kIn + 1, kPadT = kT + 1;   // odd row strides: no bank conflicts
 
 struct Win {
   float w[kWin];
 };
 
+// Symmetric 11-tap window over v[c .. c + 10] (output at the centre c + 5).
+__device__ __forceinline__ float win11(const float* v, const Win& w) {
+  float a = w.w[kHalf] * v[kHalf];
+#pragma unroll
+  for (int t = 1; t <= kHalf; ++t) a = fmaf(w.w[kHalf - t], v[kHalf - t] + v[kHalf + t], a);
+  return a;
+}
+
 // Input tile of one plane with zeros outside the image.
-__device__ __forceinline__ void load_tile(const float* __restrict__ src, int W, int H, int x0, int y0, float* dst) {
-  for (int k = threadIdx.x; k < kIx * kIy; k += blockDim.x) {
-    const int lx = k % kIx, ly = k / kIx;
+__device__ __forceinline__ void load_tile(const float* __restrict__ src, int W, int H, int x0, int y0,
+                                          float (*dst)[kPadIn]) {
+  for (int k = threadIdx.x; k < kIn * kIn; k += blockDim.x) {
+    const int ly = k / kIn, lx = k - ly * kIn;
     const int gx = x0 - kHalf + lx, gy = y0 - kHalf + ly;
-    dst[k] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? src[(size_t)gy * W + gx] : 0.0f;
+    dst[ly][lx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? src[(size_t)gy * W + gx] : 0.0f;
   }
 }
 
-// Per tile: windowed means of x, y, x^2, y^2, x y (horizontal then vertical pass through
-// LDS), the SSIM map S and its partial derivatives with respect to mu_x, E[x^2] and E[x y]
-// at every pixel:
+// Per tile: windowed means of x, y, x^2, y^2, x y, the SSIM map S and its partial
+// derivatives with respect to mu_x, E[x^2] and E[x y] at every pixel:
 //   N = (2 mu_x mu_y + C1)(2 s_xy + C2) = A1 A2,  D = (mu_x^2 + mu_y^2 + C1)(s_x + s_y + C2) = B1 B2,
 //   dS/dmu_x = (2 mu_y (A2 - A1) - 2 mu_x S (B2 - B1)) / D,  dS/dE[x^2] = -S B1 / D,
 //   dS/dE[xy] = 2 A1 / D.
@@ -40,55 +52,67 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ src, int W, 
 __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
                                                        int W, int H, float weight, double* __restrict__ loss,
                                                        float* __restrict__ dmaps, size_t plane_stride, Win win) {
-  __shared__ float s_x[kIx * kIy], s_y[kIx * kIy];
-  __shared__ float s_h[5][kIy * kTx];
+  __shared__ float s_x[kIn][kPadIn], s_y[kIn][kPadIn];
+  __shared__ float s_h[5][kIn][kPadT];
   __shared__ double s_part[4];
-  const int x0 = blockIdx.x * kTx, y0 = blockIdx.y * kTy;
+  const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
   const size_t plane = blockIdx.z;
-  const float* xs = img + plane * (size_t)W * H;
-  const float* ys = tgt + plane * (size_t)W * H;
-  load_tile(xs, W, H, x0, y0, s_x);
-  load_tile(ys, W, H, x0, y0, s_y);
+  const size_t HW = (size_t)W * H;
+  load_tile(img + plane * HW, W, H, x0, y0, s_x);
+  load_tile(tgt + plane * HW, W, H, x0, y0, s_y);
   __syncthreads();
-  for (int k = threadIdx.x; k < kIy * kTx; k += blockDim.x) {
-    const int ox = k % kTx, ly = k / kTx;
-    float a[5] = {0, 0, 0, 0, 0};
-    for (int t = 0; t < kWin; ++t) {
-      const float wv = win.w[t];
-      const float xv = s_x[ly * kIx + ox + t], yv = s_y[ly * kIx + ox + t];
-      a[0] += wv * xv;
-      a[1] += wv * yv;
-      a[2] += wv * (xv * xv);
-      a[3] += wv * (yv * yv);
-      a[4] += wv * (xv * yv);
+  // horizontal: 42 rows x 8 groups of 4 columns
+  for (int task = threadIdx.x; task < kIn * (kT / kB); task += blockDim.x) {
+    const int r = task / (kT / kB), c0 = (task - r * (kT / kB)) * kB;
+    float p[5][kB + 2 * kHalf];
+#pragma unroll
+    for (int i = 0; i < kB + 2 * kHalf; ++i) {
+      const float xv = s_x[r][c0 + i], yv = s_y[r][c0 + i];
+      p[0][i] = xv;
+      p[1][i] = yv;
+      p[2][i] = xv * xv;
+      p[3][i] = yv * yv;
+      p[4][i] = xv * yv;
     }
-    for (int c = 0; c < 5; ++c) s_h[c][k] = a[c];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int i = 0; i < kB; ++i) s_h[q][r][c0 + i] = win11(&p[q][i], win);
   }
   __syncthreads();
+  // vertical: 32 columns x 8 groups of 4 rows, one task per thread
   double part = 0.0;
-  for (int k = threadIdx.x; k < kTx * kTy; k += blockDim.x) {
-    const int ox = k % kTx, oy = k / kTx;
-    const int gx = x0 + ox, gy = y0 + oy;
-    if (gx >= W || gy >= H) continue;
-    float m[5] = {0, 0, 0, 0, 0};
-    for (int t = 0; t < kWin; ++t) {
-      const float wv = win.w[t];
-      for (int c = 0; c < 5; ++c) m[c] += wv * s_h[c][(oy + t) * kTx + ox];
+  {
+    const int c = threadIdx.x & (kT - 1), r0 = (threadIdx.x / kT) * kB;
+    float m[5][kB];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      float v[kB + 2 * kHalf];
+#pragma unroll
+      for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_h[q][r0 + i][c];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) m[q][i] = win11(&v[i], win);
     }
-    const float mx = m[0], my = m[1];
-    const float sx = m[2] - mx * mx, sy = m[3] - my * my, sxy = m[4] - mx * my;
-    const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * sxy + kC2;
-    const float B1 = mx * mx + my * my + kC1, B2 = sx + sy + kC2;
-    const float D = B1 * B2;
-    const float S = (A1 * A2) / D;
-    part += (double)(1.0f - S);
-    const float dmu = (2.0f * my * (A2 - A1) - 2.0f * mx * S * (B2 - B1)) / D;
-    const float dex2 = -S * B1 / D;
-    const float dexy = 2.0f * A1 / D;
-    const size_t pi = plane * (size_t)W * H + (size_t)gy * W + gx;
-    dmaps[pi] = -weight * dmu;
-    dmaps[plane_stride + pi] = -weight * dex2;
-    dmaps[2 * plane_stride + pi] = -weight * dexy;
+    const int gx = x0 + c;
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int gy = y0 + r0 + i;
+      if (gx >= W || gy >= H) continue;
+      const float mx = m[0][i], my = m[1][i];
+      const float sx = m[2][i] - mx * mx, sy = m[3][i] - my * my, sxy = m[4][i] - mx * my;
+      const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * sxy + kC2;
+      const float B1 = mx * mx + my * my + kC1, B2 = sx + sy + kC2;
+      const float D = B1 * B2;
+      const float S = (A1 * A2) / D;
+      part += (double)(1.0f - S);
+      const float dmu = (2.0f * my * (A2 - A1) - 2.0f * mx * S * (B2 - B1)) / D;
+      const float dex2 = -S * B1 / D;
+      const float dexy = 2.0f * A1 / D;
+      const size_t pi = plane * HW + (size_t)gy * W + gx;
+      dmaps[pi] = -weight * dmu;
+      dmaps[plane_stride + pi] = -weight * dex2;
+      dmaps[2 * plane_stride + pi] = -weight * dexy;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
   if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
@@ -105,33 +129,42 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
 __global__ __launch_bounds__(256) void ssim_bwd_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
                                                        int W, int H, const float* __restrict__ dmaps,
                                                        size_t plane_stride, float* __restrict__ dimg, Win win) {
-  __shared__ float s_m[3][kIx * kIy];
-  __shared__ float s_h[3][kIy * kTx];
-  const int x0 = blockIdx.x * kTx, y0 = blockIdx.y * kTy;
+  __shared__ float s_m[3][kIn][kPadIn];
+  __shared__ float s_h[3][kIn][kPadT];
+  const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
   const size_t plane = blockIdx.z;
-  for (int c = 0; c < 3; ++c) load_tile(dmaps + c * plane_stride + plane * (size_t)W * H, W, H, x0, y0, s_m[c]);
+  const size_t HW = (size_t)W * H;
+  for (int q = 0; q < 3; ++q) load_tile(dmaps + q * plane_stride + plane * HW, W, H, x0, y0, s_m[q]);
   __syncthreads();
-  for (int k = threadIdx.x; k < kIy * kTx; k += blockDim.x) {
-    const int ox = k % kTx, ly = k / kTx;
-    float a[3] = {0, 0, 0};
-    for (int t = 0; t < kWin; ++t) {
-      const float wv = win.w[t];
-      for (int c = 0; c < 3; ++c) a[c] += wv * s_m[c][ly * kIx + ox + t];
+  for (int task = threadIdx.x; task < kIn * (kT / kB); task += blockDim.x) {
+    const int r = task / (kT / kB), c0 = (task - r * (kT / kB)) * kB;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      float v[kB + 2 * kHalf];
+#pragma unroll
+      for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_m[q][r][c0 + i];
+#pragma unroll
+      for (int i = 0; i < kB; ++i) s_h[q][r][c0 + i] = win11(&v[i], win);
     }
-    for (int c = 0; c < 3; ++c) s_h[c][k] = a[c];
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < kTx * kTy; k += blockDim.x) {
-    const int ox = k % kTx, oy = k / kTx;
-    const int gx = x0 + ox, gy = y0 + oy;
+  const int c = threadIdx.x & (kT - 1), r0 = (threadIdx.x / kT) * kB;
+  float m[3][kB];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    float v[kB + 2 * kHalf];
+#pragma unroll
+    for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_h[q][r0 + i][c];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) m[q][i] = win11(&v[i], win);
+  }
+  const int gx = x0 + c;
+#pragma unroll
+  for (int i = 0; i < kB; ++i) {
+    const int gy = y0 + r0 + i;
     if (gx >= W || gy >= H) continue;
-    float m[3] = {0, 0, 0};
-    for (int t = 0; t < kWin; ++t) {
-      const float wv = win.w[t];
-      for (int c = 0; c < 3; ++c) m[c] += wv * s_h[c][(oy + t) * kTx + ox];
-    }
-    const size_t pi = plane * (size_t)W * H + (size_t)gy * W + gx;
-    dimg[pi] += (m[0] + 2.0f * img[pi] * m[1]) + tgt[pi] * m[2];
+    const size_t pi = plane * HW + (size_t)gy * W + gx;
+    dimg[pi] += (m[0][i] + 2.0f * img[pi] * m[1][i]) + tgt[pi] * m[2][i];
   }
 }
 
@@ -196,7 +229,7 @@ hipError_t launch_ssim(const float* image, const float* target, int64_t n_planes
                        double* loss, float* d_image, float* dmaps, hipStream_t stream) {
   if (n_planes <= 0 || W <= 0 || H <= 0) return hipSuccess;
   const size_t plane_stride = (size_t)n_planes * W * H;
-  const dim3 grid((W + kTx - 1) / kTx, (H + kTy - 1) / kTy, (unsigned)n_planes);
+  const dim3 grid((W + kT - 1) / kT, (H + kT - 1) / kT, (unsigned)n_planes);
   const Win win = ssim_window();
   hipLaunchKernelGGL(ssim_fwd_kernel, grid, dim3(256), 0, stream, image, target, W, H, weight, loss, dmaps,
                      plane_stride, win);
