@@ -16,6 +16,7 @@ kernel with the largest share of the step, timed with HIP events on the library'
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -312,8 +313,11 @@ def main():
         res = l1_step(g, grads)
         log(f"bench: warm-up step {k} loss {res.loss:.6f}")
 
-    # timed steps
+    # timed steps (Python's cycle collector paused: a collection mid-step stalls the host
+    # while the GPU waits for the next launch)
     timer = R.EventTimer()
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step_ms = []
@@ -325,6 +329,7 @@ def main():
             log(f"bench: step {k} loss {res.loss:.6f}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gc.enable()
     ms_step = dt * 1e3 / args.steps
     value = F * H * W * args.steps / dt / 1e6
 
@@ -333,6 +338,8 @@ def main():
     launches = {k: len(v) // args.steps for k, v in times.items()}
 
     # forward-only throughput (project + bin + blend for all frames, no backward)
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for k in range(args.steps):
@@ -343,6 +350,7 @@ def main():
             del st
     torch.cuda.synchronize()
     fwd_mpix = F * H * W * args.steps / (time.perf_counter() - t1) / 1e6
+    gc.enable()
 
     # the same training step with Blinn-Phong lighting attributes on every Gaussian
     lit_mpix = None
@@ -354,12 +362,15 @@ def main():
                          **{k: torch.as_tensor(getattr(sh, k)).cuda() for k in V.LIGHTING})
         grads_l = R.Grads.zeros(gl)
         l1_step(gl, grads_l)
+        gc.collect()
+        gc.disable()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         for k in range(args.lit_steps):
             l1_step(gl, grads_l)
         torch.cuda.synchronize()
         lit_mpix = F * H * W * args.lit_steps / (time.perf_counter() - t2) / 1e6
+        gc.enable()
         del grads_l, gl
 
     # a whole training iteration: the (1 - 0.2) L1 + 0.2 (1 - SSIM) loss, densification
@@ -385,11 +396,14 @@ def main():
         full_iter()
         torch.cuda.synchronize()
         ftimer = R.EventTimer()
+        gc.collect()
+        gc.disable()
         t3 = time.perf_counter()
         for k in range(args.full_steps):
             full_iter(ftimer)
         torch.cuda.synchronize()
         fdt = time.perf_counter() - t3
+        gc.enable()
         ft = {k: round(sum(v) / args.full_steps, 3) for k, v in ftimer.totals_ms().items()
               if k in ("l1_loss", "ssim_loss", "densify_stats", "adam")}
         full = {"mpix_s": round(F * H * W * args.full_steps / fdt / 1e6, 2),

@@ -42,6 +42,30 @@ __device__ __forceinline__ Staged stage(const float4 r0, const float4 r1, const 
   return s;
 }
 
+// Quadrants of the tile (bit r: pixel centres x in 8 (r & 1) + [0.5, 7.5], y in
+// 8 (r >> 1) + [0.5, 7.5]) that can hold a pixel passing the skip test.  A pixel passes when
+// the computed exponent l2A - Q(dx, dy) reaches l2min, Q = q0 dx^2 + q1 dx dy + q2 dy^2;
+// rounding moves the computed value by far less than 1e-4 (1 + |l2A|), so every passing
+// pixel lies in the ellipse Q <= R' = l2A - l2min + 1e-4 (1 + |l2A|), whose half-extents are
+// sqrt(4 R' q2 / D) and sqrt(4 R' q0 / D), D = 4 q0 q2 - q1^2; they are widened once more
+// before the overlap test.  A quadrant outside that box has no passing pixel, so skipping
+// it changes nothing.  Degenerate forms keep every quadrant.
+__device__ __forceinline__ uint32_t quad_mask(const Staged& s, float l2min) {
+  const float rp = (s.l2A - l2min) + 1e-4f * (1.0f + fabsf(s.l2A));
+  if (!(rp >= 0.0f)) return 0u;   // below the threshold everywhere (or A = 0)
+  const float D = 4.0f * s.q0 * s.q2 - s.q1 * s.q1;
+  if (!(s.q0 > 0.0f) || !(s.q2 > 0.0f) || !(D > 0.0f)) return 0xfu;
+  const float ex = sqrtf(4.0f * rp * s.q2 / D) * 1.001f + 0.01f;
+  const float ey = sqrtf(4.0f * rp * s.q0 / D) * 1.001f + 0.01f;
+  if (!(ex < 1e30f) || !(ey < 1e30f)) return 0xfu;
+  const bool xl = s.mx - ex <= 7.5f && s.mx + ex >= 0.5f;    // columns 0..7
+  const bool xh = s.mx - ex <= 15.5f && s.mx + ex >= 8.5f;   // columns 8..15
+  const bool yl = s.my - ey <= 7.5f && s.my + ey >= 0.5f;
+  const bool yh = s.my - ey <= 15.5f && s.my + ey >= 8.5f;
+  return (uint32_t)(xl && yl) | ((uint32_t)(xh && yl) << 1) | ((uint32_t)(xl && yh) << 2) |
+         ((uint32_t)(xh && yh) << 3);
+}
+
 // log2 of A exp(-sigma) for a pixel centre at (px, py) in tile-local coordinates:
 //   base = l2A - q0 dx^2,  e = base - dy (q2 dy + q1 dx).
 __device__ __forceinline__ float exponent_base(float q0, float l2A, float dx) { return fmaf(-q0 * dx, dx, l2A); }
@@ -106,7 +130,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   __shared__ float4 s_geo[kBatch];   // mx, my, q0, q1
   __shared__ float4 s_col[kBatch];   // q2, l2A, R, G
   __shared__ float s_b[kBatch];      // B
-  __shared__ int s_k[kShared ? kBatch : 1];   // batch position of a packed entry
+  __shared__ int s_k[kBatch];        // batch position of a packed entry | quadrant mask << 8
 
   const float tmin = o.t_min;
   float T[4], C[4][3];
@@ -123,49 +147,47 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   const float aclamp = o.alpha_clamp;
   for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
     if (__all(T[0] < tmin && T[1] < tmin && T[2] < tmin && T[3] < tmin)) break;
+    // stage the batch: only entries that can blend into some pixel of this tile (a quadrant
+    // mask from the ellipse's box; for a frame on a shared list also its own footprint),
+    // packed to the front; s_k keeps each one's position in the batch
     const uint32_t j = base + lane;
-    int n;
-    if constexpr (kShared) {
-      float4 r0, r1, r2;
-      const float4* rp = nullptr;
-      bool live = j < rg.y;
-      if (live) {   // the live test needs the second and third float4 only
-        rp = rec + 3 * (size_t)(vals[j] + roff);
-        r1 = rp[1];
-        r2 = rp[2];
+    bool live = j < rg.y;
+    float4 r0, r1, r2;
+    const float4* rp = nullptr;
+    if (live) {
+      rp = rec + 3 * (size_t)(vals[j] + roff);
+      r1 = rp[1];
+      r2 = rp[2];
+      if (kShared) {
         const uint32_t in = __float_as_uint(r2.w) >> kFrameBits;
         const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
         const int x0 = (int)((a & 0xffffu) + (in & 31u)), y0 = (int)((a >> 16) + ((in >> 5) & 31u));
         const int x1 = (int)((b & 0xffffu) - ((in >> 10) & 31u)), y1 = (int)((b >> 16) - ((in >> 15) & 31u));
         live = r1.y > 0.0f && tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1;
       }
-      const uint64_t m = __ballot(live);
+    }
+    Staged st;
+    uint32_t qm = 0u;
+    if (live) {
+      r0 = rp[0];
+      st = stage(r0, r1, r2, tx, ty);
+      qm = quad_mask(st, l2min);
+      live = qm != 0u;
+    }
+    const uint64_t m = __ballot(live);
+    const int n = __popcll(m);
+    if (live) {
       const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      n = __popcll(m);
-      if (live) {
-        r0 = rp[0];
-        const Staged s = stage(r0, r1, r2, tx, ty);
-        s_geo[slot] = make_float4(s.mx, s.my, s.q0, s.q1);
-        s_col[slot] = make_float4(s.q2, s.l2A, r1.z, r1.w);
-        s_b[slot] = r2.x;
-        s_k[slot] = lane;
-      }
-    } else {
-      if (j < rg.y) {
-        const float4* rp = rec + 3 * (size_t)vals[j];
-        const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
-        const Staged s = stage(r0, r1, r2, tx, ty);
-        s_geo[lane] = make_float4(s.mx, s.my, s.q0, s.q1);
-        s_col[lane] = make_float4(s.q2, s.l2A, r1.z, r1.w);
-        s_b[lane] = r2.x;
-      }
-      n = (int)min((uint32_t)kBatch, rg.y - base);
+      s_geo[slot] = make_float4(st.mx, st.my, st.q0, st.q1);
+      s_col[slot] = make_float4(st.q2, st.l2A, r1.z, r1.w);
+      s_b[slot] = r2.x;
+      s_k[slot] = (int)(lane | (qm << 8));
     }
     __syncthreads();
     uint64_t lh = 0;   // bit k: this lane blended entry base + k
-    uint64_t bk = 1;
-    for (int k = 0; k < n; ++k, bk <<= 1) {
-      const int kk = kShared ? s_k[k] : k;   // position in the batch
+    for (int k = 0; k < n; ++k) {
+      const uint32_t kq = (uint32_t)__builtin_amdgcn_readfirstlane(s_k[k]);
+      const int kk = (int)(kq & 0xffu);       // position in the batch
       const float4 g = s_geo[k];
       const float4 c = s_col[k];
       const float cb = s_b[k];
@@ -175,9 +197,10 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
       const float dy0 = pyl0 - g.y, dy1 = pyl1 - g.y;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
+        if (!(kq & (0x100u << r))) continue;   // quadrant out of the entry's reach (uniform)
         const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, c.x, (r >> 1) ? dy1 : dy0);
         if (T[r] >= tmin && e >= l2min) {
-          if (kHits) lh |= kShared ? (1ull << kk) : bk;
+          if (kHits) lh |= 1ull << kk;
           const float alpha = fminf(__builtin_amdgcn_exp2f(e), aclamp);
           const float w = alpha * T[r];
           C[r][0] = fmaf(w, c.z, C[r][0]);
