@@ -32,6 +32,8 @@ Three parts:
 * O3 ``gradients`` -- the gradient of a linear functional of O2's image, by torch
   autograd in float64 on the CPU.
 * ``vq_decode`` -- attributes stored as codebook indices, expanded into the model arrays.
+* ``densify_plan`` / ``densify_apply`` -- adaptive density control: clone, split or prune
+  decisions from the densification statistics and the model they produce.
 * ``footprint_shared_f32`` -- the key list of frames that share a camera (several transfer
   functions over one view, as in opacity-guided training): the footprint at the largest
   opacity over the frames' tables, which contains each frame's own footprint.  The images
@@ -61,7 +63,8 @@ __all__ = [
     "TILE", "QNORM2_MIN", "exp32", "log32", "footprint_f32", "footprint_shared_f32", "key_list", "project_f64",
     "render_pixels", "render_image", "gradients", "quat_to_rot_f64", "OracleProjection",
     "depth_order", "frame_pairs", "ssim_window_1d", "ssim_map", "ssim_loss", "adam_step", "densify_stats",
-    "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA", "vq_decode",
+    "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA", "vq_decode", "densify_plan", "densify_apply",
+    "KEEP", "CLONE", "SPLIT", "PRUNE", "SPLIT_SHRINK",
 ]
 
 TILE = 16
@@ -749,4 +752,66 @@ def vq_decode(idx, book, widths):
         f = rows[:, c:c + w]
         out.append(f[:, 0].copy() if w == 1 else f.copy())
         c += w
+    return out
+
+
+# Adaptive density control (section "Training": Gaussians with large view-space positional
+# gradients are cloned or split, low-weight Gaussians are pruned, after Kerbl et al.).
+KEEP, CLONE, SPLIT, PRUNE = 0, 1, 2, 3
+SPLIT_SHRINK = 1.6      # children's scale = parent's / (0.8 * 2 children)
+
+
+def densify_plan(grad_accum, vis_count, log_scales, weights, grad_thresh, log_scale_thresh, prune_weight):
+    """Per-Gaussian decision, every comparison in float32 (the kernel's precision):
+    g = accum / vis (0 where vis = 0);  PRUNE when the weight is not >= prune_weight (no weight
+    array: never);  else SPLIT when g >= grad_thresh and the largest log-scale exceeds
+    log_scale_thresh (a large Gaussian is divided), CLONE when g >= grad_thresh otherwise (a
+    small one is copied);  else KEEP.  Returns (action uint8 [n], counts [4])."""
+    f32 = np.float32
+    acc = np.asarray(grad_accum, np.float32)
+    vis = np.asarray(vis_count, np.int64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        g = np.where(vis > 0, acc / np.maximum(vis, 1).astype(np.float32), f32(0)).astype(np.float32)
+    big = np.asarray(log_scales, np.float32).max(1) > f32(log_scale_thresh)
+    hot = g >= f32(grad_thresh)
+    act = np.where(hot, np.where(big, SPLIT, CLONE), KEEP).astype(np.uint8)
+    if weights is not None:
+        low = ~(np.asarray(weights, np.float32) >= f32(prune_weight))
+        act[low] = PRUNE
+    return act, np.bincount(act, minlength=4).astype(np.int64)
+
+
+def densify_apply(action, means, log_scales, quats, z, fields):
+    """The model after the decisions, in float64: first the survivors (KEEP and CLONE) in
+    index order, then one copy of each CLONE Gaussian in index order, then the two children
+    of each SPLIT Gaussian in index order.  Child c of parent i sits at
+    mu_i + R(q_i) diag(exp(log_s_i)) z[i, c] (z [n, 2, 3], standard normal draws passed in)
+    with log-scales log_s_i - ln 1.6.  ``fields`` is a list of (array [n] or [n, w], role):
+    role 0 copies the value to clones and children, 1 means (children as above), 2 log-scales
+    (children as above), 3 zero for every new Gaussian (optimizer moments).  Returns the new
+    arrays in the same order."""
+    act = np.asarray(action)
+    surv = np.nonzero((act == KEEP) | (act == CLONE))[0]
+    clo = np.nonzero(act == CLONE)[0]
+    spl = np.nonzero(act == SPLIT)[0]
+    q = torch.as_tensor(np.asarray(quats, np.float64))
+    q = q / q.norm(dim=1, keepdim=True)
+    R = quat_to_rot_f64(q).numpy()
+    s = np.exp(np.asarray(log_scales, np.float64))
+    zz = np.asarray(z, np.float64)
+    # offsets of the children: R diag(s) z
+    off = np.einsum("nij,ncj->nci", R, s[:, None, :] * zz)           # [n, 2, 3]
+    out = []
+    for arr, role in fields:
+        a = np.asarray(arr, np.float64)
+        if role == 1:
+            child = (a[spl, None, :] + off[spl]).reshape(-1, a.shape[1])
+        elif role == 2:
+            child = np.repeat(a[spl] - math.log(SPLIT_SHRINK), 2, axis=0)
+        elif role == 3:
+            child = np.zeros((2 * len(spl),) + a.shape[1:])
+        else:
+            child = np.repeat(a[spl], 2, axis=0)
+        copies = np.zeros((len(clo),) + a.shape[1:]) if role == 3 else a[clo]
+        out.append(np.concatenate([a[surv], copies, child], axis=0))
     return out

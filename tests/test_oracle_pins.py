@@ -747,3 +747,50 @@ def test_vq_encoding_reduces_distortion_with_iterations():
         return float(((rows - x) ** 2).sum())
     d0, d4 = distortion(0), distortion(4)
     assert d4 < d0
+
+
+# ---------------------------------------------------------------------------------------
+# Adaptive density control
+# ---------------------------------------------------------------------------------------
+
+def test_densify_plan_decisions_by_hand():
+    """Six Gaussians built to land in each branch (thresholds: gradient 0.5, log-scale -2,
+    weight 0.005)."""
+    acc = np.array([0.0, 3.0, 3.0, 0.9, 3.0, 10.0], np.float32)
+    vis = np.array([0, 4, 4, 2, 4, 1], np.int32)          # means: 0, .75, .75, .45, .75, 10
+    ls = np.full((6, 3), -3.0, np.float32)
+    ls[2, 1] = -1.0                                        # large: split instead of clone
+    w = np.array([0.5, 0.5, 0.5, 0.5, 0.001, np.nan], np.float32)
+    act, cnt = oracle.densify_plan(acc, vis, ls, w, 0.5, -2.0, 0.005)
+    assert list(act) == [oracle.KEEP, oracle.CLONE, oracle.SPLIT, oracle.KEEP, oracle.PRUNE, oracle.PRUNE]
+    assert list(cnt) == [2, 1, 1, 2]
+    act2, _ = oracle.densify_plan(acc, vis, ls, None, 0.5, -2.0, 0.005)   # no weights: no pruning
+    assert list(act2) == [0, 1, 2, 0, 1, 1]
+
+
+def test_densify_apply_layout_and_split_children_closed_form():
+    """Survivors, then clone copies, then split children; with z = +e_x and -e_x the two
+    children of a Gaussian rotated 90 degrees about z sit at mu +- s_x e_y, and their scales
+    are the parent's divided by 1.6; new Gaussians get zero optimizer moments."""
+    act = np.array([oracle.KEEP, oracle.SPLIT, oracle.CLONE, oracle.PRUNE, oracle.SPLIT], np.uint8)
+    means = np.arange(15, dtype=np.float64).reshape(5, 3)
+    ls = np.log(np.array([[0.1, 0.2, 0.3]] * 5))
+    c = math.cos(math.pi / 4)
+    quats = np.array([[1, 0, 0, 0], [c, 0, 0, c], [1, 0, 0, 0], [1, 0, 0, 0], [2, 0, 0, 0]], np.float64)
+    z = np.zeros((5, 2, 3))
+    z[1, 0, 0], z[1, 1, 0] = 1.0, -1.0
+    z[4, 0, 1], z[4, 1, 2] = 1.0, 1.0
+    w = np.arange(5, dtype=np.float64)
+    mom = np.ones((5, 3))
+    m2, ls2, w2, mom2 = oracle.densify_apply(act, means, ls, quats, z, [(means, 1), (ls, 2), (w, 0), (mom, 3)])
+    # n + clones + splits - prunes = 5 + 1 + 2 - 1
+    assert m2.shape == (7, 3) and ls2.shape == (7, 3) and mom2.shape == (7, 3)
+    # survivors 0 and 2, the copy of 2, the children of 1 and of 4
+    assert list(w2) == [0.0, 2.0, 2.0, 1.0, 1.0, 4.0, 4.0]
+    assert np.array_equal(m2[:3], means[[0, 2, 2]]) and np.array_equal(ls2[:3], ls[[0, 2, 2]])
+    assert np.all(mom2[:2] == 1.0) and np.all(mom2[2:] == 0.0)
+    # a rotation of 90 degrees about z maps e_x to e_y
+    assert np.allclose(m2[3], means[1] + [0, 0.1, 0]) and np.allclose(m2[4], means[1] - [0, 0.1, 0])
+    # the unnormalised quaternion (2, 0, 0, 0) is the identity: mu + 0.2 e_y and mu + 0.3 e_z
+    assert np.allclose(m2[5], means[4] + [0, 0.2, 0]) and np.allclose(m2[6], means[4] + [0, 0, 0.3])
+    assert np.allclose(np.exp(ls2[3:]), np.array([[0.1, 0.2, 0.3]]) / 1.6)
