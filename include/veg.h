@@ -401,6 +401,62 @@ veg_status veg_adam_step(float* param, const float* grad, float* m, float* v, in
 veg_status veg_densify_stats(const veg_proj* proj, const float* g2d, float* grad_accum, int32_t* vis_count,
                              veg_stream_t stream);
 
+/* Adaptive density control (section "Training": densification and pruning after Kerbl et
+ * al.; Gaussians with large view-space positional gradients are cloned or split, Gaussians
+ * with a low weight are pruned).  Two calls: veg_densify_plan decides, veg_densify_apply
+ * writes the new model.
+ *
+ * veg_densify_plan -- per Gaussian, with float32 comparisons:
+ *   g = grad_accum / vis_count (0 where vis_count = 0: the statistics of veg_densify_stats);
+ *   PRUNE (3) unless weights[i] >= prune_weight (weights NULL: never);
+ *   else SPLIT (2) when g >= grad_thresh and max(log_scales[i]) > log_scale_thresh;
+ *   else CLONE (1) when g >= grad_thresh;  else KEEP (0).
+ *   grad_thresh is in pixels (the units of veg_densify_stats), log_scale_thresh in the
+ *   model's log-scale units.
+ *   action   device [n] uint8 out
+ *   counts   host [4] out (optional): KEEP, CLONE, SPLIT, PRUNE; when non-NULL the call
+ *            synchronises `stream` to read them.  The new model has
+ *            n + CLONE + SPLIT - PRUNE Gaussians.
+ *   ws       device scratch >= veg_densify_workspace_bytes(n); keeps per-block offsets for
+ *            the following veg_densify_apply.
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+size_t veg_densify_workspace_bytes(int64_t n);
+veg_status veg_densify_plan(int64_t n, const float* grad_accum, const int32_t* vis_count,
+                            const float* log_scales, const float* weights, float grad_thresh,
+                            float log_scale_thresh, float prune_weight, uint8_t* action,
+                            int64_t* counts, void* ws, size_t ws_bytes, veg_stream_t stream);
+
+/* veg_densify_apply -- writes the model the plan describes into new arrays: first the
+ * survivors (KEEP and CLONE) in index order, then one copy of each CLONE Gaussian in index
+ * order, then the two children of each SPLIT Gaussian in index order (PRUNE Gaussians are
+ * dropped).  Child c of parent i sits at mu_i + R(q_i) diag(exp(log_s_i)) z[i][c] and has
+ * log-scales log_s_i - ln 1.6 (the 3DGS split: two samples of the parent, scale / 0.8 N);
+ * the rest is copied.
+ *   action, ws   as left by veg_densify_plan for the same n (same stream order)
+ *   quats        device [n,4], log_scales device [n,3]: the parent's rotation and scale
+ *   z            device [n][2][3] float: standard normal draws (only SPLIT rows are read);
+ *                the random numbers are the caller's
+ *   fields       host [n_fields] (1..16): src device [n][width], dst device
+ *                [n + CLONE + SPLIT - PRUNE][width] (no overlap with src), role
+ *                VEG_FIELD_COPY (copied to clones and children), VEG_FIELD_MEANS (width 3,
+ *                children offset as above), VEG_FIELD_LOG_SCALES (width 3, children
+ *                shrunk), VEG_FIELD_ZERO_NEW (0 for every new Gaussian: optimizer moments)
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+#define VEG_FIELD_COPY 0
+#define VEG_FIELD_MEANS 1
+#define VEG_FIELD_LOG_SCALES 2
+#define VEG_FIELD_ZERO_NEW 3
+typedef struct {
+  const float* src;
+  float* dst;
+  int32_t width;
+  int32_t role;
+} veg_densify_field;
+veg_status veg_densify_apply(int64_t n, const uint8_t* action, const float* quats,
+                             const float* log_scales, const float* z,
+                             const veg_densify_field* fields, int32_t n_fields, const void* ws,
+                             size_t ws_bytes, veg_stream_t stream);
+
 /* veg_vq_decode -- expands vector-quantised model attributes into the structure-of-arrays
  * model (trained models are stored with most parameters clustered into a codebook; the
  * paper adopts this from the compact-3DGS work it cites): Gaussian i's attribute vector is

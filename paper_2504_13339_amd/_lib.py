@@ -54,6 +54,10 @@ class veg_vq_field(Structure):
     _fields_ = [("dst", c_void_p), ("width", c_int32)]
 
 
+class veg_densify_field(Structure):
+    _fields_ = [("src", c_void_p), ("dst", c_void_p), ("width", c_int32), ("role", c_int32)]
+
+
 class veg_bins(Structure):
     _fields_ = [("keys", c_void_p), ("vals", c_void_p), ("keys_alt", c_void_p), ("vals_alt", c_void_p),
                 ("ranges", c_void_p), ("capacity", c_int64), ("hits", c_void_p), ("hit_words", c_int64)]
@@ -112,6 +116,11 @@ _SIGS = {
                               c_int32, c_void_p]),
     "veg_densify_stats": (c_int, [P(veg_proj), c_void_p, c_void_p, c_void_p, c_void_p]),
     "veg_vq_decode": (c_int, [c_void_p, c_int64, c_void_p, c_int32, c_int32, P(veg_vq_field), c_int32, c_void_p]),
+    "veg_densify_workspace_bytes": (c_size_t, [c_int64]),
+    "veg_densify_plan": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float, c_void_p,
+                                 c_void_p, c_void_p, c_size_t, c_void_p]),
+    "veg_densify_apply": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, P(veg_densify_field), c_int32,
+                                  c_void_p, c_size_t, c_void_p]),
     "veg_debug_math": (c_int, [c_int32, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     "veg_serve_arena_bytes": (c_size_t, [P(veg_serve_config)]),
     "veg_serve_create": (c_int, [P(veg_serve_config), P(c_void_p)]),

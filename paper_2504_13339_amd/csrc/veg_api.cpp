@@ -460,6 +460,78 @@ veg_status veg_densify_stats(const veg_proj* proj, const float* g2d, float* grad
   return VEG_OK;
 }
 
+// Densification scratch: 3 counters per block of 256 Gaussians, then the 3 totals.
+static int64_t densify_blocks(int64_t n) { return (n + 255) / 256; }
+
+size_t veg_densify_workspace_bytes(int64_t n) {
+  if (n < 0) return 0;
+  return (size_t)(3 * densify_blocks(n) + 4) * sizeof(uint32_t);
+}
+
+veg_status veg_densify_plan(int64_t n, const float* grad_accum, const int32_t* vis_count, const float* log_scales,
+                            const float* weights, float grad_thresh, float log_scale_thresh, float prune_weight,
+                            uint8_t* action, int64_t* counts, void* ws, size_t ws_bytes, veg_stream_t stream) {
+  g_err.clear();
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(VEG_ERR_INVALID_ARG, "densify_plan: n out of range");
+  if (std::isnan(grad_thresh) || std::isnan(log_scale_thresh) || std::isnan(prune_weight))
+    return fail(VEG_ERR_INVALID_ARG, "densify_plan: NaN threshold");
+  if (n == 0) {
+    if (counts) counts[0] = counts[1] = counts[2] = counts[3] = 0;
+    return VEG_OK;
+  }
+  if (!grad_accum || !vis_count || !log_scales || !action || !ws)
+    return fail(VEG_ERR_INVALID_ARG, "densify_plan: NULL argument");
+  if (ws_bytes < veg_densify_workspace_bytes(n)) return fail(VEG_ERR_INVALID_ARG, "densify_plan: workspace too small");
+  uint32_t* blk = (uint32_t*)ws;
+  uint32_t* tot = blk + 3 * densify_blocks(n);
+  hipStream_t st = (hipStream_t)stream;
+  VEG_CHECK_HIP(launch_densify_plan(n, grad_accum, vis_count, log_scales, weights, grad_thresh, log_scale_thresh,
+                                    prune_weight, action, blk, tot, st),
+                "veg_densify_plan");
+  if (counts) {
+    uint32_t t[3];
+    VEG_CHECK_HIP(hipMemcpyAsync(t, tot, sizeof(t), hipMemcpyDeviceToHost, st), "veg_densify_plan: read");
+    VEG_CHECK_HIP(hipStreamSynchronize(st), "veg_densify_plan: sync");
+    counts[0] = (int64_t)t[0] - t[1];
+    counts[1] = t[1];
+    counts[2] = t[2];
+    counts[3] = n - (int64_t)t[0] - t[2];
+  }
+  return VEG_OK;
+}
+
+veg_status veg_densify_apply(int64_t n, const uint8_t* action, const float* quats, const float* log_scales,
+                             const float* z, const veg_densify_field* fields, int32_t n_fields, const void* ws,
+                             size_t ws_bytes, veg_stream_t stream) {
+  g_err.clear();
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(VEG_ERR_INVALID_ARG, "densify_apply: n out of range");
+  if (!fields || n_fields < 1 || n_fields > kDensifyMaxFields)
+    return fail(VEG_ERR_INVALID_ARG, "densify_apply: need 1..%d fields", kDensifyMaxFields);
+  DensifyFields fl;
+  std::memset(&fl, 0, sizeof(fl));
+  for (int f = 0; f < n_fields; ++f) {
+    const veg_densify_field& d = fields[f];
+    if (d.width < 1 || d.width > 64 || d.role < 0 || d.role > 3)
+      return fail(VEG_ERR_INVALID_ARG, "densify_apply: field %d has a bad width or role", f);
+    if ((d.role == VEG_FIELD_MEANS || d.role == VEG_FIELD_LOG_SCALES) && d.width != 3)
+      return fail(VEG_ERR_INVALID_ARG, "densify_apply: field %d: means and log-scales have width 3", f);
+    if (n > 0 && (!d.src || !d.dst)) return fail(VEG_ERR_INVALID_ARG, "densify_apply: field %d is NULL", f);
+    fl.src[f] = d.src;
+    fl.dst[f] = d.dst;
+    fl.width[f] = d.width;
+    fl.role[f] = d.role;
+  }
+  fl.n_fields = n_fields;
+  if (n == 0) return VEG_OK;
+  if (!action || !quats || !log_scales || !z || !ws) return fail(VEG_ERR_INVALID_ARG, "densify_apply: NULL argument");
+  if (ws_bytes < veg_densify_workspace_bytes(n)) return fail(VEG_ERR_INVALID_ARG, "densify_apply: workspace too small");
+  const uint32_t* blk = (const uint32_t*)ws;
+  VEG_CHECK_HIP(launch_densify_apply(n, action, quats, log_scales, z, blk, blk + 3 * densify_blocks(n), fl,
+                                     (hipStream_t)stream),
+                "veg_densify_apply");
+  return VEG_OK;
+}
+
 veg_status veg_vq_decode(const uint16_t* idx, int64_t n, const float* book, int32_t k, int32_t dim,
                          const veg_vq_field* fields, int32_t n_fields, veg_stream_t stream) {
   g_err.clear();

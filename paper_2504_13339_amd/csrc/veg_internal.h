@@ -197,6 +197,23 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float eps, float bc1, float bc2, hipStream_t stream);
 hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float4* rec,
                                 const float* g2d, float* acc, int32_t* vis, hipStream_t stream);
+// Attribute arrays carried through a densification (kernel argument by value); role:
+// 0 copied to clones and children, 1 means, 2 log-scales, 3 zero for new Gaussians.
+constexpr int kDensifyMaxFields = 16;
+struct DensifyFields {
+  const float* src[kDensifyMaxFields];
+  float* dst[kDensifyMaxFields];
+  int32_t width[kDensifyMaxFields];
+  int32_t role[kDensifyMaxFields];
+  int32_t n_fields;
+};
+hipError_t launch_densify_plan(int64_t n, const float* acc, const int32_t* vis, const float* log_scales,
+                               const float* weights, float grad_thresh, float log_scale_thresh, float prune_weight,
+                               uint8_t* action, uint32_t* blk, uint32_t* tot, hipStream_t stream);
+hipError_t launch_densify_apply(int64_t n, const uint8_t* action, const float* quats, const float* log_scales,
+                                const float* z, const uint32_t* blk, const uint32_t* tot, const DensifyFields& fl,
+                                hipStream_t stream);
+
 // Destination fields of a codebook decode (kernel argument by value).
 constexpr int kVqMaxFields = 8;
 struct VqFields {

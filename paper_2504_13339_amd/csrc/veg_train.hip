@@ -210,6 +210,149 @@ __global__ __launch_bounds__(256) void densify_stats_kernel(const FrameDesc* __r
   vis[i] += c;
 }
 
+// Adaptive density control.  Decision per Gaussian (float32 comparisons): g = accum / vis
+// (0 where vis = 0); PRUNE unless weight >= prune_weight; else SPLIT when g >= grad_thresh
+// and the largest log-scale exceeds log_scale_thresh, CLONE when g >= grad_thresh otherwise;
+// else KEEP.  Each block of 256 Gaussians also counts its survivors (KEEP, CLONE), clones
+// and splits: blk[3 b + 0..2].
+constexpr int kDensifyBlock = 256;
+
+__device__ __forceinline__ int wave_excl_count(bool v, uint64_t& m) {
+  m = __ballot(v);
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Exclusive position of this thread among the block's threads with v set, and the total.
+__device__ __forceinline__ uint32_t block_excl_count(bool v, uint32_t* s_w, uint32_t& total) {
+  uint64_t m;
+  const int in_wave = wave_excl_count(v, m);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) s_w[w] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t before = 0;
+  total = 0;
+  for (int k = 0; k < kDensifyBlock / 64; ++k) {
+    if (k < w) before += s_w[k];
+    total += s_w[k];
+  }
+  __syncthreads();
+  return before + (uint32_t)in_wave;
+}
+
+__global__ __launch_bounds__(kDensifyBlock) void densify_plan_kernel(
+    int64_t n, const float* __restrict__ acc, const int32_t* __restrict__ vis, const float* __restrict__ log_scales,
+    const float* __restrict__ weights, float grad_thresh, float log_scale_thresh, float prune_weight,
+    uint8_t* __restrict__ action, uint32_t* __restrict__ blk) {
+  __shared__ uint32_t s_w[kDensifyBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kDensifyBlock + threadIdx.x;
+  uint8_t a = 0xff;   // past the end
+  if (i < n) {
+    const int32_t c = vis[i];
+    const float g = c > 0 ? acc[i] / (float)c : 0.0f;
+    const float* ls = log_scales + 3 * i;
+    const bool big = fmaxf(fmaxf(ls[0], ls[1]), ls[2]) > log_scale_thresh;
+    a = g >= grad_thresh ? (big ? 2 : 1) : 0;
+    if (weights && !(weights[i] >= prune_weight)) a = 3;
+    action[i] = a;
+  }
+  uint32_t ts, tc, tp;
+  block_excl_count(a == 0 || a == 1, s_w, ts);
+  block_excl_count(a == 1, s_w, tc);
+  block_excl_count(a == 2, s_w, tp);
+  if (threadIdx.x == 0) {
+    blk[3 * blockIdx.x + 0] = ts;
+    blk[3 * blockIdx.x + 1] = tc;
+    blk[3 * blockIdx.x + 2] = tp;
+  }
+}
+
+// Exclusive scan of the per-block counts (one block; blk rewritten in place), totals in
+// tot[0..2] (survivors, clones, splits).
+__global__ __launch_bounds__(1024) void densify_scan_kernel(uint32_t* __restrict__ blk, int G,
+                                                            uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_sum[3][1024];
+  const int per = (G + 1023) / 1024;
+  const int b0 = threadIdx.x * per, b1 = min(G, b0 + per);
+  uint32_t loc[3] = {0, 0, 0};
+  for (int b = b0; b < b1; ++b)
+    for (int q = 0; q < 3; ++q) loc[q] += blk[3 * b + q];
+  for (int q = 0; q < 3; ++q) s_sum[q][threadIdx.x] = loc[q];
+  __syncthreads();
+  if (threadIdx.x < 3) {   // serial scan of 1024 partial sums per stream
+    uint32_t run = 0;
+    for (int k = 0; k < 1024; ++k) {
+      const uint32_t v = s_sum[threadIdx.x][k];
+      s_sum[threadIdx.x][k] = run;
+      run += v;
+    }
+    tot[threadIdx.x] = run;
+  }
+  __syncthreads();
+  uint32_t run[3] = {s_sum[0][threadIdx.x], s_sum[1][threadIdx.x], s_sum[2][threadIdx.x]};
+  for (int b = b0; b < b1; ++b)
+    for (int q = 0; q < 3; ++q) {
+      const uint32_t v = blk[3 * b + q];
+      blk[3 * b + q] = run[q];
+      run[q] += v;
+    }
+}
+
+// The new model: survivors in order, then a copy of every clone in order, then two children
+// of every split in order; child c of parent i at mu_i + R(q_i) diag(exp(log_s_i)) z[i, c],
+// with log-scales log_s_i - ln 1.6.
+__global__ __launch_bounds__(kDensifyBlock) void densify_apply_kernel(
+    int64_t n, const uint8_t* __restrict__ action, const float* __restrict__ quats,
+    const float* __restrict__ log_scales, const float* __restrict__ z, const uint32_t* __restrict__ blk,
+    const uint32_t* __restrict__ tot, DensifyFields fl) {
+  __shared__ uint32_t s_w[kDensifyBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kDensifyBlock + threadIdx.x;
+  const uint8_t a = i < n ? action[i] : (uint8_t)0xff;
+  uint32_t ts, tc, tp;
+  const uint32_t ps = block_excl_count(a == 0 || a == 1, s_w, ts);
+  const uint32_t pc = block_excl_count(a == 1, s_w, tc);
+  const uint32_t pp = block_excl_count(a == 2, s_w, tp);
+  if (i >= n || a == 3) return;
+  const size_t n_surv = tot[0], n_clone = tot[1];
+  const size_t surv = (size_t)blk[3 * blockIdx.x + 0] + ps;
+  const size_t clone = n_surv + (size_t)blk[3 * blockIdx.x + 1] + pc;
+  const size_t child = n_surv + n_clone + 2 * ((size_t)blk[3 * blockIdx.x + 2] + pp);
+  float off[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  if (a == 2) {
+    const float* q = quats + 4 * i;
+    const float qn = 1.0f / sqrtf(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
+    const float w = q[0] * qn, x = q[1] * qn, y = q[2] * qn, zq = q[3] * qn;
+    const float R[9] = {1.0f - 2.0f * (y * y + zq * zq), 2.0f * (x * y - w * zq), 2.0f * (x * zq + w * y),
+                        2.0f * (x * y + w * zq), 1.0f - 2.0f * (x * x + zq * zq), 2.0f * (y * zq - w * x),
+                        2.0f * (x * zq - w * y), 2.0f * (y * zq + w * x), 1.0f - 2.0f * (x * x + y * y)};
+    const float* ls = log_scales + 3 * i;
+    const float sc[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+    for (int c = 0; c < 2; ++c) {
+      const float* zc = z + 6 * i + 3 * c;
+      for (int r = 0; r < 3; ++r)
+        off[c][r] = (R[3 * r + 0] * (sc[0] * zc[0]) + R[3 * r + 1] * (sc[1] * zc[1])) + R[3 * r + 2] * (sc[2] * zc[2]);
+    }
+  }
+  for (int f = 0; f < fl.n_fields; ++f) {
+    const int wd = fl.width[f], role = fl.role[f];
+    const float* src = fl.src[f] + (size_t)i * wd;
+    float* dst = fl.dst[f];
+    if (a != 2) {
+      for (int k = 0; k < wd; ++k) dst[surv * wd + k] = src[k];
+      if (a == 1)
+        for (int k = 0; k < wd; ++k) dst[clone * wd + k] = role == 3 ? 0.0f : src[k];
+    } else {
+      for (int c = 0; c < 2; ++c)
+        for (int k = 0; k < wd; ++k) {
+          float v = src[k];
+          if (role == 1 && k < 3) v = src[k] + off[c][k];
+          else if (role == 2) v = src[k] - 0.47000362924573558f;   // ln 1.6
+          else if (role == 3) v = 0.0f;
+          dst[(child + c) * wd + k] = v;
+        }
+    }
+  }
+}
+
 }  // namespace
 
 // The window taps: exp(-x^2 / (2 sigma^2)) at x = -5..5, sigma 1.5, divided by their sum.
@@ -245,6 +388,27 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   if (blocks > 65535) blocks = 65535;
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, g, m, v, n, lr, b1, b2, eps, bc1,
                      bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_densify_plan(int64_t n, const float* acc, const int32_t* vis, const float* log_scales,
+                               const float* weights, float grad_thresh, float log_scale_thresh, float prune_weight,
+                               uint8_t* action, uint32_t* blk, uint32_t* tot, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int G = (int)((n + kDensifyBlock - 1) / kDensifyBlock);
+  hipLaunchKernelGGL(densify_plan_kernel, dim3(G), dim3(kDensifyBlock), 0, stream, n, acc, vis, log_scales, weights,
+                     grad_thresh, log_scale_thresh, prune_weight, action, blk);
+  hipLaunchKernelGGL(densify_scan_kernel, dim3(1), dim3(1024), 0, stream, blk, G, tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_densify_apply(int64_t n, const uint8_t* action, const float* quats, const float* log_scales,
+                                const float* z, const uint32_t* blk, const uint32_t* tot, const DensifyFields& fl,
+                                hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int G = (int)((n + kDensifyBlock - 1) / kDensifyBlock);
+  hipLaunchKernelGGL(densify_apply_kernel, dim3(G), dim3(kDensifyBlock), 0, stream, n, action, quats, log_scales, z,
+                     blk, tot, fl);
   return hipGetLastError();
 }
 

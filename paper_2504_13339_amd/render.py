@@ -324,3 +324,42 @@ class Adam:
         self.t += 1
         for (p, lr), gr, m, v in zip(self.params, grads, self.m, self.v):
             V.veg_adam_step(p, gr, m, v, lr, self.t, self.betas[0], self.betas[1], self.eps, stream=stream)
+
+
+def densify_model(g: V.Gaussians, stats: DensifyStats, grad_thresh: float, log_scale_thresh: float,
+                  prune_weight: float, z: torch.Tensor, adam: Optional[Adam] = None, stream=None):
+    """One densification step: clone, split and prune decisions from ``stats`` (see
+    veg_densify_plan), then the new model (see veg_densify_apply); ``z`` [n, 2, 3] holds the
+    standard normal draws for split children.  With ``adam`` its parameters are rebound to
+    the new tensors and its moments carried over (zero for new Gaussians).  Returns
+    (new Gaussians, counts [KEEP, CLONE, SPLIT, PRUNE])."""
+    n = g.n
+    action, counts, ws = V.veg_densify_plan(stats.grad_accum, stats.vis_count, g.log_scales, g.weights, grad_thresh,
+                                            log_scale_thresh, prune_weight, stream=stream)
+    n_new = n + counts[V.CLONE] + counts[V.SPLIT] - counts[V.PRUNE]
+
+    def like(t):
+        return torch.empty((n_new,) + tuple(t.shape[1:]), dtype=t.dtype, device=t.device)
+    names = ("means", "log_scales", "quats", "scalars", "weights") + V.LIGHTING
+    out, fields = {}, []
+    for name in names:
+        t = getattr(g, name)
+        if t is None:
+            continue
+        out[name] = like(t)
+        role = V.FIELD_MEANS if name == "means" else V.FIELD_LOG_SCALES if name == "log_scales" else V.FIELD_COPY
+        fields.append((t, out[name], role))
+    V.veg_densify_apply(action, g.quats, g.log_scales, z, fields, ws, stream=stream)
+    if adam is not None:
+        params, moms = [], []
+        for (p, lr), m, v in zip(adam.params, adam.m, adam.v):
+            name = next(k for k in out if getattr(g, k) is p)
+            nm, nv = like(m), like(v)
+            moms += [(m, nm, V.FIELD_ZERO_NEW), (v, nv, V.FIELD_ZERO_NEW)]
+            params.append((out[name], lr, nm, nv))
+        for k in range(0, len(moms), 16):
+            V.veg_densify_apply(action, g.quats, g.log_scales, z, moms[k:k + 16], ws, stream=stream)
+        adam.params = [(p, lr) for p, lr, _, _ in params]
+        adam.m = [m for _, _, m, _ in params]
+        adam.v = [v for _, _, _, v in params]
+    return V.Gaussians(**out), counts

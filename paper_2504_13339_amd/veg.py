@@ -20,8 +20,12 @@ __all__ = [
     "veg_bin_overflow", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
     "veg_debug_math", "veg_bin_hit_words", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
     "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_adam_step", "veg_densify_stats", "veg_project_views",
-    "veg_vq_decode", "decode_vq_model",
+    "veg_vq_decode", "decode_vq_model", "veg_densify_plan", "veg_densify_apply", "veg_densify_workspace_bytes",
+    "KEEP", "CLONE", "SPLIT", "PRUNE", "FIELD_COPY", "FIELD_MEANS", "FIELD_LOG_SCALES", "FIELD_ZERO_NEW",
 ]
+
+KEEP, CLONE, SPLIT, PRUNE = 0, 1, 2, 3
+FIELD_COPY, FIELD_MEANS, FIELD_LOG_SCALES, FIELD_ZERO_NEW = 0, 1, 2, 3
 
 
 def stream_handle(stream: Optional[torch.cuda.Stream] = None):
@@ -338,6 +342,48 @@ def decode_vq_model(means: torch.Tensor, scalars: torch.Tensor, shape_idx: torch
     q = torch.empty((n, 4), dtype=torch.float32, device=means.device)
     veg_vq_decode(shape_idx, shape_book, [ls, q], stream=stream)
     return Gaussians(means, ls, q, scalars, weights)
+
+
+def veg_densify_workspace_bytes(n: int) -> int:
+    return int(load().veg_densify_workspace_bytes(int(n)))
+
+
+def veg_densify_plan(grad_accum: torch.Tensor, vis_count: torch.Tensor, log_scales: torch.Tensor,
+                     weights: Optional[torch.Tensor], grad_thresh: float, log_scale_thresh: float,
+                     prune_weight: float, read_counts: bool = True, stream=None):
+    """Clone / split / prune decisions; returns (action uint8 [n], counts [KEEP, CLONE, SPLIT,
+    PRUNE] or None, workspace for veg_densify_apply)."""
+    n = int(log_scales.shape[0])
+    if grad_accum.dtype != torch.float32 or vis_count.dtype != torch.int32 or grad_accum.numel() < n \
+            or vis_count.numel() < n:
+        raise ValueError("grad_accum float32 [n] and vis_count int32 [n] expected")
+    action = torch.empty(max(1, n), dtype=torch.uint8, device=log_scales.device)
+    ws = torch.empty(max(4, veg_densify_workspace_bytes(n)), dtype=torch.uint8, device=log_scales.device)
+    counts = (ctypes.c_int64 * 4)() if read_counts else None
+    check(load().veg_densify_plan(n, _ptr(grad_accum), _ptr(vis_count), _ptr(log_scales.contiguous()), _ptr(weights),
+                                  float(grad_thresh), float(log_scale_thresh), float(prune_weight), _ptr(action),
+                                  ctypes.cast(counts, ctypes.c_void_p) if counts is not None else None, _ptr(ws),
+                                  ws.numel(), stream_handle(stream)), "veg_densify_plan")
+    return action, (list(counts) if counts is not None else None), ws
+
+
+def veg_densify_apply(action: torch.Tensor, quats: torch.Tensor, log_scales: torch.Tensor, z: torch.Tensor,
+                      fields: Sequence[tuple], ws: torch.Tensor, stream=None):
+    """Writes the new model: fields are (src [n] or [n, w], dst [n_new] or [n_new, w], role)."""
+    n = int(log_scales.shape[0])
+    if z.dtype != torch.float32 or z.numel() < 6 * n:
+        raise ValueError("z must be float32 [n, 2, 3]")
+    fs = []
+    for src, dst, role in fields:
+        w = 1 if src.dim() == 1 else int(src.shape[1])
+        if src.dtype != torch.float32 or dst.dtype != torch.float32 or not src.is_contiguous() \
+                or not dst.is_contiguous() or (dst.numel() // max(1, w)) * w != dst.numel():
+            raise ValueError("fields must be contiguous float32 tensors of one width")
+        fs.append(_lib.veg_densify_field(_ptr(src), _ptr(dst), w, int(role)))
+    arr = (_lib.veg_densify_field * len(fs))(*fs)
+    check(load().veg_densify_apply(n, _ptr(action), _ptr(quats.contiguous()), _ptr(log_scales.contiguous()),
+                                   _ptr(z.contiguous()), arr, len(fs), _ptr(ws), ws.numel(), stream_handle(stream)),
+          "veg_densify_apply")
 
 
 def veg_fill_u32(t: torch.Tensor, value: int = 0, stream=None):

@@ -127,3 +127,20 @@ def test_vq_decode_arguments_are_checked_on_host():
     assert lib.veg_vq_decode(fake, 10, fake, 0, 6, f, 2, None) == 1           # empty codebook
     assert lib.veg_vq_decode(fake, 10, fake, 16, 6, f, 9, None) == 1          # too many fields
     assert lib.veg_vq_decode(None, 0, None, 16, 6, f, 2, None) == 0           # nothing to decode
+
+
+def test_densify_arguments_are_checked_on_host():
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.veg_densify_workspace_bytes(1000) == (3 * 4 + 4) * 4
+    f = (_lib.veg_densify_field * 1)(_lib.veg_densify_field(fake, fake, 4, 1))      # means must have width 3
+    assert lib.veg_densify_apply(10, fake, fake, fake, fake, f, 1, fake, 1 << 20, None) == 1
+    assert b"width 3" in lib.veg_last_error()
+    f[0].width, f[0].role = 3, 7
+    assert lib.veg_densify_apply(10, fake, fake, fake, fake, f, 1, fake, 1 << 20, None) == 1
+    assert lib.veg_densify_plan(10, fake, fake, fake, None, ctypes.c_float(float("nan")), ctypes.c_float(0.0),
+                                ctypes.c_float(0.0), fake, None, fake, 1 << 20, None) == 1
+    assert lib.veg_densify_plan(10, fake, fake, fake, None, ctypes.c_float(0.1), ctypes.c_float(0.0),
+                                ctypes.c_float(0.0), fake, None, fake, 4, None) == 1          # small workspace
