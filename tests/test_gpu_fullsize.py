@@ -115,3 +115,72 @@ def test_stress_workload_2048px_4M():
         res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
         gpu = image_pixels(st.image[f])[px[:, 1] * w.width + px[:, 0]]
         compare_image(gpu, res)
+
+
+# ----------------------------------------------------------------------------- shared views
+# The benchmark's launch configuration: all 48 frames in one group, the three frames of each
+# view sharing its projection and key list (tiles numbered per view).
+
+def _shared_all(w):
+    from paper_2504_13339_amd import render as R
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    st = R.render(g, w.cameras, [luts[t] for _, t in w.frames], w.opts, shared=True)
+    torch.cuda.synchronize()
+    return g, luts, st
+
+
+def test_train_workload_shared_views_all_48_frames():
+    w = synth.workload(2)
+    K = len(w.tfs)
+    n = w.gaussians.n
+    g, luts, st = _shared_all(w)
+    keys, vals, rg = _check_whole_list(st, n, len(w.frames))
+    assert int(st.proj.struct.total_tiles) == len(w.cameras) * 64 * 64
+    # sampled tiles of two views: the list equals the oracle's shared-footprint mirror
+    rng = np.random.default_rng(3)
+    per = 64 * 64
+    for v in (0, 11):
+        un = oracle.footprint_shared_f32(w.gaussians, w.cameras[v], w.tfs, w.opts)
+        lens = rg[v * per:(v + 1) * per, 1] - rg[v * per:(v + 1) * per, 0]
+        for t in list(rng.integers(0, per, 5)) + [int(np.argmax(lens))]:
+            ty, tx = divmod(int(t), 64)
+            cover = (un.count > 0) & (un.rect[:, 0] <= tx) & (un.rect[:, 2] >= tx) & \
+                    (un.rect[:, 1] <= ty) & (un.rect[:, 3] >= ty)
+            idx = np.nonzero(cover)[0]
+            ref = idx[np.lexsort((idx, un.depth_bits[idx]))] + v * K * n
+            s, e = rg[v * per + t]
+            got = vals[s:e] if e > s else np.zeros(0, np.int64)
+            assert np.array_equal(got, ref), (v, t)
+    # sampled pixels of frames in every slot of a view, against the per-frame oracle
+    prng = synth.rng_for(2, 80)
+    for f in (0, 1, 2, 35):
+        ci, ti = w.frames[f]
+        px = synth.sample_pixels(prng, w.width, w.height, 160)
+        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
+        gpu = image_pixels(st.image[f])[px[:, 1] * w.width + px[:, 0]]
+        compare_image(gpu, res)
+
+
+def test_train_workload_shared_views_sampled_pixel_gradient():
+    """dL/dparams for L = sum over 48 sampled pixels of d . image of frame 4 (view 1, second
+    table: a frame that blends its view's list without owning it)."""
+    from paper_2504_13339_amd import render as R
+    w = synth.workload(2)
+    g, luts, st = _shared_all(w)
+    f = 4
+    ci, ti = w.frames[f]
+    rng = synth.rng_for(2, 81)
+    px = synth.sample_pixels(rng, w.width, w.height, 48)
+    d = rng.standard_normal((48, 3))
+    res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
+    d[res.flag_grad] = 0.0
+    d_np = np.zeros((len(w.frames), 3, w.height, w.width), np.float32)
+    for ch in range(3):
+        np.add.at(d_np[f, ch], (px[:, 1], px[:, 0]), d[:, ch].astype(np.float32))
+    grads = R.Grads.zeros(g)
+    R.render_backward(g, st, torch.as_tensor(d_np).cuda(), grads)
+    torch.cuda.synchronize()
+    ref = oracle.gradients(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, d, pixels=px)
+    for name in ("d_means", "d_log_scales", "d_quats", "d_scalars"):
+        assert rel_err(getattr(grads, name).cpu().numpy(), getattr(ref, name)) <= 1e-3, name
