@@ -130,6 +130,48 @@ def eval_counts(st, t_min):
     return int(fwd.sum()), int(bwd.sum()), blended
 
 
+def opacity_guided_bench(steps, warmup=2):
+    """The opacity-guided training family (500k shell-clustered Gaussians, 8 views x 10 tent
+    opacity maps, 800x800, targets from a perturbed copy): L1 training steps over all 80
+    frames, with the views' frames on shared lists and on their own lists."""
+    import torch
+
+    import synth
+    from paper_2504_13339_amd import render as R
+    from paper_2504_13339_amd import veg as V
+    w = synth.workload(5)
+    g = V.Gaussians.from_numpy(w.gaussians)
+    gt = V.Gaussians.from_numpy(w.target_gaussians)
+    luts = [torch.as_tensor(t).cuda() for t in w.tfs]
+    F = len(w.frames)
+    K = R.views_of(w.frames)
+    st = R.render(gt, w.cameras, [luts[t] for _, t in w.frames], w.opts, shared=True, hits=False)
+    targets = st.image.clone()
+    del st
+    grads = R.Grads.zeros(g)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    out = {"workload": w.name, "frames": F, "tables_per_view": K, "width": w.width, "height": w.height}
+    for shared in (True, False):
+        def step():
+            return R.train_step(g, w.cameras, luts, w.frames, targets, grads, F, w.opts, loss_acc=loss, shared=shared)
+        for _ in range(warmup):
+            step()
+        gc.collect()
+        gc.disable()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gc.enable()
+        out["shared_mpix_s" if shared else "own_lists_mpix_s"] = round(F * w.width * w.height * steps / dt / 1e6, 2)
+        out["shared_ms_per_step" if shared else "own_lists_ms_per_step"] = round(dt * 1e3 / steps, 3)
+    del grads, targets, g, gt
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, n_pixels, seed=5):
     """The oracle (float64 brute force + autograd adjoint) on ``n_pixels`` sampled pixels of
     the first frame of the workload, forward and backward."""
@@ -253,6 +295,9 @@ def main():
     ap.add_argument("--cpu-pixels", type=int, default=640)
     ap.add_argument("--lit-steps", type=int, default=5,
                     help="timed steps of the same workload with lighting attributes (0 to skip)")
+    ap.add_argument("--og-steps", type=int, default=5,
+                    help="timed training steps of the opacity-guided family (8 views x 10 tent opacity maps, "
+                         "800x800, 500k Gaussians), shared and own lists (0 to skip)")
     ap.add_argument("--full-steps", type=int, default=5,
                     help="timed whole training iterations: L1 + SSIM loss, densification statistics, Adam (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -443,6 +488,12 @@ def main():
         "roofline": roof,
         "roofline_other_blend": other,
     }
+    if args.og_steps > 0:
+        del grads, targets
+        torch.cuda.empty_cache()
+        log("bench: opacity-guided family")
+        out["opacity_guided"] = opacity_guided_bench(args.og_steps)
+        grads = targets = None
     if args.serve_rates:
         del grads, targets
         torch.cuda.empty_cache()

@@ -153,7 +153,10 @@ void veg_opts_default(veg_opts* opts);
  *           is the inverse 2D covariance [[a,b],[b,c]], A = O(v) w, RGB = C(v), and
  *           rect01 / rect23 hold the tile rectangle (x0 | y0<<16, x1 | y1<<16) as uint32
  *   count   device [n_frames*n] uint32: tiles covered, 0 when culled
- *   depth   device [n_frames*n] uint32: float32 bits of camera z (kept pairs only)   */
+ *   depth   device [n_frames*n] uint32: float32 bits of camera z (kept pairs only); for
+ *           the views of veg_project_views, the slots of a view's second frame hold, per
+ *           Gaussian in the view's list, the bits of the frames that keep it (bit k: frame
+ *           v * tfs_per_view + k; all bits from 31 on for views of more than 32 frames) */
 typedef struct {
   int64_t n;            /* in: Gaussians per frame */
   int32_t n_frames;     /* in */

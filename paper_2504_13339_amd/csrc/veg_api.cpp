@@ -345,7 +345,7 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
   VEG_CHECK_HIP(launch_blend_fwd((const FrameDesc*)proj->frames, proj->n_frames, per_view_of(proj),
                                  proj->tiles_x * proj->tiles_y, kopts(&o), (const float4*)proj->rec, bins->vals,
                                  bins->ranges, image, t_final, n_last, n_contrib, bins->hits,
-                                 hit_stride_of(proj, bins), (hipStream_t)stream),
+                                 hit_stride_of(proj, bins), proj->depth, (hipStream_t)stream),
                 "veg_render_fwd");
   return VEG_OK;
 }

@@ -181,7 +181,8 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
-                            uint64_t* hits, uint64_t hit_stride, hipStream_t stream);
+                            uint64_t* hits, uint64_t hit_stride, const uint32_t* keep_bits,
+                            hipStream_t stream);
 hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             const float* tfinal, const int32_t* nlast, const float* dimage,

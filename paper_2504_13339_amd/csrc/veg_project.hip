@@ -315,6 +315,7 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
     const float c0 = p.S11 / p.det, c1 = -p.S01 / p.det, c2 = p.S00 / p.det;
     const float mxr = (float)(p.mx - 16.0 * (double)x0);
     const float myr = (float)(p.my - 16.0 * (double)y0);
+    uint32_t keep_bits = 0u;   // frames of the view that keep the Gaussian (bit k: slot k)
     // one record per frame: the shared geometry with the frame's own A and colour.  A = 0
     // where the frame's own footprint culls the Gaussian (A below alpha_min, or an ellipse
     // that covers no pixel centre), so the frame keeps exactly the Gaussians it would keep
@@ -344,12 +345,16 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
         Lit L;
         shade(dk, g, tk.rgb, rgb, L);
       }
+      if (Ak > 0.0f || k >= 32) keep_bits |= 1u << min(k, 31);
       float4* r = rec + 3 * (size_t)(dk.pair_base + (uint32_t)i);
       r[0] = make_float4(mxr, myr, c0, c1);
       r[1] = make_float4(c2, Ak, rgb[0], rgb[1]);
       r[2] = make_float4(rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
                          __uint_as_float((uint32_t)(f + k) | (inset << kFrameBits)));
     }
+    // a shared list's frames skip entries by these bits before loading their records; the
+    // depth slots of the frames after the owner are otherwise unused (never counted)
+    if (n_share > 1) depth[descs[f + 1].pair_base + (uint32_t)i] = keep_bits;
   }
 }
 

@@ -56,6 +56,12 @@ def test_shared_key_list_and_records_bit_exact(K, tents):
         assert np.array_equal(count[o], un.count), f"view {v}: shared tile counts differ"
         assert np.array_equal(depth[o][kept], un.depth_bits[kept])
         assert np.array_equal(_rects(rec[o][kept]), un.rect[kept])
+        if K > 1:   # keep bits of the view's frames, in the depth slots of its second frame
+            bits = np.zeros(n, np.int64)
+            for k in range(K):
+                own_k = oracle.footprint_f32(w.gaussians, cam, w.tfs[k], OPTS)
+                bits |= own_k.keep.astype(np.int64) << min(k, 31)
+            assert np.array_equal(depth[o + 1][kept].astype(np.int64), bits[kept])
         for k in range(K):
             f = o + k
             if k > 0:
