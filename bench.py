@@ -133,7 +133,8 @@ def eval_counts(st, t_min):
 def opacity_guided_bench(steps, warmup=2):
     """The opacity-guided training family (500k shell-clustered Gaussians, 8 views x 10 tent
     opacity maps, 800x800, targets from a perturbed copy): L1 training steps over all 80
-    frames, with the views' frames on shared lists and on their own lists."""
+    frames with a view's ten frames on one shared list, with neighbouring maps sharing in
+    pairs, and with every frame on its own list."""
     import torch
 
     import synth
@@ -151,7 +152,7 @@ def opacity_guided_bench(steps, warmup=2):
     grads = R.Grads.zeros(g)
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     out = {"workload": w.name, "frames": F, "tables_per_view": K, "width": w.width, "height": w.height}
-    for shared in (True, False):
+    for shared in (True, 2, False):
         def step():
             return R.train_step(g, w.cameras, luts, w.frames, targets, grads, F, w.opts, loss_acc=loss, shared=shared)
         for _ in range(warmup):
@@ -165,8 +166,9 @@ def opacity_guided_bench(steps, warmup=2):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         gc.enable()
-        out["shared_mpix_s" if shared else "own_lists_mpix_s"] = round(F * w.width * w.height * steps / dt / 1e6, 2)
-        out["shared_ms_per_step" if shared else "own_lists_ms_per_step"] = round(dt * 1e3 / steps, 3)
+        key = "shared" if shared is True else "pairs_shared" if shared else "own_lists"
+        out[key + "_mpix_s"] = round(F * w.width * w.height * steps / dt / 1e6, 2)
+        out[key + "_ms_per_step"] = round(dt * 1e3 / steps, 3)
     del grads, targets, g, gt
     torch.cuda.empty_cache()
     return out

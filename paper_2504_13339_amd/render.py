@@ -242,7 +242,7 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
                targets: torch.Tensor, grads: Grads, group: int, opts=None, ssim_lambda: float = 0.0, stream=None,
                loss_acc: Optional[torch.Tensor] = None, read_loss: bool = True, timer=NO_TIMER, on_group=None,
                want_contrib: bool = False, densify: Optional[DensifyStats] = None,
-               shared: bool = False) -> StepResult:
+               shared=False) -> StepResult:
     """One multi-view x multi-TF training step with the image loss
     (1 - lambda) mean|image - target| + lambda mean(1 - SSIM), means over all frames,
     channels and pixels.
@@ -254,18 +254,26 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
     stays inside one image plane), so the accumulated gradient equals the full-step
     gradient.  With ``densify`` the densification statistics of every group are added.
 
-    With ``shared`` the frames must be a view-major product of cameras and tables; a
-    group is then a whole number of views (``group`` rounded down to a multiple of the
-    tables per view, at least one view) and each view's frames share one projection and
-    key list."""
+    With ``shared`` the frames share projections and key lists in runs of K consecutive
+    frames that have one camera: ``shared=True`` takes K = all the tables of a view (the
+    frames must be a view-major product of cameras and tables), an integer ``shared=K``
+    takes runs of K (e.g. neighbouring maps of a tent family, whose footprints overlap).  A
+    group is then a whole number of runs (``group`` rounded down to a multiple of K, at
+    least one run)."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
     if not 0.0 <= ssim_lambda <= 1.0:
         raise ValueError("ssim_lambda must lie in [0, 1]")
     K = 1
-    if shared:
+    if shared is True:
         K = views_of(frames)
         if K == 0:
             raise ValueError("shared views need frames ordered as views x the same tables")
+    elif shared:
+        K = int(shared)
+        if K < 1 or len(frames) % K or any(frames[i][0] != frames[i - i % K][0] for i in range(len(frames))):
+            raise ValueError("shared runs need K consecutive frames with one camera")
+    shared = K > 1 or shared is True
+    if shared:
         group = max(K, group // K * K)
     F = len(frames)
     H, W = int(targets.shape[-2]), int(targets.shape[-1])

@@ -144,3 +144,14 @@ def test_densify_arguments_are_checked_on_host():
                                 ctypes.c_float(0.0), fake, None, fake, 1 << 20, None) == 1
     assert lib.veg_densify_plan(10, fake, fake, fake, None, ctypes.c_float(0.1), ctypes.c_float(0.0),
                                 ctypes.c_float(0.0), fake, None, fake, 4, None) == 1          # small workspace
+
+
+def test_shared_runs_must_share_a_camera():
+    import pytest
+    from paper_2504_13339_amd import render as R
+    with pytest.raises(ValueError):
+        R.train_step(None, None, None, [(0, 0), (1, 0)], None, None, 2, shared=2)
+    with pytest.raises(ValueError):
+        R.train_step(None, None, None, [(0, 0), (0, 1), (0, 2)], None, None, 2, shared=2)
+    with pytest.raises(ValueError):
+        R.train_step(None, None, None, [(0, 0), (0, 1), (1, 1), (1, 0)], None, None, 4, shared=True)
