@@ -397,7 +397,10 @@ veg_status veg_adam_step(float* param, const float* grad, float* m, float* v, in
 /* veg_densify_stats -- statistics for the adaptive density control (section "Training":
  * gradients drive densification and pruning): for every Gaussian, over the frames of
  * `proj` in which it was kept, the norm of dL/d(projected centre) in pixels taken from
- * g2d, and the number of such frames.
+ * g2d, and the number of such frames.  Kept in a frame: its own footprint keeps it (tile
+ * count > 0 from veg_project; for the views of veg_project_views, in the view's list
+ * with the frame's own A > 0 in its record, which is the same set).
+ *   g2d         device [n_frames*n][9], as accumulated by veg_render_bwd
  *   grad_accum  device [n] float, ADDED
  *   vis_count   device [n] int32, ADDED
  * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
