@@ -188,3 +188,42 @@ def test_shared_train_step_matches_unshared():
         assert rel_err(v, out[False][1][k]) <= 1e-3, k
     assert np.array_equal(out[True][2], out[False][2])
 
+
+
+def test_shared_view_with_a_table_that_culls_everything():
+    """A zero-opacity table in the middle of a view: its frame is background everywhere and
+    adds nothing to any gradient; the other frames match the oracle."""
+    V, R = hip()
+    w = _case(n=2000, K=3, res=64, views=1)
+    w.tfs[1] = synth.constant_tf(rgba=(0.3, 0.6, 0.9, 0.0))
+    g, luts, st = _render_shared(w)
+    bg = np.array(OPTS["bg"], np.float32)
+    assert np.array_equal(st.image[1].cpu().numpy(), np.broadcast_to(bg[:, None, None], (3, 64, 64)))
+    assert bool((st.t_final[1] == 1.0).all()) and bool((st.n_last[1] == -1).all())
+    for f in (0, 2):
+        res, *_ = oracle.render_image(w.gaussians, w.cameras[0], w.tfs[f], OPTS)
+        compare_image(image_pixels(st.image[f]), res)
+    d = torch.zeros_like(st.image)
+    d[1] = 1.0                                     # only the culled frame has a loss gradient
+    grads = R.Grads.zeros(g)
+    R.render_backward(g, st, d, grads)
+    torch.cuda.synchronize()
+    assert float(grads.d_means.abs().max()) == 0.0 and float(grads.d_scalars.abs().max()) == 0.0
+
+
+def test_one_table_per_view_is_the_plain_projection_bit_for_bit():
+    """veg_project_views with one table per view takes exactly veg_project's path."""
+    V, R = hip()
+    w = _case(n=3000, K=1, res=80, views=3)
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    a = R.render(g, w.cameras, [luts[t] for _, t in w.frames], OPTS, shared=True)
+    b = R.render(g, [w.cameras[c] for c, _ in w.frames], [luts[t] for _, t in w.frames], OPTS)
+    torch.cuda.synchronize()
+    assert torch.equal(a.image, b.image) and torch.equal(a.n_last, b.n_last)
+    assert torch.equal(a.proj.count, b.proj.count)
+    kept = a.proj.count[: a.proj.n_pairs] > 0          # records exist for counted pairs only
+    ra, rb = a.proj.rec.view(-1, 12)[: a.proj.n_pairs], b.proj.rec.view(-1, 12)[: b.proj.n_pairs]
+    assert torch.equal(ra[kept], rb[kept])
+    assert a.n_entries == b.n_entries and torch.equal(a.bins.keys[:a.n_entries], b.bins.keys[:b.n_entries])
+    assert torch.equal(a.bins.vals[:a.n_entries], b.bins.vals[:b.n_entries])
