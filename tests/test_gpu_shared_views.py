@@ -227,3 +227,39 @@ def test_one_table_per_view_is_the_plain_projection_bit_for_bit():
     assert torch.equal(ra[kept], rb[kept])
     assert a.n_entries == b.n_entries and torch.equal(a.bins.keys[:a.n_entries], b.bins.keys[:b.n_entries])
     assert torch.equal(a.bins.vals[:a.n_entries], b.bins.vals[:b.n_entries])
+
+
+def test_shared_views_with_lighting_match_oracle():
+    """Blinn-Phong shading on a shared list: each frame shades its own table's colour under
+    the view's headlight."""
+    V, R = hip()
+    w = _case(n=2000, K=3, res=64, views=1)
+    w.gaussians.shading = synth.random_shading(synth.rng_for(0, 93), w.gaussians.n)
+    g, luts, st = _render_shared(w)
+    assert g.lit
+    for f, (ci, ti) in enumerate(w.frames):
+        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], OPTS)
+        compare_image(image_pixels(st.image[f]), res)
+
+
+def test_train_step_sharing_in_runs_of_two_matches_own_lists():
+    """Tent maps shared by neighbouring pairs (shared=2) against every frame on its own list:
+    same loss and gradients up to the centre's rounding, same visibility counts."""
+    V, R = hip()
+    w = _case(n=4000, views=2, K=4, res=80, tents=True)
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    rng = np.random.default_rng(94)
+    tgt = torch.as_tensor(rng.uniform(0, 1, (len(w.frames), 3, 80, 80)).astype(np.float32)).cuda()
+    out = {}
+    for shared in (False, 2):
+        grads = R.Grads.zeros(g)
+        dens = R.DensifyStats.zeros(w.gaussians.n)
+        res = R.train_step(g, w.cameras, luts, w.frames, tgt, grads, 8, OPTS, densify=dens, shared=shared)
+        torch.cuda.synchronize()
+        out[shared] = (res.loss, {k: getattr(grads, k).cpu().numpy() for k in ("d_means", "d_scalars")},
+                       dens.vis_count.cpu().numpy())
+    assert abs(out[2][0] - out[False][0]) <= 1e-5 * abs(out[False][0])
+    for k, v in out[2][1].items():
+        assert rel_err(v, out[False][1][k]) <= 1e-3, k
+    assert np.array_equal(out[2][2], out[False][2])
