@@ -318,7 +318,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": a.numel() * 4}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(frames would be split across GPUs with one gradient all-reduce; not built)", file=sys.stderr)
         sys.exit(2)
 

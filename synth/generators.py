@@ -30,7 +30,7 @@ __all__ = [
 ]
 
 # Renderer options used by every workload (alpha clamp, skip threshold, stop threshold
-# from the workload definitions; low-pass, near plane and guard band are this build's
+# from the workload definitions; low-pass, near plane and guard band are this library's
 # readings where the paper is silent).
 DEFAULT_OPTS = dict(alpha_clamp=0.99, alpha_min=1.0 / 255.0, t_min=1e-4, lowpass=0.3,
                     near_z=0.2, guard=1.3, bg=(0.0, 0.0, 0.0))
