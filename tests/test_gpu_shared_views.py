@@ -263,3 +263,15 @@ def test_train_step_sharing_in_runs_of_two_matches_own_lists():
     for k, v in out[2][1].items():
         assert rel_err(v, out[False][1][k]) <= 1e-3, k
     assert np.array_equal(out[2][2], out[False][2])
+
+
+def test_views_of_more_than_32_tables_keep_every_frame_from_slot_31():
+    """The keep bits hold 32 frames; from slot 31 on every frame reads bit 31, which a view of
+    more than 32 frames sets for every Gaussian, so those frames are never filtered by it."""
+    V, R = hip()
+    w = _case(n=800, views=1, K=34, res=48, tents=True)
+    g, luts, st = _render_shared(w)
+    for f in (0, 30, 31, 32, 33):
+        ci, ti = w.frames[f]
+        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], OPTS)
+        compare_image(image_pixels(st.image[f]), res)
