@@ -239,7 +239,12 @@ veg_status veg_project_views(const veg_gaussians* g, int32_t n_views, int32_t tf
  * veg_project_views, whose lists are the views' owners' pairs).  Entries are ordered by (tile, depth
  * key, Gaussian index).  ranges[2t], ranges[2t+1] = [start, end) of tile t (0,0 if empty).
  *   keys, vals          device [capacity] uint32 (final sorted list)
- *   keys_alt, vals_alt  device [capacity] uint32 (ping-pong buffers)
+ *   keys_alt, vals_alt  device [capacity] uint32 (ping-pong buffers of the sort; afterwards
+ *                       veg_render_fwd and veg_render_bwd overwrite keys_alt with the order
+ *                       in which they dispatch the (frame, tile) blocks, longest list
+ *                       first, when capacity >= n_frames * tiles_x * tiles_y + 128; with
+ *                       less they dispatch in natural order.  Results do not depend on it.
+ *                       Calls that share a veg_bins must therefore be ordered on one stream.)
  *   ranges              device [2 * total_tiles] uint32
  *   capacity            entries the buffers hold (<= 2^31 - 1)
  *   hits, hit_words     optional (NULL, 0): device [hit_words] uint64, hit_words >=

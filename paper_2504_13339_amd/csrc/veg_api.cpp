@@ -330,6 +330,11 @@ static veg_status check_hits(const veg_proj* proj, const veg_bins* bins, const c
   return VEG_OK;
 }
 
+// After the sort, keys_alt is free: the blend launches keep their dispatch order there.
+static uint64_t order_words(const veg_bins* bins) {
+  return bins->keys_alt && bins->capacity > 0 ? (uint64_t)bins->capacity : 0u;
+}
+
 veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts, float* image,
                           float* t_final, int32_t* n_last, int32_t* n_contrib, veg_stream_t stream) {
   g_err.clear();
@@ -345,7 +350,8 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
   VEG_CHECK_HIP(launch_blend_fwd((const FrameDesc*)proj->frames, proj->n_frames, per_view_of(proj),
                                  proj->tiles_x * proj->tiles_y, kopts(&o), (const float4*)proj->rec, bins->vals,
                                  bins->ranges, image, t_final, n_last, n_contrib, bins->hits,
-                                 hit_stride_of(proj, bins), proj->depth, (hipStream_t)stream),
+                                 hit_stride_of(proj, bins), proj->depth, bins->keys_alt, order_words(bins),
+                                 (hipStream_t)stream),
                 "veg_render_fwd");
   return VEG_OK;
 }
@@ -365,7 +371,7 @@ veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_
   VEG_CHECK_HIP(launch_blend_bwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
                                  kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, t_final, n_last,
                                  d_image, g2d, (uint32_t)pairs_of(proj), bins->hits, hit_stride_of(proj, bins),
-                                 (hipStream_t)stream),
+                                 bins->keys_alt, order_words(bins), (hipStream_t)stream),
                 "veg_render_bwd");
   return VEG_OK;
 }

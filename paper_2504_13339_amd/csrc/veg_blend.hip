@@ -95,13 +95,79 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
   return ((uint64_t)wave_or_u32((uint32_t)(v >> 32)) << 32) | wave_or_u32((uint32_t)v);
 }
 
+// ---------------------------------------------------------------------------------------
+// Dispatch order.  A block's cost grows with its tile's list length, and lengths span
+// several orders of magnitude (a dense centre tile holds thousands of entries, a border tile
+// a handful).  In natural order the heavy centre tiles of the last frames start late and
+// run nearly alone at the end of the launch.  Blocks are therefore dispatched longest list
+// first: a counting sort buckets the (frame, tile) blocks by floor(log2(list length)),
+// heaviest bucket first and empty tiles last (a histogram pass, then a scatter pass).  The
+// order within a bucket is arbitrary.  No result depends on it: a pixel is blended by one
+// block alone, and the backward pass's float atomics are unordered in any case.
+constexpr int kOrderBuckets = 33;        // clz(length) = 0..31, then empty tiles
+constexpr uint32_t kOrderHeader = 128;   // scratch words ahead of the order: counts, cursors
+
+__device__ __forceinline__ int order_bucket(const FrameDesc* __restrict__ descs, const uint2* __restrict__ ranges,
+                                            uint32_t g, uint32_t max_tiles) {
+  const FrameDesc& d = descs[g / max_tiles];
+  const int t = (int)(g % max_tiles);
+  if (t >= d.tiles_x * d.tiles_y) return kOrderBuckets - 1;
+  const uint2 rg = ranges[descs[d.list_frame].tile_base + t];
+  return rg.y > rg.x ? (int)__clz(rg.y - rg.x) : kOrderBuckets - 1;
+}
+
+// cnt[b] += blocks of bucket b (one LDS histogram per 256 blocks)
+__global__ __launch_bounds__(256) void order_count_kernel(const FrameDesc* __restrict__ descs,
+                                                          const uint2* __restrict__ ranges, uint32_t n,
+                                                          uint32_t max_tiles, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t h[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+  if (g < n) atomicAdd(&h[order_bucket(descs, ranges, g, max_tiles)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+}
+
+// order[start of bucket b + running slot] = g; a bucket's slots are claimed 256 blocks at a
+// time through the cursors cnt[kOrderBuckets + b]
+__global__ __launch_bounds__(256) void order_scatter_kernel(const FrameDesc* __restrict__ descs,
+                                                            const uint2* __restrict__ ranges, uint32_t n,
+                                                            uint32_t max_tiles, uint32_t* __restrict__ cnt,
+                                                            uint32_t* __restrict__ order) {
+  __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+  int b = 0;
+  uint32_t r = 0u;
+  if (g < n) {
+    b = order_bucket(descs, ranges, g, max_tiles);
+    r = atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets) {
+    uint32_t start = 0u;
+    for (int i = 0; i < (int)threadIdx.x; ++i) start += cnt[i];
+    base[threadIdx.x] = start + (h[threadIdx.x] ? atomicAdd(&cnt[kOrderBuckets + threadIdx.x], h[threadIdx.x]) : 0u);
+  }
+  __syncthreads();
+  if (g < n) order[base[b] + r] = g;
+}
+
+// The block's (frame, tile) id, frame * gridDim.x + tile, in dispatch order.
+__device__ __forceinline__ uint32_t block_id(const uint32_t* __restrict__ order) {
+  const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
+  return order ? order[lin] : lin;
+}
+
 // One wave per tile.  A pixel is finished exactly when its T < t_min (blend-then-stop),
 // so T itself is the "still active" flag; pixels outside the image start with T = 0.
 // With kHits, bit k of word b records whether entry rg.x + 64 b + k was blended into any
 // pixel of the tile (the backward pass skips the others).
 //
-// Block y renders frame y over the key list of frame list_frame (itself unless the frame
-// shares its view's list); the frame's record of an entry sits at the list's pair id plus
+// A block renders one tile of one frame (block_id) over the key list of frame list_frame
+// (itself unless the frame shares its view's list); the frame's record of an entry sits at the list's pair id plus
 // the difference of the two frames' pair bases.  With kShared the staged batch keeps only
 // the entries live for this frame (its own A > 0 and the tile inside its own rectangle,
 // from the record's insets), packed to the front of the batch, so the walk costs what the
@@ -113,10 +179,13 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
                                                        const uint2* __restrict__ ranges, float* __restrict__ image,
                                                        float* __restrict__ tfinal, int32_t* __restrict__ nlast,
                                                        int32_t* __restrict__ ncontrib, uint64_t* __restrict__ hits,
-                                                       uint64_t hit_stride, const uint32_t* __restrict__ keep_bits) {
-  const FrameDesc& d = descs[blockIdx.y];
+                                                       uint64_t hit_stride, const uint32_t* __restrict__ keep_bits,
+                                                       const uint32_t* __restrict__ order) {
+  const uint32_t gid = block_id(order);
+  const uint32_t frame = gid / gridDim.x;
+  const FrameDesc& d = descs[frame];
   const FrameDesc& dl = kShared ? descs[d.list_frame] : d;
-  const int tile = blockIdx.x;
+  const int tile = (int)(gid % gridDim.x);
   if (tile >= d.tiles_x * d.tiles_y) return;
   const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
   const uint2 rg = ranges[dl.tile_base + tile];
@@ -230,10 +299,10 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   }
   const size_t HW = (size_t)d.W * d.H;
   const bool own = d.out_image != nullptr;   // per-frame outputs (server batches)
-  float* img = own ? d.out_image : image + (size_t)blockIdx.y * 3 * HW;
-  float* tf = own ? d.out_tfinal : (tfinal ? tfinal + (size_t)blockIdx.y * HW : nullptr);
-  int32_t* nl = own ? d.out_nlast : (nlast ? nlast + (size_t)blockIdx.y * HW : nullptr);
-  int32_t* nc = own ? nullptr : (ncontrib ? ncontrib + (size_t)blockIdx.y * HW : nullptr);
+  float* img = own ? d.out_image : image + (size_t)frame * 3 * HW;
+  float* tf = own ? d.out_tfinal : (tfinal ? tfinal + (size_t)frame * HW : nullptr);
+  int32_t* nl = own ? d.out_nlast : (nlast ? nlast + (size_t)frame * HW : nullptr);
+  int32_t* nc = own ? nullptr : (ncontrib ? ncontrib + (size_t)frame * HW : nullptr);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int px = tx * kTile + qx + 8 * (r & 1), py = ty * kTile + qy + 8 * (r >> 1);
@@ -312,10 +381,12 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
                                                        const int32_t* __restrict__ nlast,
                                                        const float* __restrict__ dimage, float* __restrict__ g2d,
                                                        uint32_t n_pairs, const uint64_t* __restrict__ hits,
-                                                       uint64_t hit_stride) {
-  const FrameDesc& d = descs[blockIdx.y];
+                                                       uint64_t hit_stride, const uint32_t* __restrict__ order) {
+  const uint32_t gid = block_id(order);
+  const uint32_t frame = gid / gridDim.x;
+  const FrameDesc& d = descs[frame];
   const FrameDesc& dl = descs[d.list_frame];   // owner of the key list this frame blended
-  const int tile = blockIdx.x;
+  const int tile = (int)(gid % gridDim.x);
   if (tile >= d.tiles_x * d.tiles_y) return;
   const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
   const uint2 rg = ranges[dl.tile_base + tile];
@@ -328,9 +399,9 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   const float pxl0 = (float)qx + 0.5f, pxl1 = (float)(qx + 8) + 0.5f;
   const float pyl0 = (float)qy + 0.5f, pyl1 = (float)(qy + 8) + 0.5f;
   const size_t HW = (size_t)d.W * d.H;
-  const float* tfp = tfinal + (size_t)blockIdx.y * HW;
-  const int32_t* nlp = nlast + (size_t)blockIdx.y * HW;
-  const float* dip = dimage + (size_t)blockIdx.y * 3 * HW;
+  const float* tfp = tfinal + (size_t)frame * HW;
+  const int32_t* nlp = nlast + (size_t)frame * HW;
+  const float* dip = dimage + (size_t)frame * 3 * HW;
 
   __shared__ float4 s_geo[kBatch];   // mx, my, q0, q1
   __shared__ float4 s_q[kBatch];     // q2, l2A, R, G
@@ -518,51 +589,72 @@ namespace {
 template <bool kShared>
 void launch_fwd(dim3 grid, hipStream_t stream, const FrameDesc* descs, const KOpts& o, const float4* rec,
                 const uint32_t* vals, const uint2* rg, float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
-                uint64_t* hits, uint64_t hit_stride, const uint32_t* keep_bits) {
+                uint64_t* hits, uint64_t hit_stride, const uint32_t* keep_bits, const uint32_t* order) {
   const dim3 block(64);
   if (ncontrib && hits)
     hipLaunchKernelGGL((blend_fwd_kernel<true, true, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
-                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits);
+                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order);
   else if (ncontrib)
     hipLaunchKernelGGL((blend_fwd_kernel<true, false, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
-                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits);
+                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order);
   else if (hits)
     hipLaunchKernelGGL((blend_fwd_kernel<false, true, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
-                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits);
+                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order);
   else
     hipLaunchKernelGGL((blend_fwd_kernel<false, false, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg,
-                       image, tfinal, nlast, ncontrib, hits, hit_stride, keep_bits);
+                       image, tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order);
+}
+
+// Longest-list-first order of the n_frames x max_tiles blocks in ws[kOrderHeader ..], or
+// nullptr (natural order) when ws cannot hold it.
+const uint32_t* dispatch_order(const FrameDesc* descs, int n_frames, int max_tiles, const uint2* rg, uint32_t* ws,
+                               uint64_t ws_words, hipStream_t stream) {
+  const uint64_t n = (uint64_t)n_frames * (uint64_t)max_tiles;
+  if (!ws || n >= 0x80000000ull || ws_words < n + kOrderHeader) return nullptr;
+  if (launch_fill_u32(ws, 2 * kOrderBuckets, 0u, stream) != hipSuccess) return nullptr;
+  const dim3 grid((uint32_t)((n + 255) / 256));
+  hipLaunchKernelGGL(order_count_kernel, grid, dim3(256), 0, stream, descs, rg, (uint32_t)n, (uint32_t)max_tiles,
+                     ws);
+  hipLaunchKernelGGL(order_scatter_kernel, grid, dim3(256), 0, stream, descs, rg, (uint32_t)n,
+                     (uint32_t)max_tiles, ws, ws + kOrderHeader);
+  return ws + kOrderHeader;
 }
 
 }  // namespace
 
-hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& o,
+hipError_t launch_blend_fwd(
+const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges, float* image,
                             float* tfinal, int32_t* nlast, int32_t* ncontrib, uint64_t* hits, uint64_t hit_stride,
-                            const uint32_t* keep_bits, hipStream_t stream) {
+                            const uint32_t* keep_bits, uint32_t* order_ws, uint64_t order_ws_words,
+                            hipStream_t stream) {
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
   if (per_view < 1 || n_frames % per_view != 0) return hipErrorInvalidValue;
   const dim3 grid(max_tiles, n_frames);
   const uint2* rg = (const uint2*)ranges;
+  const uint32_t* order = dispatch_order(descs, n_frames, max_tiles, rg, order_ws, order_ws_words, stream);
   // The keep bits cost a third dependent load per entry; they pay off only when most of a
   // shared list is dead for each frame, i.e. with many tables per view (measured: 3 random
   // tables per view lose 6% of the forward pass with them, 10 narrow tent maps gain 15%).
   if (per_view > 1)
     launch_fwd<true>(grid, stream, descs, o, rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride,
-                     per_view >= kKeepBitsMinFrames ? keep_bits : nullptr);
+                     per_view >= kKeepBitsMinFrames ? keep_bits : nullptr, order);
   else
     launch_fwd<false>(grid, stream, descs, o, rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride,
-                      nullptr);
+                      nullptr, order);
   return hipGetLastError();
 }
 
 hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o, const float4* rec,
                             const uint32_t* vals, const uint32_t* ranges, const float* tfinal, const int32_t* nlast,
                             const float* dimage, float* g2d, uint32_t n_pairs, const uint64_t* hits,
-                            uint64_t hit_stride, hipStream_t stream) {
+                            uint64_t hit_stride, uint32_t* order_ws, uint64_t order_ws_words,
+                            hipStream_t stream) {
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(blend_bwd_kernel, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
-                     (const uint2*)ranges, tfinal, nlast, dimage, g2d, n_pairs, hits, hit_stride);
+  const uint2* rg = (const uint2*)ranges;
+  const uint32_t* order = dispatch_order(descs, n_frames, max_tiles, rg, order_ws, order_ws_words, stream);
+  hipLaunchKernelGGL(blend_bwd_kernel, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals, rg,
+                     tfinal, nlast, dimage, g2d, n_pairs, hits, hit_stride, order);
   return hipGetLastError();
 }
 

@@ -177,17 +177,18 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
 
 // Frames come in views of `per_view` consecutive frames that share the first one's key
 // list (per_view = 1: every frame owns its list).  Hit bits of the frame in slot k start at
-// word k * hit_stride.
+// word k * hit_stride.  order_ws (order_ws_words uint32, may be NULL) is scratch for the
+// blocks' dispatch order, used when it holds n_frames * max_tiles + 128 words.
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
                             uint64_t* hits, uint64_t hit_stride, const uint32_t* keep_bits,
-                            hipStream_t stream);
+                            uint32_t* order_ws, uint64_t order_ws_words, hipStream_t stream);
 hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             const float* tfinal, const int32_t* nlast, const float* dimage,
                             float* g2d, uint32_t n_pairs, const uint64_t* hits, uint64_t hit_stride,
-                            hipStream_t stream);
+                            uint32_t* order_ws, uint64_t order_ws_words, hipStream_t stream);
 
 hipError_t launch_l1(const float* image, const float* target, int64_t count, float scale,
                      double* loss, float* dimage, hipStream_t stream);

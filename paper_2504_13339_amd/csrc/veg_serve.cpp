@@ -221,7 +221,8 @@ hipError_t run_pipeline(veg_server* s, Slot& sl, const KOpts& ko) {
                       sl.keys, sl.vals, sl.keys_alt, sl.vals_alt, sl.ranges, (uint32_t)s->entries_cap, sl.stream);
   if (e != hipSuccess) return e;
   return launch_blend_fwd(sl.d_descs, c.max_batch, 1, s->max_tiles_frame, ko, sl.rec, sl.vals, sl.ranges, nullptr,
-                          nullptr, nullptr, nullptr, nullptr, 0, nullptr, sl.stream);
+                          nullptr, nullptr, nullptr, nullptr, 0, nullptr, sl.keys_alt, (uint64_t)s->entries_cap,
+                          sl.stream);
 }
 
 // Called with the lock held: writes the batch's descriptors and launches it.
