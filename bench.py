@@ -153,19 +153,24 @@ def opacity_guided_bench(steps, warmup=2):
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     out = {"workload": w.name, "frames": F, "tables_per_view": K, "width": w.width, "height": w.height}
     for shared in (True, 2, False):
-        def step():
-            return R.train_step(g, w.cameras, luts, w.frames, targets, grads, F, w.opts, loss_acc=loss, shared=shared)
+        def step(**kw):
+            return R.train_step(g, w.cameras, luts, w.frames, targets, grads, F, w.opts, loss_acc=loss, shared=shared,
+                                **kw)
+        cap = max(step().n_entries)   # lists sized ahead, as in the main timed loop
         for _ in range(warmup):
-            step()
+            step(capacity=cap)
+        stat = []
         gc.collect()
         gc.disable()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            step()
+            stat.append(step(capacity=cap, read_loss=False).status)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         gc.enable()
+        for st in stat:
+            R.check_status(st, cap)
         key = "shared" if shared is True else "pairs_shared" if shared else "own_lists"
         out[key + "_mpix_s"] = round(F * w.width * w.height * steps / dt / 1e6, 2)
         out[key + "_ms_per_step"] = round(dt * 1e3 / steps, 3)
@@ -360,23 +365,36 @@ def main():
         res = l1_step(g, grads)
         log(f"bench: warm-up step {k} loss {res.loss:.6f}")
 
-    # timed steps (Python's cycle collector paused: a collection mid-step stalls the host
-    # while the GPU waits for the next launch)
+    # Timed steps.  The key lists are sized from the last warm-up step (the model does not
+    # change between these steps, so neither do the lists), so a step needs no host
+    # synchronisation: each one's loss and key-list flags are copied aside on the device
+    # and read once after the loop, where an overflow would fail the run.  Step times are
+    # the intervals between events recorded at the step boundaries.  Python's cycle
+    # collector is paused (a collection stalls the host).
+    cap = max(res.n_entries)
     timer = R.EventTimer()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    step_loss = torch.empty(args.steps, dtype=torch.float64, device="cuda")
+    status = []
     gc.collect()
     gc.disable()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    step_ms = []
+    marks[0].record()
     for k in range(args.steps):
-        ts = time.perf_counter()
-        res = l1_step(g, grads, timer=timer)   # reading the loss ends the step on the host
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-        if k % 10 == 0 or k == args.steps - 1:
-            log(f"bench: step {k} loss {res.loss:.6f}")
+        res = l1_step(g, grads, timer=timer, capacity=cap, read_loss=False)
+        step_loss[k:k + 1].copy_(loss_acc)
+        status.append(res.status)
+        marks[k + 1].record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     gc.enable()
+    for st in status:
+        R.check_status(st, cap)
+    step_ms = [marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)]
+    for k, v in enumerate(step_loss.cpu().tolist()):
+        if k % 10 == 0 or k == args.steps - 1:
+            log(f"bench: step {k} loss {v:.6f}")
     ms_step = dt * 1e3 / args.steps
     value = F * H * W * args.steps / dt / 1e6
 
@@ -384,7 +402,10 @@ def main():
     per_step = {k: sum(v) / args.steps for k, v in times.items()}
     launches = {k: len(v) // args.steps for k, v in times.items()}
 
-    # forward-only throughput (project + bin + blend for all frames, no backward)
+    # forward-only throughput (project + bin + blend for all frames, no backward), lists
+    # sized as in the timed steps
+    n_groups = (F + group_frames - 1) // group_frames
+    fstat = torch.empty((args.steps, n_groups, 2), dtype=torch.int64, device="cuda")
     gc.collect()
     gc.disable()
     torch.cuda.synchronize()
@@ -393,11 +414,13 @@ def main():
         for f0 in range(0, F, group_frames):
             fr = w.frames[f0:f0 + group_frames]
             cams = [w.cameras[c] for c, _ in (fr[::K] if args.shared else fr)]
-            st = R.render(g, cams, [luts[t] for _, t in fr], w.opts, hits=False, shared=args.shared)
+            st = R.render(g, cams, [luts[t] for _, t in fr], w.opts, hits=False, shared=args.shared,
+                          capacity=cap, status=fstat[k, f0 // group_frames])
             del st
     torch.cuda.synchronize()
     fwd_mpix = F * H * W * args.steps / (time.perf_counter() - t1) / 1e6
     gc.enable()
+    R.check_status(fstat.view(-1, 2), cap)
 
     # the same training step with Blinn-Phong lighting attributes on every Gaussian
     lit_mpix = None
@@ -409,15 +432,18 @@ def main():
                          **{k: torch.as_tensor(getattr(sh, k)).cuda() for k in V.LIGHTING})
         grads_l = R.Grads.zeros(gl)
         l1_step(gl, grads_l)
+        lstat = []
         gc.collect()
         gc.disable()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         for k in range(args.lit_steps):
-            l1_step(gl, grads_l)
+            lstat.append(l1_step(gl, grads_l, capacity=cap, read_loss=False).status)
         torch.cuda.synchronize()
         lit_mpix = F * H * W * args.lit_steps / (time.perf_counter() - t2) / 1e6
         gc.enable()
+        for st in lstat:
+            R.check_status(st, cap)
         del grads_l, gl
 
     # a whole training iteration: the (1 - 0.2) L1 + 0.2 (1 - SSIM) loss, densification
@@ -431,26 +457,31 @@ def main():
             lrs.append((g.weights, 2.5e-2))
         opt = R.Adam(lrs)
 
+        # Adam moves the model, so the lists may grow a little: 10% headroom, checked after
+        fcap = int(cap * 1.1) + 4096
+
         def full_iter(timer=R.NO_TIMER):
             grads.zero_()
             r = R.train_step(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, ssim_lambda=0.2,
-                             shared=args.shared,
+                             shared=args.shared, capacity=fcap,
                              loss_acc=loss_acc, densify=dens, timer=timer, read_loss=False)
             with timer("adam"):
                 opt.step([grads.d_means, grads.d_log_scales, grads.d_quats, grads.d_scalars] +
                          ([grads.d_weights] if g.weights is not None else []))
             return r
-        full_iter()
-        torch.cuda.synchronize()
+        R.check_status(full_iter().status, fcap)
         ftimer = R.EventTimer()
+        fst = []
         gc.collect()
         gc.disable()
         t3 = time.perf_counter()
         for k in range(args.full_steps):
-            full_iter(ftimer)
+            fst.append(full_iter(ftimer).status)
         torch.cuda.synchronize()
         fdt = time.perf_counter() - t3
         gc.enable()
+        for st in fst:
+            R.check_status(st, fcap)
         ft = {k: round(sum(v) / args.full_steps, 3) for k, v in ftimer.totals_ms().items()
               if k in ("l1_loss", "ssim_loss", "densify_stats", "adam")}
         full = {"mpix_s": round(F * H * W * args.full_steps / fdt / 1e6, 2),

@@ -306,6 +306,16 @@ veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32
   return VEG_OK;
 }
 
+veg_status veg_bin_status(void* ws, size_t ws_bytes, int64_t* dst, veg_stream_t stream) {
+  g_err.clear();
+  if (!ws || ws_bytes < bin_ws_bytes(1)) return fail(VEG_ERR_INVALID_ARG, "bin workspace too small");
+  if (!dst || ((uintptr_t)dst & 7u)) return fail(VEG_ERR_INVALID_ARG, "bin_status: NULL or misaligned dst");
+  BinWs w;
+  carve_bin_ws(ws, 1, &w);
+  VEG_CHECK_HIP(launch_bin_status(w.counters, dst, (hipStream_t)stream), "veg_bin_status");
+  return VEG_OK;
+}
+
 int64_t veg_bin_hit_words(int64_t capacity, int64_t total_tiles) {
   if (capacity < 0 || total_tiles < 0) return 0;
   return capacity / 64 + total_tiles + 2;

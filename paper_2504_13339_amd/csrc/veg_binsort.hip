@@ -570,6 +570,12 @@ __global__ void finalize_kernel(uint32_t* counters, uint32_t capacity) {
   counters[4] = e > (uint64_t)capacity ? capacity : (uint32_t)e;   // entries actually written
 }
 
+// dst[0] = entries E, dst[1] = overflow flag (one thread; for a later, batched read).
+__global__ void status_kernel(const uint32_t* __restrict__ counters, int64_t* __restrict__ dst) {
+  dst[0] = (int64_t)((uint64_t)counters[1] | ((uint64_t)counters[2] << 32));
+  dst[1] = (int64_t)counters[3];
+}
+
 // Per-tile [start, end) from the boundaries of the sorted keys; each thread takes 4
 // consecutive keys (one vector load) and compares with its neighbours.
 __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __restrict__ keys,
@@ -749,6 +755,11 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
   if (capacity > 0)
     hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(capacity, kThreads * 4, 8192)), dim3(kThreads), 0, stream,
                        keys, ws.counters + 4, capacity, ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_status(const uint32_t* counters, int64_t* dst, hipStream_t stream) {
+  hipLaunchKernelGGL(status_kernel, dim3(1), dim3(1), 0, stream, counters, dst);
   return hipGetLastError();
 }
 

@@ -330,37 +330,42 @@ __device__ __forceinline__ float dpp_perm(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 
-// Two entries' nine per-lane partial sums (a, b) summed over each 16-lane row by a
-// reduce-scatter butterfly: at every step a lane keeps half of the values it carries and
-// adds its partner's copy of that half (partners: lane ^ 8 by row rotation, the mirror
-// inside each half-row, then ^ 2 and ^ 1 inside quads).  Afterwards, within each half-row
-// (the lower half carries entry a, the upper half entry b), the lane with i = lane & 7
-// holds component ((i & 4) ? 5 : 0) + ((i & 2) ? 3 : 0) + (i & 1) in w0 (not i = 7) and,
-// when i & 3 == 0, component (i & 4) ? 7 : 2 in w1.
-__device__ __forceinline__ void row_reduce_pair(const float (&a)[9], const float (&b)[9], int lane, float& w0,
-                                                float& w1) {
-  const bool l1 = (lane & 8) == 0, l2 = (lane & 4) == 0, l3 = (lane & 2) == 0, l4 = (lane & 1) == 0;
-  float r[9];
+// Two entries' nine per-lane partial sums (a, b) summed over the wave by a reduce-scatter
+// in which every step halves what a lane carries.  A swap of the wave's halves pairs a
+// with b (lanes 0-31 go on with a's sums, lanes 32-63 with b's), a swap of adjacent rows
+// pairs components (even rows go on with components 0, 2, 4, 6, odd rows with 1, 3, 5, 7,
+// both with 8), and a butterfly over each 16-lane row (partners lane ^ 8 by row rotation,
+// the mirror inside each half-row, then ^ 2 and ^ 1 inside quads) leaves every total in a
+// lane of its row: with j = lane & 15 and r = lane >> 4, lane j = 0, 8, 4, 12 holds
+// component 2 q + (r & 1) for q = 0, 1, 2, 3, and lane j = 2 of an even row component 8,
+// of entry a in rows 0-1 and of entry b in rows 2-3.  The swaps need no lane selects, so
+// a pair costs about 43 instructions instead of 59 for a butterfly over rows first.
+__device__ __forceinline__ float wave_reduce_pair(const float (&a)[9], const float (&b)[9], int lane) {
+  float p[9];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) r[c] = (l1 ? a[c] : b[c]) + dpp_perm<0x128>(l1 ? b[c] : a[c]);   // row_ror:8
-  float s[5];
+  for (int c = 0; c < 9; ++c) {
+    const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(a[c]), __float_as_uint(b[c]), false, false);
+    p[c] = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  }
+  float q[5];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) s[c] = (l2 ? r[c] : r[c + 5]) + dpp_perm<0x141>(l2 ? r[c + 5] : r[c]);   // half mirror
-  s[4] = r[4] + dpp_perm<0x141>(r[4]);
-  const float u0 = (l3 ? s[0] : s[3]) + dpp_perm<0x4e>(l3 ? s[3] : s[0]);   // quad_perm 2,3,0,1
-  const float u1 = (l3 ? s[1] : s[4]) + dpp_perm<0x4e>(l3 ? s[4] : s[1]);
-  const float u2 = s[2] + dpp_perm<0x4e>(s[2]);
-  w0 = (l4 ? u0 : u1) + dpp_perm<0xb1>(l4 ? u1 : u0);   // quad_perm 1,0,3,2
-  w1 = u2 + dpp_perm<0xb1>(u2);
-}
-
-// Sum of a value over the four 16-lane rows of the wave, in every lane: swap the halves of
-// the wave, then adjacent rows.
-__device__ __forceinline__ float sum_rows(float v) {
-  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  const float x = __uint_as_float(h[0]) + __uint_as_float(h[1]);
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  for (int c = 0; c < 4; ++c) {
+    const auto r =
+        __builtin_amdgcn_permlane16_swap(__float_as_uint(p[2 * c]), __float_as_uint(p[2 * c + 1]), false, false);
+    q[c] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(p[8]), __float_as_uint(p[8]), false, false);
+    q[4] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool l1 = (lane & 8) == 0, l2 = (lane & 4) == 0, l3 = (lane & 2) == 0;
+  const float r0 = (l1 ? q[0] : q[1]) + dpp_perm<0x128>(l1 ? q[1] : q[0]);   // row_ror:8
+  const float r1 = (l1 ? q[2] : q[3]) + dpp_perm<0x128>(l1 ? q[3] : q[2]);
+  const float r2 = q[4] + dpp_perm<0x128>(q[4]);
+  const float s0 = (l2 ? r0 : r1) + dpp_perm<0x141>(l2 ? r1 : r0);   // half mirror
+  const float s1 = r2 + dpp_perm<0x141>(r2);
+  const float u = (l3 ? s0 : s1) + dpp_perm<0x4e>(l3 ? s1 : s0);   // quad_perm 2,3,0,1
+  return u + dpp_perm<0xb1>(u);                                    // quad_perm 1,0,3,2
 }
 
 // Backward: the same tile walk in reverse.  Per pixel and blended entry it accumulates
@@ -368,11 +373,10 @@ __device__ __forceinline__ float sum_rows(float v) {
 // the conic is applied once per entry when the batch is flushed:
 //   dL/dconic = (1/2 S_xx, S_xy, 1/2 S_yy),  dL/dmu' = -(a S_x + b S_y, b S_x + c S_y),
 //   dL/dA = -S_d / A   with S_d = sum dsigma and dsigma = dL/dsigma = -dL/dalpha * a.
-// Entries are taken in pairs: a reduce-scatter butterfly over each 16-lane row sums both
-// entries' nine values at once, two lane swaps add up the four rows, and the first row
-// stores the entries' totals into a per-entry LDS slot (plain stores: an entry is reduced
-// once per tile); each 64-entry batch ends with nine vector atomics into the pair-major
-// gradient records.
+// Entries are taken in pairs: one reduce-scatter over the wave sums both entries' nine
+// values at once, and the lanes left holding the totals store them into a per-entry LDS
+// slot (plain stores: an entry is reduced once per tile); each 64-entry batch ends with
+// nine vector atomics into the pair-major gradient records.
 __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -433,12 +437,10 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   const float l2min = o.log2_alpha_min;
   const float aclamp = o.alpha_clamp;
   for (int c = 0; c < 9; ++c) s_acc[lane][c] = 0.0f;
-  // lanes' share of a pair's butterfly result: which component of which entry, if any
-  const int bi = lane & 7;
-  const int comp0 = ((bi & 4) ? 5 : 0) + ((bi & 2) ? 3 : 0) + (bi & 1);
-  const bool own0 = bi != 7;
-  const int comp1 = (bi & 4) ? 7 : 2;
-  const bool own1 = (bi & 3) == 0;
+  // lanes' share of a pair's reduction: which component of which entry, if any
+  const int rj = lane & 15;
+  const bool own = (rj & 3) == 0 || (rj == 2 && ((lane >> 4) & 1) == 0);
+  const int comp = rj == 2 ? 8 : 2 * ((rj >> 3) + 2 * ((rj >> 2) & 1)) + ((lane >> 4) & 1);
   for (int hi = jmax + 1; hi > (int)rg.x; hi -= kBatch) {
     const int lo = max((int)rg.x, hi - kBatch);
     const int nb = hi - lo;
@@ -540,17 +542,10 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       entry_adjoint(ka, acc_a, con_a);
       if (has_b) entry_adjoint(kb, acc_b, con_b);
       if (__ballot(con_a || con_b) == 0ull) continue;
-      float w0, w1;
-      row_reduce_pair(acc_a, acc_b, lane, w0, w1);
-      // sum the four rows' results; every processed entry is reduced exactly once per tile,
-      // so row 0 stores its totals (no atomics)
-      w0 = sum_rows(w0);
-      w1 = sum_rows(w1);
-      if (lane < (has_b ? 16 : 8)) {   // without a B entry the upper half carries zeros for A's slots
-        const int ke = (lane & 8) ? kb : ka;
-        if (own0) s_acc[ke][comp0] = w0;
-        if (own1) s_acc[ke][comp1] = w1;
-      }
+      // every processed entry is reduced exactly once per tile, so the owning lanes store
+      // its totals (no atomics); without a B entry lanes 32-63 carry zeros for A's slots
+      const float wsum = wave_reduce_pair(acc_a, acc_b, lane);
+      if (own && (lane < 32 || has_b)) s_acc[lane < 32 ? ka : kb][comp] = wsum;
     }
     __syncthreads();
     // flush.  Lane l first turns staged entry l's sums into screen-space gradients (in

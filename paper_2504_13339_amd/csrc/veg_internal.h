@@ -193,6 +193,7 @@ hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles,
 hipError_t launch_l1(const float* image, const float* target, int64_t count, float scale,
                      double* loss, float* dimage, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* dst, int64_t count, uint32_t value, hipStream_t stream);
+hipError_t launch_bin_status(const uint32_t* counters, int64_t* dst, hipStream_t stream);
 hipError_t launch_ssim(const float* image, const float* target, int64_t n_planes, int W, int H, float weight,
                        double* loss, float* d_image, float* dmaps, hipStream_t stream);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,

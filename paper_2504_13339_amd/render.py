@@ -69,7 +69,7 @@ class EventTimer:
 
 def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=None, stream=None,
            capacity: Optional[int] = None, timer=NO_TIMER, want_contrib: bool = False,
-           hits: bool = True, shared: bool = False) -> FwdState:
+           hits: bool = True, shared: bool = False, status: Optional[torch.Tensor] = None) -> FwdState:
     """Forward render of len(tfs) frames (one model, one image size).
 
     Frame f uses cams[f] and tfs[f]; with ``shared`` there are len(tfs) // len(cams) tables
@@ -77,8 +77,10 @@ def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=Non
     share one projection and key list.  With ``capacity`` None the key-list length is read
     back (one stream synchronisation) and the buffers are sized exactly; otherwise
     ``capacity`` entries are allocated, no synchronisation happens, and an overflow must be
-    checked with ``veg_bin_overflow``.  ``hits`` records which entries were blended
-    anywhere, for a following backward pass (set it False for forward-only rendering)."""
+    checked with ``veg_bin_overflow``, or later from ``status`` (device int64 [2], written
+    with the entry count and the overflow flag).  ``hits`` records which entries were
+    blended anywhere, for a following backward pass (set it False for forward-only
+    rendering)."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
     dev = g.means.device
     proj = V.alloc_proj(g.n, len(tfs), device=dev)
@@ -98,6 +100,8 @@ def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=Non
     bins = V.alloc_bins(proj, cap, device=dev, hits=hits)
     with timer("bin_sort"):
         V.veg_bin_sort(proj, ws, bins, stream=stream)
+    if status is not None:
+        V.veg_bin_status(ws, status, stream=stream)
     F, H, W = len(tfs), int(proj.struct.height), int(proj.struct.width)
     image = torch.empty((F, 3, H, W), dtype=torch.float32, device=dev)
     t_final = torch.empty((F, H, W), dtype=torch.float32, device=dev)
@@ -202,6 +206,21 @@ def render_autograd(means, log_scales, quats, scalars, weights, cams, tfs, opts=
 class StepResult:
     loss: float
     n_entries: List[int]
+    status: Optional[torch.Tensor] = None   # device [groups, 2] (entries, overflow) with a capacity
+
+
+class KeyListOverflow(RuntimeError):
+    """A key list needed more entries than the capacity given for it."""
+
+
+def check_status(status: torch.Tensor, capacity: int) -> List[int]:
+    """Entries per group from a training step's ``status`` (one synchronisation); raises
+    KeyListOverflow if a group's key list did not fit ``capacity``."""
+    st = status.cpu().tolist()
+    bad = [e for e, ov in st if ov]
+    if bad:
+        raise KeyListOverflow(f"key list of {max(bad)} entries exceeds the capacity {capacity}")
+    return [int(e) for e, _ in st]
 
 
 @dataclass
@@ -242,7 +261,7 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
                targets: torch.Tensor, grads: Grads, group: int, opts=None, ssim_lambda: float = 0.0, stream=None,
                loss_acc: Optional[torch.Tensor] = None, read_loss: bool = True, timer=NO_TIMER, on_group=None,
                want_contrib: bool = False, densify: Optional[DensifyStats] = None,
-               shared=False) -> StepResult:
+               shared=False, capacity: Optional[int] = None) -> StepResult:
     """One multi-view x multi-TF training step with the image loss
     (1 - lambda) mean|image - target| + lambda mean(1 - SSIM), means over all frames,
     channels and pixels.
@@ -259,7 +278,13 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
     frames must be a view-major product of cameras and tables), an integer ``shared=K``
     takes runs of K (e.g. neighbouring maps of a tent family, whose footprints overlap).  A
     group is then a whole number of runs (``group`` rounded down to a multiple of K, at
-    least one run)."""
+    least one run).
+
+    With ``capacity`` every group's key list gets that many entries and the step runs
+    without a host synchronisation until the loss is read (``read_loss``), when the entry
+    counts and overflow flags are read with it; a list that did not fit raises
+    KeyListOverflow (the gradients of that step are then incomplete).  With ``read_loss``
+    False the flags are in ``StepResult.status``, for ``check_status`` later."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
     if not 0.0 <= ssim_lambda <= 1.0:
         raise ValueError("ssim_lambda must lie in [0, 1]")
@@ -283,11 +308,15 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
     V.veg_fill_u32(loss_acc, 0, stream=stream)
     entries = []
     ssim_ws = None
+    status = None
+    if capacity is not None:
+        status = torch.empty(((F + group - 1) // group, 2), dtype=torch.int64, device=g.means.device)
     for f0 in range(0, F, group):
         fr = frames[f0:f0 + group]
         view_cams = [cams[c] for c, _ in fr[::K]] if shared else [cams[c] for c, _ in fr]
         st = render(g, view_cams, [tfs[t] for _, t in fr], o, stream=stream, timer=timer,
-                    want_contrib=want_contrib, shared=shared)
+                    want_contrib=want_contrib, shared=shared, capacity=capacity,
+                    status=status[f0 // group] if status is not None else None)
         entries.append(st.n_entries)
         d_image = torch.empty_like(st.image)
         tgt = targets[f0:f0 + len(fr)].contiguous()
@@ -305,7 +334,9 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
             on_group(f0, st)
         del st, d_image, g2d
     loss = float(loss_acc.item()) if read_loss else float("nan")
-    return StepResult(loss, entries)
+    if status is not None and read_loss:
+        entries = check_status(status, capacity)
+    return StepResult(loss, entries, status)
 
 
 def train_step_l1(*args, **kw) -> StepResult:

@@ -17,7 +17,7 @@ from ._lib import check, load
 
 __all__ = [
     "Gaussians", "Proj", "Bins", "default_opts", "make_opts", "veg_project", "veg_bin_count", "veg_bin_sort",
-    "veg_bin_overflow", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
+    "veg_bin_overflow", "veg_bin_status", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
     "veg_debug_math", "veg_bin_hit_words", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
     "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_adam_step", "veg_densify_stats", "veg_project_views",
     "veg_vq_decode", "decode_vq_model", "veg_densify_plan", "veg_densify_apply", "veg_densify_workspace_bytes",
@@ -229,6 +229,15 @@ def veg_bin_sort(proj: Proj, ws: torch.Tensor, bins: Bins, stream=None) -> Bins:
     check(load().veg_bin_sort(ctypes.byref(proj.struct), _ptr(ws), ws.numel(), ctypes.byref(bins.struct),
                               stream_handle(stream)), "veg_bin_sort")
     return bins
+
+
+def veg_bin_status(ws: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:
+    """dst (device int64 [2]) <- (entries E, overflow flag) of the last veg_bin_sort on ``ws``,
+    without synchronising."""
+    if dst.dtype != torch.int64 or dst.numel() < 2 or not dst.is_contiguous():
+        raise ValueError("dst must be a contiguous int64 tensor of at least 2 elements")
+    check(load().veg_bin_status(_ptr(ws), ws.numel(), _ptr(dst), stream_handle(stream)), "veg_bin_status")
+    return dst
 
 
 def veg_bin_overflow(ws: torch.Tensor, stream=None):
