@@ -164,7 +164,11 @@ __device__ __forceinline__ uint32_t block_id(const uint32_t* __restrict__ order)
 // One wave per tile.  A pixel is finished exactly when its T < t_min (blend-then-stop),
 // so T itself is the "still active" flag; pixels outside the image start with T = 0.
 // With kHits, bit k of word b records whether entry rg.x + 64 b + k was blended into any
-// pixel of the tile (the backward pass skips the others).
+// pixel of the tile (the backward pass skips the others).  A pixel's blended entries of a
+// batch are kept as a 64-bit mask (one OR per blend); the batch end derives from it both
+// the hit word (OR over the wave) and the pixel's last blended entry (highest bit).  The
+// alpha clamp is an integer minimum of the float bits (both operands are positive), which
+// needs no canonicalising of the clamp inside the loop.
 //
 // A block renders one tile of one frame (block_id) over the key list of frame list_frame
 // (itself unless the frame shares its view's list); the frame's record of an entry sits at the list's pair id plus
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
     cnt[r] = 0;
   }
   const float l2min = o.log2_alpha_min;
-  const float aclamp = o.alpha_clamp;
+  const uint32_t aclamp_bits = __float_as_uint(o.alpha_clamp);
   for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
     if (__all(T[0] < tmin && T[1] < tmin && T[2] < tmin && T[3] < tmin)) break;
     // stage the batch: only entries that can blend into some pixel of this tile (a quadrant
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
       s_k[slot] = (int)(lane | (qm << 8));
     }
     __syncthreads();
-    uint64_t lh = 0;   // bit k: this lane blended entry base + k
+    uint64_t lq[4] = {0ull, 0ull, 0ull, 0ull};   // bit k: pixel r of this lane blended entry base + k
     for (int k = 0; k < n; ++k) {
       const uint32_t kq = (uint32_t)__builtin_amdgcn_readfirstlane(s_k[k]);
       const int kk = (int)(kq & 0xffu);       // position in the batch
@@ -279,20 +283,22 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
         if (!(kq & (0x100u << r))) continue;   // quadrant out of the entry's reach (uniform)
         const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, c.x, (r >> 1) ? dy1 : dy0);
         if (T[r] >= tmin && e >= l2min) {
-          if (kHits) lh |= 1ull << kk;
-          const float alpha = fminf(__builtin_amdgcn_exp2f(e), aclamp);
+          lq[r] |= 1ull << kk;
+          const float alpha = __uint_as_float(min(__float_as_uint(__builtin_amdgcn_exp2f(e)), aclamp_bits));
           const float w = alpha * T[r];
           C[r][0] = fmaf(w, c.z, C[r][0]);
           C[r][1] = fmaf(w, c.w, C[r][1]);
           C[r][2] = fmaf(w, cb, C[r][2]);
           T[r] = fmaf(-alpha, T[r], T[r]);
-          last[r] = (int)base + kk;
           if (kCount) ++cnt[r];
         }
       }
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (lq[r]) last[r] = (int)base + 63 - __clzll(lq[r]);
     if (kHits) {
-      const uint64_t word = wave_or_u64(lh);
+      const uint64_t word = wave_or_u64(lq[0] | lq[1] | lq[2] | lq[3]);
       if (lane == 63) fhits[hit_word(rg.x, dl.tile_base + tile, (base - rg.x) >> 6)] = word;
     }
     __syncthreads();
