@@ -442,6 +442,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   if (jmax < (int)rg.x) return;
   const float l2min = o.log2_alpha_min;
   const float aclamp = o.alpha_clamp;
+  const uint32_t aclamp_bits = __float_as_uint(aclamp);
   for (int c = 0; c < 9; ++c) s_acc[lane][c] = 0.0f;
   // lanes' share of a pair's reduction: which component of which entry, if any
   const int rj = lane & 15;
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
           contrib = true;
           const float a = __builtin_amdgcn_exp2f(e);
           const bool clamped = !(a < aclamp);
-          const float alpha = clamped ? aclamp : a;
+          const float alpha = __uint_as_float(min(__float_as_uint(a), aclamp_bits));   // a, aclamp > 0
           const float Tk = T[r] * __builtin_amdgcn_rcpf(1.0f - alpha);
           const float w = alpha * Tk;
           float dalpha = 0.0f;
