@@ -371,38 +371,61 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __res
   float dmu[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ds[3] = {0, 0, 0};
   float dv = 0.0f, dw = 0.0f;
   float dn[3] = {0, 0, 0}, dka = 0.0f, dkd = 0.0f, dks = 0.0f, dbeta = 0.0f;
-  for (int f = 0; f < n_frames; ++f) {
+  for (int f = 0; f < n_frames;) {
+    // The frames of a view (veg_project_views) share one camera, so one projected geometry:
+    // the chain from the screen-space geometry (centre, conic) and from the shading's
+    // geometric terms back to the parameters is linear in their gradients, which are summed
+    // over the view's frames and taken through the chain once.  Opacity and colour go
+    // through each frame's own table.
     const FrameDesc& d = descs[f];
-    const size_t pid = (size_t)d.pair_base + (size_t)i;
-    float gg[9];
+    const int K = d.n_share > 1 ? d.n_share : 1;
+    float dmx = 0.0f, dmy = 0.0f, dc0 = 0.0f, dc1 = 0.0f, dc2 = 0.0f;
+    float P = 0.0f, Dsum = 0.0f;   // shading: sum over frames of dC . C(v) and of sum_c dC
     bool any = false;
-    for (int c = 0; c < 9; ++c) {
-      gg[c] = g2d[pid * 9 + c];
-      any |= (gg[c] != 0.0f);
+    Lit L;
+    for (int k = 0; k < K; ++k) {
+      const FrameDesc& dk = descs[f + k];
+      const size_t pid = (size_t)dk.pair_base + (size_t)i;
+      float gg[9];
+      bool anyk = false;
+      for (int c = 0; c < 9; ++c) {
+        gg[c] = g2d[pid * 9 + c];
+        anyk |= (gg[c] != 0.0f);
+      }
+      if (!anyk) continue;
+      TfSample tf;
+      tf_lookup(dk, g.v, tf);
+      // lighting: rgb = C (k_a + k_d s) + k_s s^beta, s = |n^ . l|, l = (mu - campos) / |.|
+      float dC[3] = {gg[5], gg[6], gg[7]};
+      if (g.lit) {
+        if (!any) {
+          float rgb[3];
+          shade(d, g, tf.rgb, rgb, L);   // L depends on the view's camera and the Gaussian only
+        }
+        P += (gg[5] * tf.rgb[0] + gg[6] * tf.rgb[1]) + gg[7] * tf.rgb[2];
+        Dsum += (gg[5] + gg[6]) + gg[7];
+        for (int c = 0; c < 3; ++c) dC[c] = gg[5 + c] * L.f;
+      }
+      any = true;
+      dmx += gg[0];
+      dmy += gg[1];
+      dc0 += gg[2];
+      dc1 += gg[3];
+      dc2 += gg[4];
+      // transfer function: A = O w, C = C(v)
+      dv += (gg[8] * g.w) * tf.slope[3] + dC[0] * tf.slope[0] + dC[1] * tf.slope[1] + dC[2] * tf.slope[2];
+      dw += gg[8] * tf.O;
     }
+    f += K;
     if (!any) continue;
-    Proj p;
-    project_one(d, o, g, p);
-    TfSample tf;
-    tf_lookup(d, g.v, tf);
-    const float dmx = gg[0], dmy = gg[1], dc0 = gg[2], dc1 = gg[3], dc2 = gg[4];
-    const float dA = gg[8];
-    // lighting: rgb = C (k_a + k_d s) + k_s s^beta, s = |n^ . l|, l = (mu - campos) / |.|
-    float dC[3] = {gg[5], gg[6], gg[7]};
     if (g.lit) {
-      float rgb[3];
-      Lit L;
-      shade(d, g, tf.rgb, rgb, L);
-      const float P = (gg[5] * tf.rgb[0] + gg[6] * tf.rgb[1]) + gg[7] * tf.rgb[2];
-      const float D = (gg[5] + gg[6]) + gg[7];
-      for (int c = 0; c < 3; ++c) dC[c] = gg[5 + c] * L.f;
       dka += P;
       dkd += P * L.s;
       float dsv = g.kd * P;
       if (L.sb > 0.0f) {
-        dks += D * L.sb;
-        dbeta += D * g.ks * L.sb * log32(L.s);
-        dsv += D * g.ks * g.beta * L.sb / L.s;
+        dks += Dsum * L.sb;
+        dbeta += Dsum * g.ks * L.sb * log32(L.s);
+        dsv += Dsum * g.ks * g.beta * L.sb / L.s;
       }
       const float du = L.u > 0.0f ? dsv : (L.u < 0.0f ? -dsv : 0.0f);
       float dnh[3], dl[3];
@@ -417,9 +440,8 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __res
         dmu[k] += (dl[k] - L.l[k] * dotl) * L.dinv;
       }
     }
-    // transfer function: A = O w, C = C(v)
-    dv += (dA * g.w) * tf.slope[3] + dC[0] * tf.slope[0] + dC[1] * tf.slope[1] + dC[2] * tf.slope[2];
-    dw += dA * tf.O;
+    Proj p;
+    project_one(d, o, g, p);
     // projected centre
     const float tz = p.depth;
     const float invz = 1.0f / tz;
