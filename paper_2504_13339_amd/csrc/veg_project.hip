@@ -256,13 +256,37 @@ __global__ __launch_bounds__(256) void blob_kernel(uint32_t* dst, const uint32_t
   for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = blob.w[i];
 }
 
+// A wave's 64 consecutive records (lane l's at rec + 3 l) written as 192 contiguous
+// float4, lane l storing pieces l, 64 + l and 128 + l, so each store instruction covers
+// 1 KB without holes; only pieces of lanes set in `keep` are written.  The pieces pass
+// through the wave's own LDS slice (LDS operations of one wave complete in order).
+__device__ __forceinline__ void store_wave_records(float4* __restrict__ rec, uint64_t keep, const float4& a,
+                                                   const float4& b, const float4& c, float4* __restrict__ s) {
+  const int ln = threadIdx.x & 63;
+  s[3 * ln] = a;
+  s[3 * ln + 1] = b;
+  s[3 * ln + 2] = c;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int e = 64 * j + ln;
+    if ((keep >> (e / 3)) & 1ull) rec[e] = s[e];
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // One thread per Gaussian; blockIdx.y selects a chunk of `fpb` frames processed in a loop,
-// so a model shared by the frames is read from HBM once per chunk.
+// so a model shared by the frames is read from HBM once per chunk.  The loops over frames
+// and over a view's tables are uniform across the block, so every wave takes part in each
+// record store.
 __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restrict__ descs, int n_frames,
                                                       int fpb, KOpts o, float4* __restrict__ rec,
                                                       uint32_t* __restrict__ count,
                                                       uint32_t* __restrict__ depth) {
+  __shared__ float4 s_rec[4][3 * 64];   // one slice per wave of the 256-thread block
   const int i = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t i0 = (uint32_t)(i - (int)(threadIdx.x & 63));   // the wave's first Gaussian
+  float4* sw = s_rec[threadIdx.x >> 6];
   const int f0 = blockIdx.y * fpb;
   const int f1 = min(n_frames, f0 + fpb);
   GParams g;
@@ -272,49 +296,57 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
   const float* cur_n = nullptr;
   for (int f = f0; f < f1; ++f) {
     const FrameDesc& d = descs[f];
-    if (i >= d.n || d.n_share == 0) continue;   // a frame sharing another's list is projected with it
-    if (d.means != cur || d.scalars != cur_v || d.weights != cur_w || d.normals != cur_n) {
-      load_params(d, i, g);
-      cur = d.means;
-      cur_v = d.scalars;
-      cur_w = d.weights;
-      cur_n = d.normals;
-    }
-    const uint32_t pid = d.pair_base + (uint32_t)i;
+    if (d.n_share == 0) continue;   // a frame sharing another's list is projected with it
     const int n_share = d.n_share;
-    bool keep = g.finite && g.n2 >= 1e-24f && g.nn2 >= 1e-24f;
-    TfSample tf;
-    tf_lookup(d, keep ? g.v : 0.0f, tf);
-    // Frames sharing this list: the footprint at the largest A over their tables contains
-    // each frame's own, so it decides the list; only the owner's pair is counted.
-    float A = tf.O * g.w;
-    for (int k = 1; k < n_share; ++k) {
-      const FrameDesc& dk = descs[f + k];
-      count[dk.pair_base + (uint32_t)i] = 0u;
-      TfSample tk;
-      tf_lookup(dk, keep ? g.v : 0.0f, tk);
-      A = fmaxf(A, tk.O * g.w);
-    }
-    keep = keep && (A >= o.alpha_min);
+    const bool act = i < d.n;
+    bool kept = false;
     Proj p;
-    project_one(d, o, g, p);
-    keep = keep && (p.depth > o.near_z) && (p.det > 0.0f);
-    if (!keep) {
-      count[pid] = 0u;
-      continue;
+    TfSample tf;
+    uint32_t x0 = 0u, x1 = 0u, y0 = 0u, y1 = 0u;
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, mxr = 0.0f, myr = 0.0f;
+    if (act) {
+      if (d.means != cur || d.scalars != cur_v || d.weights != cur_w || d.normals != cur_n) {
+        load_params(d, i, g);
+        cur = d.means;
+        cur_v = d.scalars;
+        cur_w = d.weights;
+        cur_n = d.normals;
+      }
+      const uint32_t pid = d.pair_base + (uint32_t)i;
+      bool keep = g.finite && g.n2 >= 1e-24f && g.nn2 >= 1e-24f;
+      tf_lookup(d, keep ? g.v : 0.0f, tf);
+      // Frames sharing this list: the footprint at the largest A over their tables contains
+      // each frame's own, so it decides the list; only the owner's pair is counted.
+      float A = tf.O * g.w;
+      for (int k = 1; k < n_share; ++k) {
+        const FrameDesc& dk = descs[f + k];
+        count[dk.pair_base + (uint32_t)i] = 0u;
+        TfSample tk;
+        tf_lookup(dk, keep ? g.v : 0.0f, tk);
+        A = fmaxf(A, tk.O * g.w);
+      }
+      keep = keep && (A >= o.alpha_min);
+      project_one(d, o, g, p);
+      keep = keep && (p.depth > o.near_z) && (p.det > 0.0f);
+      double xlo, xhi, ylo, yhi;
+      kept = keep && pixel_range(p, A, o, d.W, d.H, xlo, xhi, ylo, yhi);
+      if (kept) {
+        x0 = (uint32_t)xlo / kTile;
+        x1 = (uint32_t)xhi / kTile;
+        y0 = (uint32_t)ylo / kTile;
+        y1 = (uint32_t)yhi / kTile;
+        count[pid] = (x1 - x0 + 1) * (y1 - y0 + 1);
+        depth[pid] = __float_as_uint(p.depth);
+        c0 = p.S11 / p.det;
+        c1 = -p.S01 / p.det;
+        c2 = p.S00 / p.det;
+        mxr = (float)(p.mx - 16.0 * (double)x0);
+        myr = (float)(p.my - 16.0 * (double)y0);
+      } else {
+        count[pid] = 0u;
+      }
     }
-    double xlo, xhi, ylo, yhi;
-    if (!pixel_range(p, A, o, d.W, d.H, xlo, xhi, ylo, yhi)) {
-      count[pid] = 0u;
-      continue;
-    }
-    const uint32_t x0 = (uint32_t)xlo / kTile, x1 = (uint32_t)xhi / kTile;
-    const uint32_t y0 = (uint32_t)ylo / kTile, y1 = (uint32_t)yhi / kTile;
-    count[pid] = (x1 - x0 + 1) * (y1 - y0 + 1);
-    depth[pid] = __float_as_uint(p.depth);
-    const float c0 = p.S11 / p.det, c1 = -p.S01 / p.det, c2 = p.S00 / p.det;
-    const float mxr = (float)(p.mx - 16.0 * (double)x0);
-    const float myr = (float)(p.my - 16.0 * (double)y0);
+    const uint64_t wkeep = __ballot(kept);
     uint32_t keep_bits = 0u;   // frames of the view that keep the Gaussian (bit k: slot k)
     // one record per frame: the shared geometry with the frame's own A and colour.  A = 0
     // where the frame's own footprint culls the Gaussian (A below alpha_min, or an ellipse
@@ -322,39 +354,42 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
     // on its own list and its blend skips the rest.
     for (int k = 0; k < n_share; ++k) {
       const FrameDesc& dk = descs[f + k];
-      TfSample tk = tf;
-      if (k > 0) tf_lookup(dk, g.v, tk);
-      float Ak = tk.O * g.w;
-      if (!(Ak >= o.alpha_min)) Ak = 0.0f;
-      uint32_t inset = 0u;   // own tile rectangle inside the shared one
-      if (n_share > 1 && Ak > 0.0f) {
-        double a0, a1, b0, b1;
-        if (!pixel_range(p, Ak, o, d.W, d.H, a0, a1, b0, b1)) {
-          Ak = 0.0f;
-        } else {
-          const uint32_t ox0 = (uint32_t)a0 / kTile, ox1 = (uint32_t)a1 / kTile;
-          const uint32_t oy0 = (uint32_t)b0 / kTile, oy1 = (uint32_t)b1 / kTile;
-          // each inset clamped to [0, 31]: never claims more than the shared rectangle excludes
-          const uint32_t ix0 = ox0 > x0 ? min(ox0 - x0, 31u) : 0u, iy0 = oy0 > y0 ? min(oy0 - y0, 31u) : 0u;
-          const uint32_t ix1 = x1 > ox1 ? min(x1 - ox1, 31u) : 0u, iy1 = y1 > oy1 ? min(y1 - oy1, 31u) : 0u;
-          inset = ix0 | (iy0 << 5) | (ix1 << 10) | (iy1 << 15);
+      float4 r0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), r1 = r0, r2 = r0;
+      if (kept) {
+        TfSample tk = tf;
+        if (k > 0) tf_lookup(dk, g.v, tk);
+        float Ak = tk.O * g.w;
+        if (!(Ak >= o.alpha_min)) Ak = 0.0f;
+        uint32_t inset = 0u;   // own tile rectangle inside the shared one
+        if (n_share > 1 && Ak > 0.0f) {
+          double a0, a1, b0, b1;
+          if (!pixel_range(p, Ak, o, d.W, d.H, a0, a1, b0, b1)) {
+            Ak = 0.0f;
+          } else {
+            const uint32_t ox0 = (uint32_t)a0 / kTile, ox1 = (uint32_t)a1 / kTile;
+            const uint32_t oy0 = (uint32_t)b0 / kTile, oy1 = (uint32_t)b1 / kTile;
+            // each inset clamped to [0, 31]: never claims more than the shared rectangle excludes
+            const uint32_t ix0 = ox0 > x0 ? min(ox0 - x0, 31u) : 0u, iy0 = oy0 > y0 ? min(oy0 - y0, 31u) : 0u;
+            const uint32_t ix1 = x1 > ox1 ? min(x1 - ox1, 31u) : 0u, iy1 = y1 > oy1 ? min(y1 - oy1, 31u) : 0u;
+            inset = ix0 | (iy0 << 5) | (ix1 << 10) | (iy1 << 15);
+          }
         }
-      }
-      float rgb[3] = {tk.rgb[0], tk.rgb[1], tk.rgb[2]};
-      if (g.lit) {
-        Lit L;
-        shade(dk, g, tk.rgb, rgb, L);
-      }
-      if (Ak > 0.0f || k >= 32) keep_bits |= 1u << min(k, 31);
-      float4* r = rec + 3 * (size_t)(dk.pair_base + (uint32_t)i);
-      r[0] = make_float4(mxr, myr, c0, c1);
-      r[1] = make_float4(c2, Ak, rgb[0], rgb[1]);
-      r[2] = make_float4(rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
+        float rgb[3] = {tk.rgb[0], tk.rgb[1], tk.rgb[2]};
+        if (g.lit) {
+          Lit L;
+          shade(dk, g, tk.rgb, rgb, L);
+        }
+        if (Ak > 0.0f || k >= 32) keep_bits |= 1u << min(k, 31);
+        r0 = make_float4(mxr, myr, c0, c1);
+        r1 = make_float4(c2, Ak, rgb[0], rgb[1]);
+        r2 = make_float4(rgb[2], __uint_as_float(x0 | (y0 << 16)), __uint_as_float(x1 | (y1 << 16)),
                          __uint_as_float((uint32_t)(f + k) | (inset << kFrameBits)));
+      }
+      if (wkeep) store_wave_records(rec + 3 * (size_t)(dk.pair_base + i0), wkeep, r0, r1, r2, sw);
     }
     // a shared list's frames skip entries by these bits before loading their records; the
     // depth slots of the frames after the owner are otherwise unused (never counted)
-    if (n_share > 1) depth[descs[f + 1].pair_base + (uint32_t)i] = keep_bits;
+    if (kept && n_share > 1) depth[descs[f + 1].pair_base + (uint32_t)i] = keep_bits;
   }
 }
 
