@@ -390,15 +390,24 @@ def test_backward_matches_finite_differences_tiny():
 
 # ----------------------------------------------------------------------------- loss
 
-def test_l1_loss_kernel():
+@pytest.mark.parametrize("n,offset", [(100003, 0), (100004, 0), (100004, 1)])
+def test_l1_loss_kernel(n, offset):
+    """Sizes and alignments that take the scalar path (odd size; views one element past an
+    aligned start) and the 16-byte path (size a multiple of 4, aligned)."""
     V, R = hip()
     rng = np.random.default_rng(24)
-    a = rng.uniform(0, 1, 100003).astype(np.float32)
+    a = rng.uniform(0, 1, n).astype(np.float32)
     b = a.copy()
     b[::3] += rng.uniform(-0.5, 0.5, b[::3].shape).astype(np.float32)
+    b[5::7] = a[5::7]   # some exact zeros of the difference
     loss = torch.zeros(1, dtype=torch.float64).cuda()
-    d = torch.empty(a.shape[0], dtype=torch.float32).cuda()
-    V.veg_l1_loss(torch.as_tensor(a).cuda(), torch.as_tensor(b).cuda(), 1.0 / a.size, loss, d)
+    da = torch.zeros(n + offset, dtype=torch.float32).cuda()
+    db = torch.zeros(n + offset, dtype=torch.float32).cuda()
+    dd = torch.zeros(n + offset, dtype=torch.float32).cuda()
+    da[offset:] = torch.as_tensor(a).cuda()
+    db[offset:] = torch.as_tensor(b).cuda()
+    d = dd[offset:]
+    V.veg_l1_loss(da[offset:], db[offset:], 1.0 / a.size, loss, d)
     ref = np.abs(a.astype(np.float64) - b).mean()
     assert abs(loss.item() - ref) <= 1e-6 * ref
     s = np.sign(a - b).astype(np.float32) * np.float32(1.0 / a.size)
