@@ -54,6 +54,24 @@ def test_host_side_argument_errors_without_gpu():
     assert lib.veg_status_str(6) == b"HIP error"
 
 
+def test_bin_status_arguments_are_checked_on_host():
+    """veg_bin_status rejects a missing or small workspace and a NULL or misaligned
+    destination before any device call (host pointers stand in for device ones)."""
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    nb = int(lib.veg_bin_workspace_bytes(1, 0))
+    ws = (ctypes.c_uint8 * nb)()
+    dst = (ctypes.c_int64 * 4)()
+    base = ctypes.addressof(dst)
+    assert lib.veg_bin_status(None, nb, base, None) == 1
+    assert lib.veg_bin_status(ctypes.addressof(ws), 8, base, None) == 1
+    assert b"workspace" in lib.veg_last_error()
+    assert lib.veg_bin_status(ctypes.addressof(ws), nb, None, None) == 1
+    assert lib.veg_bin_status(ctypes.addressof(ws), nb, base + 4, None) == 1
+    assert b"misaligned" in lib.veg_last_error()
+
+
 def test_serve_config_validation_on_host():
     import ctypes
     from paper_2504_13339_amd import _lib
