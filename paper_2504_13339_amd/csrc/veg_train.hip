@@ -124,9 +124,12 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
       const float D = B1 * B2;
       const float S = (A1 * A2) / D;
       part += (double)(1.0f - S);
-      const float dmu = (2.0f * my * (A2 - A1) - 2.0f * mx * S * (B2 - B1)) / D;
-      const float dex2 = -S * B1 / D;
-      const float dexy = 2.0f * A1 / D;
+      // one reciprocal for the three maps (S keeps its division: identical images give
+      // S = 1 exactly, and then dex2 = -(B1 rD) and dexy = 2 (B1 rD) cancel in the adjoint)
+      const float rD = 1.0f / D;
+      const float dmu = (2.0f * my * (A2 - A1) - 2.0f * mx * S * (B2 - B1)) * rD;
+      const float dex2 = -S * B1 * rD;
+      const float dexy = 2.0f * A1 * rD;
       const size_t pi = plane * HW + (size_t)gy * W + gx;
       dmaps[pi] = -weight * dmu;
       dmaps[plane_stride + pi] = -weight * dex2;
