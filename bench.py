@@ -257,7 +257,7 @@ def serve_bench(rates, n_per_rate, max_batch=8, n_streams=3, use_graphs=True):
             target = t0 + r.arrival_s
             while time.perf_counter() < target:
                 pass
-            st = R.render(models[r.model], [r.camera], [luts[i]], opts)
+            st = R.render(models[r.model], [r.camera], [luts[i]], opts, hits=False)   # forward only
             torch.cuda.synchronize()
             lat.append((time.perf_counter() - target) * 1e3)
             del st
