@@ -457,8 +457,8 @@ def main():
             lrs.append((g.weights, 2.5e-2))
         opt = R.Adam(lrs)
 
-        # Adam moves the model, so the lists may grow a little: 10% headroom, checked after
-        fcap = int(cap * 1.1) + 4096
+        # Adam moves the model, so the lists may grow a little: 50% headroom, checked after
+        fcap = int(cap * 1.5) + 4096
 
         def full_iter(timer=R.NO_TIMER):
             grads.zero_()
