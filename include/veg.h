@@ -298,7 +298,8 @@ veg_status veg_bin_sort(const veg_proj* proj, void* ws, size_t ws_bytes, const v
 veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32_t* overflow,
                             veg_stream_t stream);
 
-/* veg_bin_status -- the same two values without synchronisation: writes dst[0] = E and
+/* veg_bin_status -- the same two values of the tile key list (the binning of section
+ * "Rendering of VEGs") without synchronisation: writes dst[0] = E and
  * dst[1] = overflow flag (0 or 1) as int64, ordered on `stream` after the veg_bin_sort that
  * used `ws`.  Lets a caller that sizes the key list ahead (e.g. from an earlier step) keep
  * the GPU busy and check the flags of many calls in one later read.
