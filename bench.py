@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "train-1M-1024px-16x3_hbm_traffic.md")
 BLEND_SOURCES = ("paper_2504_13339_amd/csrc/veg_blend.hip", "paper_2504_13339_amd/csrc/veg_internal.h")
-PROFILE_KERNEL = {"blend_bwd": "blend_bwd_kernel", "blend_fwd": "void blend_fwd_kernel<false, true, {shared}>"}
+PROFILE_KERNEL = {"blend_bwd": "void blend_bwd_kernel<true>", "blend_fwd": "void blend_fwd_kernel<false, true, {shared}>"}
 
 
 def profiled_traffic(name, shared=True):

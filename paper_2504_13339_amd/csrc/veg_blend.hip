@@ -383,6 +383,7 @@ __device__ __forceinline__ float wave_reduce_pair(const float (&a)[9], const flo
 // values at once, and the lanes left holding the totals store them into a per-entry LDS
 // slot (plain stores: an entry is reduced once per tile); each 64-entry batch ends with
 // nine vector atomics into the pair-major gradient records.
+template <bool kHits>
 __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restrict__ descs, KOpts o,
                                                        const float4* __restrict__ rec,
                                                        const uint32_t* __restrict__ vals,
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   if (rg.y <= rg.x) return;
   const uint32_t roff = d.pair_base - dl.pair_base;   // list pair id -> this frame's pair id
   const bool shared = dl.n_share > 1;
-  const uint64_t* fhits = hits ? hits + (uint64_t)d.slot * hit_stride : nullptr;
+  const uint64_t* fhits = kHits ? hits + (uint64_t)d.slot * hit_stride : nullptr;
   const int lane = threadIdx.x;
   const int qx = lane & 7, qy = lane >> 3;
   const float pxl0 = (float)qx + 0.5f, pxl1 = (float)(qx + 8) + 0.5f;
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
     // that are live for this frame.  Only they are staged, packed to the front of the batch
     // in list order; s_pos keeps each one's position in the batch.
     uint64_t todo = ~0ull >> (64 - nb);
-    if (fhits) {
+    if (kHits) {
       const uint32_t off = (uint32_t)lo - rg.x;
       const size_t w0 = hit_word(rg.x, dl.tile_base + tile, off >> 6);
       const uint32_t sh = off & 63u;
@@ -473,7 +474,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       r0 = rp[0];
       r1 = rp[1];
       r2 = rp[2];
-      if (shared && !fhits) {   // the forward pass's live test for a frame on a shared list
+      if (!kHits && shared) {   // the forward pass's live test for a frame on a shared list
         const uint32_t in = __float_as_uint(r2.w) >> kFrameBits;
         const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
         const int x0 = (int)((a & 0xffffu) + (in & 31u)), y0 = (int)((a >> 16) + ((in >> 5) & 31u));
@@ -511,7 +512,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
         const float dx = (r & 1) ? dx1 : dx0, dy = (r >> 1) ? dy1 : dy0;
         const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, q.x, dy);
         if (jj <= last[r] && e >= l2min) {
-          contrib = true;
+          if (!kHits) contrib = true;
           const float a = __builtin_amdgcn_exp2f(e);
           const bool clamped = !(a < aclamp);
           const float alpha = __uint_as_float(min(__float_as_uint(a), aclamp_bits));   // a, aclamp > 0
@@ -548,7 +549,9 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
       bool con_a = false, con_b = false;
       entry_adjoint(ka, acc_a, con_a);
       if (has_b) entry_adjoint(kb, acc_b, con_b);
-      if (__ballot(con_a || con_b) == 0ull) continue;
+      // an entry with a hit bit is blended in some pixel of the tile (the backward's test is
+      // the forward's), so only without hit bits can a pair contribute nothing
+      if (!kHits && __ballot(con_a || con_b) == 0ull) continue;
       // every processed entry is reduced exactly once per tile, so the owning lanes store
       // its totals (no atomics); without a B entry lanes 32-63 carry zeros for A's slots
       const float wsum = wave_reduce_pair(acc_a, acc_b, lane);
@@ -655,8 +658,12 @@ hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles,
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
   const uint2* rg = (const uint2*)ranges;
   const uint32_t* order = dispatch_order(descs, n_frames, max_tiles, rg, order_ws, order_ws_words, stream);
-  hipLaunchKernelGGL(blend_bwd_kernel, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals, rg,
-                     tfinal, nlast, dimage, g2d, n_pairs, hits, hit_stride, order);
+  if (hits)
+    hipLaunchKernelGGL(blend_bwd_kernel<true>, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
+                       rg, tfinal, nlast, dimage, g2d, n_pairs, hits, hit_stride, order);
+  else
+    hipLaunchKernelGGL(blend_bwd_kernel<false>, dim3(max_tiles, n_frames), dim3(64), 0, stream, descs, o, rec, vals,
+                       rg, tfinal, nlast, dimage, g2d, n_pairs, hits, hit_stride, order);
   return hipGetLastError();
 }
 
