@@ -38,7 +38,8 @@ Three parts:
   functions over one view, as in opacity-guided training): the footprint at the largest
   opacity over the frames' tables, which contains each frame's own footprint.  The images
   and gradients of such frames are still O2 / O3 per frame.
-* The training-loop neighbours of section "Training": ``ssim_map`` / ``ssim_loss`` (the
+* The training-loop neighbours of section "Training": ``l1_loss`` (the L1 term and its
+  gradient), ``ssim_map`` / ``ssim_loss`` (the
   SSIM term of the image loss, Gaussian 11-tap window, float64, gradient by autograd),
   ``adam_step`` (the optimizer update) and ``densify_stats`` (per-Gaussian accumulated
   screen-space gradient norm and visibility count that drive densification).
@@ -60,9 +61,9 @@ import numpy as np
 import torch
 
 __all__ = [
-    "TILE", "QNORM2_MIN", "exp32", "log32", "footprint_f32", "footprint_shared_f32", "key_list", "project_f64",
+    "TILE", "QNORM2_MIN", "exp32", "log32", "footprint_f32", "footprint_shared_f32", "key_list", "tile_occupancy", "project_f64",
     "render_pixels", "render_image", "gradients", "quat_to_rot_f64", "OracleProjection",
-    "depth_order", "frame_pairs", "ssim_window_1d", "ssim_map", "ssim_loss", "adam_step", "densify_stats",
+    "depth_order", "frame_pairs", "l1_loss", "ssim_window_1d", "ssim_map", "ssim_loss", "adam_step", "densify_stats",
     "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA", "vq_decode", "densify_plan", "densify_apply",
     "KEEP", "CLONE", "SPLIT", "PRUNE", "SPLIT_SHRINK",
 ]
@@ -141,6 +142,7 @@ class Footprint:
     ex: np.ndarray          # [n] float32 half extents of the alpha >= alpha_min ellipse
     ey: np.ndarray
     A: Optional[np.ndarray] = None   # [n] float32 peak opacity O(v) w (before the cull)
+    cov: Optional[np.ndarray] = None  # [n,3] float32 screen covariance (S00, S01, S11) as rounded above
 
 
 def _finite_rows(*arrs):
@@ -273,7 +275,8 @@ def footprint_f32(g, cam, lut, opts) -> Footprint:
     rect[kk, 3] = yhi[kk].astype(np.int64) // TILE
     count = np.where(kk, (rect[:, 2] - rect[:, 0] + 1).astype(np.int64) * (rect[:, 3] - rect[:, 1] + 1), 0)
     return Footprint(keep=keep, depth=depth, depth_bits=depth.view(np.uint32).copy(), rect=rect,
-                     count=count, mx=mx, my=my, ex=ex, ey=ey, A=np.asarray(A, np.float32))
+                     count=count, mx=mx, my=my, ex=ex, ey=ey, A=np.asarray(A, np.float32),
+                     cov=np.stack([S00, S01, S11], 1).astype(np.float32))
 
 
 def footprint_shared_f32(g, cam, luts, opts) -> Footprint:
@@ -296,7 +299,8 @@ def footprint_shared_f32(g, cam, luts, opts) -> Footprint:
     def pick(name):
         return np.stack([getattr(fp, name) for fp in fps])[k, idx]
     return Footprint(keep=pick("keep"), depth=fps[0].depth, depth_bits=fps[0].depth_bits, rect=pick("rect"),
-                     count=pick("count"), mx=fps[0].mx, my=fps[0].my, ex=pick("ex"), ey=pick("ey"), A=pick("A"))
+                     count=pick("count"), mx=fps[0].mx, my=fps[0].my, ex=pick("ex"), ey=pick("ey"), A=pick("A"),
+                     cov=fps[0].cov)
 
 
 def tiles_of(cam):
@@ -343,6 +347,19 @@ def key_list(fps, cams):
         ranges[:, 0] = np.where(ends > starts, starts, 0)
         ranges[:, 1] = np.where(ends > starts, ends, 0)
     return tiles, depths, pairs, ranges, np.asarray(bases, np.int64)
+
+
+def tile_occupancy(fp: Footprint, cam) -> np.ndarray:
+    """[tiles_y, tiles_x] number of Gaussians whose tile rectangle covers each tile (the
+    length of each tile's key list), by a 2D difference array over the rectangles."""
+    tx_n, ty_n = tiles_of(cam)
+    diff = np.zeros((ty_n + 1, tx_n + 1), np.int64)
+    r = fp.rect[fp.count > 0].astype(np.int64)
+    np.add.at(diff, (r[:, 1], r[:, 0]), 1)
+    np.add.at(diff, (r[:, 1], r[:, 2] + 1), -1)
+    np.add.at(diff, (r[:, 3] + 1, r[:, 0]), -1)
+    np.add.at(diff, (r[:, 3] + 1, r[:, 2] + 1), 1)
+    return diff.cumsum(0).cumsum(1)[:ty_n, :tx_n]
 
 
 def frame_pairs(n, n_frames):
@@ -480,9 +497,14 @@ class PixelResult:
                              #       through near-threshold decisions (sum of their impact bounds)
 
 
+# Unit roundoff of float32 and the safety factor of the per-evaluation error bound below.
+U32 = 2.0 ** -24
+ERR_COEF = 32.0
+
+
 def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray, opts,
-                  bg=(0.0, 0.0, 0.0), batch: int = 0, skip_margin=1e-4, stop_margin=1e-3,
-                  clamp_margin=1e-5, skip_impact=2.5e-5, t_min: Optional[float] = None) -> PixelResult:
+                  bg=(0.0, 0.0, 0.0), batch: int = 0, err_coef: float = ERR_COEF,
+                  skip_impact=2.5e-5, t_min: Optional[float] = None) -> PixelResult:
     """Front-to-back compositing (Eq. 1) at pixel centres (x+0.5, y+0.5), brute force.
 
     For each pixel and each Gaussian of ``order`` (front to back):
@@ -491,16 +513,33 @@ def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray,
       T *= 1 - alpha, and if T < t_min the pixel stops (the Gaussian that crossed the
       threshold is blended).  Output C + T bg.
 
-    Decision margins.  A skip test with |a - alpha_min| < skip_margin * alpha_min may be
-    decided either way by float32 arithmetic; flipping it moves the pixel by at most
-    alpha_min * T_before * max|c - S| <= alpha_min * T_before * (1 + skip_margin) (colours
-    and background in [0,1]).  A stop test with |T - t_min| < stop_margin * t_min may also
-    flip; then one side blends the Gaussians the other one drops until its T falls below
-    t_min, which moves the pixel by at most (stop_margin + alpha_max_after) * T, with
-    alpha_max_after the largest alpha blended after that point.  ``slack`` sums these
-    bounds per pixel; ``flag`` marks pixels whose slack reaches ``skip_impact``;
-    ``flag_grad`` marks every pixel with any near-threshold skip, stop or clamp decision
-    (where the gradient is discontinuous).
+    Decision margins.  The tiled float32 renderer decides the same skips, stops and clamps
+    from float32 values, so a decision may flip where the float64 value lies within the
+    float32 evaluation's error of its threshold.  That error is bounded per evaluation
+    (pair of Gaussian and pixel): to first order, with u = 2^-24,
+      |ln a_32 - ln a_64| <= eps = err_coef u (1 + |ln A| + (|y_0| sqrt(S00) + |y_1| sqrt(S11))^2),
+    y = conic d.  The last term is the propagation of a relative perturbation of order u in
+    every entry of the float32 screen covariance S (from the chain R, s, W, J, S = G G^T +
+    lowpass I) through conic = S^-1: d(d^T S^-1 d) = -y^T dS y with |dS_ij| <= c u
+    sqrt(S_ii S_jj); it grows with the ellipse's elongation.  |ln A| covers the table
+    lookup and the log2 of A, the 1 the remaining roundings of the exponent (centre offset,
+    quadratic form).  err_coef = 32 is twice the largest ratio of the observed float32
+    error to (1 + |ln A| + that term) over 675k evaluations near the threshold on the 1k-,
+    200k- and 1M-Gaussian workloads, emulating the kernel's op order.
+      skip:  |ln(a / alpha_min)| < eps.  A flip moves the pixel by at most
+             alpha_min T_before max|c - S| <= alpha_min T_before (1 + eps) (colours and
+             background in [0, 1]).
+      stop:  the float32 transmittance after k blends carries a relative error of at most
+             m_k = sum over the blends j <= k of (u + alpha_j / (1 - alpha_j) (eps_j + 2u))
+             (an unclamped alpha inherits a's error, the exp2 rounds once, the update
+             T - alpha T rounds once), so |ln(T_k / t_min)| < m_k may flip.  Then one side
+             blends the Gaussians the other drops until its T falls below t_min, which
+             moves the pixel by at most (m_k + alpha_max_after) T_k (1 + m_k), with
+             alpha_max_after the largest alpha after that point.
+      clamp: |ln(a / alpha_clamp)| < eps (only the gradient is discontinuous there).
+    ``slack`` sums the image bounds per pixel; ``flag`` marks pixels whose slack reaches
+    ``skip_impact``; ``flag_grad`` marks every pixel with any near-threshold skip, stop or
+    clamp decision (where the gradient is discontinuous).
     """
     aclamp = float(np.float32(opts["alpha_clamp"]))
     amin = float(np.float32(opts["alpha_min"]))
@@ -516,53 +555,103 @@ def render_pixels(proj: OracleProjection, order: np.ndarray, pixels: np.ndarray,
     if batch <= 0:
         batch = max(1, min(P, (1 << 23) // max(M, 1)))
     cols, Ts, lasts, nevs, flags, gflags, slacks = [], [], [], [], [], [], []
+    with torch.no_grad():
+        cov = proj.cov2d[order_t].detach()
+        sq00 = torch.sqrt(cov[:, 0].clamp(min=0.0))
+        sq11 = torch.sqrt(cov[:, 2].clamp(min=0.0))
+        conD = con.detach()
+        muD = mu.detach()
+        with np.errstate(divide="ignore"):
+            lnA_all = torch.log(A.detach())
+        ln_amin, ln_aclamp = math.log(amin), math.log(aclamp)
+        ln_tmin = math.log(tmin) if tmin > 0 else -math.inf
     for s in range(0, P, batch):
         pix = torch.as_tensor(np.asarray(pixels[s:s + batch], np.float64))
+        Pb = pix.shape[0]
         if M == 0:
-            cols.append(bgt.expand(pix.shape[0], 3).clone())
-            Ts.append(torch.ones(pix.shape[0], dtype=torch.float64))
-            lasts.append(np.full(pix.shape[0], -1))
-            nevs.append(np.zeros(pix.shape[0], np.int64))
-            flags.append(np.zeros(pix.shape[0], bool))
-            gflags.append(np.zeros(pix.shape[0], bool))
-            slacks.append(np.zeros(pix.shape[0]))
+            cols.append(bgt.expand(Pb, 3).clone())
+            Ts.append(torch.ones(Pb, dtype=torch.float64))
+            lasts.append(np.full(Pb, -1))
+            nevs.append(np.zeros(Pb, np.int64))
+            flags.append(np.zeros(Pb, bool))
+            gflags.append(np.zeros(Pb, bool))
+            slacks.append(np.zeros(Pb))
             continue
-        dx = (pix[:, 0:1] + 0.5) - mu[None, :, 0]
-        dy = (pix[:, 1:2] + 0.5) - mu[None, :, 1]
-        sigma = 0.5 * (con[None, :, 0] * dx * dx + 2.0 * con[None, :, 1] * dx * dy + con[None, :, 2] * dy * dy)
-        a = A[None, :] * torch.exp(-sigma)
-        blend = a >= amin
-        alpha = torch.where(blend, torch.where(a < aclamp, a, torch.full_like(a, aclamp)), torch.zeros_like(a))
+        # Every Gaussian at every pixel.  A Gaussian with a below alpha_min has alpha = 0
+        # and multiplies T by exactly 1, so the compositing below runs over each pixel's
+        # candidates in depth order: every Gaussian with ln a >= ln alpha_min - 1/2 (a
+        # superset of the blended ones and of those within any decision margin), padded
+        # with alpha = 0; a is evaluated again, differentiably, for the candidates.
+        with torch.no_grad():
+            dxD = (pix[:, 0:1] + 0.5) - muD[None, :, 0]
+            dyD = (pix[:, 1:2] + 0.5) - muD[None, :, 1]
+            lnaD = lnA_all[None, :] - 0.5 * (conD[None, :, 0] * dxD * dxD + 2.0 * conD[None, :, 1] * dxD * dyD +
+                                             conD[None, :, 2] * dyD * dyD)
+            cand = lnaD >= ln_amin - 0.5
+            del dxD, dyD, lnaD
+            cnt = cand.sum(1)
+            Kp = max(int(cnt.max()), 1)
+            rows, colsi = cand.nonzero(as_tuple=True)
+            del cand
+            pos = torch.arange(rows.shape[0]) - (torch.cumsum(cnt, 0) - cnt)[rows]
+            valid = torch.zeros((Pb, Kp), dtype=torch.bool)
+            valid[rows, pos] = True
+            gidx = torch.full((Pb, Kp), -1, dtype=torch.int64)
+            gidx[rows, pos] = colsi
+        dxf = (pix[rows, 0] + 0.5) - mu[colsi, 0]
+        dyf = (pix[rows, 1] + 0.5) - mu[colsi, 1]
+        cf = con[colsi]
+        sigf = 0.5 * (cf[:, 0] * dxf * dxf + 2.0 * cf[:, 1] * dxf * dyf + cf[:, 2] * dyf * dyf)
+        ac = torch.zeros((Pb, Kp), dtype=torch.float64).index_put((rows, pos), A[colsi] * torch.exp(-sigf))
+        rgbc = torch.zeros((Pb, Kp, 3), dtype=torch.float64).index_put((rows, pos), rgb[colsi])
+        blend = (ac >= amin) & valid
+        alpha = torch.where(blend, torch.where(ac < aclamp, ac, torch.full_like(ac, aclamp)), torch.zeros_like(ac))
         T_incl = torch.cumprod(1.0 - alpha, dim=1)
         with torch.no_grad():
             stop = T_incl < tmin
             has_stop = stop.any(1)
-            k = torch.where(has_stop, stop.to(torch.int8).argmax(1), torch.full_like(has_stop, M - 1, dtype=torch.int64))
-            ar = torch.arange(M)[None, :]
+            k = torch.where(has_stop, stop.to(torch.int8).argmax(1), torch.full_like(has_stop, Kp - 1, dtype=torch.int64))
+            ar = torch.arange(Kp)[None, :]
             upto = ar <= k[:, None]
         T_excl = torch.cat([torch.ones_like(T_incl[:, :1]), T_incl[:, :-1]], dim=1)
         wgt = alpha * T_excl * upto.to(alpha.dtype)
-        C = wgt @ rgb
+        C = (wgt[:, :, None] * rgbc).sum(1)
         T_fin = T_incl.gather(1, k[:, None])[:, 0]
         cols.append(C + T_fin[:, None] * bgt[None, :])
         Ts.append(T_fin)
         with torch.no_grad():
             bl = blend & upto
-            lastpos = torch.where(bl.any(1), (bl.to(torch.int64) * (ar + 1)).max(1).values - 1, torch.full_like(k, -1))
-            lasts.append(lastpos.numpy())
-            nevs.append((k + 1).numpy())
-            ad = a.detach()
+            last_c = torch.where(bl, gidx, torch.full_like(gidx, -1)).max(1).values
+            lasts.append(last_c.numpy())
+            stop_col = gidx.gather(1, k[:, None])[:, 0]
+            nevs.append(torch.where(has_stop, stop_col + 1, torch.full_like(stop_col, M)).numpy())
+            ad = ac.detach()
             al = alpha.detach()
             Ti, Te = T_incl.detach(), T_excl.detach()
-            near_skip = ((ad - amin).abs() < skip_margin * amin) & upto
-            near_stop = ((Ti - tmin).abs() < stop_margin * tmin) & bl
+            g0 = gidx.clamp(min=0)
+            dxc = torch.zeros((Pb, Kp), dtype=torch.float64)
+            dyc = torch.zeros((Pb, Kp), dtype=torch.float64)
+            dxc[rows, pos] = dxf.detach()
+            dyc[rows, pos] = dyf.detach()
+            # per-evaluation bound on the float32 error of ln a
+            y0 = conD[g0, 0] * dxc + conD[g0, 1] * dyc
+            y1 = conD[g0, 1] * dxc + conD[g0, 2] * dyc
+            lnA = torch.log(A.detach()[g0])
+            eps = err_coef * U32 * (1.0 + lnA.abs() + (y0.abs() * sq00[g0] + y1.abs() * sq11[g0]) ** 2)
+            ln_a = torch.log(ad.clamp(min=1e-300))
+            near_skip = ((ln_a - ln_amin).abs() < eps) & upto & valid
+            unclamped = ad < aclamp
+            step = torch.where(bl, U32 + torch.where(unclamped, al / (1.0 - al), torch.zeros_like(al)) * (eps + 2 * U32),
+                               torch.zeros_like(al))
+            m_t = torch.cumsum(step, dim=1)
+            near_stop = ((torch.log(Ti) - ln_tmin).abs() < m_t) & bl
             amax_from = torch.flip(torch.cummax(torch.flip(al, [1]), 1).values, [1])
             amax_after = torch.cat([amax_from[:, 1:], torch.zeros_like(amax_from[:, :1])], 1)
-            slack = (near_skip.to(al.dtype) * (amin * (1 + skip_margin)) * Te).sum(1) + \
-                    (near_stop.to(al.dtype) * (stop_margin + amax_after) * Ti * (1 + stop_margin)).sum(1)
+            slack = (near_skip.to(al.dtype) * (amin * (1 + eps)) * Te).sum(1) + \
+                    (near_stop.to(al.dtype) * (m_t + amax_after) * Ti * (1 + m_t)).sum(1)
             slacks.append(slack.numpy())
             flags.append((slack >= skip_impact).numpy())
-            near_clamp = ((ad - aclamp).abs() < clamp_margin) & bl
+            near_clamp = ((ln_a - ln_aclamp).abs() < eps) & bl
             gflags.append((near_skip.any(1) | near_stop.any(1) | near_clamp.any(1)).numpy())
     return PixelResult(color=torch.cat(cols, 0), T=torch.cat(Ts, 0), last=np.concatenate(lasts),
                        n_eval=np.concatenate(nevs), flag=np.concatenate(flags),
@@ -663,6 +752,16 @@ SSIM_WINDOW = 11
 SSIM_SIGMA = 1.5
 SSIM_C1 = 0.01 ** 2
 SSIM_C2 = 0.03 ** 2
+
+
+def l1_loss(image, target, scale: Optional[float] = None):
+    """The L1 term of the training loss (section "Training"): scale * sum |image - target|
+    over every pixel-channel, scale = 1 / (number of pixel-channels) unless given, and its
+    gradient scale * sign(image - target) with sign(0) = 0.  float64."""
+    x = np.asarray(image, np.float64) - np.asarray(target, np.float64)
+    if scale is None:
+        scale = 1.0 / max(x.size, 1)
+    return float(scale * np.abs(x).sum()), scale * np.sign(x)
 
 
 def ssim_window_1d(size: int = SSIM_WINDOW, sigma: float = SSIM_SIGMA) -> np.ndarray:

@@ -1,11 +1,13 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark times
-(groups of 16 frames of 1024x1024 over 1M Gaussians; 2048x2048 over 4M Gaussians).
+(groups of 16 frames and all 48 frames of 1024x1024 over 1M Gaussians; all 32 frames of
+800x800 over 200k Gaussians; 2048x2048 over 4M Gaussians).
 
-The oracle cannot brute-force whole frames at these sizes, so the checks are: sampled
-pixels (float64 brute force over all Gaussians), sampled tiles' key lists (bit-exact
-against the float32 footprint mirror), properties of the whole key list that hold at any
-size (sorted, every kept pair appears exactly count times, ranges partition the list), and
-the gradient of a loss restricted to sampled pixels.
+The oracle cannot brute-force whole frames at these sizes, so the checks are: 1024 sampled
+pixels per tested frame (float64 brute force over all Gaussians), stratified to include
+every pixel of the frame's fullest tile and weighted towards long tile lists; sampled
+tiles' key lists (bit-exact against the float32 footprint mirror); properties of the whole
+key list that hold at any size (sorted, every kept pair appears exactly count times, ranges
+partition the list); and the gradient of a loss restricted to sampled pixels.
 """
 import numpy as np
 import pytest
@@ -13,9 +15,23 @@ import torch
 
 import oracle
 import synth
-from gpu_helpers import compare_image, image_pixels, luts_to_dev, rel_err, to_dev
+from gpu_helpers import compare_image, image_pixels, luts_to_dev, rel_err, stratified_pixels, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N_PIXELS = 1024
+
+
+def _compare_frame(w, img_chw, ci, ti, rng, n=N_PIXELS):
+    """Stratified sample pixels of one frame against the oracle; returns the pixels."""
+    cam = w.cameras[ci]
+    fp = oracle.footprint_f32(w.gaussians, cam, w.tfs[ti], w.opts)
+    px, hottest = stratified_pixels(rng, fp, cam, n)
+    assert hottest > 0
+    res, *_ = oracle.render_image(w.gaussians, cam, w.tfs[ti], w.opts, pixels=px)
+    gpu = image_pixels(img_chw)[px[:, 1] * cam.width + px[:, 0]]
+    compare_image(gpu, res)
+    return px
 
 
 def _group(w, frames):
@@ -50,8 +66,7 @@ def _check_sampled_tiles(w, st, frames, keys, vals, rg, n_tiles, seed):
     for f in (0, len(frames) - 1):
         ci, ti = frames[f]
         fp = oracle.footprint_f32(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts)
-        lens = rg[f * per_frame:(f + 1) * per_frame, 1] - rg[f * per_frame:(f + 1) * per_frame, 0]
-        pick = list(rng.integers(0, per_frame, n_tiles)) + [int(np.argmax(lens))]
+        pick = list(rng.integers(0, per_frame, n_tiles)) + [int(np.argmax(oracle.tile_occupancy(fp, w.cameras[ci])))]
         for t in pick:
             ty, tx = divmod(int(t), tx_n)
             cover = (fp.count > 0) & (fp.rect[:, 0] <= tx) & (fp.rect[:, 2] >= tx) & \
@@ -72,10 +87,7 @@ def test_train_workload_group_of_16_frames():
     rng = synth.rng_for(2, 77)
     for f in (0, 9):
         ci, ti = frames[f]
-        px = synth.sample_pixels(rng, w.width, w.height, 192)
-        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
-        gpu = image_pixels(st.image[f])[px[:, 1] * w.width + px[:, 0]]
-        compare_image(gpu, res)
+        _compare_frame(w, st.image[f], ci, ti, rng)
 
 
 def test_train_workload_sampled_pixel_gradient():
@@ -111,10 +123,7 @@ def test_stress_workload_2048px_4M():
     _check_sampled_tiles(w, st, frames, keys, vals, rg, 3, 2)
     rng = synth.rng_for(4, 79)
     for f, (ci, ti) in enumerate(frames):
-        px = synth.sample_pixels(rng, w.width, w.height, 96)
-        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
-        gpu = image_pixels(st.image[f])[px[:, 1] * w.width + px[:, 0]]
-        compare_image(gpu, res)
+        _compare_frame(w, st.image[f], ci, ti, rng)
 
 
 # ----------------------------------------------------------------------------- shared views
@@ -142,8 +151,7 @@ def test_train_workload_shared_views_all_48_frames():
     per = 64 * 64
     for v in (0, 11):
         un = oracle.footprint_shared_f32(w.gaussians, w.cameras[v], w.tfs, w.opts)
-        lens = rg[v * per:(v + 1) * per, 1] - rg[v * per:(v + 1) * per, 0]
-        for t in list(rng.integers(0, per, 5)) + [int(np.argmax(lens))]:
+        for t in list(rng.integers(0, per, 5)) + [int(np.argmax(oracle.tile_occupancy(un, w.cameras[v])))]:
             ty, tx = divmod(int(t), 64)
             cover = (un.count > 0) & (un.rect[:, 0] <= tx) & (un.rect[:, 2] >= tx) & \
                     (un.rect[:, 1] <= ty) & (un.rect[:, 3] >= ty)
@@ -156,10 +164,7 @@ def test_train_workload_shared_views_all_48_frames():
     prng = synth.rng_for(2, 80)
     for f in (0, 1, 2, 35):
         ci, ti = w.frames[f]
-        px = synth.sample_pixels(prng, w.width, w.height, 160)
-        res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
-        gpu = image_pixels(st.image[f])[px[:, 1] * w.width + px[:, 0]]
-        compare_image(gpu, res)
+        _compare_frame(w, st.image[f], ci, ti, prng)
 
 
 def test_train_workload_shared_views_sampled_pixel_gradient():
@@ -173,6 +178,47 @@ def test_train_workload_shared_views_sampled_pixel_gradient():
     rng = synth.rng_for(2, 81)
     px = synth.sample_pixels(rng, w.width, w.height, 48)
     d = rng.standard_normal((48, 3))
+    res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
+    d[res.flag_grad] = 0.0
+    d_np = np.zeros((len(w.frames), 3, w.height, w.width), np.float32)
+    for ch in range(3):
+        np.add.at(d_np[f, ch], (px[:, 1], px[:, 0]), d[:, ch].astype(np.float32))
+    grads = R.Grads.zeros(g)
+    R.render_backward(g, st, torch.as_tensor(d_np).cuda(), grads)
+    torch.cuda.synchronize()
+    ref = oracle.gradients(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, d, pixels=px)
+    for name in ("d_means", "d_log_scales", "d_quats", "d_scalars"):
+        assert rel_err(getattr(grads, name).cpu().numpy(), getattr(ref, name)) <= 1e-3, name
+
+
+# ------------------------------------------------------------------ multi-TF training
+# 200k shell-clustered Gaussians, 8 views x 4 tables = 32 frames of 800x800, every frame on
+# its own list, all 32 frames in one group.
+
+def test_multi_tf_workload_all_32_frames():
+    w = synth.workload(1)
+    assert w.gaussians.n == 200_000 and len(w.frames) == 32 and w.width == 800
+    g, luts, st = _group(w, w.frames)
+    keys, vals, rg = _check_whole_list(st, w.gaussians.n, len(w.frames))
+    _check_sampled_tiles(w, st, w.frames, keys, vals, rg, 6, 4)
+    rng = synth.rng_for(1, 82)
+    for f in (0, 13, 31):
+        ci, ti = w.frames[f]
+        _compare_frame(w, st.image[f], ci, ti, rng)
+
+
+def test_multi_tf_workload_sampled_pixel_gradient():
+    """dL/dparams for L = sum over 256 stratified sample pixels of d . image of frame 21
+    (all 32 frames rendered and back-propagated together; the other frames' d is 0)."""
+    from paper_2504_13339_amd import render as R
+    w = synth.workload(1)
+    g, luts, st = _group(w, w.frames)
+    f = 21
+    ci, ti = w.frames[f]
+    rng = synth.rng_for(1, 83)
+    fp = oracle.footprint_f32(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts)
+    px, _ = stratified_pixels(rng, fp, w.cameras[ci], 256)
+    d = rng.standard_normal((px.shape[0], 3))
     res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, pixels=px)
     d[res.flag_grad] = 0.0
     d_np = np.zeros((len(w.frames), 3, w.height, w.width), np.float32)

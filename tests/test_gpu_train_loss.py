@@ -203,8 +203,9 @@ def test_train_step_with_ssim_matches_oracle_and_grouping_does_not_matter():
         img = c.T.reshape(3, H, W)
         t64 = tgt_np[f].astype(np.float64)
         sl, sd = oracle.ssim_loss(img, t64, lam / M)
-        loss_ref += (1 - lam) * np.abs(img - t64).sum() / M + sl
-        d_img = (1 - lam) * np.sign(img - t64) / M + sd      # [3, H, W]
+        l1, d_l1 = oracle.l1_loss(img, t64, scale=(1 - lam) / M)
+        loss_ref += l1 + sl
+        d_img = d_l1 + sd      # [3, H, W]
         gr = oracle.gradients(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, d_img.reshape(3, -1).T)
         cur = {"d_means": gr.d_means, "d_log_scales": gr.d_log_scales, "d_quats": gr.d_quats,
                "d_scalars": gr.d_scalars}
