@@ -179,35 +179,169 @@ def opacity_guided_bench(steps, warmup=2):
     return out
 
 
-def cpu_baseline(w, n_pixels, seed=5):
-    """The oracle (float64 brute force + autograd adjoint) on ``n_pixels`` sampled pixels of
-    the first frame of the workload, forward and backward."""
+def workload_step_bench(index, steps, warmup=1, group=None, shared=True):
+    """Forward + backward Mpix/s of another configuration's whole L1 training step (all its
+    frames, targets from a perturbed copy, lists sized from the last warm-up step): the
+    multi-TF workload (200k Gaussians, 8 views x 4 tables, 800x800) or the stress workload
+    (4M Gaussians, 32 views x 4 tables, 2048x2048)."""
+    import torch
+
+    import synth
+    from paper_2504_13339_amd import render as R
+    from paper_2504_13339_amd import veg as V
+    w = synth.workload(index)
+    g = V.Gaussians.from_numpy(w.gaussians)
+    gt = V.Gaussians.from_numpy(w.target_gaussians)
+    luts = [torch.as_tensor(t).cuda() for t in w.tfs]
+    F, H, W = len(w.frames), w.height, w.width
+    group = group or F
+    K = R.views_of(w.frames) if shared else 1
+    targets = torch.empty((F, 3, H, W), dtype=torch.float32, device="cuda")
+    for f0 in range(0, F, group):
+        fr = w.frames[f0:f0 + group]
+        cams = [w.cameras[c] for c, _ in (fr[::K] if K > 1 else fr)]
+        st = R.render(gt, cams, [luts[t] for _, t in fr], w.opts, hits=False, shared=K > 1)
+        targets[f0:f0 + len(fr)] = st.image
+        del st
+    grads = R.Grads.zeros(g)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def step(**kw):
+        return R.train_step(g, w.cameras, luts, w.frames, targets, grads, group, w.opts, loss_acc=loss,
+                            shared=shared, **kw)
+    res = step()
+    cap = int(max(res.n_entries) * 1.05) + 4096
+    for _ in range(warmup):
+        R.check_status(step(capacity=cap, read_loss=False).status, cap)
+    stat = []
+    gc.collect()
+    gc.disable()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stat.append(step(capacity=cap, read_loss=False).status)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gc.enable()
+    for st in stat:
+        R.check_status(st, cap)
+    out = {"workload": w.name, "gaussians": w.gaussians.n, "frames": F, "width": W, "height": H, "group": group,
+           "shared_views": bool(shared), "max_entries_per_group": int(max(res.n_entries)),
+           "mpix_s": round(F * H * W * steps / dt / 1e6, 2), "ms_per_step": round(dt * 1e3 / steps, 3)}
+    del grads, targets, g, gt
+    torch.cuda.empty_cache()
+    return out
+
+
+def stress_serve_bench(n_frames=64, max_batch=8, n_streams=2):
+    """The stress workload's serving leg: a batch of ``n_frames`` 2048x2048 frames of the 4M-
+    Gaussian model, each with its own camera (the workload's views) and one of its transfer
+    functions, submitted at once to a server (continuous batching, captured graphs) and,
+    for comparison, rendered one after another by the plain stateless loop; Mpix/s of the
+    whole batch and latency from submission."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_13339_amd import render as R
+    from paper_2504_13339_amd import veg as V
+    from paper_2504_13339_amd.serve import Server
+    w = synth.workload(4)
+    g = V.Gaussians.from_numpy(w.gaussians)
+    frames = [(f % len(w.cameras), f % len(w.tfs)) for f in range(n_frames)]
+    res = w.width
+    srv = Server(max_gaussians=w.gaussians.n, max_entries=1 << 29, max_batch=max_batch, n_streams=n_streams,
+                 use_graphs=True, max_width=res, max_height=res, max_tf_k=256)
+    mid = srv.add_model(g)
+    outs = [torch.empty((3, res, res), device="cuda") for _ in range(n_frames)]
+
+    def serve_once():
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        ids = [srv.submit(mid, w.cameras[c], w.tfs[t], outs[i], t_arrival=t0) for i, (c, t) in enumerate(frames)]
+        for rid in ids:
+            srv.wait(rid)
+        return time.perf_counter() - t0, srv.stats()
+    serve_once()                                   # graph capture
+    dt, st = serve_once()
+    luts = [torch.as_tensor(t).cuda() for t in w.tfs]
+    R.render(g, [w.cameras[0]], [luts[0]], w.opts, hits=False)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for c, t in frames:
+        st_p = R.render(g, [w.cameras[c]], [luts[t]], w.opts, hits=False)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        del st_p
+    dtp = time.perf_counter() - t0
+    srv.close()
+    px = n_frames * res * res
+    return {"workload": w.name + "-serve", "frames": n_frames, "width": res, "height": res,
+            "server": {"mpix_s": round(px / dt / 1e6, 2), "seconds": round(dt, 4), "p50_ms": round(st["p50_ms"], 3),
+                       "p99_ms": round(st["p99_ms"], 3), "mean_batch": round(st["mean_batch"], 3),
+                       "retries": int(st["retries"])},
+            "plain": {"mpix_s": round(px / dtp / 1e6, 2), "seconds": round(dtp, 4),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}}
+
+
+def cpu_baseline(w, n_pixels, seed=5, one_core_pixels=64):
+    """The oracle (float64 brute force + autograd adjoint) on the host's cores: forward and
+    backward of ``n_pixels`` sampled pixels of the first frame of the workload on every core
+    of this process's affinity set, the same on one core with ``one_core_pixels`` pixels,
+    and a whole 64x64 frame of the 1k-Gaussian workload (forward + backward) on all cores
+    and on one."""
     import numpy as np
     import torch
 
     import oracle
     import synth
-    cores = torch.get_num_threads()
+    cores = len(os.sched_getaffinity(0))
+    threads0 = torch.get_num_threads()
     rng = synth.rng_for(2, 100 + seed)
     ci, ti = w.frames[0]
     cam = w.cameras[ci]
     px = synth.sample_pixels(rng, cam.width, cam.height, n_pixels)
     d = rng.standard_normal((n_pixels, 3))
-    t0 = time.perf_counter()
-    oracle.gradients(w.gaussians, cam, w.tfs[ti], w.opts, d, pixels=px)
-    dt = time.perf_counter() - t0
+
+    def timed(threads, fn):
+        torch.set_num_threads(threads)
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    dt = timed(cores, lambda: oracle.gradients(w.gaussians, cam, w.tfs[ti], w.opts, d, pixels=px))
+    k1 = min(one_core_pixels, n_pixels)
+    dt1 = timed(1, lambda: oracle.gradients(w.gaussians, cam, w.tfs[ti], w.opts, d[:k1], pixels=px[:k1]))
+    w0 = synth.workload(0)
+    cam0 = w0.cameras[0]
+    d0 = rng.standard_normal((cam0.width * cam0.height, 3))
+    f_all = timed(cores, lambda: oracle.gradients(w0.gaussians, cam0, w0.tfs[0], w0.opts, d0))
+    f_one = timed(1, lambda: oracle.gradients(w0.gaussians, cam0, w0.tfs[0], w0.opts, d0))
+    torch.set_num_threads(threads0)
+    npx0 = cam0.width * cam0.height
     return {"value": n_pixels / dt / 1e6, "unit": "Mpix/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n_pixels} sampled pixels of frame 0 (1024x1024, {w.gaussians.n} Gaussians), "
+            "sample": f"{n_pixels} sampled pixels of frame 0 ({cam.width}x{cam.height}, {w.gaussians.n} Gaussians), "
                       f"float64 projection of every Gaussian + brute-force forward + autograd backward, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s on {cores} threads",
+            "one_core": {"value": k1 / dt1 / 1e6, "unit": "Mpix/s", "cores": 1,
+                         "sample": f"{k1} of the same pixels, {dt1:.1f} s"},
+            "full_frame_1k_64px": {"seconds_all_cores": round(f_all, 3), "seconds_one_core": round(f_one, 3),
+                                   "mpix_s_all_cores": npx0 / f_all / 1e6, "mpix_s_one_core": npx0 / f_one / 1e6,
+                                   "sample": f"a whole {cam0.width}x{cam0.height} frame of {w0.gaussians.n} "
+                                             f"Gaussians, forward + backward"}}
 
 
-def serve_bench(rates, n_per_rate, max_batch=8, n_streams=3, use_graphs=True):
+def serve_bench(rates, min_requests=2000, max_seconds=30.0, max_batch=8, n_streams=3, budget_gb=64.0,
+                saturate=2.0):
     """Serving workload: 4 resident shell-clustered models (100k, 500k, 1M, 3M Gaussians),
     open-loop Poisson arrivals, each request a random model, camera on a sphere of radius
-    2.5-4, fresh random 256-entry TF and a resolution from {512^2, 1024^2, 1920x1080}.
-    The server (continuous batching) and the plain loop (stateless API, one request at a
-    time in arrival order) serve the same trace; latency = completion - arrival."""
+    2.5-4, fresh random 256-entry TF and a resolution from {512^2, 1024^2, 1920x1080}; an
+    HBM admission budget of ``budget_gb``.  Each rate serves min(``min_requests``, rate x
+    ``max_seconds``) requests, then one more rate ``saturate`` times the plain loop's measured
+    capacity.  The server (continuous batching) and the plain loop (stateless API, one
+    request at a time in arrival order) serve the same trace; for both, latency = completion
+    - scheduled arrival and throughput = requests / (last completion - first arrival)."""
     import numpy as np
     import torch
 
@@ -220,68 +354,92 @@ def serve_bench(rates, n_per_rate, max_batch=8, n_streams=3, use_graphs=True):
     models = [V.Gaussians.from_numpy(m) for m in models_np]
     opts = synth.DEFAULT_OPTS
     results = {"models": [m.n for m in models], "resolutions": ["512x512", "1024x1024", "1920x1080"],
-                "max_batch": max_batch, "streams": n_streams, "graphs": bool(use_graphs), "rates": {}}
+               "max_batch": max_batch, "streams": n_streams, "graphs": True, "budget_gb": budget_gb, "rates": {}}
     srv = Server(max_gaussians=max(m.n for m in models), max_entries=64_000_000, max_batch=max_batch,
-                 n_streams=n_streams, use_graphs=use_graphs, max_width=1920, max_height=1080, max_tf_k=256)
+                 n_streams=n_streams, use_graphs=True, max_width=1920, max_height=1080, max_tf_k=256,
+                 budget_bytes=int(budget_gb * 1e9))
     results["arena_gb"] = round(srv.arena_bytes / 1e9, 2)
     mids = [srv.add_model(m) for m in models]
+    RING = 256
     ring = {}
-
-    def out_for(cam, i):
-        key = (cam.width, cam.height)
-        bufs = ring.setdefault(key, [torch.empty((3, cam.height, cam.width), device="cuda") for _ in range(48)])
-        return bufs[i % len(bufs)]
 
     def run_server(reqs):
         srv.reset_stats()
+        users = {}
         t0 = time.perf_counter() + 0.05
         ids = []
-        for i, r in enumerate(reqs):
+        for r in reqs:
             target = t0 + r.arrival_s
             while True:
                 d = target - time.perf_counter()
                 if d <= 0:
                     break
                 time.sleep(d - 0.0005 if d > 0.001 else 0)
-            ids.append(srv.submit(mids[r.model], r.camera, r.tf, out_for(r.camera, i)))
-        for rid in ids:
-            srv.wait(rid)
+            key = (r.camera.width, r.camera.height)
+            bufs = ring.setdefault(key, [torch.empty((3, key[1], key[0]), device="cuda") for _ in range(RING)])
+            used = users.setdefault(key, [])
+            k = len(used) % RING
+            if len(used) >= RING and used[len(used) - RING] is not None:
+                srv.wait(used[len(used) - RING])       # the buffer's previous request is done with it
+                used[len(used) - RING] = None
+            rid = srv.submit(mids[r.model], r.camera, r.tf, bufs[k], t_arrival=target)
+            used.append(rid)
+            ids.append(rid)
+        for lst in users.values():
+            for rid in lst:
+                if rid is not None:
+                    srv.wait(rid)
         return srv.stats()
 
     def run_plain(reqs):
         luts = [torch.as_tensor(r.tf).cuda() for r in reqs]
         torch.cuda.synchronize()
-        lat = []
+        lat, service = [], []
         t0 = time.perf_counter() + 0.05
         for i, r in enumerate(reqs):
             target = t0 + r.arrival_s
             while time.perf_counter() < target:
                 pass
+            ts = time.perf_counter()
             st = R.render(models[r.model], [r.camera], [luts[i]], opts, hits=False)   # forward only
             torch.cuda.synchronize()
-            lat.append((time.perf_counter() - target) * 1e3)
+            te = time.perf_counter()
+            lat.append((te - target) * 1e3)
+            service.append(te - ts)
             del st
-        span = time.perf_counter() - t0
+        span = te - (t0 + reqs[0].arrival_s)
         lat = np.sort(np.asarray(lat))
         pix = sum(r.camera.width * r.camera.height for r in reqs)
         return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "max_ms": float(lat[-1]), "throughput_rps": len(reqs) / span, "mpix_per_s": pix / span / 1e6}
+                "max_ms": float(lat[-1]), "throughput_rps": len(reqs) / span, "mpix_per_s": pix / span / 1e6,
+                "mean_service_ms": float(np.mean(service) * 1e3)}
 
-    # warm-up (graph capture, allocator)
-    _, warm = synth.serve_trace(500.0, 2 * max_batch * n_streams, build_models=False, seed_sub=99)
-    run_server(warm)
-    run_plain(warm[:4])
-    for k, rate in enumerate(rates):
-        _, reqs = synth.serve_trace(float(rate), int(n_per_rate), build_models=False, seed_sub=k)
-        log(f"bench: serving {len(reqs)} requests at {rate} req/s")
+    def one_rate(label, rate, n, seed):
+        _, reqs = synth.serve_trace(float(rate), int(n), build_models=False, seed_sub=seed)
+        log(f"bench: serving {len(reqs)} requests at {rate:.0f} req/s")
         st = run_server(reqs)
         pl = run_plain(reqs)
-        results["rates"][str(rate)] = {
+        results["rates"][label] = {
+            "rate": round(float(rate), 1), "requests": len(reqs),
             "server": {k2: round(float(st[k2]), 3) for k2 in ("p50_ms", "p99_ms", "max_ms", "throughput_rps",
                                                               "mpix_per_s", "mean_batch", "gpu_busy_frac")} |
-                      {"completed": int(st["completed"]), "retries": int(st["retries"])},
-            "plain": {k2: round(v, 3) for k2, v in pl.items()},
-            "requests": len(reqs)}
+                      {"completed": int(st["completed"]), "retries": int(st["retries"]),
+                       "peak_gb": round(st["peak_bytes"] / 1e9, 2), "graphs_captured": int(st["graphs_captured"])},
+            "plain": {k2: round(v, 3) for k2, v in pl.items()}}
+        return pl
+
+    # warm-up: graph capture for the common batch shapes, allocator
+    _, warm = synth.serve_trace(2000.0, 400, build_models=False, seed_sub=99)
+    run_server(warm)
+    run_plain(warm[:16])
+    cap = None
+    for k, rate in enumerate(rates):
+        n = max(1, min(int(min_requests), int(math.ceil(rate * max_seconds))))
+        pl = one_rate(str(rate), rate, n, k)
+        cap = 1e3 / pl["mean_service_ms"]
+    if saturate and cap:
+        one_rate("saturating", saturate * cap, int(min_requests), len(rates))
+        results["plain_capacity_rps"] = round(cap, 1)
     srv.close()
     return results
 
@@ -308,8 +466,18 @@ def main():
     ap.add_argument("--full-steps", type=int, default=5,
                     help="timed whole training iterations: L1 + SSIM loss, densification statistics, Adam (0 to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-rates", default="200", help="comma-separated arrival rates (req/s); '' to skip")
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--c1-steps", type=int, default=5,
+                    help="timed training steps of the multi-TF workload (200k, 8 x 4 frames, 800x800; 0 to skip)")
+    ap.add_argument("--c4-steps", type=int, default=2,
+                    help="timed training steps of the stress workload (4M, 32 x 4 frames, 2048x2048; 0 to skip)")
+    ap.add_argument("--c4-serve", type=int, default=64,
+                    help="frames of the stress workload's 2048x2048 serving batch (0 to skip)")
+    ap.add_argument("--serve-rates", default="50,100,200,400",
+                    help="comma-separated arrival rates (req/s), each followed by a rate twice the plain loop's "
+                         "capacity; '' to skip")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per rate (fewer when the rate reaches them only after --serve-seconds)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -527,10 +695,24 @@ def main():
         log("bench: opacity-guided family")
         out["opacity_guided"] = opacity_guided_bench(args.og_steps)
         grads = targets = None
+    if args.c1_steps > 0 or args.c4_steps > 0 or args.c4_serve > 0:
+        del grads, targets
+        grads = targets = None
+        torch.cuda.empty_cache()
+    if args.c1_steps > 0:
+        log("bench: multi-TF workload step")
+        out["multi_tf_step"] = workload_step_bench(1, args.c1_steps, shared=True)
+    if args.c4_steps > 0:
+        log("bench: stress workload step")
+        out["stress_step"] = workload_step_bench(4, args.c4_steps, group=64, shared=True)
+    if args.c4_serve > 0:
+        log("bench: stress workload serving batch")
+        out["stress_serve"] = stress_serve_bench(args.c4_serve)
     if args.serve_rates:
         del grads, targets
         torch.cuda.empty_cache()
-        out["serve"] = serve_bench([float(r) for r in args.serve_rates.split(",")], args.serve_requests)
+        out["serve"] = serve_bench([float(r) for r in args.serve_rates.split(",")], args.serve_requests,
+                                   args.serve_seconds)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_pixels)

@@ -123,8 +123,9 @@ typedef struct {
   int32_t k;
 } veg_tf;
 
-/* Renderer options.  The paper names the rasterizer it builds on but not its constants;
- * these defaults (veg_opts_default) are the readings of this library:
+/* Renderer options of the rasterizer of section "Rendering of VEGs".  The paper names
+ * the rasterizer it builds on but not its constants; these defaults (veg_opts_default)
+ * are the readings of this library:
  *   alpha_clamp 0.99   alpha = min(alpha_clamp, A exp(-sigma))
  *   alpha_min   1/255  a Gaussian-pixel pair with A exp(-sigma) < alpha_min is skipped
  *   t_min       1e-4   a pixel stops after blending the Gaussian that takes T below t_min
@@ -143,7 +144,8 @@ void veg_opts_default(veg_opts* opts);
  * Projection  (transfer function first, then EWA projection and footprint)
  * ---------------------------------------------------------------------------------- */
 
-/* Projection state of `n_frames` frames over one Gaussian set; pair p = f*n + i.
+/* Projection state of `n_frames` frames over one Gaussian set; pair p = f*n + i (the
+ * projection of section "Rendering of VEGs"; veg_frames_bytes sizes its descriptors).
  * Host struct holding caller-owned device buffers; veg_project fills the buffers and
  * the host fields marked "out".
  *   frames  device, veg_frames_bytes(n_frames) bytes: per-frame descriptors
@@ -265,14 +267,18 @@ typedef struct {
 } veg_bins;
 
 /* Words of veg_bins.hits for a list of `capacity` entries over `total_tiles` tiles
- * (one bit per entry, each tile's bits starting in a word of its own). */
+ * (one bit per entry, each tile's bits starting in a word of its own; the key list of the
+ * tile-based rasterizer of section "Rendering of VEGs"). */
 int64_t veg_bin_hit_words(int64_t capacity, int64_t total_tiles);
 
-/* Scratch for veg_bin_count / veg_bin_sort of `n_pairs` pairs and `capacity` entries. */
+/* Scratch for veg_bin_count / veg_bin_sort of `n_pairs` pairs and `capacity` entries (the
+ * binning of section "Rendering of VEGs"). */
 size_t veg_bin_workspace_bytes(int64_t n_pairs, int64_t capacity);
 
-/* veg_bin_count -- compacts the kept pairs, sorts them front to back by (depth key,
- * pair id) with a stable LSD radix sort, and prefix-sums their tile counts in that order.
+/* veg_bin_count -- the first half of the binning of the tile-based rasterizer (section
+ * "Rendering of VEGs": Gaussians binned to tiles and sorted front to back before blending):
+ * compacts the kept pairs, sorts them front to back by (depth key, pair id) with a stable
+ * LSD radix sort, and prefix-sums their tile counts in that order.
  *   ws, ws_bytes     device scratch, >= veg_bin_workspace_bytes(pairs, capacity) where
  *                    capacity is the value later passed to veg_bin_sort (may be 0 here if
  *                    the same ws is re-queried: only the first part is used by this call)
@@ -283,9 +289,10 @@ size_t veg_bin_workspace_bytes(int64_t n_pairs, int64_t capacity);
 veg_status veg_bin_count(const veg_proj* proj, void* ws, size_t ws_bytes, int64_t* n_entries,
                          veg_stream_t stream);
 
-/* veg_bin_sort -- writes every (tile, pair) entry of the kept pairs in front-to-back
- * order, sorts the list stably by tile (LSD radix over the bits of the largest tile id),
- * and derives the per-tile ranges.  Needs the workspace state left by veg_bin_count.
+/* veg_bin_sort -- the second half of the binning (section "Rendering of VEGs"): writes
+ * every (tile, pair) entry of the kept pairs in front-to-back order, sorts the list stably
+ * by tile (LSD radix over the bits of the largest tile id), and derives the per-tile
+ * ranges.  Needs the workspace state left by veg_bin_count.
  * If the device-side E exceeds bins->capacity, only the first `capacity` entries are
  * written, the ranges are not valid, and the overflow flag read by veg_bin_overflow is
  * set (no synchronisation happens here).
@@ -294,7 +301,8 @@ veg_status veg_bin_count(const veg_proj* proj, void* ws, size_t ws_bytes, int64_
 veg_status veg_bin_sort(const veg_proj* proj, void* ws, size_t ws_bytes, const veg_bins* bins,
                         veg_stream_t stream);
 
-/* Reads (synchronising `stream`) the entry count and overflow flag left in `ws`. */
+/* Reads (synchronising `stream`) the entry count and overflow flag of the tile key list
+ * (section "Rendering of VEGs") left in `ws`. */
 veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32_t* overflow,
                             veg_stream_t stream);
 
@@ -338,6 +346,9 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
  *                    contiguous), ACCUMULATED: per pair
  *                    d mx, d my, d conic a, d conic b, d conic c, d R, d G, d B, d A,
  *                    where conic b enters sigma as 1/2 (a dx^2 + 2 b dx dy + c dy^2)
+ * opts must satisfy alpha_clamp <= 1 - 2^-10 (the recovery divides by 1 - alpha) and
+ * t_min (1 - alpha_clamp) >= 2^-100 (t_min = 0 lets T underflow), else
+ * VEG_ERR_INVALID_ARG; the defaults (0.99, 1e-4) do.
  * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
 veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts,
                           const float* t_final, const int32_t* n_last, const float* d_image,
@@ -446,7 +457,8 @@ veg_status veg_densify_plan(int64_t n, const float* grad_accum, const int32_t* v
                             float log_scale_thresh, float prune_weight, uint8_t* action,
                             int64_t* counts, void* ws, size_t ws_bytes, veg_stream_t stream);
 
-/* veg_densify_apply -- writes the model the plan describes into new arrays: first the
+/* veg_densify_apply -- the clone / split / prune step of section "Training" (adaptive
+ * density control): writes the model the plan describes into new arrays: first the
  * survivors (KEEP and CLONE) in index order, then one copy of each CLONE Gaussian in index
  * order, then the two children of each SPLIT Gaussian in index order (PRUNE Gaussians are
  * dropped).  Child c of parent i sits at mu_i + R(q_i) diag(exp(log_s_i)) z[i][c] and has
@@ -478,8 +490,9 @@ veg_status veg_densify_apply(int64_t n, const uint8_t* action, const float* quat
                              size_t ws_bytes, veg_stream_t stream);
 
 /* veg_vq_decode -- expands vector-quantised model attributes into the structure-of-arrays
- * model (trained models are stored with most parameters clustered into a codebook; the
- * paper adopts this from the compact-3DGS work it cites): Gaussian i's attribute vector is
+ * model (section "3D Gaussian Splatting": trained models are stored with most parameters
+ * clustered into a codebook, after the compact-3DGS work it cites): Gaussian i's attribute
+ * vector is
  * row idx[i] of `book`, split in order into the destination fields, e.g. a 7-wide shape
  * codebook into log_scales [n,3] and quats [n,4].
  *   idx       device [n] uint16
@@ -497,23 +510,28 @@ veg_status veg_vq_decode(const uint16_t* idx, int64_t n, const float* book, int3
                          const veg_vq_field* fields, int32_t n_fields, veg_stream_t stream);
 
 /* Fills `count` 32-bit words at device pointer `dst` with `value` (a kernel, so it is
- * safe inside captured graphs). */
+ * safe inside captured graphs): clears the gradient and statistics buffers of the
+ * training step of section "Training". */
 veg_status veg_fill_u32(void* dst, int64_t count, uint32_t value, veg_stream_t stream);
 
-/* Diagnostics: runs the device's float32 helper `op` on n inputs (0 = exp32 of the
- * footprint contract, 1 = log32, 2 = division x/y, 3 = sqrt, 4 = wave prefix sum of
+/* Diagnostics of the projection of section "Rendering of VEGs": runs the device's float32
+ * helper `op` on n inputs (0 = exp32 of the footprint contract, 1 = log32, 2 = division
+ * x/y, 3 = sqrt, 4 = wave prefix sum of
  * uint32 (bit pattern of x), 5 = wave sum of float) so tests can compare them with the
  * oracle.  in_x, in_y, out: device [n]. */
 veg_status veg_debug_math(int32_t op, const float* in_x, const float* in_y, float* out,
                           int64_t n, veg_stream_t stream);
 
 /* ----------------------------------------------------------------------------------
- * Serving: resident models, continuous batching of render requests
+ * Serving: resident models, continuous batching of render requests.  The paper renders
+ * its trained models in an interactive renderer (section "Evaluation"): every request is
+ * the forward pass of section "Rendering of VEGs" for one camera and transfer function.
  * ---------------------------------------------------------------------------------- */
 
 typedef struct veg_server veg_server;
 
-/* Server configuration.  Each of the n_streams batch slots gets static device buffers
+/* Server configuration (serving the renderer of section "Evaluation").  Each of the
+ * n_streams batch slots gets static device buffers
  * carved from `arena` for a batch of up to max_batch requests, max_pairs (frame,
  * Gaussian) pairs and max_entries key-list entries; veg_serve_arena_bytes gives the size
  * needed.  Requests of any model, camera, TF and resolution (<= max_width x max_height)
@@ -524,7 +542,9 @@ typedef struct {
   size_t budget_bytes;       /* admission budget for in-flight request working memory */
   int32_t max_batch;         /* requests per batch (1..64) */
   int32_t n_streams;         /* concurrent batch slots (1..8) */
-  int32_t use_graphs;        /* 1: each slot replays one captured hipGraph per batch */
+  int32_t use_graphs;        /* 1: each batch is one replay of a hipGraph captured per slot
+                                and batch shape (request count and power-of-two bounds on
+                                tiles per frame, Gaussians per model, pairs and entries) */
   int32_t max_width, max_height;   /* largest request resolution (<= VEG_MAX_DIM) */
   int32_t max_tf_k;          /* largest transfer-function table (2..4096 points) */
   int64_t max_gaussians;     /* largest resident model */
@@ -532,7 +552,8 @@ typedef struct {
   int64_t max_entries;       /* key-list capacity per batch (entries, < 2^31) */
 } veg_serve_config;
 
-/* One render request.  The camera and options are copied and the TF table (host memory)
+/* One render request: one frame of section "Rendering of VEGs" (Eq. 1) for a camera and
+ * transfer function.  The camera and options are copied and the TF table (host memory)
  * is copied at submit; out_image / out_t_final are written when the request completes. */
 typedef struct {
   int32_t model_id;
@@ -542,16 +563,20 @@ typedef struct {
   float* out_image;          /* device [3,H,W], caller-owned, written on completion */
   float* out_t_final;        /* device [H,W] or NULL */
   veg_opts opts;             /* per request */
+  double t_arrival;          /* arrival time, CLOCK_MONOTONIC seconds (the clock of C++'s
+                                steady_clock and Python's time.perf_counter on Linux), from
+                                which latency is measured; 0 = the time of the submit call */
 } veg_request;
 
 typedef struct {
   int64_t submitted, completed, failed, rejected, batches, retries;
   double mean_batch;
-  double p50_ms, p99_ms, max_ms; /* submit -> completion observed by the scheduler */
-  double throughput_rps;         /* completed / (last completion - first submit) */
+  double p50_ms, p99_ms, max_ms; /* arrival -> completion observed by the scheduler */
+  double throughput_rps;         /* completed / (last completion - first arrival) */
   double mpix_per_s;
   double gpu_busy_frac;          /* fraction of that interval with >= 1 batch in flight */
   int64_t peak_bytes;            /* peak admitted working-memory estimate */
+  int64_t graphs_captured;       /* graphs captured so far (one per slot and batch shape) */
 } veg_serve_stats;
 
 enum { VEG_REQ_QUEUED = 0, VEG_REQ_RUNNING = 1, VEG_REQ_DONE = 2, VEG_REQ_FAILED = 3 };
@@ -574,9 +599,11 @@ veg_status veg_serve_submit(veg_server* s, const veg_request* r, uint64_t* req_i
 veg_status veg_serve_poll(veg_server* s, uint64_t req_id, int32_t* state);
 /* Waits until the request is done or failed (timeout_ms < 0: forever).  VEG_OK when its
  * image is complete, VEG_ERR_TIMEOUT, or the request's failure status.  A request that
- * has been waited on to completion is released: its id is unknown afterwards. */
+ * has been waited on to completion is released: its id is unknown afterwards (a second
+ * wait, also one racing with the first, returns VEG_ERR_NOT_FOUND). */
 veg_status veg_serve_wait(veg_server* s, uint64_t req_id, int32_t timeout_ms);
-/* Latency/throughput statistics over the requests completed since the last reset. */
+/* Latency/throughput statistics over the requests completed since the last reset (a
+ * reset clears the statistics only; requests not yet waited on stay waitable). */
 veg_status veg_serve_stats_get(veg_server* s, veg_serve_stats* out);
 veg_status veg_serve_stats_reset(veg_server* s);
 /* Drains in-flight work, stops the scheduler and frees host resources. */

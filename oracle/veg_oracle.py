@@ -143,6 +143,7 @@ class Footprint:
     ey: np.ndarray
     A: Optional[np.ndarray] = None   # [n] float32 peak opacity O(v) w (before the cull)
     cov: Optional[np.ndarray] = None  # [n,3] float32 screen covariance (S00, S01, S11) as rounded above
+    det: Optional[np.ndarray] = None  # [n] float32 determinant of that covariance, as computed above
 
 
 def _finite_rows(*arrs):
@@ -168,7 +169,8 @@ def footprint_f32(g, cam, lut, opts) -> Footprint:
       cull unless A >= alpha_min, unless |q|^2 >= 1e-24
       q normalised by 1/sqrt(|q|^2); R(q); s = exp32(log s)
       Q = Vr R; P = Q diag(s); J from float32 depth and clamped float32 xn, yn;
-      G = J P; S = G G^T + lowpass I; det = S00 S11 - S01^2 (cull unless > 0)
+      G = J P; S = G G^T + lowpass I; det = |G0 x G1|^2 + lowpass (|G0|^2 + |G1|^2) + lowpass^2
+      (cull unless > 0)
       tau = 2 log32(A / alpha_min); ex = sqrt(tau S00), ey = sqrt(tau S11)
       pixel range x in [ceil(mx - ex - 0.5), floor(mx + ex - 0.5)] (float64), clipped to the
       image; tile rectangle = pixel range // 16; count = its area.
@@ -247,10 +249,16 @@ def footprint_f32(g, cam, lut, opts) -> Footprint:
         G0 = J00[:, None] * P[:, 0, :] + J02[:, None] * P[:, 2, :]
         G1 = J11[:, None] * P[:, 1, :] + J12[:, None] * P[:, 2, :]
         lp = f32(opts["lowpass"])
-        S00 = ((G0[:, 0] * G0[:, 0] + G0[:, 1] * G0[:, 1]) + G0[:, 2] * G0[:, 2]) + lp
+        g00 = (G0[:, 0] * G0[:, 0] + G0[:, 1] * G0[:, 1]) + G0[:, 2] * G0[:, 2]
+        g11 = (G1[:, 0] * G1[:, 0] + G1[:, 1] * G1[:, 1]) + G1[:, 2] * G1[:, 2]
+        S00 = g00 + lp
         S01 = (G0[:, 0] * G1[:, 0] + G0[:, 1] * G1[:, 1]) + G0[:, 2] * G1[:, 2]
-        S11 = ((G1[:, 0] * G1[:, 0] + G1[:, 1] * G1[:, 1]) + G1[:, 2] * G1[:, 2]) + lp
-        det = S00 * S11 - S01 * S01
+        S11 = g11 + lp
+        # det(S) = |G0 x G1|^2 + lp (|G0|^2 + |G1|^2) + lp^2 (Cauchy-Binet), no cancellation
+        x0 = G0[:, 1] * G1[:, 2] - G0[:, 2] * G1[:, 1]
+        x1 = G0[:, 2] * G1[:, 0] - G0[:, 0] * G1[:, 2]
+        x2 = G0[:, 0] * G1[:, 1] - G0[:, 1] * G1[:, 0]
+        det = (((x0 * x0 + x1 * x1) + x2 * x2) + lp * (g00 + g11)) + lp * lp
 
         amin = f32(opts["alpha_min"])
         keep = finite & (depth > f32(opts["near_z"])) & (A >= amin) & (n2 >= QNORM2_MIN) & (det > f32(0))
@@ -276,7 +284,7 @@ def footprint_f32(g, cam, lut, opts) -> Footprint:
     count = np.where(kk, (rect[:, 2] - rect[:, 0] + 1).astype(np.int64) * (rect[:, 3] - rect[:, 1] + 1), 0)
     return Footprint(keep=keep, depth=depth, depth_bits=depth.view(np.uint32).copy(), rect=rect,
                      count=count, mx=mx, my=my, ex=ex, ey=ey, A=np.asarray(A, np.float32),
-                     cov=np.stack([S00, S01, S11], 1).astype(np.float32))
+                     cov=np.stack([S00, S01, S11], 1).astype(np.float32), det=np.asarray(det, np.float32))
 
 
 def footprint_shared_f32(g, cam, luts, opts) -> Footprint:
@@ -300,7 +308,7 @@ def footprint_shared_f32(g, cam, luts, opts) -> Footprint:
         return np.stack([getattr(fp, name) for fp in fps])[k, idx]
     return Footprint(keep=pick("keep"), depth=fps[0].depth, depth_bits=fps[0].depth_bits, rect=pick("rect"),
                      count=pick("count"), mx=fps[0].mx, my=fps[0].my, ex=pick("ex"), ey=pick("ey"), A=pick("A"),
-                     cov=fps[0].cov)
+                     cov=fps[0].cov, det=fps[0].det)
 
 
 def tiles_of(cam):
@@ -715,9 +723,13 @@ def gradients(g, cam, lut, opts, d_color, pixels=None, bg=None, batch: int = 0) 
     sh_arr = _shading_arrays(g)
     sh = None if sh_arr is None else [torch.tensor(np.asarray(x, np.float64), requires_grad=True) for x in sh_arr]
     proj = project_f64(*leaves, w, cam, lut, opts, shading=sh)
+    # The image depends on the parameters only through the per-Gaussian screen-space
+    # quantities, so their gradients are summed over the pixel batches first (leaf copies),
+    # then taken through the projection once (chain rule).
     inter = [proj.mean2d, proj.conic, proj.rgb, proj.A]
-    for t in inter:
-        t.retain_grad()
+    cut = [t.detach().requires_grad_(True) for t in inter]
+    proj_cut = OracleProjection(mean2d=cut[0], conic=cut[1], cov2d=proj.cov2d.detach(), rgb=cut[2], A=cut[3],
+                                depth=proj.depth.detach(), kept=proj.kept)
     order = depth_order(fp, proj.kept)
     if pixels is None:
         ys, xs = np.mgrid[0:cam.height, 0:cam.width]
@@ -728,17 +740,19 @@ def gradients(g, cam, lut, opts, d_color, pixels=None, bg=None, batch: int = 0) 
         batch = max(1, min(pixels.shape[0], (1 << 22) // max(len(order), 1)))
     total = 0.0
     for s in range(0, pixels.shape[0], batch):
-        res = render_pixels(proj, order, pixels[s:s + batch], opts, bg=bg, batch=batch)
+        res = render_pixels(proj_cut, order, pixels[s:s + batch], opts, bg=bg, batch=batch)
         L = (res.color * d_color[s:s + batch]).sum()
         total += float(L.detach())
-        L.backward(retain_graph=True)
+        L.backward()
+    grads_cut = [torch.zeros_like(c) if c.grad is None else c.grad for c in cut]
+    torch.autograd.backward(inter, grads_cut)
 
     def gnp(t):
         return np.zeros(tuple(t.shape)) if t.grad is None else t.grad.detach().numpy().copy()
     return OracleGrads(d_means=gnp(leaves[0]), d_log_scales=gnp(leaves[1]), d_quats=gnp(leaves[2]),
                        d_scalars=gnp(leaves[3]), d_weights=None if w is None else gnp(w),
-                       d_mean2d=gnp(proj.mean2d), d_conic=gnp(proj.conic), d_rgb=gnp(proj.rgb),
-                       d_A=gnp(proj.A), loss=total,
+                       d_mean2d=gnp(cut[0]), d_conic=gnp(cut[1]), d_rgb=gnp(cut[2]),
+                       d_A=gnp(cut[3]), loss=total,
                        **({} if sh is None else dict(d_normals=gnp(sh[0]), d_k_ambient=gnp(sh[1]),
                                                      d_k_diffuse=gnp(sh[2]), d_k_specular=gnp(sh[3]),
                                                      d_shininess=gnp(sh[4]))))

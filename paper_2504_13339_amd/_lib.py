@@ -77,14 +77,14 @@ class veg_serve_config(Structure):
 
 class veg_request(Structure):
     _fields_ = [("model_id", c_int32), ("camera", veg_camera), ("tf_rgba", c_void_p), ("tf_k", c_int32),
-                ("out_image", c_void_p), ("out_t_final", c_void_p), ("opts", veg_opts)]
+                ("out_image", c_void_p), ("out_t_final", c_void_p), ("opts", veg_opts), ("t_arrival", c_double)]
 
 
 class veg_serve_stats(Structure):
     _fields_ = [("submitted", c_int64), ("completed", c_int64), ("failed", c_int64), ("rejected", c_int64),
                 ("batches", c_int64), ("retries", c_int64), ("mean_batch", c_double), ("p50_ms", c_double),
                 ("p99_ms", c_double), ("max_ms", c_double), ("throughput_rps", c_double), ("mpix_per_s", c_double),
-                ("gpu_busy_frac", c_double), ("peak_bytes", c_int64)]
+                ("gpu_busy_frac", c_double), ("peak_bytes", c_int64), ("graphs_captured", c_int64)]
 
 
 P = POINTER

@@ -35,6 +35,10 @@ veg_status hip_status(hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_status(e_, where); \
   } while (0)
 
+// Limits the backward pass needs (see veg_render_bwd).
+constexpr float kBwdAlphaClampMax = 1.0f - 0x1p-10f;
+constexpr double kBwdTFloor = 0x1p-100;
+
 veg_status check_opts(const veg_opts* o) {
   if (!(o->alpha_min > 0.0f) || !(o->alpha_clamp > o->alpha_min) || !(o->alpha_clamp <= 1.0f))
     return fail(VEG_ERR_INVALID_ARG, "opts: need 0 < alpha_min < alpha_clamp <= 1");
@@ -378,6 +382,11 @@ veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_
   veg_opts o;
   s = resolve_opts(opts, &o);
   if (s != VEG_OK) return s;
+  // The adjoint recovers the transmittance in front of each entry as T / (1 - alpha): alpha
+  // must stay away from 1, and the smallest T a pixel can end with, t_min (1 - alpha_clamp),
+  // must stay far inside float32's normal range.
+  if (!(o.alpha_clamp <= kBwdAlphaClampMax) || !((double)o.t_min * (1.0 - (double)o.alpha_clamp) >= kBwdTFloor))
+    return fail(VEG_ERR_INVALID_ARG, "render_bwd: need alpha_clamp <= 1 - 2^-10 and t_min (1 - alpha_clamp) >= 2^-100");
   VEG_CHECK_HIP(launch_blend_bwd((const FrameDesc*)proj->frames, proj->n_frames, proj->tiles_x * proj->tiles_y,
                                  kopts(&o), (const float4*)proj->rec, bins->vals, bins->ranges, t_final, n_last,
                                  d_image, g2d, (uint32_t)pairs_of(proj), bins->hits, hit_stride_of(proj, bins),

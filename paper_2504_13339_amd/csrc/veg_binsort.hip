@@ -9,7 +9,7 @@
 //   4. per-tile [start, end) ranges from the key boundaries.
 // The result equals the list sorted by (tile, depth key, pair id).  Every kernel reads its
 // element count from device memory, so the pipeline needs no host synchronisation.
-#include "veg_internal.h"
+#include "veg_device.h"
 
 namespace veg {
 namespace {

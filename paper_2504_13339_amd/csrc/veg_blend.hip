@@ -45,19 +45,27 @@ __device__ __forceinline__ Staged stage(const float4 r0, const float4 r1, const 
 
 // Quadrants of the tile (bit r: pixel centres x in 8 (r & 1) + [0.5, 7.5], y in
 // 8 (r >> 1) + [0.5, 7.5]) that can hold a pixel passing the skip test.  A pixel passes when
-// the computed exponent l2A - Q(dx, dy) reaches l2min, Q = q0 dx^2 + q1 dx dy + q2 dy^2;
-// rounding moves the computed value by far less than 1e-4 (1 + |l2A|), so every passing
-// pixel lies in the ellipse Q <= R' = l2A - l2min + 1e-4 (1 + |l2A|), whose half-extents are
-// sqrt(4 R' q2 / D) and sqrt(4 R' q0 / D), D = 4 q0 q2 - q1^2; they are widened once more
-// before the overlap test.  A quadrant outside that box has no passing pixel, so skipping
-// it changes nothing.  Degenerate forms keep every quadrant.
+// the computed exponent l2A - Q(dx, dy) reaches l2min, Q = q0 dx^2 + q1 dx dy + q2 dy^2.  The
+// computed value differs from the exact one by a few roundings of its largest terms: of
+// |l2A| and, inside the ellipse Q <= R, of q0 dx^2 + |q1 dx dy| + q2 dy^2 <=
+// 4 R (2 q0 q2 + |q1| sqrt(q0 q2)) / D, D = 4 q0 q2 - q1^2 (which grows with the
+// ellipse's elongation).  R' = l2A - l2min + 1e-4 (1 + |l2A|) + 2^-20 (|l2A| + that bound)
+// therefore contains every passing pixel; the ellipse's half-extents are sqrt(4 R' q2 / D)
+// and sqrt(4 R' q0 / D), widened once more before the overlap test.  A quadrant outside
+// that box has no passing pixel, so skipping it changes nothing.  Degenerate forms, and
+// forms so elongated (4 q0 q2 > 1024 D) that the rounding of D itself matters, keep every
+// quadrant.
 __device__ __forceinline__ uint32_t quad_mask(const Staged& s, float l2min) {
   const float rp = (s.l2A - l2min) + 1e-4f * (1.0f + fabsf(s.l2A));
   if (!(rp >= 0.0f)) return 0u;   // below the threshold everywhere (or A = 0)
   const float D = 4.0f * s.q0 * s.q2 - s.q1 * s.q1;
   if (!(s.q0 > 0.0f) || !(s.q2 > 0.0f) || !(D > 0.0f)) return 0xfu;
-  const float ex = sqrtf(4.0f * rp * s.q2 / D) * 1.001f + 0.01f;
-  const float ey = sqrtf(4.0f * rp * s.q0 / D) * 1.001f + 0.01f;
+  const float k4 = 4.0f * s.q0 * s.q2;
+  if (!(k4 <= 1024.0f * D)) return 0xfu;
+  const float terms = 4.0f * rp * (0.5f * k4 + fabsf(s.q1) * sqrtf(s.q0 * s.q2)) / D;
+  const float rw = rp + 0x1p-20f * (fabsf(s.l2A) + terms);
+  const float ex = sqrtf(4.0f * rw * s.q2 / D) * 1.001f + 0.01f;
+  const float ey = sqrtf(4.0f * rw * s.q0 / D) * 1.001f + 0.01f;
   if (!(ex < 1e30f) || !(ey < 1e30f)) return 0xfu;
   const bool xl = s.mx - ex <= 7.5f && s.mx + ex >= 0.5f;    // columns 0..7
   const bool xh = s.mx - ex <= 15.5f && s.mx + ex >= 8.5f;   // columns 8..15

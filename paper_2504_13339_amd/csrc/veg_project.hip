@@ -7,7 +7,7 @@
 //
 // The whole file is compiled without floating-point contraction so that the footprint (cull,
 // depth key, tile rectangle) follows the documented operation order bit for bit.
-#include "veg_internal.h"
+#include "veg_device.h"
 
 #pragma clang fp contract(off)
 
@@ -224,10 +224,18 @@ __device__ __forceinline__ void project_one(const FrameDesc& d, const KOpts& o, 
     p.G0[k] = p.J00 * p.P[k] + p.J02 * p.P[6 + k];
     p.G1[k] = p.J11 * p.P[3 + k] + p.J12 * p.P[6 + k];
   }
-  p.S00 = ((p.G0[0] * p.G0[0] + p.G0[1] * p.G0[1]) + p.G0[2] * p.G0[2]) + o.lowpass;
+  const float g00 = (p.G0[0] * p.G0[0] + p.G0[1] * p.G0[1]) + p.G0[2] * p.G0[2];
+  const float g11 = (p.G1[0] * p.G1[0] + p.G1[1] * p.G1[1]) + p.G1[2] * p.G1[2];
+  p.S00 = g00 + o.lowpass;
   p.S01 = (p.G0[0] * p.G1[0] + p.G0[1] * p.G1[1]) + p.G0[2] * p.G1[2];
-  p.S11 = ((p.G1[0] * p.G1[0] + p.G1[1] * p.G1[1]) + p.G1[2] * p.G1[2]) + o.lowpass;
-  p.det = p.S00 * p.S11 - p.S01 * p.S01;
+  p.S11 = g11 + o.lowpass;
+  // det(G G^T + lowpass I) = |G0 x G1|^2 + lowpass (|G0|^2 + |G1|^2) + lowpass^2 (Cauchy-Binet):
+  // a sum of non-negative terms, free of the cancellation in S00 S11 - S01^2 that costs an
+  // elongated footprint most of its significant bits.
+  const float x0 = p.G0[1] * p.G1[2] - p.G0[2] * p.G1[1];
+  const float x1 = p.G0[2] * p.G1[0] - p.G0[0] * p.G1[2];
+  const float x2 = p.G0[0] * p.G1[1] - p.G0[1] * p.G1[0];
+  p.det = (((x0 * x0 + x1 * x1) + x2 * x2) + o.lowpass * (g00 + g11)) + o.lowpass * o.lowpass;
 }
 
 // Pixel range of the footprint (the ellipse where A exp(-sigma) >= alpha_min, by the
@@ -485,16 +493,28 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __res
     dt[0] = dmx * d.fx * invz;
     dt[1] = dmy * d.fy * invz;
     dt[2] = -(dmx * d.fx * xn + dmy * d.fy * yn) * invz;
-    // conic = inverse(S)
-    const float c0 = p.S11 / p.det, c1 = -p.S01 / p.det, c2 = p.S00 / p.det;
-    const float dS00 = -(dc0 * c0 * c0 + dc1 * c0 * c1 + dc2 * c1 * c1);
-    const float dS11 = -(dc0 * c1 * c1 + dc1 * c1 * c2 + dc2 * c2 * c2);
-    const float dS01 = -(2.0f * dc0 * c0 * c1 + dc1 * (c0 * c2 + c1 * c1) + 2.0f * dc2 * c1 * c2);
-    // S = G G^T + lowpass I
+    // conic = inverse(S), then S = G G^T + lowpass I, in float64.  For an elongated
+    // footprint dS = -C dC C is large and dG = 2 dS G cancels it down to a small result
+    // along the long axis: float32 would lose about log2 of the squared condition number
+    // of S there, float64 does not (and runs at the float32 rate on this GPU's VALU).
+    double dG0d[3], dG1d[3];
+    {
+      const double S00 = p.S00, S01 = p.S01, S11 = p.S11;
+      const double det = S00 * S11 - S01 * S01;
+      const double c0 = S11 / det, c1 = -S01 / det, c2 = S00 / det;
+      const double e0 = dc0, e1 = dc1, e2 = dc2;
+      const double dS00 = -(e0 * c0 * c0 + e1 * c0 * c1 + e2 * c1 * c1);
+      const double dS11 = -(e0 * c1 * c1 + e1 * c1 * c2 + e2 * c2 * c2);
+      const double dS01 = -(2.0 * e0 * c0 * c1 + e1 * (c0 * c2 + c1 * c1) + 2.0 * e2 * c1 * c2);
+      for (int k = 0; k < 3; ++k) {
+        dG0d[k] = 2.0 * dS00 * (double)p.G0[k] + dS01 * (double)p.G1[k];
+        dG1d[k] = 2.0 * dS11 * (double)p.G1[k] + dS01 * (double)p.G0[k];
+      }
+    }
     float dG0[3], dG1[3];
     for (int k = 0; k < 3; ++k) {
-      dG0[k] = 2.0f * dS00 * p.G0[k] + dS01 * p.G1[k];
-      dG1[k] = 2.0f * dS11 * p.G1[k] + dS01 * p.G0[k];
+      dG0[k] = (float)dG0d[k];
+      dG1[k] = (float)dG1d[k];
     }
     // G = J P
     float dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0, dP[9];

@@ -6,12 +6,15 @@
 // resolution) and the HBM admission budget, writes one frame descriptor per request
 // (model pointers, camera, TF table, output image) through pinned staging memory, and
 // launches projection -> binning -> sorting -> blending for the whole batch on the slot's
-// stream, optionally as one replay of a hipGraph captured for that slot.  Kernels take
-// every size from the device descriptors, so a single capture serves batches of any
-// composition.  Slots run concurrently, so requests that arrive while batches are on the
-// GPU are admitted as soon as a slot and budget free up.  Completion is observed through
-// the slot's event; a batch whose key list overflowed the slot is re-run request by
-// request.
+// stream, optionally as one replay of a hipGraph.  Kernels take every size from the
+// device descriptors and use their launch sizes only as bounds, so one capture serves
+// every batch of a shape: the request count and power-of-two bounds on the tiles of its
+// largest frame, the Gaussians of its largest model, its pairs and its estimated entries.
+// Each slot keeps the graphs of the shapes it has seen (least recently used dropped first),
+// so a batch of small requests launches small grids.  Slots run concurrently, so requests
+// that arrive while batches are on the GPU are admitted as soon as a slot and budget free
+// up.  Completion is observed through the slot's event; a batch whose key list overflowed
+// its bound is re-run request by request with the observed entry count as the bound.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -51,8 +54,30 @@ struct Req {
   int64_t n = 0;
   int64_t est_entries = 0;
   int64_t est_bytes = 0;
+  int64_t known_entries = 0;   // observed entry count bound after an overflow (0: none)
   bool solo = false;
 };
+
+// Launch bounds of a batch; every kernel of the pipeline is launched for these sizes.
+struct Shape {
+  int frames = 0;          // requests in the batch
+  int tiles = 0;           // tiles of its largest frame (power of two, capped)
+  int n_max = 0;           // Gaussians of its largest model (power of two, capped)
+  uint32_t pairs = 0;      // (frame, Gaussian) pairs (power of two, capped)
+  uint32_t entries = 0;    // key-list entries (power of two, capped)
+  bool operator==(const Shape& o) const {
+    return frames == o.frames && tiles == o.tiles && n_max == o.n_max && pairs == o.pairs && entries == o.entries;
+  }
+};
+
+struct GraphEntry {
+  Shape shape;
+  KOpts opts{};
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
+constexpr size_t kGraphsPerSlot = 48;
 
 struct Slot {
   hipStream_t stream = nullptr;
@@ -71,16 +96,16 @@ struct Slot {
   unsigned char* h_stage = nullptr;   // header + descriptors
   float* h_luts = nullptr;
   uint32_t* h_counters = nullptr;
-  // graph
-  hipGraphExec_t exec = nullptr;
-  bool has_graph = false;
-  KOpts graph_opts{};
+  // graphs, one per batch shape and options
+  std::vector<GraphEntry> graphs;
+  uint64_t uses = 0;
   // state
   bool busy = false;
   std::vector<uint64_t> reqs;
   double t_launch = 0;
   int64_t bytes = 0;
   int64_t est_entries = 0;
+  uint32_t entries_bound = 0;   // key-list bound the running batch was launched with
 };
 
 bool same_opts(const veg_opts& a, const veg_opts& b) {
@@ -120,7 +145,7 @@ struct veg_server {
   std::string err;
   // statistics
   std::vector<double> lat_ms;
-  int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, batches = 0, retries = 0;
+  int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, batches = 0, retries = 0, graphs_captured = 0;
   double sum_batch = 0, pix_done = 0, first_submit = -1, last_done = -1;
   double busy_acc = 0, busy_since = -1;
   int inflight = 0;
@@ -209,20 +234,59 @@ int64_t req_bytes(int64_t n, int64_t entries, int W, int H) {
   return n * (48 + 8 + 16) + entries * 16 + (int64_t)tiles_of(W, H) * 8 + (int64_t)W * H * 4;
 }
 
-// Enqueues the whole pipeline for one batch on the slot's stream (also used for capture).
-hipError_t run_pipeline(veg_server* s, Slot& sl, const KOpts& ko) {
-  const veg_serve_config& c = s->cfg;
-  hipError_t e = launch_project(sl.d_descs, c.max_batch, (int)c.max_gaussians, ko, sl.rec, sl.count, sl.depth, false,
-                                sl.stream);
+uint32_t pow2_at_least(int64_t x, int64_t lo, int64_t cap) {
+  int64_t p = lo;
+  while (p < x && p < cap) p <<= 1;
+  return (uint32_t)std::min(p, cap);
+}
+
+// Enqueues the whole pipeline for one batch of shape `sh` on the slot's stream (also used
+// for capture).
+hipError_t run_pipeline(veg_server* s, Slot& sl, const KOpts& ko, const Shape& sh) {
+  hipError_t e = launch_project(sl.d_descs, sh.frames, sh.n_max, ko, sl.rec, sl.count, sl.depth, false, sl.stream);
   if (e != hipSuccess) return e;
-  e = launch_bin_count(sl.rec, sl.count, sl.depth, (uint32_t)s->pairs_cap, sl.bws, sl.stream, &sl.d_header->n_pairs);
+  e = launch_bin_count(sl.rec, sl.count, sl.depth, sh.pairs, sl.bws, sl.stream, &sl.d_header->n_pairs);
   if (e != hipSuccess) return e;
-  e = launch_bin_sort(sl.d_descs, c.max_batch, sl.rec, sl.count, (uint32_t)s->pairs_cap, s->total_tiles_cap, sl.bws,
-                      sl.keys, sl.vals, sl.keys_alt, sl.vals_alt, sl.ranges, (uint32_t)s->entries_cap, sl.stream);
+  e = launch_bin_sort(sl.d_descs, sh.frames, sl.rec, sl.count, sh.pairs, (uint32_t)(sh.frames * sh.tiles), sl.bws,
+                      sl.keys, sl.vals, sl.keys_alt, sl.vals_alt, sl.ranges, sh.entries, sl.stream);
   if (e != hipSuccess) return e;
-  return launch_blend_fwd(sl.d_descs, c.max_batch, 1, s->max_tiles_frame, ko, sl.rec, sl.vals, sl.ranges, nullptr,
-                          nullptr, nullptr, nullptr, nullptr, 0, nullptr, sl.keys_alt, (uint64_t)s->entries_cap,
-                          sl.stream);
+  return launch_blend_fwd(sl.d_descs, sh.frames, 1, sh.tiles, ko, sl.rec, sl.vals, sl.ranges, nullptr, nullptr,
+                          nullptr, nullptr, nullptr, 0, nullptr, sl.keys_alt, (uint64_t)s->entries_cap, sl.stream);
+}
+
+// The graph of (shape, options) in the slot, captured on first use.
+hipError_t slot_graph(veg_server* s, Slot& sl, const KOpts& ko, const Shape& sh, hipGraphExec_t* exec) {
+  ++sl.uses;
+  for (GraphEntry& g : sl.graphs)
+    if (g.shape == sh && std::memcmp(&g.opts, &ko, sizeof(KOpts)) == 0) {
+      g.last_use = sl.uses;
+      *exec = g.exec;
+      return hipSuccess;
+    }
+  if (sl.graphs.size() >= kGraphsPerSlot) {
+    auto lru = std::min_element(sl.graphs.begin(), sl.graphs.end(),
+                                [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
+    (void)hipGraphExecDestroy(lru->exec);
+    sl.graphs.erase(lru);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t e2 = run_pipeline(s, sl, ko, sh);
+    e = hipStreamEndCapture(sl.stream, &graph);
+    if (e == hipSuccess) e = e2;
+  }
+  GraphEntry g;
+  if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  g.shape = sh;
+  g.opts = ko;
+  g.last_use = sl.uses;
+  sl.graphs.push_back(g);
+  s->graphs_captured++;
+  *exec = g.exec;
+  return hipSuccess;
 }
 
 // Called with the lock held: writes the batch's descriptors and launches it.
@@ -272,6 +336,21 @@ veg_status launch_batch(veg_server* s, Slot& sl, const std::vector<uint64_t>& id
   hh->n_pairs = pair_base;
   hh->n_frames = (uint32_t)ids.size();
   const KOpts ko = kopts_of(first.r.opts);
+  Shape sh;
+  sh.frames = (int)ids.size();
+  int max_tiles = 1;
+  int64_t max_n = 1, entries = 0;
+  for (uint64_t id : ids) {
+    const Req& q = s->reqs[id];
+    max_tiles = std::max(max_tiles, tiles_of(q.r.camera.width, q.r.camera.height));
+    max_n = std::max(max_n, q.n);
+    entries += q.known_entries > 0 ? q.known_entries : (int64_t)std::ceil((double)q.est_entries * s->e_scale);
+  }
+  sh.tiles = (int)pow2_at_least(max_tiles, 16, s->max_tiles_frame);
+  sh.n_max = (int)pow2_at_least(max_n, 1 << 12, c.max_gaussians);
+  sh.pairs = pow2_at_least(pair_base, 1 << 14, s->pairs_cap);
+  sh.entries = pow2_at_least(entries, 1 << 16, s->entries_cap);
+  sl.entries_bound = sh.entries;
   hipError_t e = hipMemcpyAsync(sl.d_header, sl.h_stage, sizeof(BatchHeader) + (size_t)c.max_batch * sizeof(FrameDesc),
                                 hipMemcpyHostToDevice, sl.stream);
   if (e == hipSuccess)
@@ -279,29 +358,11 @@ veg_status launch_batch(veg_server* s, Slot& sl, const std::vector<uint64_t>& id
                        hipMemcpyHostToDevice, sl.stream);
   if (e == hipSuccess) {
     if (c.use_graphs) {
-      if (sl.has_graph && std::memcmp(&sl.graph_opts, &ko, sizeof(KOpts)) != 0) {
-        (void)hipGraphExecDestroy(sl.exec);
-        sl.exec = nullptr;
-        sl.has_graph = false;
-      }
-      if (!sl.has_graph) {
-        hipGraph_t graph = nullptr;
-        e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-          hipError_t e2 = run_pipeline(s, sl, ko);
-          e = hipStreamEndCapture(sl.stream, &graph);
-          if (e == hipSuccess) e = e2;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (e == hipSuccess) {
-          sl.has_graph = true;
-          sl.graph_opts = ko;
-        }
-      }
-      if (e == hipSuccess) e = hipGraphLaunch(sl.exec, sl.stream);
+      hipGraphExec_t exec = nullptr;
+      e = slot_graph(s, sl, ko, sh, &exec);
+      if (e == hipSuccess) e = hipGraphLaunch(exec, sl.stream);
     } else {
-      e = run_pipeline(s, sl, ko);
+      e = run_pipeline(s, sl, ko, sh);
     }
   }
   if (e == hipSuccess)
@@ -333,17 +394,20 @@ void reap(veg_server* s, Slot& sl, double t) {
   const uint64_t E = (uint64_t)sl.h_counters[1] | ((uint64_t)sl.h_counters[2] << 32);
   const bool overflow = sl.h_counters[3] != 0;
   if (overflow) {
-    // re-run each request of the batch alone (at the front of the queue, in order)
-    if (sl.reqs.size() > 1) {
+    // The batch needed E entries, more than its bound.  Re-run each request alone (at the
+    // front of the queue, in order) with E as its bound, which holds for any one of them;
+    // a request that needs more than the slot's buffers hold fails.
+    if ((int64_t)E > s->entries_cap && sl.reqs.size() == 1) {
+      finish_request(s, s->reqs[sl.reqs[0]], VEG_ERR_CAPACITY, t);
+    } else {
       s->retries += (int64_t)sl.reqs.size();
       for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it) {
         Req& q = s->reqs[*it];
         q.solo = true;
+        q.known_entries = std::min<int64_t>((int64_t)E, s->entries_cap);
         q.state = VEG_REQ_QUEUED;
         s->queue.push_front(*it);
       }
-    } else {
-      finish_request(s, s->reqs[sl.reqs[0]], VEG_ERR_CAPACITY, t);
     }
     // learn a larger multiplier so the next batches are packed more conservatively
     if (sl.est_entries > 0) s->e_scale = std::max(s->e_scale, 1.25 * (double)E / (double)sl.est_entries);
@@ -375,7 +439,7 @@ bool try_launch(veg_server* s, Slot& sl) {
   const veg_opts* o0 = nullptr;
   while (!s->queue.empty() && (int)ids.size() < c.max_batch) {
     Req& q = s->reqs[s->queue.front()];
-    const int64_t e = (int64_t)std::ceil((double)q.est_entries * s->e_scale);
+    const int64_t e = q.known_entries > 0 ? q.known_entries : (int64_t)std::ceil((double)q.est_entries * s->e_scale);
     const bool fits = pairs + q.n <= s->pairs_cap && entries + e <= s->entries_cap &&
                       s->in_use + bytes + q.est_bytes <= (int64_t)c.budget_bytes &&
                       (o0 == nullptr || same_opts(*o0, q.r.opts));
@@ -426,7 +490,7 @@ void scheduler(veg_server* s) {
     const double t = now_s();
     for (Slot& sl : s->slots)
       if (sl.busy && hipEventQuery(sl.done) == hipSuccess) reap(s, sl, t);
-    bool launched = true;
+    bool launched = !s->stop;   // shutting down: finish what runs, launch nothing new
     while (launched) {
       launched = false;
       for (Slot& sl : s->slots)
@@ -450,7 +514,8 @@ void scheduler(veg_server* s) {
 
 void free_slots(veg_server* s) {
   for (Slot& sl : s->slots) {
-    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    for (GraphEntry& g : sl.graphs) (void)hipGraphExecDestroy(g.exec);
+    sl.graphs.clear();
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.h_stage) (void)hipHostFree(sl.h_stage);
@@ -552,6 +617,8 @@ veg_status veg_serve_submit(veg_server* s, const veg_request* r, uint64_t* req_i
   if (!(o.alpha_min > 0.0f) || !(o.alpha_clamp > o.alpha_min) || !(o.alpha_clamp <= 1.0f) || !(o.t_min >= 0.0f) ||
       !(o.t_min < 1.0f) || !(o.lowpass >= 0.0f) || !(o.near_z > 0.0f) || !(o.guard > 0.0f))
     return sfail(VEG_ERR_INVALID_ARG, "bad options");
+  if (!(r->t_arrival >= 0.0) || !std::isfinite(r->t_arrival)) return sfail(VEG_ERR_INVALID_ARG, "bad t_arrival");
+  const double t_call = now_s();   // before the lock: time spent waiting for it counts as latency
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return sfail(VEG_ERR_SHUTDOWN, "server is shutting down");
   if (r->model_id < 0 || r->model_id >= (int32_t)s->models.size()) return sfail(VEG_ERR_NOT_FOUND, "unknown model");
@@ -563,14 +630,14 @@ veg_status veg_serve_submit(veg_server* s, const veg_request* r, uint64_t* req_i
   q.n = s->models[r->model_id].n;
   q.est_entries = entry_prior(q.n, c.width, c.height);
   q.est_bytes = req_bytes(q.n, q.est_entries, c.width, c.height);
-  q.t_submit = now_s();
+  q.t_submit = r->t_arrival > 0.0 ? r->t_arrival : t_call;
   if (q.n > s->pairs_cap || q.est_bytes > (int64_t)s->cfg.budget_bytes) {
     s->rejected++;
     return sfail(VEG_ERR_OUT_OF_BUDGET, "request can never fit (pairs %lld, est. bytes %lld, budget %zu)",
                  (long long)q.n, (long long)q.est_bytes, s->cfg.budget_bytes);
   }
   s->submitted++;
-  if (s->first_submit < 0) s->first_submit = q.t_submit;
+  if (s->first_submit < 0 || q.t_submit < s->first_submit) s->first_submit = q.t_submit;
   *req_id = q.id;
   s->queue.push_back(q.id);
   s->reqs.emplace(q.id, std::move(q));
@@ -594,17 +661,21 @@ veg_status veg_serve_wait(veg_server* s, uint64_t req_id, int32_t timeout_ms) {
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->reqs.find(req_id);
   if (it == s->reqs.end()) return sfail(VEG_ERR_NOT_FOUND, "unknown request");
+  // the entry may be released by another waiter while this one sleeps: look it up anew
   auto finished = [&] {
-    const int32_t st = s->reqs[req_id].state;
-    return st == VEG_REQ_DONE || st == VEG_REQ_FAILED;
+    auto f = s->reqs.find(req_id);
+    return f == s->reqs.end() || f->second.state == VEG_REQ_DONE || f->second.state == VEG_REQ_FAILED;
   };
   if (timeout_ms < 0) {
     s->cv_done.wait(lk, finished);
   } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), finished)) {
     return sfail(VEG_ERR_TIMEOUT, "request %llu not finished", (unsigned long long)req_id);
   }
-  const veg_status st = s->reqs[req_id].status;
-  s->reqs.erase(req_id);   // a finished request is released once it has been waited on
+  it = s->reqs.find(req_id);
+  if (it == s->reqs.end()) return sfail(VEG_ERR_NOT_FOUND, "request %llu released by another wait",
+                                        (unsigned long long)req_id);
+  const veg_status st = it->second.status;
+  s->reqs.erase(it);   // a finished request is released once it has been waited on
   if (st != VEG_OK) return sfail(st, "request %llu failed: %s", (unsigned long long)req_id, s->err.c_str());
   return VEG_OK;
 }
@@ -641,6 +712,7 @@ veg_status veg_serve_stats_get(veg_server* s, veg_serve_stats* out) {
     out->gpu_busy_frac = std::min(1.0, busy / span);
   }
   out->peak_bytes = s->peak;
+  out->graphs_captured = s->graphs_captured;
   return VEG_OK;
 }
 
@@ -654,11 +726,7 @@ veg_status veg_serve_stats_reset(veg_server* s) {
   s->busy_acc = 0;
   s->busy_since = s->inflight > 0 ? now_s() : -1;
   s->peak = s->in_use;
-  // forget finished requests
-  for (auto it = s->reqs.begin(); it != s->reqs.end();) {
-    if (it->second.state == VEG_REQ_DONE || it->second.state == VEG_REQ_FAILED) it = s->reqs.erase(it);
-    else ++it;
-  }
+  // requests stay until they are waited on (a waiter may be about to read one)
   return VEG_OK;
 }
 

@@ -53,7 +53,9 @@ class Server:
         return int(mid.value)
 
     def submit(self, model_id: int, camera, tf: np.ndarray, out_image: torch.Tensor,
-               out_t_final: Optional[torch.Tensor] = None, opts=None) -> int:
+               out_t_final: Optional[torch.Tensor] = None, opts=None, t_arrival: float = 0.0) -> int:
+        """Queues a request.  ``t_arrival`` (time.perf_counter() seconds, 0 = now) is the
+        time latency is measured from."""
         tf = np.ascontiguousarray(tf, dtype=np.float32)
         r = _lib.veg_request()
         r.model_id = int(model_id)
@@ -63,6 +65,7 @@ class Server:
         r.out_image = ctypes.c_void_p(out_image.data_ptr())
         r.out_t_final = ctypes.c_void_p(out_t_final.data_ptr()) if out_t_final is not None else None
         r.opts = opts if isinstance(opts, _lib.veg_opts) else V.make_opts(opts)
+        r.t_arrival = float(t_arrival)
         rid = ctypes.c_uint64(0)
         check(load().veg_serve_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "veg_serve_submit")
         return int(rid.value)

@@ -55,10 +55,11 @@ def stratified_pixels(rng, fp, cam, n):
     return px.astype(np.int32), int(occ.max())
 
 
-# Largest fraction of compared pixels allowed a decision-margin flag.  Twice the worst
-# fraction measured over every parity case of the GPU suite (tests report theirs in the
-# session summary; see PARITY_STATS).
-MAX_FLAG_FRAC = 2e-2
+# Largest fraction of compared pixels allowed a decision-margin flag: twice the worst
+# fraction measured over every parity case of the GPU suite (0.0078, 1024 stratified pixels
+# of a 1M-Gaussian frame, where the fullest tile's pixels carry many near-threshold
+# evaluations).  Tests report theirs in the session summary (PARITY_STATS).
+MAX_FLAG_FRAC = 1.6e-2
 
 # One record per image comparison: (test id, pixels, unflagged max-abs, flagged fraction,
 # largest slack, largest error on a flagged pixel); printed at the end of the session.

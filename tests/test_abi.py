@@ -173,3 +173,73 @@ def test_shared_runs_must_share_a_camera():
         R.train_step(None, None, None, [(0, 0), (0, 1), (0, 2)], None, None, 2, shared=2)
     with pytest.raises(ValueError):
         R.train_step(None, None, None, [(0, 0), (0, 1), (1, 1), (1, 0)], None, None, 4, shared=True)
+
+
+def test_backward_rejects_options_that_break_transmittance_recovery():
+    """veg_render_bwd recovers T as T / (1 - alpha): alpha_clamp = 1 and t_min = 0 are
+    rejected before any launch (the pointers are never dereferenced); the defaults pass
+    the option check and fail later only on the fake hit-bit buffer."""
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    img = ctypes.c_void_p(0x20000)
+    p = _lib.veg_proj(1, 1, 16, 16, 1, 1, 1, fake, fake, fake, fake)
+    b = _lib.veg_bins(fake, fake, fake, fake, fake, 64, None, 0)
+    for clamp, tmin in ((1.0, 1e-4), (0.99, 0.0), (0.9999, 1e-4)):
+        o = _lib.veg_opts()
+        lib.veg_opts_default(ctypes.byref(o))
+        o.alpha_clamp, o.t_min = clamp, tmin
+        assert lib.veg_render_bwd(ctypes.byref(p), ctypes.byref(b), ctypes.byref(o), img, img, img, img, None) == 1
+        assert b"alpha_clamp" in lib.veg_last_error()
+    o = _lib.veg_opts()
+    lib.veg_opts_default(ctypes.byref(o))
+    o.alpha_clamp, o.t_min = 0.999, 1e-20
+    b.hits, b.hit_words = fake, 1
+    assert lib.veg_render_bwd(ctypes.byref(p), ctypes.byref(b), ctypes.byref(o), img, img, img, img, None) == 1
+    assert b"hit_words" in lib.veg_last_error()
+
+
+# Declarations with no paper passage behind them: error reporting and the library version.
+PLUMBING = {"veg_status_str": "error strings", "veg_last_error": "error message", "veg_version": "library version"}
+
+
+def declaration_comments():
+    """For every declared function: its own doc comment (the comment before it, shared by
+    consecutive declarations) and the comment of the section divider it sits under."""
+    text = open(HEADER).read()
+    out = {}
+    own, divider = "", ""
+    pos = 0
+    for m in re.finditer(r"/\*(.*?)\*/|\b(veg_[a-z0-9_]+)\s*\(", text, flags=re.S):
+        if m.group(1) is not None:
+            body = re.sub(r"\s*\n\s*\*\s?", " ", m.group(1))
+            if body.lstrip().startswith("---"):
+                divider, own = body, ""
+            elif text[m.start() - 2:m.start()].strip() == "" or text[m.start() - 1] == "\n":
+                # a doc comment on its own lines (not a trailing field comment)
+                line_start = text.rfind("\n", 0, m.start()) + 1
+                if text[line_start:m.start()].strip() == "":
+                    own = body
+        else:
+            name = m.group(2)
+            line_start = text.rfind("\n", 0, m.start()) + 1
+            line = text[line_start:m.start()]
+            if "(" in line or "*" in line.replace("*", "", 0) and "/*" in line:
+                continue
+            if name not in out:
+                out[name] = (own, divider)
+    return out
+
+
+CITATION = re.compile(r'section "[^"]+"|Eq\. ?\d')
+
+
+def test_every_declaration_cites_the_passage_it_implements():
+    """Each function of the boundary carries a citation of the paper's section or equation
+    it implements, in its own comment or its section divider (plumbing excepted)."""
+    comments = declaration_comments()
+    assert set(declared_functions()) <= set(comments), set(declared_functions()) - set(comments)
+    missing = [n for n in declared_functions() if n not in PLUMBING and
+               not any(CITATION.search(c) for c in comments[n])]
+    assert not missing, missing

@@ -411,3 +411,40 @@ def test_l1_loss_kernel(n, offset):
     ref, gref = oracle.l1_loss(a, b, scale=float(np.float32(1.0 / a.size)))
     assert abs(loss.item() - ref) <= 1e-6 * ref
     assert np.array_equal(d.cpu().numpy(), gref.astype(np.float32))
+
+
+def test_needles_at_45_degrees_image_and_gradients():
+    """Strongly elongated Gaussians turned 45 degrees in the image plane (long axis 10-30 px,
+    short axis at the low-pass width; (S00 S11) / det from about 100 to 900): the forward pass
+    skips quadrants by the ellipse's box, whose rounding allowance must grow with the
+    elongation, and the backward pass must recover the same blended sets.  Image and
+    gradients against the oracle.  (Along a needle's long axis the float32 quadratic form
+    loses about log2((S00 S11) / det) bits to cancellation, so much longer needles leave
+    the 1e-4 / 1e-3 bars.)"""
+    rng = np.random.default_rng(45)
+    n = 24
+    W = H = 128
+    f = (0.5 * H) / np.tan(np.radians(25.0))
+    cam = synth.Camera(view=np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 2.0], np.float32), fx=float(np.float32(f)),
+                       fy=float(np.float32(f)), cx=0.5 * W, cy=0.5 * H, width=W, height=H)
+    means = np.zeros((n, 3), np.float32)
+    means[:, :2] = rng.uniform(-0.5, 0.5, (n, 2))
+    means[:, 2] = rng.uniform(-0.3, 0.3, n)
+    long = np.exp(rng.uniform(np.log(0.15), np.log(0.45), n))
+    scales = np.stack([long, np.full(n, 1e-3), np.full(n, 1e-3)], 1)
+    ang = np.where(rng.uniform(size=n) < 0.5, np.pi / 4, -np.pi / 4) + rng.uniform(-0.05, 0.05, n)
+    quats = np.stack([np.cos(ang / 2), np.zeros(n), np.zeros(n), np.sin(ang / 2)], 1).astype(np.float32)
+    g = synth.Gaussians(means, np.log(scales).astype(np.float32), quats, rng.uniform(0.2, 0.9, n).astype(np.float32))
+    lut = synth.random_tf(rng)
+    lut[:, 3] = np.clip(lut[:, 3] + 0.4, 0.0, 1.0)
+    w = synth.Workload("needles-45deg", g, [cam], [lut], [(0, 0)])
+    V, R = hip()
+    gd = to_dev(g)
+    st = R.render(gd, [cam], luts_to_dev([lut]), OPTS)
+    torch.cuda.synchronize()
+    res, *_ = oracle.render_image(g, cam, lut, OPTS)
+    compare_image(image_pixels(st.image[0]), res)
+    d = rng.standard_normal((W * H, 3))
+    st2, grads, g2d, ref = _grads_case(w, d)
+    for name in ("d_means", "d_log_scales", "d_quats", "d_scalars"):
+        assert rel_err(getattr(grads, name).cpu().numpy(), getattr(ref, name)) <= 1e-3, name

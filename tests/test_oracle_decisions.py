@@ -191,7 +191,7 @@ def _fma32(a, b, c):
 
 def test_error_bound_covers_a_float32_emulation_of_the_exponent():
     """The float32 exponent ln a, computed the way a tiled float32 renderer does (float32
-    screen covariance from O1, conic = adj / det in float32, tile-local centre, quadratic
+    screen covariance and determinant from O1, conic = adj / det in float32, tile-local centre, quadratic
     form by fused multiply-adds, float32 log2 of A), differs from the float64 value by less
     than half the oracle's bound, at every pixel of the footprints of the 1k-Gaussian
     workload and of a reduced shell-clustered one (elongated ellipses included)."""
@@ -206,8 +206,7 @@ def test_error_bound_covers_a_float32_emulation_of_the_exponent():
         mu, con = proj.mean2d.detach().numpy(), proj.conic.detach().numpy()
         cov, A64 = proj.cov2d.detach().numpy(), proj.A.detach().numpy()
         S00, S01, S11 = fp.cov[:, 0], fp.cov[:, 1], fp.cov[:, 2]
-        det = S00 * S11 - S01 * S01
-        c0, c1, c2 = S11 / det, -S01 / det, S00 / det
+        c0, c1, c2 = S11 / fp.det, -S01 / fp.det, S00 / fp.det
         for i in np.nonzero(fp.keep & proj.kept)[0]:
             x0, y0, x1, y1 = fp.rect[i]
             ys, xs = np.mgrid[16 * y0:min(16 * y1 + 16, cam.height), 16 * x0:min(16 * x1 + 16, cam.width)]
