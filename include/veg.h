@@ -315,6 +315,24 @@ veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32
  * Errors: VEG_ERR_INVALID_ARG (workspace too small, dst NULL or misaligned), VEG_ERR_HIP. */
 veg_status veg_bin_status(void* ws, size_t ws_bytes, int64_t* dst, veg_stream_t stream);
 
+/* veg_bin_static -- veg_bin_count followed by veg_bin_sort and veg_bin_status in one
+ * call that allocates nothing and takes no workspace: for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Its scratch is a fixed device array of the library (13 MiB per GPU, held
+ * until the process ends), which limits a call to n_frames * n <= VEG_BIN_STATIC_MAX_PAIRS
+ * pairs (e.g. one frame of a model of up to 262,144 Gaussians); larger calls fail with
+ * VEG_ERR_INVALID_ARG before anything is enqueued.  The output is bit for bit that of
+ * veg_bin_count + veg_bin_sort with a caller workspace.
+ *   bins     as for veg_bin_sort
+ *   status   device int64 [2], 8-byte aligned: (entries E, overflow flag), as veg_bin_status
+ *            writes them, ordered on `stream` after the sort
+ * Every call on one GPU shares that GPU's array, whose contents the next call overwrites
+ * (it clears what must start at zero itself): calls ordered on one stream are safe, calls
+ * that overlap on one GPU (different streams or host threads without ordering) race.
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+#define VEG_BIN_STATIC_MAX_PAIRS 262144
+veg_status veg_bin_static(const veg_proj* proj, const veg_bins* bins, int64_t* status, veg_stream_t stream);
+
 /* ----------------------------------------------------------------------------------
  * Forward and backward blending  (Eq. 1 and its adjoint)
  * ---------------------------------------------------------------------------------- */

@@ -102,6 +102,7 @@ _SIGS = {
     "veg_bin_sort": (c_int, [P(veg_proj), c_void_p, c_size_t, P(veg_bins), c_void_p]),
     "veg_bin_overflow": (c_int, [c_void_p, c_size_t, P(c_int64), P(c_int32), c_void_p]),
     "veg_bin_status": (c_int, [c_void_p, c_size_t, c_void_p, c_void_p]),
+    "veg_bin_static": (c_int, [P(veg_proj), P(veg_bins), c_void_p, c_void_p]),
     "veg_bin_hit_words": (c_int64, [c_int64, c_int64]),
     "veg_render_fwd": (c_int, [P(veg_proj), P(veg_bins), P(veg_opts), c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p]),

@@ -296,6 +296,41 @@ veg_status veg_bin_sort(const veg_proj* proj, void* ws, size_t ws_bytes, const v
   return VEG_OK;
 }
 
+veg_status veg_bin_static(const veg_proj* proj, const veg_bins* bins, int64_t* status, veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  if (!bins) return fail(VEG_ERR_INVALID_ARG, "bins is NULL");
+  if (bins->capacity < 0 || bins->capacity >= ((int64_t)1 << 31))
+    return fail(VEG_ERR_INVALID_ARG, "bins: capacity must be in [0, 2^31)");
+  if (bins->capacity > 0 && (!bins->keys || !bins->vals || !bins->keys_alt || !bins->vals_alt))
+    return fail(VEG_ERR_INVALID_ARG, "bins: NULL key buffer");
+  if (!bins->ranges) return fail(VEG_ERR_INVALID_ARG, "bins: NULL ranges");
+  if (!status || ((uintptr_t)status & 7u)) return fail(VEG_ERR_INVALID_ARG, "bin_static: NULL or misaligned status");
+  const size_t pairs = pairs_of(proj);
+  if ((int64_t)pairs > VEG_BIN_STATIC_MAX_PAIRS || bin_ws_bytes((int64_t)pairs) > kStaticBinBytes)
+    return fail(VEG_ERR_INVALID_ARG, "bin_static: %zu pairs exceed the library scratch's limit of %d pairs", pairs,
+                (int)VEG_BIN_STATIC_MAX_PAIRS);
+  void* ws = nullptr;
+  VEG_CHECK_HIP(static_bin_scratch(&ws), "veg_bin_static: scratch");
+  BinWs w;
+  carve_bin_ws(ws, (int64_t)pairs, &w);
+  hipStream_t st = (hipStream_t)stream;
+  if (pairs > 0) {
+    VEG_CHECK_HIP(launch_bin_count((const float4*)proj->rec, proj->count, proj->depth, (uint32_t)pairs, w, st),
+                  "veg_bin_static: count");
+  } else {
+    VEG_CHECK_HIP(launch_fill_u32(w.counters, 64, 0u, st), "veg_bin_static: count");
+  }
+  VEG_CHECK_HIP(launch_bin_sort((const FrameDesc*)proj->frames, proj->n_frames, (const float4*)proj->rec, proj->count,
+                                (uint32_t)pairs, (uint32_t)proj->total_tiles, w, bins->keys, bins->vals,
+                                bins->keys_alt, bins->vals_alt, bins->ranges,
+                                pairs > 0 ? (uint32_t)bins->capacity : 0u, st),
+                "veg_bin_static: sort");
+  VEG_CHECK_HIP(launch_bin_status(w.counters, status, st), "veg_bin_static: status");
+  return VEG_OK;
+}
+
 veg_status veg_bin_overflow(void* ws, size_t ws_bytes, int64_t* n_entries, int32_t* overflow, veg_stream_t stream) {
   g_err.clear();
   if (!ws || ws_bytes < bin_ws_bytes(1)) return fail(VEG_ERR_INVALID_ARG, "bin workspace too small");

@@ -9,6 +9,8 @@
 //   4. per-tile [start, end) ranges from the key boundaries.
 // The result equals the list sorted by (tile, depth key, pair id).  Every kernel reads its
 // element count from device memory, so the pipeline needs no host synchronisation.
+#include <mutex>
+
 #include "veg_device.h"
 
 namespace veg {
@@ -645,6 +647,29 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, co
 }
 
 }  // namespace
+
+// Binning scratch of veg_bin_static, for callers that cannot allocate: one copy per GPU,
+// held until the process ends.  Host code never uses this name as an address (on the host
+// it is only a stand-in for the symbol); static_bin_scratch looks up each device's copy.
+static __device__ __align__(256) unsigned char scratch[kStaticBinBytes];
+
+hipError_t static_bin_scratch(void** out) {
+  static std::mutex mu;
+  static void* ptrs[kStaticBinMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kStaticBinMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the current device's copy
+    if (e != hipSuccess) return e;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
+}
 
 size_t bin_ws_bytes(int64_t pairs) {
   const size_t p = (size_t)(pairs > 0 ? pairs : 1);

@@ -122,6 +122,13 @@ constexpr int kMaxHistBlocks = kMaxScanBlocks > kMaxSortBlocks ? kMaxScanBlocks 
 size_t bin_ws_bytes(int64_t pairs);
 void carve_bin_ws(void* ws, int64_t pairs, BinWs* out);
 
+// The library's own binning scratch (veg_bin_static): room for the workspace of
+// VEG_BIN_STATIC_MAX_PAIRS pairs (bin_ws_bytes(2^18) is 12.07 MiB), one copy per device.
+constexpr size_t kStaticBinBytes = (size_t)13 << 20;
+constexpr int kStaticBinMaxDevices = 64;
+// Address of the current device's copy (looked up once per device, then cached).
+hipError_t static_bin_scratch(void** out);
+
 // n_pairs bounds the pair count; when n_pairs_dev is non-null the actual count is read
 // from device memory (capacity mode, used by the server's captured graphs).
 hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,

@@ -240,6 +240,16 @@ def veg_bin_status(ws: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Te
     return dst
 
 
+def veg_bin_static(proj: Proj, bins: Bins, status: torch.Tensor, stream=None) -> Bins:
+    """veg_bin_count + veg_bin_sort + veg_bin_status in one call with the library's own
+    scratch (nothing allocated, no workspace); status (device int64 [2]) <- (E, overflow)."""
+    if status.dtype != torch.int64 or status.numel() < 2 or not status.is_contiguous():
+        raise ValueError("status must be a contiguous int64 tensor of at least 2 elements")
+    check(load().veg_bin_static(ctypes.byref(proj.struct), ctypes.byref(bins.struct), _ptr(status),
+                                stream_handle(stream)), "veg_bin_static")
+    return bins
+
+
 def veg_bin_overflow(ws: torch.Tensor, stream=None):
     e = ctypes.c_int64(0)
     ov = ctypes.c_int32(0)

@@ -188,6 +188,15 @@ void carve_bin_ws(void* ws, int64_t, BinWs* out) {
   out->counters = (uint32_t*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
 }
 
+hipError_t static_bin_scratch(void** out) {
+  static unsigned char* buf = nullptr;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!buf) buf = (unsigned char*)std::calloc(1, kStaticBinBytes + 256);   // held until exit, as the device array
+  *out = (void*)(((uintptr_t)buf + 255) & ~(uintptr_t)255);
+  return hipSuccess;
+}
+
 hipError_t write_blob(void* dst, const void* src, size_t bytes, hipStream_t s) {
   std::vector<unsigned char> copy((const unsigned char*)src, (const unsigned char*)src + bytes);
   return on_stream(s, [=] { std::memcpy(dst, copy.data(), bytes); });

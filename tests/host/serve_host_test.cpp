@@ -387,6 +387,12 @@ void stateless_entry_points_on_host_buffers() {
   double loss = 0;
   CHECK(veg_l1_loss(img.data(), img.data(), (int64_t)img.size(), 1.0f, &loss, img.data(), nullptr) == VEG_OK);
   CHECK(veg_l1_loss(img.data(), img.data(), -1, 1.0f, &loss, img.data(), nullptr) == VEG_ERR_INVALID_ARG);
+  // the allocation-free binning call: same status as the workspace calls, limit enforced
+  int64_t st2[2] = {-1, -1};
+  CHECK(veg_bin_static(&p, &b, st2, nullptr) == VEG_OK && st2[0] == status[0] && st2[1] == status[1]);
+  veg_proj big = p;
+  big.n = VEG_BIN_STATIC_MAX_PAIRS;   // two frames: twice the limit
+  CHECK(veg_bin_static(&big, &b, st2, nullptr) == VEG_ERR_INVALID_ARG);
   std::printf("ok stateless_entry_points_on_host_buffers\n");
 }
 

@@ -235,11 +235,39 @@ def declaration_comments():
 CITATION = re.compile(r'section "[^"]+"|Eq\. ?\d')
 
 
+# The allocation-free variant names the callers it is for instead of a passage.
+NO_ALLOC = {"veg_bin_static"}
+
+
 def test_every_declaration_cites_the_passage_it_implements():
     """Each function of the boundary carries a citation of the paper's section or equation
-    it implements, in its own comment or its section divider (plumbing excepted)."""
+    it implements, in its own comment or its section divider (plumbing excepted; the
+    allocation-free variant names its callers: those that cannot allocate)."""
     comments = declaration_comments()
     assert set(declared_functions()) <= set(comments), set(declared_functions()) - set(comments)
-    missing = [n for n in declared_functions() if n not in PLUMBING and
+    missing = [n for n in declared_functions() if n not in PLUMBING and n not in NO_ALLOC and
                not any(CITATION.search(c) for c in comments[n])]
     assert not missing, missing
+    for n in NO_ALLOC:
+        assert "cannot allocate" in comments[n][0], n
+
+
+def test_bin_static_rejects_sizes_beyond_its_scratch_on_host():
+    """veg_bin_static checks its arguments and its pair limit before touching the device
+    (the pointers are never dereferenced)."""
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    status = ctypes.c_void_p(0x20000)
+    b = _lib.veg_bins(fake, fake, fake, fake, fake, 64, None, 0)
+    big = _lib.veg_proj(262145, 1, 16, 16, 1, 1, 1, fake, fake, fake, fake)
+    assert lib.veg_bin_static(ctypes.byref(big), ctypes.byref(b), status, None) == 1
+    assert b"262144" in lib.veg_last_error()
+    two = _lib.veg_proj(131073, 2, 16, 16, 1, 1, 2, fake, fake, fake, fake)
+    assert lib.veg_bin_static(ctypes.byref(two), ctypes.byref(b), status, None) == 1
+    ok = _lib.veg_proj(1000, 1, 16, 16, 1, 1, 1, fake, fake, fake, fake)
+    assert lib.veg_bin_static(ctypes.byref(ok), ctypes.byref(b), None, None) == 1
+    assert b"status" in lib.veg_last_error()
+    assert lib.veg_bin_static(ctypes.byref(ok), ctypes.byref(b), ctypes.c_void_p(0x20004), None) == 1
+    assert lib.veg_bin_static(ctypes.byref(ok), None, status, None) == 1
