@@ -354,6 +354,23 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
                           float* image, float* t_final, int32_t* n_last, int32_t* n_contrib,
                           veg_stream_t stream);
 
+/* veg_render_fwd_l1 -- veg_render_fwd fused with the L1 term of the training loss (section
+ * "Training"; the image of Eq. 1): for every pixel and channel the final colour
+ * c = C + T_final bg is compared with the target, and in place of the image
+ *   d_image    = scale * sign(c - target)          (device [n_frames,3,H,W] float, overwritten;
+ *                                                    sign(0) = 0; veg_l1_loss's d_image)
+ *   loss_slots += scale * sum |c - target|         (device [VEG_L1_SLOTS] double: the loss is
+ *                                                    the slots' sum; each tile adds to one slot)
+ * are written; t_final, n_last and bins->hits as for veg_render_fwd (what veg_render_bwd
+ * needs).  The colour is the one veg_render_fwd writes, so d_image equals what
+ * veg_render_fwd followed by veg_l1_loss gives, without storing and re-reading the image.
+ *   target   device [n_frames,3,H,W] float
+ * Errors: VEG_ERR_INVALID_ARG, VEG_ERR_HIP. */
+#define VEG_L1_SLOTS 64
+veg_status veg_render_fwd_l1(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts, const float* target,
+                             float scale, double* loss_slots, float* d_image, float* t_final, int32_t* n_last,
+                             veg_stream_t stream);
+
 /* veg_render_bwd -- adjoint of veg_render_fwd (section "Rendering of VEGs": gradients
  * computed manually through the rasterizer).  Walks each tile's list backwards from
  * n_last, recovering T before each entry as T / (1 - alpha), and accumulates per pair

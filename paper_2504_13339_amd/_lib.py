@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libveg.so")
 
 VEG_TILE = 16
 VEG_MAX_FRAMES = 4096
+VEG_L1_SLOTS = 64
 VEG_REC_FLOATS = 12
 VEG_G2D_COMPONENTS = 9
 
@@ -106,6 +107,8 @@ _SIGS = {
     "veg_bin_hit_words": (c_int64, [c_int64, c_int64]),
     "veg_render_fwd": (c_int, [P(veg_proj), P(veg_bins), P(veg_opts), c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p]),
+    "veg_render_fwd_l1": (c_int, [P(veg_proj), P(veg_bins), P(veg_opts), c_void_p, c_float, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p]),
     "veg_render_bwd": (c_int, [P(veg_proj), P(veg_bins), P(veg_opts), c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p]),
     "veg_project_bwd": (c_int, [P(veg_gaussians), P(veg_proj), P(veg_opts), c_void_p, P(veg_grads), c_void_p]),

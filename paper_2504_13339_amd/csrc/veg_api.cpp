@@ -405,6 +405,34 @@ veg_status veg_render_fwd(const veg_proj* proj, const veg_bins* bins, const veg_
   return VEG_OK;
 }
 
+veg_status veg_render_fwd_l1(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts, const float* target,
+                             float scale, double* loss_slots, float* d_image, float* t_final, int32_t* n_last,
+                             veg_stream_t stream) {
+  g_err.clear();
+  veg_status s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  if (!bins || !bins->ranges || !target || !loss_slots || !d_image)
+    return fail(VEG_ERR_INVALID_ARG, "render_fwd_l1: NULL argument");
+  if (!std::isfinite(scale)) return fail(VEG_ERR_INVALID_ARG, "render_fwd_l1: scale must be finite");
+  if (proj->n > 0 && bins->capacity > 0 && !bins->vals) return fail(VEG_ERR_INVALID_ARG, "render_fwd_l1: NULL vals");
+  s = check_hits(proj, bins, "render_fwd_l1");
+  if (s != VEG_OK) return s;
+  veg_opts o;
+  s = resolve_opts(opts, &o);
+  if (s != VEG_OK) return s;
+  L1Fuse l1;
+  l1.target = target;
+  l1.loss = loss_slots;
+  l1.scale = scale;
+  VEG_CHECK_HIP(launch_blend_fwd((const FrameDesc*)proj->frames, proj->n_frames, per_view_of(proj),
+                                 proj->tiles_x * proj->tiles_y, kopts(&o), (const float4*)proj->rec, bins->vals,
+                                 bins->ranges, d_image, t_final, n_last, nullptr, bins->hits,
+                                 hit_stride_of(proj, bins), proj->depth, bins->keys_alt, order_words(bins),
+                                 (hipStream_t)stream, l1),
+                "veg_render_fwd_l1");
+  return VEG_OK;
+}
+
 veg_status veg_render_bwd(const veg_proj* proj, const veg_bins* bins, const veg_opts* opts, const float* t_final,
                           const int32_t* n_last, const float* d_image, float* g2d, veg_stream_t stream) {
   g_err.clear();
@@ -514,7 +542,7 @@ veg_status veg_densify_stats(const veg_proj* proj, const float* g2d, float* grad
   if (s != VEG_OK) return s;
   if (proj->n > 0 && (!g2d || !grad_accum || !vis_count)) return fail(VEG_ERR_INVALID_ARG, "densify_stats: NULL");
   VEG_CHECK_HIP(launch_densify_stats((const FrameDesc*)proj->frames, proj->n_frames, (int)proj->n, proj->count,
-                                     (const float4*)proj->rec, g2d,
+                                     proj->depth, (const float4*)proj->rec, g2d,
                                      grad_accum, vis_count, (hipStream_t)stream),
                 "veg_densify_stats");
   return VEG_OK;

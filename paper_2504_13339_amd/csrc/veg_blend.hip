@@ -192,7 +192,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
                                                        float* __restrict__ tfinal, int32_t* __restrict__ nlast,
                                                        int32_t* __restrict__ ncontrib, uint64_t* __restrict__ hits,
                                                        uint64_t hit_stride, const uint32_t* __restrict__ keep_bits,
-                                                       const uint32_t* __restrict__ order) {
+                                                       const uint32_t* __restrict__ order, L1Fuse l1) {
   const uint32_t gid = block_id(order);
   const uint32_t frame = gid / gridDim.x;
   const FrameDesc& d = descs[frame];
@@ -317,18 +317,36 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
   float* tf = own ? d.out_tfinal : (tfinal ? tfinal + (size_t)frame * HW : nullptr);
   int32_t* nl = own ? d.out_nlast : (nlast ? nlast + (size_t)frame * HW : nullptr);
   int32_t* nc = own ? nullptr : (ncontrib ? ncontrib + (size_t)frame * HW : nullptr);
+  // With the L1 term fused (the training loss of section "Training"), the pixel's colour is
+  // compared with the target and the output holds scale * sign(colour - target) in place of
+  // the colour; scale * sum |colour - target| goes to one of 64 loss slots.
+  const bool fuse = l1.target != nullptr && !own;
+  const float* tg = fuse ? l1.target + (size_t)frame * 3 * HW : nullptr;
+  double lsum = 0.0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int px = tx * kTile + qx + 8 * (r & 1), py = ty * kTile + qy + 8 * (r >> 1);
     if (px < d.W && py < d.H) {
       const size_t pi = (size_t)py * d.W + px;
-      img[pi] = C[r][0] + T[r] * d.bg[0];
-      img[HW + pi] = C[r][1] + T[r] * d.bg[1];
-      img[2 * HW + pi] = C[r][2] + T[r] * d.bg[2];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float c = C[r][ch] + T[r] * d.bg[ch];
+        if (fuse) {
+          const float df = c - tg[ch * HW + pi];
+          lsum += (double)fabsf(df);
+          img[ch * HW + pi] = df > 0.0f ? l1.scale : (df < 0.0f ? -l1.scale : 0.0f);
+        } else {
+          img[ch * HW + pi] = c;
+        }
+      }
       if (tf) tf[pi] = T[r];
       if (nl) nl[pi] = last[r];
       if (kCount && nc) nc[pi] = cnt[r];
     }
+  }
+  if (fuse) {
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+    if (lane == 0 && lsum != 0.0) unsafeAtomicAdd(l1.loss + (gid & (kL1Slots - 1)), lsum * (double)l1.scale);
   }
 }
 
@@ -429,7 +447,10 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
   __shared__ int s_pos[kBatch];      // position of a staged entry in its batch
   __shared__ float s_acc[kBatch][9];
 
-  float T[4], S[4][3], gr[4][3];
+  // GS = g . S: the colour behind the current entry (S, background first) enters the adjoint
+  // only through dL/dalpha = g . (rgb - S) with the pixel's fixed g = dL/dC, so the walk keeps
+  // the scalar g . S instead of S: S <- S + alpha (rgb - S) becomes GS <- GS + alpha (g.rgb - GS).
+  float T[4], GS[4], gr[4][3];
   int last[4];
   int jmax = -1;
 #pragma unroll
@@ -442,9 +463,7 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
     gr[r][0] = in ? dip[pi] : 0.0f;
     gr[r][1] = in ? dip[HW + pi] : 0.0f;
     gr[r][2] = in ? dip[2 * HW + pi] : 0.0f;
-    S[r][0] = d.bg[0];
-    S[r][1] = d.bg[1];
-    S[r][2] = d.bg[2];
+    GS[r] = fmaf(gr[r][2], d.bg[2], fmaf(gr[r][1], d.bg[1], gr[r][0] * d.bg[0]));
     jmax = max(jmax, last[r]);
   }
   jmax = min(wave_max_i32(jmax), (int)rg.y - 1);   // n_last lies inside this tile's range
@@ -526,14 +545,11 @@ __global__ __launch_bounds__(64) void blend_bwd_kernel(const FrameDesc* __restri
           const float alpha = __uint_as_float(min(__float_as_uint(a), aclamp_bits));   // a, aclamp > 0
           const float Tk = T[r] * __builtin_amdgcn_rcpf(1.0f - alpha);
           const float w = alpha * Tk;
-          float dalpha = 0.0f;
 #pragma unroll
-          for (int ch = 0; ch < 3; ++ch) {
-            const float diff = rgbv[ch] - S[r][ch];
-            acc[5 + ch] = fmaf(w, gr[r][ch], acc[5 + ch]);
-            dalpha = fmaf(gr[r][ch], diff, dalpha);
-            S[r][ch] = fmaf(alpha, diff, S[r][ch]);
-          }
+          for (int ch = 0; ch < 3; ++ch) acc[5 + ch] = fmaf(w, gr[r][ch], acc[5 + ch]);
+          const float grgb = fmaf(gr[r][2], rgbv[2], fmaf(gr[r][1], rgbv[1], gr[r][0] * rgbv[0]));
+          const float dalpha = grgb - GS[r];
+          GS[r] = fmaf(alpha, dalpha, GS[r]);
           T[r] = Tk;
           const float dsig = clamped ? 0.0f : -(dalpha * Tk) * a;   // dL/dsigma
           const float u = dsig * dx, v = dsig * dy;
@@ -602,20 +618,21 @@ namespace {
 template <bool kShared>
 void launch_fwd(dim3 grid, hipStream_t stream, const FrameDesc* descs, const KOpts& o, const float4* rec,
                 const uint32_t* vals, const uint2* rg, float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
-                uint64_t* hits, uint64_t hit_stride, const uint32_t* keep_bits, const uint32_t* order) {
+                uint64_t* hits, uint64_t hit_stride, const uint32_t* keep_bits, const uint32_t* order,
+                const L1Fuse& l1) {
   const dim3 block(64);
   if (ncontrib && hits)
     hipLaunchKernelGGL((blend_fwd_kernel<true, true, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
-                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order);
+                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order, l1);
   else if (ncontrib)
     hipLaunchKernelGGL((blend_fwd_kernel<true, false, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
-                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order);
+                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order, l1);
   else if (hits)
     hipLaunchKernelGGL((blend_fwd_kernel<false, true, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg, image,
-                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order);
+                       tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order, l1);
   else
     hipLaunchKernelGGL((blend_fwd_kernel<false, false, kShared>), grid, block, 0, stream, descs, o, rec, vals, rg,
-                       image, tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order);
+                       image, tfinal, nlast, ncontrib, hits, hit_stride, keep_bits, order, l1);
 }
 
 // Longest-list-first order of the n_frames x max_tiles blocks in ws[kOrderHeader ..], or
@@ -640,7 +657,7 @@ const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& 
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges, float* image,
                             float* tfinal, int32_t* nlast, int32_t* ncontrib, uint64_t* hits, uint64_t hit_stride,
                             const uint32_t* keep_bits, uint32_t* order_ws, uint64_t order_ws_words,
-                            hipStream_t stream) {
+                            hipStream_t stream, const L1Fuse& l1) {
   if (n_frames <= 0 || max_tiles <= 0) return hipSuccess;
   if (per_view < 1 || n_frames % per_view != 0) return hipErrorInvalidValue;
   const dim3 grid(max_tiles, n_frames);
@@ -651,10 +668,10 @@ const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& 
   // tables per view lose 6% of the forward pass with them, 10 narrow tent maps gain 15%).
   if (per_view > 1)
     launch_fwd<true>(grid, stream, descs, o, rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride,
-                     per_view >= kKeepBitsMinFrames ? keep_bits : nullptr, order);
+                     per_view >= kKeepBitsMinFrames ? keep_bits : nullptr, order, l1);
   else
     launch_fwd<false>(grid, stream, descs, o, rec, vals, rg, image, tfinal, nlast, ncontrib, hits, hit_stride,
-                      nullptr, order);
+                      nullptr, order, l1);
   return hipGetLastError();
 }
 

@@ -143,11 +143,19 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
 // list (per_view = 1: every frame owns its list).  Hit bits of the frame in slot k start at
 // word k * hit_stride.  order_ws (order_ws_words uint32, may be NULL) is scratch for the
 // blocks' dispatch order, used when it holds n_frames * max_tiles + 128 words.
+// The L1 term of the loss fused into the forward pass's epilogue (target NULL: off).
+constexpr int kL1Slots = 64;
+struct L1Fuse {
+  const float* target = nullptr;   // [n_frames,3,H,W]
+  double* loss = nullptr;          // [kL1Slots], added
+  float scale = 0.0f;
+};
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int per_view, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             float* image, float* tfinal, int32_t* nlast, int32_t* ncontrib,
                             uint64_t* hits, uint64_t hit_stride, const uint32_t* keep_bits,
-                            uint32_t* order_ws, uint64_t order_ws_words, hipStream_t stream);
+                            uint32_t* order_ws, uint64_t order_ws_words, hipStream_t stream,
+                            const L1Fuse& l1 = L1Fuse{});
 hipError_t launch_blend_bwd(const FrameDesc* descs, int n_frames, int max_tiles, const KOpts& o,
                             const float4* rec, const uint32_t* vals, const uint32_t* ranges,
                             const float* tfinal, const int32_t* nlast, const float* dimage,
@@ -162,8 +170,9 @@ hipError_t launch_ssim(const float* image, const float* target, int64_t n_planes
                        double* loss, float* d_image, float* dmaps, hipStream_t stream);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, float bc1, float bc2, hipStream_t stream);
-hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float4* rec,
-                                const float* g2d, float* acc, int32_t* vis, hipStream_t stream);
+hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count,
+                                const uint32_t* depth, const float4* rec, const float* g2d, float* acc, int32_t* vis,
+                                hipStream_t stream);
 // Attribute arrays carried through a densification (kernel argument by value); role:
 // 0 copied to clones and children, 1 means, 2 log-scales, 3 zero for new Gaussians.
 constexpr int kDensifyMaxFields = 16;

@@ -141,7 +141,7 @@ struct veg_server {
   bool stop = false;
   uint64_t next_id = 1;
   int64_t in_use = 0, peak = 0;
-  double e_scale = 1.0;   // learned multiplier on the entry-count prior
+  std::vector<double> m_scale;   // per model: learned multiplier on the entry-count prior
   std::string err;
   // statistics
   std::vector<double> lat_ms;
@@ -224,10 +224,17 @@ KOpts kopts_of(const veg_opts& o) {
 }
 
 // Entry-count prior for one request: about (1 + extent/16)^2 tiles per Gaussian, with the
-// extent taken proportional to the image height; scaled by the learned e_scale.
+// extent taken proportional to the image height; scaled by the model's learned multiplier.
 int64_t entry_prior(int64_t n, int W, int H) {
   const double f = std::max(1.0, (double)std::max(W, H) / 1024.0);
   return (int64_t)std::ceil((double)n * 6.0 * f * f) + 1024;
+}
+
+// Predicted key-list entries of a request: the count observed after an overflow, else the
+// prior times its model's learned multiplier.
+int64_t predicted_entries(const veg_server* s, const Req& q) {
+  if (q.known_entries > 0) return q.known_entries;
+  return (int64_t)std::ceil((double)q.est_entries * s->m_scale[(size_t)q.r.model_id]);
 }
 
 int64_t req_bytes(int64_t n, int64_t entries, int W, int H) {
@@ -344,12 +351,13 @@ veg_status launch_batch(veg_server* s, Slot& sl, const std::vector<uint64_t>& id
     const Req& q = s->reqs[id];
     max_tiles = std::max(max_tiles, tiles_of(q.r.camera.width, q.r.camera.height));
     max_n = std::max(max_n, q.n);
-    entries += q.known_entries > 0 ? q.known_entries : (int64_t)std::ceil((double)q.est_entries * s->e_scale);
+    entries += predicted_entries(s, q);
   }
   sh.tiles = (int)pow2_at_least(max_tiles, 16, s->max_tiles_frame);
   sh.n_max = (int)pow2_at_least(max_n, 1 << 12, c.max_gaussians);
   sh.pairs = pow2_at_least(pair_base, 1 << 14, s->pairs_cap);
-  sh.entries = pow2_at_least(entries, 1 << 16, s->entries_cap);
+  // twice the prediction (the prior varies with the camera distance within a model)
+  sh.entries = pow2_at_least(2 * entries, 1 << 16, s->entries_cap);
   sl.entries_bound = sh.entries;
   hipError_t e = hipMemcpyAsync(sl.d_header, sl.h_stage, sizeof(BatchHeader) + (size_t)c.max_batch * sizeof(FrameDesc),
                                 hipMemcpyHostToDevice, sl.stream);
@@ -409,14 +417,16 @@ void reap(veg_server* s, Slot& sl, double t) {
         s->queue.push_front(*it);
       }
     }
-    // learn a larger multiplier so the next batches are packed more conservatively
-    if (sl.est_entries > 0) s->e_scale = std::max(s->e_scale, 1.25 * (double)E / (double)sl.est_entries);
   } else {
     for (uint64_t id : sl.reqs) finish_request(s, s->reqs[id], VEG_OK, t);
-    if (sl.est_entries > 0) {
-      // observed / prior; jump up at once, decay slowly, keep a 25% margin
-      const double ratio = (double)E / (double)sl.est_entries;
-      s->e_scale = std::max(1.25 * ratio, 0.95 * s->e_scale + 0.05 * 1.25 * ratio);
+  }
+  // Learn the models' multipliers from observed / predicted (shared by a mixed batch's
+  // models): up at once, down slowly, with a 25% margin.
+  if (sl.est_entries > 0) {
+    const double f = 1.25 * (double)E / (double)sl.est_entries;
+    for (uint64_t id : sl.reqs) {
+      double& m = s->m_scale[(size_t)s->reqs[id].r.model_id];
+      m = f > 1.0 ? m * f : m * (0.9 + 0.1 * f);
     }
   }
   s->in_use -= sl.bytes;
@@ -439,7 +449,7 @@ bool try_launch(veg_server* s, Slot& sl) {
   const veg_opts* o0 = nullptr;
   while (!s->queue.empty() && (int)ids.size() < c.max_batch) {
     Req& q = s->reqs[s->queue.front()];
-    const int64_t e = q.known_entries > 0 ? q.known_entries : (int64_t)std::ceil((double)q.est_entries * s->e_scale);
+    const int64_t e = predicted_entries(s, q);
     const bool fits = pairs + q.n <= s->pairs_cap && entries + e <= s->entries_cap &&
                       s->in_use + bytes + q.est_bytes <= (int64_t)c.budget_bytes &&
                       (o0 == nullptr || same_opts(*o0, q.r.opts));
@@ -458,7 +468,7 @@ bool try_launch(veg_server* s, Slot& sl) {
   sl.reqs = ids;
   sl.bytes = bytes;
   sl.est_entries = 0;
-  for (uint64_t id : ids) sl.est_entries += s->reqs[id].est_entries;
+  for (uint64_t id : ids) sl.est_entries += predicted_entries(s, s->reqs[id]);
   s->in_use += bytes;
   s->peak = std::max(s->peak, s->in_use);
   s->batches++;
@@ -597,6 +607,7 @@ veg_status veg_serve_add_model(veg_server* s, const veg_gaussians* g, int32_t* m
   if (reinterpret_cast<uintptr_t>(g->quats) & 15u) return sfail(VEG_ERR_INVALID_ARG, "quats must be 16-byte aligned");
   std::lock_guard<std::mutex> lk(s->mu);
   s->models.push_back(*g);
+  s->m_scale.push_back(1.0);
   *model_id = (int32_t)s->models.size() - 1;
   return VEG_OK;
 }

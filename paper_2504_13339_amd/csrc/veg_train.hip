@@ -207,11 +207,14 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const 
 
 // Densification statistics: for every Gaussian, over the frames in which it was kept, the
 // norm of the gradient w.r.t. its projected centre and the count of such frames (added).
-// Kept in a frame: its list holds the Gaussian (count of the list owner's pair) and the
-// frame's own A is not culled (A is 0 in the record otherwise; a frame owning its list
-// alone never stores A = 0 for a counted pair).
+// Kept in a frame: its list holds the Gaussian (count of the list owner's pair) and, for a
+// frame on a list shared by several frames, the frame's own footprint keeps it: the view's
+// keep bits (bit = the frame's slot, in the depth slots of the view's second frame) tell,
+// for slots from 31 on the record's A > 0 does.  A frame owning its list alone keeps every
+// counted pair.
 __global__ __launch_bounds__(256) void densify_stats_kernel(const FrameDesc* __restrict__ descs, int n_frames, int n,
                                                             const uint32_t* __restrict__ count,
+                                                            const uint32_t* __restrict__ depth,
                                                             const float4* __restrict__ rec,
                                                             const float* __restrict__ g2d, float* __restrict__ acc,
                                                             int32_t* __restrict__ vis) {
@@ -221,9 +224,16 @@ __global__ __launch_bounds__(256) void densify_stats_kernel(const FrameDesc* __r
   int c = 0;
   for (int f = 0; f < n_frames; ++f) {
     const FrameDesc& d = descs[f];
+    const FrameDesc& dl = descs[d.list_frame];
     const size_t pid = (size_t)d.pair_base + (size_t)i;
-    if (count[(size_t)descs[d.list_frame].pair_base + (size_t)i] == 0u) continue;
-    if (!(rec[3 * pid + 1].y > 0.0f)) continue;
+    if (count[(size_t)dl.pair_base + (size_t)i] == 0u) continue;
+    if (dl.n_share > 1) {
+      if (d.slot < 31) {
+        if (!((depth[(size_t)descs[d.list_frame + 1].pair_base + (size_t)i] >> d.slot) & 1u)) continue;
+      } else if (!(rec[3 * pid + 1].y > 0.0f)) {
+        continue;
+      }
+    }
     const float gx = g2d[pid * 9 + 0], gy = g2d[pid * 9 + 1];
     a += sqrtf(gx * gx + gy * gy);
     ++c;
@@ -434,11 +444,12 @@ hipError_t launch_densify_apply(int64_t n, const uint8_t* action, const float* q
   return hipGetLastError();
 }
 
-hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count, const float4* rec,
-                                const float* g2d, float* acc, int32_t* vis, hipStream_t stream) {
+hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count,
+                                const uint32_t* depth, const float4* rec, const float* g2d, float* acc, int32_t* vis,
+                                hipStream_t stream) {
   if (n <= 0 || n_frames <= 0) return hipSuccess;
   hipLaunchKernelGGL(densify_stats_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, descs, n_frames, n, count,
-                     rec, g2d, acc, vis);
+                     depth, rec, g2d, acc, vis);
   return hipGetLastError();
 }
 

@@ -69,7 +69,8 @@ class EventTimer:
 
 def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=None, stream=None,
            capacity: Optional[int] = None, timer=NO_TIMER, want_contrib: bool = False,
-           hits: bool = True, shared: bool = False, status: Optional[torch.Tensor] = None) -> FwdState:
+           hits: bool = True, shared: bool = False, status: Optional[torch.Tensor] = None,
+           l1: Optional[tuple] = None) -> FwdState:
     """Forward render of len(tfs) frames (one model, one image size).
 
     Frame f uses cams[f] and tfs[f]; with ``shared`` there are len(tfs) // len(cams) tables
@@ -80,7 +81,9 @@ def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=Non
     checked with ``veg_bin_overflow``, or later from ``status`` (device int64 [2], written
     with the entry count and the overflow flag).  ``hits`` records which entries were
     blended anywhere, for a following backward pass (set it False for forward-only
-    rendering)."""
+    rendering).  With ``l1`` = (target, scale, loss_slots) the L1 term of the loss is fused
+    into the forward pass: ``image`` then holds scale * sign(image - target) (the loss's
+    gradient w.r.t. the image) and scale * sum |image - target| is added to loss_slots."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
     dev = g.means.device
     proj = V.alloc_proj(g.n, len(tfs), device=dev)
@@ -108,7 +111,12 @@ def render(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], opts=Non
     n_last = torch.empty((F, H, W), dtype=torch.int32, device=dev)
     n_contrib = torch.empty((F, H, W), dtype=torch.int32, device=dev) if want_contrib else None
     with timer("blend_fwd"):
-        V.veg_render_fwd(proj, bins, o, image, t_final, n_last, n_contrib, stream=stream)
+        if l1 is not None and not want_contrib:
+            V.veg_render_fwd_l1(proj, bins, o, l1[0], l1[1], l1[2], image, t_final, n_last, stream=stream)
+        else:
+            V.veg_render_fwd(proj, bins, o, image, t_final, n_last, n_contrib, stream=stream)
+            if l1 is not None:
+                V.veg_l1_loss(image, l1[0], l1[1], l1[2][:1], image, stream=stream)
     return FwdState(proj, bins, ws, image, t_final, n_last, E, o, n_contrib)
 
 
@@ -306,6 +314,12 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
     if loss_acc is None:
         loss_acc = torch.empty(1, dtype=torch.float64, device=g.means.device)
     V.veg_fill_u32(loss_acc, 0, stream=stream)
+    # With the L1 term alone it is fused into the forward pass (its gradient is written in
+    # place of the image, the loss into 64 slots summed at the end of the step).
+    fuse_l1 = ssim_lambda == 0.0
+    slots = torch.empty(V._lib.VEG_L1_SLOTS, dtype=torch.float64, device=g.means.device) if fuse_l1 else None
+    if fuse_l1:
+        V.veg_fill_u32(slots, 0, stream=stream)
     entries = []
     ssim_ws = None
     status = None
@@ -314,14 +328,18 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
     for f0 in range(0, F, group):
         fr = frames[f0:f0 + group]
         view_cams = [cams[c] for c, _ in fr[::K]] if shared else [cams[c] for c, _ in fr]
+        tgt = targets[f0:f0 + len(fr)].contiguous()
         st = render(g, view_cams, [tfs[t] for _, t in fr], o, stream=stream, timer=timer,
                     want_contrib=want_contrib, shared=shared, capacity=capacity,
-                    status=status[f0 // group] if status is not None else None)
+                    status=status[f0 // group] if status is not None else None,
+                    l1=(tgt, 1.0 / M, slots) if fuse_l1 else None)
         entries.append(st.n_entries)
-        d_image = torch.empty_like(st.image)
-        tgt = targets[f0:f0 + len(fr)].contiguous()
-        with timer("l1_loss"):
-            V.veg_l1_loss(st.image, tgt, (1.0 - ssim_lambda) / M, loss_acc, d_image, stream=stream)
+        if fuse_l1:
+            d_image = st.image
+        else:
+            d_image = torch.empty_like(st.image)
+            with timer("l1_loss"):
+                V.veg_l1_loss(st.image, tgt, (1.0 - ssim_lambda) / M, loss_acc, d_image, stream=stream)
         if ssim_lambda > 0.0:
             with timer("ssim_loss"):
                 ssim_ws = V.veg_ssim_loss(st.image, tgt, ssim_lambda / M, loss_acc, d_image, ws=ssim_ws,
@@ -333,6 +351,8 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
         if on_group is not None:
             on_group(f0, st)
         del st, d_image, g2d
+    if fuse_l1:
+        torch.sum(slots, 0, keepdim=True, out=loss_acc)
     loss = float(loss_acc.item()) if read_loss else float("nan")
     if status is not None and read_loss:
         entries = check_status(status, capacity)

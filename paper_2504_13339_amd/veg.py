@@ -266,6 +266,19 @@ def veg_render_fwd(proj: Proj, bins: Bins, opts, image: torch.Tensor, t_final: O
           "veg_render_fwd")
 
 
+def veg_render_fwd_l1(proj: Proj, bins: Bins, opts, target: torch.Tensor, scale: float, loss_slots: torch.Tensor,
+                      d_image: torch.Tensor, t_final: Optional[torch.Tensor], n_last: Optional[torch.Tensor],
+                      stream=None):
+    """Forward pass with the L1 term fused: d_image <- scale * sign(colour - target), loss_slots
+    (device float64 [VEG_L1_SLOTS]) += scale * sum |colour - target| spread over the slots."""
+    if loss_slots.dtype != torch.float64 or loss_slots.numel() < _lib.VEG_L1_SLOTS:
+        raise ValueError("loss_slots must be a float64 tensor of VEG_L1_SLOTS elements")
+    o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
+    check(load().veg_render_fwd_l1(ctypes.byref(proj.struct), ctypes.byref(bins.struct), ctypes.byref(o),
+                                   _ptr(target), float(scale), _ptr(loss_slots), _ptr(d_image), _ptr(t_final),
+                                   _ptr(n_last), stream_handle(stream)), "veg_render_fwd_l1")
+
+
 def veg_render_bwd(proj: Proj, bins: Bins, opts, t_final: torch.Tensor, n_last: torch.Tensor, d_image: torch.Tensor,
                    g2d: torch.Tensor, stream=None):
     o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)

@@ -228,7 +228,7 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4*, 
 }
 hipError_t launch_blend_fwd(const FrameDesc* descs, int n_frames, int, int, const KOpts&, const float4*,
                             const uint32_t*, const uint32_t*, float*, float*, int32_t*, int32_t*, uint64_t*, uint64_t,
-                            const uint32_t*, uint32_t*, uint64_t, hipStream_t s) {
+                            const uint32_t*, uint32_t*, uint64_t, hipStream_t s, const L1Fuse&) {
   return on_stream(s, [=] {
     ++g_blend_launches;
     for (int f = 0; f < n_frames; ++f) {
@@ -266,8 +266,8 @@ hipError_t launch_adam(float*, const float*, float*, float*, int64_t, float, flo
                        hipStream_t) {
   return hipSuccess;
 }
-hipError_t launch_densify_stats(const FrameDesc*, int, int, const uint32_t*, const float4*, const float*, float*,
-                                int32_t*, hipStream_t) {
+hipError_t launch_densify_stats(const FrameDesc*, int, int, const uint32_t*, const uint32_t*, const float4*,
+                                const float*, float*, int32_t*, hipStream_t) {
   return hipSuccess;
 }
 hipError_t launch_densify_plan(int64_t, const float*, const int32_t*, const float*, const float*, float, float, float,

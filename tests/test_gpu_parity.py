@@ -448,3 +448,45 @@ def test_needles_at_45_degrees_image_and_gradients():
     st2, grads, g2d, ref = _grads_case(w, d)
     for name in ("d_means", "d_log_scales", "d_quats", "d_scalars"):
         assert rel_err(getattr(grads, name).cpu().numpy(), getattr(ref, name)) <= 1e-3, name
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_forward_with_fused_l1_equals_forward_then_l1(shared):
+    """veg_render_fwd_l1 writes exactly what veg_render_fwd followed by veg_l1_loss gives:
+    the image gradient bit for bit (sign times scale of the same float32 colour), the same
+    transmittance, last indices and hit bits, and the loss up to summation order (both
+    calls on one projection and key list; hit words cleared before each)."""
+    V, R = hip()
+    w = synth.workload(1, n_override=6000, views_override=2, tfs_override=2, res_override=96)
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    cams = w.cameras if shared else [w.cameras[c] for c, _ in w.frames]
+    tfs = [luts[t] for _, t in w.frames]
+    F = len(w.frames)
+    st = R.render(g, cams, tfs, OPTS, shared=shared)
+    o = V.make_opts(OPTS)
+    rng = np.random.default_rng(61)
+    tgt = torch.as_tensor(rng.uniform(0, 1, (F, 3, 96, 96)).astype(np.float32)).cuda()
+    scale = 1.0 / tgt.numel()
+    img = torch.empty_like(st.image)
+    t1, n1 = torch.empty_like(st.t_final), torch.empty_like(st.n_last)
+    st.bins.hits.zero_()
+    V.veg_render_fwd(st.proj, st.bins, o, img, t1, n1)
+    h1 = st.bins.hits.clone()
+    tgt[:, :, 40:56, 40:56] = img[:, :, 40:56, 40:56]   # colour == target there: sign 0
+    loss_ref = torch.zeros(1, dtype=torch.float64).cuda()
+    d_ref = torch.empty_like(img)
+    V.veg_l1_loss(img, tgt, scale, loss_ref, d_ref)
+    slots = torch.zeros(64, dtype=torch.float64).cuda()
+    d_img = torch.empty_like(img)
+    t2, n2 = torch.empty_like(t1), torch.empty_like(n1)
+    st.bins.hits.zero_()
+    V.veg_render_fwd_l1(st.proj, st.bins, o, tgt, scale, slots, d_img, t2, n2)
+    torch.cuda.synchronize()
+    assert torch.equal(d_img, d_ref)
+    assert torch.equal(t2, t1) and torch.equal(n2, n1)
+    assert torch.equal(st.bins.hits, h1)
+    assert (d_ref == 0).any() and (d_ref > 0).any() and (d_ref < 0).any()
+    assert abs(slots.sum().item() - loss_ref.item()) <= 1e-12 * loss_ref.item()
+    l_or, _ = oracle.l1_loss(img.cpu().numpy(), tgt.cpu().numpy(), scale=scale)
+    assert abs(slots.sum().item() - l_or) <= 1e-6 * l_or

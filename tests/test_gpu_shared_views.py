@@ -275,3 +275,23 @@ def test_views_of_more_than_32_tables_keep_every_frame_from_slot_31():
         ci, ti = w.frames[f]
         res, *_ = oracle.render_image(w.gaussians, w.cameras[ci], w.tfs[ti], OPTS)
         compare_image(image_pixels(st.image[f]), res)
+
+
+def test_densify_visibility_on_a_view_of_34_tables_equals_own_lists():
+    """Densification visibility on a shared list reads the view's keep bits for slots 0-30
+    and the frame's record from slot 31 on: counts equal the own-list run's exactly."""
+    V, R = hip()
+    w = _case(n=800, views=1, K=34, res=48, tents=True)
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    rng = np.random.default_rng(95)
+    tgt = torch.as_tensor(rng.uniform(0, 1, (len(w.frames), 3, 48, 48)).astype(np.float32)).cuda()
+    vis = {}
+    for shared in (False, True):
+        grads = R.Grads.zeros(g)
+        dens = R.DensifyStats.zeros(w.gaussians.n)
+        R.train_step(g, w.cameras, luts, w.frames, tgt, grads, 34, OPTS, densify=dens, shared=shared)
+        torch.cuda.synchronize()
+        vis[shared] = dens.vis_count.cpu().numpy()
+    assert vis[False].sum() > 0
+    assert np.array_equal(vis[True], vis[False])
