@@ -651,7 +651,7 @@ def main():
         for st in fst:
             R.check_status(st, fcap)
         ft = {k: round(sum(v) / args.full_steps, 3) for k, v in ftimer.totals_ms().items()
-              if k in ("l1_loss", "ssim_loss", "densify_stats", "adam")}
+              if k in ("image_loss", "densify_stats", "adam")}
         full = {"mpix_s": round(F * H * W * args.full_steps / fdt / 1e6, 2),
                 "ms_per_step": round(fdt * 1e3 / args.full_steps, 3), "ssim_lambda": 0.2, "kernel_ms_per_step": ft}
         del dens, opt

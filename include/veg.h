@@ -445,6 +445,19 @@ veg_status veg_ssim_loss(const float* image, const float* target, int64_t n_plan
                          int32_t height, float weight, double* loss, float* d_image, void* ws,
                          size_t ws_bytes, veg_stream_t stream);
 
+/* veg_image_loss -- the whole image loss of section "Training", (1-lambda) L1 + lambda SSIM,
+ * in one pass over the images (veg_l1_loss and veg_ssim_loss fused):
+ *   loss   += l1_scale * sum |image - target| + ssim_weight * sum (1 - SSIM)   (device double)
+ *   d_image = l1_scale * sign(image - target) + ssim_weight * d/dimage sum (1 - SSIM)
+ *             (device float, OVERWRITTEN; bit for bit what veg_l1_loss followed by
+ *             veg_ssim_loss writes, without storing and re-reading the L1 gradient)
+ * Sizes, window and workspace as for veg_ssim_loss; normally l1_scale = (1-lambda)/M and
+ * ssim_weight = lambda/M for M pixel-channels.
+ * Errors: VEG_ERR_INVALID_ARG (sizes, NULLs, non-finite weights, small workspace), VEG_ERR_HIP. */
+veg_status veg_image_loss(const float* image, const float* target, int64_t n_planes, int32_t width, int32_t height,
+                          float l1_scale, float ssim_weight, double* loss, float* d_image, void* ws, size_t ws_bytes,
+                          veg_stream_t stream);
+
 /* veg_adam_step -- one Adam update of a parameter array (the optimizer of section
  * "Training"; Kingma & Ba):  m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
  *   param <- param - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).

@@ -117,6 +117,8 @@ _SIGS = {
     "veg_ssim_workspace_bytes": (c_size_t, [c_int64, c_int32, c_int32]),
     "veg_ssim_loss": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_float, c_void_p, c_void_p, c_void_p,
                               c_size_t, c_void_p]),
+    "veg_image_loss": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_float, c_float, c_void_p, c_void_p,
+                               c_void_p, c_size_t, c_void_p]),
     "veg_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_float, c_float, c_float, c_float,
                               c_int32, c_void_p]),
     "veg_densify_stats": (c_int, [P(veg_proj), c_void_p, c_void_p, c_void_p, c_void_p]),

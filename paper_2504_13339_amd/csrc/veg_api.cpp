@@ -520,6 +520,24 @@ veg_status veg_ssim_loss(const float* image, const float* target, int64_t n_plan
   return VEG_OK;
 }
 
+veg_status veg_image_loss(const float* image, const float* target, int64_t n_planes, int32_t width, int32_t height,
+                          float l1_scale, float ssim_weight, double* loss, float* d_image, void* ws, size_t ws_bytes,
+                          veg_stream_t stream) {
+  g_err.clear();
+  if (n_planes < 0 || width < 0 || height < 0 || width > VEG_MAX_DIM || height > VEG_MAX_DIM || n_planes > 65535)
+    return fail(VEG_ERR_INVALID_ARG, "image_loss: sizes out of range");
+  if (n_planes == 0 || width == 0 || height == 0) return VEG_OK;
+  if (!image || !target || !loss || !d_image || !ws) return fail(VEG_ERR_INVALID_ARG, "image_loss: NULL argument");
+  if (ws_bytes < veg_ssim_workspace_bytes(n_planes, width, height))
+    return fail(VEG_ERR_INVALID_ARG, "image_loss: workspace smaller than veg_ssim_workspace_bytes");
+  if (!std::isfinite(l1_scale) || !std::isfinite(ssim_weight))
+    return fail(VEG_ERR_INVALID_ARG, "image_loss: weights must be finite");
+  VEG_CHECK_HIP(launch_ssim(image, target, n_planes, width, height, ssim_weight, loss, d_image, (float*)ws,
+                            (hipStream_t)stream, true, l1_scale),
+                "veg_image_loss");
+  return VEG_OK;
+}
+
 veg_status veg_adam_step(float* param, const float* grad, float* m, float* v, int64_t count, float lr, float beta1,
                          float beta2, float eps, int32_t step, veg_stream_t stream) {
   g_err.clear();

@@ -146,40 +146,52 @@ __global__ __launch_bounds__(1024) void scan_partials_kernel(uint64_t* partials,
   }
 }
 
-// Downsweep of the compaction: kept pair i goes to (dkey, dval)[pos] = (depth[i], i).
+// Downsweep of the compaction: kept pair i goes to (dkey, dval)[pos] = (depth[i], i), in
+// index order.  A tile's items are read lane-strided (item t0 + k * 256 + thread, so every
+// load is coalesced); each wave ranks its 64 items of round k with a ballot, and the rounds'
+// and waves' kept counts are scanned in (round, wave) order -- index order -- so the kept
+// items of one wave and round land in consecutive slots and every store is contiguous.
 __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __restrict__ count,
                                                            const uint32_t* __restrict__ depth,
                                                            const uint32_t* __restrict__ n_ptr, uint32_t n_cap,
                                                            const uint64_t* __restrict__ partials, int G,
                                                            uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval) {
-  __shared__ uint32_t s_tmp[kWaves];
+  __shared__ uint32_t s_wc[kIpt][kWaves];
   const uint32_t n = read_count(n_ptr, n_cap);
   uint32_t begin, end;
   segment_of(n, G, blockIdx.x, begin, end);
   uint64_t base = partials[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = lanemask_lt();
   for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
-    // thread-contiguous items so the scan order equals the index order
-    const uint32_t i0 = t0 + threadIdx.x * kIpt;
-    uint32_t flags = 0, s = 0;
+    uint64_t m[kIpt];
 #pragma unroll
     for (int k = 0; k < kIpt; ++k) {
-      const uint32_t i = i0 + k;
-      const uint32_t f = (i < end && count[i] > 0u) ? 1u : 0u;
-      flags |= f << k;
-      s += f;
+      const uint32_t i = t0 + k * kThreads + threadIdx.x;
+      m[k] = __ballot(i < end && count[i] > 0u);
+      if (lane == 0) s_wc[k][w] = (uint32_t)__popcll(m[k]);
     }
-    uint32_t tot;
-    uint32_t off = block_excl_scan(s, s_tmp, &tot);
+    __syncthreads();
+    uint32_t off[kIpt], run = 0;
 #pragma unroll
     for (int k = 0; k < kIpt; ++k) {
-      if ((flags >> k) & 1u) {
-        const uint64_t pos = base + off;
-        dkey[pos] = depth[i0 + k];
-        dval[pos] = i0 + k;
-        ++off;
+#pragma unroll
+      for (int v = 0; v < kWaves; ++v) {
+        if (v == w) off[k] = run;
+        run += s_wc[k][v];
       }
     }
-    base += tot;
+    __syncthreads();   // s_wc is rewritten by the next tile
+#pragma unroll
+    for (int k = 0; k < kIpt; ++k) {
+      if ((m[k] >> lane) & 1ull) {
+        const uint32_t i = t0 + k * kThreads + threadIdx.x;
+        const uint64_t pos = base + off[k] + (uint32_t)__popcll(m[k] & lt);
+        dkey[pos] = depth[i];
+        dval[pos] = i;
+      }
+    }
+    base += run;
   }
 }
 
@@ -607,9 +619,19 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __rest
   }
 }
 
+// 16-byte stores where the buffer is 16-byte aligned (four words per lane and instruction).
 __global__ __launch_bounds__(kThreads) void fill_kernel(uint32_t* __restrict__ dst, int64_t count, uint32_t value) {
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < count; i += (int64_t)gridDim.x * kThreads)
-    dst[i] = value;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  int64_t head = 0;
+  if ((reinterpret_cast<uintptr_t>(dst) & 15u) == 0) {
+    const int64_t n4 = count >> 2;
+    const uint4 v = make_uint4(value, value, value, value);
+    uint4* d4 = reinterpret_cast<uint4*>(dst);
+    for (int64_t i = t; i < n4; i += stride) d4[i] = v;
+    head = 4 * n4;
+  }
+  for (int64_t i = head + t; i < count; i += stride) dst[i] = value;
 }
 
 int blocks_for(int64_t n, int items_per_block, int max_blocks) {

@@ -166,8 +166,11 @@ hipError_t launch_l1(const float* image, const float* target, int64_t count, flo
                      double* loss, float* dimage, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* dst, int64_t count, uint32_t value, hipStream_t stream);
 hipError_t launch_bin_status(const uint32_t* counters, int64_t* dst, hipStream_t stream);
+// With with_l1, d_image is overwritten with the L1 term's gradient plus the SSIM term's and
+// l1_scale * sum |image - target| joins the loss (the L1 pass fused in); else d_image is added to.
 hipError_t launch_ssim(const float* image, const float* target, int64_t n_planes, int W, int H, float weight,
-                       double* loss, float* d_image, float* dmaps, hipStream_t stream);
+                       double* loss, float* d_image, float* dmaps, hipStream_t stream, bool with_l1 = false,
+                       float l1_scale = 0.0f);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, float bc1, float bc2, hipStream_t stream);
 hipError_t launch_densify_stats(const FrameDesc* descs, int n_frames, int n, const uint32_t* count,

@@ -67,13 +67,16 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ src, int W, 
 //   N = (2 mu_x mu_y + C1)(2 s_xy + C2) = A1 A2,  D = (mu_x^2 + mu_y^2 + C1)(s_x + s_y + C2) = B1 B2,
 //   dS/dmu_x = (2 mu_y (A2 - A1) - 2 mu_x S (B2 - B1)) / D,  dS/dE[x^2] = -S B1 / D,
 //   dS/dE[xy] = 2 A1 / D.
-// The three maps are stored multiplied by dL/dS = -weight for the backward pass.
+// The three maps are stored multiplied by dL/dS = -weight for the backward pass.  With kL1
+// the L1 term l1_scale * sum |x - y| over the tile's own pixels joins the loss.
+template <bool kL1>
 __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
-                                                       int W, int H, float weight, double* __restrict__ loss,
-                                                       float* __restrict__ dmaps, size_t plane_stride, Win win) {
+                                                       int W, int H, float weight, float l1_scale,
+                                                       double* __restrict__ loss, float* __restrict__ dmaps,
+                                                       size_t plane_stride, Win win) {
   __shared__ float s_x[kIn][kPadIn], s_y[kIn][kPadIn];
   __shared__ float s_h[5][kIn][kPadT];
-  __shared__ double s_part[4];
+  __shared__ double s_part[2][4];
   const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
   const size_t plane = blockIdx.z;
   const size_t HW = (size_t)W * H;
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
   }
   __syncthreads();
   // vertical: 32 columns x 8 groups of 4 rows, one task per thread
-  double part = 0.0;
+  double part = 0.0, part_l1 = 0.0;
   {
     const int c = threadIdx.x & (kT - 1), r0 = (threadIdx.x / kT) * kB;
     float m[5][kB];
@@ -124,6 +127,7 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
       const float D = B1 * B2;
       const float S = (A1 * A2) / D;
       part += (double)(1.0f - S);
+      if (kL1) part_l1 += (double)fabsf(s_x[r0 + i + kHalf][c + kHalf] - s_y[r0 + i + kHalf][c + kHalf]);
       // one reciprocal for the three maps (S keeps its division: identical images give
       // S = 1 exactly, and then dex2 = -(B1 rD) and dexy = 2 (B1 rD) cancel in the adjoint)
       const float rD = 1.0f / D;
@@ -136,21 +140,33 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
       dmaps[2 * plane_stride + pi] = -weight * dexy;
     }
   }
-  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = part;
+  for (int off = 32; off > 0; off >>= 1) {
+    part += __shfl_xor(part, off);
+    if (kL1) part_l1 += __shfl_xor(part_l1, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_part[0][threadIdx.x >> 6] = part;
+    s_part[1][threadIdx.x >> 6] = part_l1;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double t = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
-    if (t != 0.0) unsafeAtomicAdd(loss, t * (double)weight);
+    const double t = (s_part[0][0] + s_part[0][1]) + (s_part[0][2] + s_part[0][3]);
+    double add = t * (double)weight;
+    if (kL1) add += ((s_part[1][0] + s_part[1][1]) + (s_part[1][2] + s_part[1][3])) * (double)l1_scale;
+    if (add != 0.0) unsafeAtomicAdd(loss, add);
   }
 }
 
 // Adjoint: dL/dx = G * D_mu + 2 x (G * D_x2) + y (G * D_xy), the window applied to the maps
 // with zeros outside the image (the adjoint of the zero-padded forward window); added to
-// d_image.
+// d_image.  With kL1, d_image is not read: it is written as the L1 term's gradient
+// l1_scale * sign(x - y) plus that sum, the same value, rounding included, as the L1 pass
+// followed by the SSIM pass.
+template <bool kL1>
 __global__ __launch_bounds__(256) void ssim_bwd_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
                                                        int W, int H, const float* __restrict__ dmaps,
-                                                       size_t plane_stride, float* __restrict__ dimg, Win win) {
+                                                       size_t plane_stride, float* __restrict__ dimg, float l1_scale,
+                                                       Win win) {
   __shared__ float s_m[3][kIn][kPadIn];
   __shared__ float s_h[3][kIn][kPadT];
   const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
@@ -186,7 +202,14 @@ __global__ __launch_bounds__(256) void ssim_bwd_kernel(const float* __restrict__
     const int gy = y0 + r0 + i;
     if (gx >= W || gy >= H) continue;
     const size_t pi = plane * HW + (size_t)gy * W + gx;
-    dimg[pi] += (m[0][i] + 2.0f * img[pi] * m[1][i]) + tgt[pi] * m[2][i];
+    const float x = img[pi], y = tgt[pi];
+    const float g = (m[0][i] + 2.0f * x * m[1][i]) + y * m[2][i];
+    if (kL1) {
+      const float d = x - y;
+      dimg[pi] = (d > 0.0f ? l1_scale : (d < 0.0f ? -l1_scale : 0.0f)) + g;
+    } else {
+      dimg[pi] += g;
+    }
   }
 }
 
@@ -401,15 +424,23 @@ static Win ssim_window() {
 }
 
 hipError_t launch_ssim(const float* image, const float* target, int64_t n_planes, int W, int H, float weight,
-                       double* loss, float* d_image, float* dmaps, hipStream_t stream) {
+                       double* loss, float* d_image, float* dmaps, hipStream_t stream, bool with_l1,
+                       float l1_scale) {
   if (n_planes <= 0 || W <= 0 || H <= 0) return hipSuccess;
   const size_t plane_stride = (size_t)n_planes * W * H;
   const dim3 grid((W + kT - 1) / kT, (H + kT - 1) / kT, (unsigned)n_planes);
   const Win win = ssim_window();
-  hipLaunchKernelGGL(ssim_fwd_kernel, grid, dim3(256), 0, stream, image, target, W, H, weight, loss, dmaps,
-                     plane_stride, win);
-  hipLaunchKernelGGL(ssim_bwd_kernel, grid, dim3(256), 0, stream, image, target, W, H, dmaps, plane_stride, d_image,
-                     win);
+  if (with_l1) {
+    hipLaunchKernelGGL(ssim_fwd_kernel<true>, grid, dim3(256), 0, stream, image, target, W, H, weight, l1_scale, loss,
+                       dmaps, plane_stride, win);
+    hipLaunchKernelGGL(ssim_bwd_kernel<true>, grid, dim3(256), 0, stream, image, target, W, H, dmaps, plane_stride,
+                       d_image, l1_scale, win);
+  } else {
+    hipLaunchKernelGGL(ssim_fwd_kernel<false>, grid, dim3(256), 0, stream, image, target, W, H, weight, 0.0f, loss,
+                       dmaps, plane_stride, win);
+    hipLaunchKernelGGL(ssim_bwd_kernel<false>, grid, dim3(256), 0, stream, image, target, W, H, dmaps, plane_stride,
+                       d_image, 0.0f, win);
+  }
   return hipGetLastError();
 }
 

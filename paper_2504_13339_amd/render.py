@@ -336,14 +336,11 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
         entries.append(st.n_entries)
         if fuse_l1:
             d_image = st.image
-        else:
+        else:   # L1 and SSIM terms in one pass, d_image written
             d_image = torch.empty_like(st.image)
-            with timer("l1_loss"):
-                V.veg_l1_loss(st.image, tgt, (1.0 - ssim_lambda) / M, loss_acc, d_image, stream=stream)
-        if ssim_lambda > 0.0:
-            with timer("ssim_loss"):
-                ssim_ws = V.veg_ssim_loss(st.image, tgt, ssim_lambda / M, loss_acc, d_image, ws=ssim_ws,
-                                          stream=stream)
+            with timer("image_loss"):
+                ssim_ws = V.veg_image_loss(st.image, tgt, (1.0 - ssim_lambda) / M, ssim_lambda / M, loss_acc,
+                                           d_image, ws=ssim_ws, stream=stream)
         g2d = render_backward(g, st, d_image, grads, stream=stream, timer=timer)
         if densify is not None:
             with timer("densify_stats"):

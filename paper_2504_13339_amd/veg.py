@@ -19,7 +19,7 @@ __all__ = [
     "Gaussians", "Proj", "Bins", "default_opts", "make_opts", "veg_project", "veg_bin_count", "veg_bin_sort",
     "veg_bin_overflow", "veg_bin_status", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
     "veg_debug_math", "veg_bin_hit_words", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
-    "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_adam_step", "veg_densify_stats", "veg_project_views",
+    "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_image_loss", "veg_adam_step", "veg_densify_stats", "veg_project_views",
     "veg_vq_decode", "decode_vq_model", "veg_densify_plan", "veg_densify_apply", "veg_densify_workspace_bytes",
     "KEEP", "CLONE", "SPLIT", "PRUNE", "FIELD_COPY", "FIELD_MEANS", "FIELD_LOG_SCALES", "FIELD_ZERO_NEW",
 ]
@@ -326,6 +326,26 @@ def veg_ssim_loss(image: torch.Tensor, target: torch.Tensor, weight: float, loss
         ws = torch.empty(max(need, 4), dtype=torch.uint8, device=image.device)
     check(load().veg_ssim_loss(_ptr(image), _ptr(target), planes, W, H, float(weight), _ptr(loss), _ptr(d_image),
                                _ptr(ws), ws.numel() * ws.element_size(), stream_handle(stream)), "veg_ssim_loss")
+    return ws
+
+
+def veg_image_loss(image: torch.Tensor, target: torch.Tensor, l1_scale: float, ssim_weight: float, loss: torch.Tensor,
+                   d_image: torch.Tensor, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The whole image loss in one pass: adds l1_scale * sum|image - target| + ssim_weight *
+    sum(1 - SSIM) to ``loss`` and writes (overwrites) its gradient into ``d_image``.  Shapes
+    and workspace as for veg_ssim_loss; returns the workspace."""
+    if loss.dtype != torch.float64:
+        raise ValueError("loss accumulator must be float64")
+    if image.shape != target.shape or image.shape != d_image.shape or image.dim() < 2:
+        raise ValueError("image, target and d_image must share one shape [..., H, W]")
+    H, W = int(image.shape[-2]), int(image.shape[-1])
+    planes = image.numel() // max(1, H * W)
+    need = veg_ssim_workspace_bytes(planes, W, H)
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(max(need, 4), dtype=torch.uint8, device=image.device)
+    check(load().veg_image_loss(_ptr(image), _ptr(target), planes, W, H, float(l1_scale), float(ssim_weight),
+                                _ptr(loss), _ptr(d_image), _ptr(ws), ws.numel() * ws.element_size(),
+                                stream_handle(stream)), "veg_image_loss")
     return ws
 
 

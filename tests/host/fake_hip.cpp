@@ -259,7 +259,8 @@ hipError_t launch_bin_status(const uint32_t* c, int64_t* dst, hipStream_t s) {
     dst[1] = c[3];
   });
 }
-hipError_t launch_ssim(const float*, const float*, int64_t, int, int, float, double*, float*, float*, hipStream_t) {
+hipError_t launch_ssim(const float*, const float*, int64_t, int, int, float, double*, float*, float*, hipStream_t, bool,
+                       float) {
   return hipSuccess;
 }
 hipError_t launch_adam(float*, const float*, float*, float*, int64_t, float, float, float, float, float, float,

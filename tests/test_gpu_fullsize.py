@@ -230,3 +230,43 @@ def test_multi_tf_workload_sampled_pixel_gradient():
     ref = oracle.gradients(w.gaussians, w.cameras[ci], w.tfs[ti], w.opts, d, pixels=px)
     for name in ("d_means", "d_log_scales", "d_quats", "d_scalars"):
         assert rel_err(getattr(grads, name).cpu().numpy(), getattr(ref, name)) <= 1e-3, name
+
+
+# ------------------------------------------------------------------ serving
+# The serving workload's largest request: the 3M-Gaussian model at 1920x1080, submitted with
+# smaller requests on the other resident models so that the server batches them together.
+
+def test_serving_workload_3M_model_at_1920x1080_in_a_mixed_batch():
+    from paper_2504_13339_amd import render as R
+    from paper_2504_13339_amd.serve import Server
+    models, reqs = synth.serve_trace(1.0, 7, seed_sub=11)
+    assert models[3].n == 3_000_000
+    rng = synth.rng_for(3, 82)
+    big_cam = synth.look_at_camera(synth.random_direction(rng), 3.0, 1920, 1080)
+    big_tf = synth.random_tf(rng)
+    dev = [to_dev(m) for m in models]
+    with Server(max_gaussians=3_000_000, max_entries=64_000_000, max_batch=8, n_streams=2, use_graphs=True,
+                max_width=1920, max_height=1080, max_tf_k=256, budget_bytes=64_000_000_000) as srv:
+        mids = [srv.add_model(m) for m in dev]
+        outs = [torch.full((3, r.camera.height, r.camera.width), -1.0, device="cuda") for r in reqs]
+        big = torch.full((3, 1080, 1920), -1.0, device="cuda")
+        ids = [srv.submit(mids[r.model], r.camera, r.tf, outs[i]) for i, r in enumerate(reqs[:4])]
+        ids.append(srv.submit(mids[3], big_cam, big_tf, big))
+        ids += [srv.submit(mids[r.model], r.camera, r.tf, outs[4 + i]) for i, r in enumerate(reqs[4:])]
+        for rid in ids:
+            srv.wait(rid)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) + 1 and st["batches"] < len(reqs) + 1   # batching happened
+    luts = luts_to_dev([big_tf])
+    ref = R.render(dev[3], [big_cam], luts, synth.DEFAULT_OPTS, hits=False)
+    torch.cuda.synchronize()
+    assert torch.equal(ref.image[0], big)                       # served == stateless, bitwise
+    for i, r in enumerate(reqs):
+        alone = R.render(dev[r.model], [r.camera], luts_to_dev([r.tf]), synth.DEFAULT_OPTS, hits=False)
+        assert torch.equal(alone.image[0], outs[i]), i
+    del dev, ref
+    fp = oracle.footprint_f32(models[3], big_cam, big_tf, synth.DEFAULT_OPTS)
+    px, hottest = stratified_pixels(synth.rng_for(3, 83), fp, big_cam, N_PIXELS)
+    assert hottest > 0
+    res, *_ = oracle.render_image(models[3], big_cam, big_tf, synth.DEFAULT_OPTS, pixels=px)
+    compare_image(image_pixels(big)[px[:, 1] * 1920 + px[:, 0]], res)

@@ -113,12 +113,18 @@ def _check_keys(w, st, frames):
     assert np.array_equal(rg, ranges)
 
 
-@pytest.mark.parametrize("case", ["c0", "c1_small", "odd_size"])
+@pytest.mark.parametrize("case", ["c0", "c1_small", "odd_size", "large_2048x2000", "large_2064x2000"])
 def test_projection_and_key_list_bit_exact(case):
+    """Small frames, a ragged one, and two frames of 16,000 and 16,125 tiles (14-bit tile ids,
+    two tile-id passes)."""
     if case == "c0":
         w = synth.workload(0)
     elif case == "c1_small":
         w = synth.workload(1, n_override=20000, views_override=3, tfs_override=2, res_override=200)
+    elif case in ("large_2048x2000", "large_2064x2000"):
+        w = synth.workload(1, n_override=20000, views_override=2, tfs_override=1, res_override=200)
+        width = 2048 if case == "large_2048x2000" else 2064
+        w.cameras = [synth.look_at_camera(d, 3.0, width, 2000) for d in synth.fibonacci_directions(2)]
     else:
         w = synth.workload(0, n_override=3000)
         w.cameras = [synth.look_at_camera(synth.random_direction(synth.rng_for(0, 7)), 2.5, 97, 61)]

@@ -58,6 +58,31 @@ def test_ssim_gradient_is_added_to_d_image_and_loss_accumulates():
     assert rel_err(d.cpu().numpy() - base, ref_d) <= 1e-3
 
 
+@pytest.mark.parametrize("planes,H,W,lam", [(6, 37, 75, 0.2), (3, 64, 64, 0.2), (1, 5, 3, 0.5), (2, 40, 48, 1.0)])
+def test_image_loss_equals_l1_then_ssim(planes, H, W, lam):
+    """The fused loss writes d_image bit for bit as veg_l1_loss followed by veg_ssim_loss,
+    the loss within summation-order rounding; both against the oracle's two terms."""
+    V, R = hip()
+    x, y = _ssim_case(planes * 31 + H + W, planes, H, W, True)
+    x[0, 0, :2] = y[0, 0, :2]   # zero differences: sign(0) = 0 on both paths
+    M = x.size
+    xd, yd = torch.as_tensor(x).cuda(), torch.as_tensor(y).cuda()
+    loss_a = torch.zeros(1, dtype=torch.float64).cuda()
+    d_a = torch.full(x.shape, float("nan")).cuda()   # overwritten, never read
+    V.veg_image_loss(xd, yd, (1 - lam) / M, lam / M, loss_a, d_a)
+    loss_b = torch.zeros(1, dtype=torch.float64).cuda()
+    d_b = torch.empty(x.shape).cuda()
+    V.veg_l1_loss(xd, yd, (1 - lam) / M, loss_b, d_b)
+    V.veg_ssim_loss(xd, yd, lam / M, loss_b, d_b)
+    torch.cuda.synchronize()
+    assert torch.equal(d_a, d_b)
+    assert abs(loss_a.item() - loss_b.item()) <= 1e-12 * abs(loss_b.item())
+    ref_l1 = oracle.l1_loss(x, y, (1 - lam) / M)
+    ref_s, ref_d = oracle.ssim_loss(x, y, lam / M)
+    assert abs(loss_a.item() - (ref_l1[0] + ref_s)) <= 1e-4 * (ref_l1[0] + ref_s)
+    assert rel_err(d_a.cpu().numpy(), ref_l1[1] + ref_d) <= 1e-3
+
+
 def test_ssim_of_identical_images_is_zero_loss_and_zero_gradient():
     x, _ = _ssim_case(7, 2, 40, 50, False)
     got_l, got_d = _gpu_ssim(x, x.copy(), 1.0)
