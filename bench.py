@@ -205,10 +205,12 @@ def workload_step_bench(index, steps, warmup=1, group=None, shared=True):
         del st
     grads = R.Grads.zeros(g)
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    # one zeroed g2d buffer for every group, left zero by each group's projection backward
+    g2d = torch.zeros(9 * w.gaussians.n * min(F, max(group, K)), dtype=torch.float32, device="cuda")
 
     def step(**kw):
         return R.train_step(g, w.cameras, luts, w.frames, targets, grads, group, w.opts, loss_acc=loss,
-                            shared=shared, **kw)
+                            shared=shared, g2d=g2d, **kw)
     res = step()
     cap = int(max(res.n_entries) * 1.05) + 4096
     for _ in range(warmup):
@@ -228,7 +230,7 @@ def workload_step_bench(index, steps, warmup=1, group=None, shared=True):
     out = {"workload": w.name, "gaussians": w.gaussians.n, "frames": F, "width": W, "height": H, "group": group,
            "shared_views": bool(shared), "max_entries_per_group": int(max(res.n_entries)),
            "mpix_s": round(F * H * W * steps / dt / 1e6, 2), "ms_per_step": round(dt * 1e3 / steps, 3)}
-    del grads, targets, g, gt
+    del grads, targets, g, gt, g2d
     torch.cuda.empty_cache()
     return out
 
@@ -510,6 +512,9 @@ def main():
 
     K = R.views_of(w.frames) if args.shared else 1
     group_frames = max(K, args.group // K * K)
+    # one zeroed g2d buffer for every group of every step: each group's projection backward
+    # reads its records and leaves them zero (no clear per group)
+    g2d_buf = torch.zeros(9 * w.gaussians.n * min(F, group_frames), dtype=torch.float32, device="cuda")
 
     # warm-up; the first warm-up step also counts the visited evaluations per group
     counts = {"fwd": 0, "bwd": 0, "blended": 0}
@@ -523,7 +528,7 @@ def main():
     # the counting pass is an extra (untimed) step that also asks the forward for n_contrib
     def l1_step(gm, gr, shared=args.shared, **kw):
         return R.train_step(gm, w.cameras, luts, w.frames, targets, gr, args.group, w.opts, loss_acc=loss_acc,
-                            shared=shared, **kw)
+                            shared=shared, g2d=g2d_buf, **kw)
 
     # Visits are counted on every frame's own list (the algorithm's work); a frame on a
     # shared list visits the same entries and drops the rest at staging.
@@ -631,7 +636,7 @@ def main():
         def full_iter(timer=R.NO_TIMER):
             grads.zero_()
             r = R.train_step(g, w.cameras, luts, w.frames, targets, grads, args.group, w.opts, ssim_lambda=0.2,
-                             shared=args.shared, capacity=fcap,
+                             shared=args.shared, capacity=fcap, g2d=g2d_buf,
                              loss_acc=loss_acc, densify=dens, timer=timer, read_loss=False)
             with timer("adam"):
                 opt.step([grads.d_means, grads.d_log_scales, grads.d_quats, grads.d_scalars] +
@@ -651,7 +656,7 @@ def main():
         for st in fst:
             R.check_status(st, fcap)
         ft = {k: round(sum(v) / args.full_steps, 3) for k, v in ftimer.totals_ms().items()
-              if k in ("image_loss", "densify_stats", "adam")}
+              if k in ("image_loss", "project_bwd", "adam")}
         full = {"mpix_s": round(F * H * W * args.full_steps / fdt / 1e6, 2),
                 "ms_per_step": round(fdt * 1e3 / args.full_steps, 3), "ssim_lambda": 0.2, "kernel_ms_per_step": ft}
         del dens, opt

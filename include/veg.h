@@ -417,6 +417,19 @@ typedef struct {
 veg_status veg_project_bwd(const veg_gaussians* g, const veg_proj* proj, const veg_opts* opts,
                            const float* g2d, const veg_grads* grads, veg_stream_t stream);
 
+/* veg_project_bwd_fused -- veg_project_bwd with two neighbours of the training loop of
+ * section "Training" folded into its pass over g2d (same gradients, bit for bit):
+ *   grad_accum, vis_count  optional (both or neither): the densification statistics of
+ *                          veg_densify_stats from the same reads (same values, ADDED)
+ *   consume_g2d            non-zero: every g2d record is left zero after it is read, so the
+ *                          buffer is ready for the next veg_render_bwd without a clear
+ *                          (g2d is then device float, written)
+ * Errors: as veg_project_bwd; VEG_ERR_INVALID_ARG when only one of grad_accum, vis_count
+ * is given. */
+veg_status veg_project_bwd_fused(const veg_gaussians* g, const veg_proj* proj, const veg_opts* opts, float* g2d,
+                                 const veg_grads* grads, float* grad_accum, int32_t* vis_count, int32_t consume_g2d,
+                                 veg_stream_t stream);
+
 /* ----------------------------------------------------------------------------------
  * Loss and utilities
  * ---------------------------------------------------------------------------------- */

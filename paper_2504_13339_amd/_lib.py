@@ -112,6 +112,8 @@ _SIGS = {
     "veg_render_bwd": (c_int, [P(veg_proj), P(veg_bins), P(veg_opts), c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p]),
     "veg_project_bwd": (c_int, [P(veg_gaussians), P(veg_proj), P(veg_opts), c_void_p, P(veg_grads), c_void_p]),
+    "veg_project_bwd_fused": (c_int, [P(veg_gaussians), P(veg_proj), P(veg_opts), c_void_p, P(veg_grads), c_void_p,
+                                      c_void_p, c_int32, c_void_p]),
     "veg_l1_loss": (c_int, [c_void_p, c_void_p, c_int64, c_float, c_void_p, c_void_p, c_void_p]),
     "veg_fill_u32": (c_int, [c_void_p, c_int64, c_uint32, c_void_p]),
     "veg_ssim_workspace_bytes": (c_size_t, [c_int64, c_int32, c_int32]),

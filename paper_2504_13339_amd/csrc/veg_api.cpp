@@ -483,9 +483,50 @@ veg_status veg_project_bwd(const veg_gaussians* g, const veg_proj* proj, const v
   veg_opts o;
   s = resolve_opts(opts, &o);
   if (s != VEG_OK) return s;
-  VEG_CHECK_HIP(launch_project_bwd((const FrameDesc*)proj->frames, proj->n_frames, (int)g->n, kopts(&o), g2d,
-                                   (uint32_t)pairs_of(proj), *grads, (hipStream_t)stream),
+  VEG_CHECK_HIP(launch_project_bwd((const FrameDesc*)proj->frames, proj->n_frames, (int)g->n, kopts(&o),
+                                   const_cast<float*>(g2d), (uint32_t)pairs_of(proj), *grads, (hipStream_t)stream),
                 "veg_project_bwd");
+  return VEG_OK;
+}
+
+veg_status veg_project_bwd_fused(const veg_gaussians* g, const veg_proj* proj, const veg_opts* opts, float* g2d,
+                                 const veg_grads* grads, float* grad_accum, int32_t* vis_count, int32_t consume_g2d,
+                                 veg_stream_t stream) {
+  g_err.clear();
+  if ((grad_accum == nullptr) != (vis_count == nullptr))
+    return fail(VEG_ERR_INVALID_ARG, "project_bwd_fused: grad_accum and vis_count must both be given or both NULL");
+  veg_status s = check_gaussians(g);
+  if (s != VEG_OK) return s;
+  s = check_projected(proj);
+  if (s != VEG_OK) return s;
+  if (proj->n != g->n) return fail(VEG_ERR_INVALID_ARG, "project_bwd_fused: proj->n != g->n");
+  if (!grads || (g->n > 0 && (!g2d || !grads->d_means || !grads->d_log_scales || !grads->d_quats ||
+                              !grads->d_scalars)))
+    return fail(VEG_ERR_INVALID_ARG, "project_bwd_fused: NULL gradient buffer");
+  if (grads->d_weights && !g->weights)
+    return fail(VEG_ERR_INVALID_ARG, "project_bwd_fused: d_weights given but the model has no weights");
+  {
+    const int lg = (grads->d_normals != nullptr) + (grads->d_k_ambient != nullptr) +
+                   (grads->d_k_diffuse != nullptr) + (grads->d_k_specular != nullptr) +
+                   (grads->d_shininess != nullptr);
+    if (lg != 0 && lg != 5)
+      return fail(VEG_ERR_INVALID_ARG, "project_bwd_fused: lighting gradients must be all NULL or all given");
+    if (lg == 5 && !g->normals)
+      return fail(VEG_ERR_INVALID_ARG, "project_bwd_fused: lighting gradients given but the model has no lighting");
+  }
+  veg_opts o;
+  s = resolve_opts(opts, &o);
+  if (s != VEG_OK) return s;
+  BwdFused fu;
+  fu.count = proj->count;
+  fu.depth = proj->depth;
+  fu.rec = (const float4*)proj->rec;
+  fu.acc = grad_accum;
+  fu.vis = vis_count;
+  fu.consume = consume_g2d != 0;
+  VEG_CHECK_HIP(launch_project_bwd((const FrameDesc*)proj->frames, proj->n_frames, (int)g->n, kopts(&o), g2d,
+                                   (uint32_t)pairs_of(proj), *grads, (hipStream_t)stream, fu),
+                "veg_project_bwd_fused");
   return VEG_OK;
 }
 

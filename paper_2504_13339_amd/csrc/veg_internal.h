@@ -79,8 +79,20 @@ hipError_t write_blob(void* dst_dev, const void* src_host, size_t bytes, hipStre
 hipError_t launch_project(const FrameDesc* descs, int n_frames, int n_max, const KOpts& o,
                           float4* rec, uint32_t* count, uint32_t* depth, bool shared_model,
                           hipStream_t stream);
+// Extras of the projection backward: the densification statistics from the same g2d reads
+// (acc, vis: per Gaussian, added; count/depth/rec of the projection for the kept test) and,
+// with consume, every g2d record left zero after it is read.
+struct BwdFused {
+  const uint32_t* count = nullptr;
+  const uint32_t* depth = nullptr;
+  const float4* rec = nullptr;
+  float* acc = nullptr;
+  int32_t* vis = nullptr;
+  int consume = 0;
+};
 hipError_t launch_project_bwd(const FrameDesc* descs, int n_frames, int n, const KOpts& o,
-                              const float* g2d, uint32_t n_pairs, const veg_grads& grads, hipStream_t stream);
+                              float* g2d, uint32_t n_pairs, const veg_grads& grads, hipStream_t stream,
+                              const BwdFused& fused = BwdFused{});
 
 // Lighting attributes of a model and the camera centre (-R^T t of the world->camera
 // transform [R|t]) into a frame descriptor.

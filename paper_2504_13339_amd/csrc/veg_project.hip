@@ -403,14 +403,53 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
 
 // Adjoint of the projection: one thread per Gaussian, loop over the frames (which share the
 // model), accumulate in registers, add once to the parameter gradients.
+// Whether frame f keeps Gaussian i (the densification statistics' definition): its list
+// holds the Gaussian and, for a frame on a list shared by several frames, the frame's own
+// footprint keeps it (keep bit of its slot in the depth slots of the view's second frame;
+// from slot 31 on, the record's A > 0).
+__device__ __forceinline__ bool frame_keeps(const FrameDesc* __restrict__ descs, const FrameDesc& d, int i,
+                                            const BwdFused& fu) {
+  const FrameDesc& dl = descs[d.list_frame];
+  if (fu.count[(size_t)dl.pair_base + (size_t)i] == 0u) return false;
+  if (dl.n_share <= 1) return true;
+  if (d.slot < 31) return (fu.depth[(size_t)descs[d.list_frame + 1].pair_base + (size_t)i] >> d.slot) & 1u;
+  return fu.rec[3 * ((size_t)d.pair_base + (size_t)i) + 1].y > 0.0f;
+}
+
+// One thread per Gaussian, over every frame.  With kFused, the densification statistics are
+// taken from the same g2d reads (fu.acc/fu.vis, when given; frames in the order the separate
+// statistics pass takes them, so the sums are the same) and, with fu.consume, every g2d
+// record read is left zero.
+template <bool kFused>
 __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __restrict__ descs, int n_frames,
-                                                          int n, KOpts o, const float* __restrict__ g2d,
-                                                          uint32_t n_pairs, veg_grads gr) {
+                                                          int n, KOpts o, float* __restrict__ g2d,
+                                                          uint32_t n_pairs, veg_grads gr, BwdFused fu) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   GParams g;
   load_params(descs[0], i, g);
-  if (!g.finite || !(g.n2 >= 1e-24f) || !(g.nn2 >= 1e-24f)) return;
+  float st_acc = 0.0f;
+  int st_vis = 0;
+  if (!g.finite || !(g.n2 >= 1e-24f) || !(g.nn2 >= 1e-24f)) {
+    // no parameter gradient; the statistics and the consumption of g2d as below
+    if (kFused) {
+      for (int f = 0; f < n_frames; ++f) {
+        const size_t pid = (size_t)descs[f].pair_base + (size_t)i;
+        if (fu.acc && frame_keeps(descs, descs[f], i, fu)) {
+          const float gx = g2d[pid * 9 + 0], gy = g2d[pid * 9 + 1];
+          st_acc += sqrtf(gx * gx + gy * gy);
+          ++st_vis;
+        }
+        if (fu.consume)
+          for (int c = 0; c < 9; ++c) g2d[pid * 9 + c] = 0.0f;
+      }
+      if (fu.acc) {
+        fu.acc[i] += st_acc;
+        fu.vis[i] += st_vis;
+      }
+    }
+    return;
+  }
   float dmu[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ds[3] = {0, 0, 0};
   float dv = 0.0f, dw = 0.0f;
   float dn[3] = {0, 0, 0}, dka = 0.0f, dkd = 0.0f, dks = 0.0f, dbeta = 0.0f;
@@ -434,6 +473,14 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __res
       for (int c = 0; c < 9; ++c) {
         gg[c] = g2d[pid * 9 + c];
         anyk |= (gg[c] != 0.0f);
+      }
+      if (kFused) {
+        if (fu.acc && frame_keeps(descs, dk, i, fu)) {
+          st_acc += sqrtf(gg[0] * gg[0] + gg[1] * gg[1]);
+          ++st_vis;
+        }
+        if (fu.consume && anyk)
+          for (int c = 0; c < 9; ++c) g2d[pid * 9 + c] = 0.0f;
       }
       if (!anyk) continue;
       TfSample tf;
@@ -578,6 +625,10 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(const FrameDesc* __res
     gr.d_k_specular[i] += dks;
     gr.d_shininess[i] += dbeta;
   }
+  if (kFused && fu.acc) {
+    fu.acc[i] += st_acc;
+    fu.vis[i] += st_vis;
+  }
 }
 
 __global__ void debug_math_kernel(int op, const float* x, const float* y, float* out, int64_t n) {
@@ -623,11 +674,15 @@ hipError_t launch_project(const FrameDesc* descs, int n_frames, int n_max, const
   return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const FrameDesc* descs, int n_frames, int n, const KOpts& o, const float* g2d,
-                              uint32_t n_pairs, const veg_grads& grads, hipStream_t stream) {
+hipError_t launch_project_bwd(const FrameDesc* descs, int n_frames, int n, const KOpts& o, float* g2d,
+                              uint32_t n_pairs, const veg_grads& grads, hipStream_t stream, const BwdFused& fused) {
   if (n <= 0 || n_frames <= 0) return hipSuccess;
-  hipLaunchKernelGGL(project_bwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, descs, n_frames, n, o, g2d,
-                     n_pairs, grads);
+  if (fused.acc || fused.consume)
+    hipLaunchKernelGGL(project_bwd_kernel<true>, dim3((n + 255) / 256), dim3(256), 0, stream, descs, n_frames, n, o,
+                       g2d, n_pairs, grads, fused);
+  else
+    hipLaunchKernelGGL(project_bwd_kernel<false>, dim3((n + 255) / 256), dim3(256), 0, stream, descs, n_frames, n, o,
+                       g2d, n_pairs, grads, fused);
   return hipGetLastError();
 }
 

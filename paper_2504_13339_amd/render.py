@@ -164,16 +164,29 @@ def alloc_g2d(proj: V.Proj, stream=None) -> torch.Tensor:
 
 
 def render_backward(g: V.Gaussians, st: FwdState, d_image: torch.Tensor, grads: Grads, stream=None,
-                    g2d: Optional[torch.Tensor] = None, timer=NO_TIMER) -> torch.Tensor:
-    """Accumulates dL/dparams into ``grads`` given dL/dimage; returns the screen-space g2d."""
+                    g2d: Optional[torch.Tensor] = None, timer=NO_TIMER, densify=None,
+                    consume_g2d: bool = False) -> torch.Tensor:
+    """Accumulates dL/dparams into ``grads`` given dL/dimage; returns the screen-space g2d.
+    ``g2d`` (optional) must hold zeros; with ``consume_g2d`` the projection backward leaves
+    it zero again, ready for the next call.  ``densify`` (with grad_accum, vis_count) adds
+    the densification statistics from the same pass."""
     if g2d is None:
         with timer("zero_g2d"):
             g2d = alloc_g2d(st.proj, stream=stream)
+    elif g2d.numel() < 9 * st.proj.n_pairs:
+        raise ValueError("g2d holds fewer than 9 floats per pair")
     with timer("blend_bwd"):
         V.veg_render_bwd(st.proj, st.bins, st.opts, st.t_final, st.n_last, d_image.contiguous(), g2d, stream=stream)
     with timer("project_bwd"):
-        V.veg_project_bwd(g, st.proj, st.opts, g2d, grads.d_means, grads.d_log_scales, grads.d_quats,
-                          grads.d_scalars, grads.d_weights, stream=stream, d_lighting=grads.lighting)
+        if densify is None and not consume_g2d:
+            V.veg_project_bwd(g, st.proj, st.opts, g2d, grads.d_means, grads.d_log_scales, grads.d_quats,
+                              grads.d_scalars, grads.d_weights, stream=stream, d_lighting=grads.lighting)
+        else:
+            V.veg_project_bwd_fused(g, st.proj, st.opts, g2d, grads.d_means, grads.d_log_scales, grads.d_quats,
+                                    grads.d_scalars, grads.d_weights, stream=stream, d_lighting=grads.lighting,
+                                    grad_accum=None if densify is None else densify.grad_accum,
+                                    vis_count=None if densify is None else densify.vis_count,
+                                    consume_g2d=consume_g2d)
     return g2d
 
 
@@ -269,7 +282,7 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
                targets: torch.Tensor, grads: Grads, group: int, opts=None, ssim_lambda: float = 0.0, stream=None,
                loss_acc: Optional[torch.Tensor] = None, read_loss: bool = True, timer=NO_TIMER, on_group=None,
                want_contrib: bool = False, densify: Optional[DensifyStats] = None,
-               shared=False, capacity: Optional[int] = None) -> StepResult:
+               shared=False, capacity: Optional[int] = None, g2d: Optional[torch.Tensor] = None) -> StepResult:
     """One multi-view x multi-TF training step with the image loss
     (1 - lambda) mean|image - target| + lambda mean(1 - SSIM), means over all frames,
     channels and pixels.
@@ -292,7 +305,11 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
     without a host synchronisation until the loss is read (``read_loss``), when the entry
     counts and overflow flags are read with it; a list that did not fit raises
     KeyListOverflow (the gradients of that step are then incomplete).  With ``read_loss``
-    False the flags are in ``StepResult.status``, for ``check_status`` later."""
+    False the flags are in ``StepResult.status``, for ``check_status`` later.
+
+    ``g2d`` (optional): a float32 buffer of at least 9 x (pairs of the largest group)
+    zeros that the caller keeps between steps; every group's backward uses it and leaves it
+    zero, so no clear is needed per group (``alloc_g2d`` sizes one for a projection)."""
     o = V.make_opts(opts) if not hasattr(opts, "alpha_clamp") else opts
     if not 0.0 <= ssim_lambda <= 1.0:
         raise ValueError("ssim_lambda must lie in [0, 1]")
@@ -341,13 +358,14 @@ def train_step(g: V.Gaussians, cams: Sequence, tfs: Sequence[torch.Tensor], fram
             with timer("image_loss"):
                 ssim_ws = V.veg_image_loss(st.image, tgt, (1.0 - ssim_lambda) / M, ssim_lambda / M, loss_acc,
                                            d_image, ws=ssim_ws, stream=stream)
-        g2d = render_backward(g, st, d_image, grads, stream=stream, timer=timer)
-        if densify is not None:
-            with timer("densify_stats"):
-                V.veg_densify_stats(st.proj, g2d, densify.grad_accum, densify.vis_count, stream=stream)
+        # the densification statistics come from the projection backward's g2d reads; a
+        # caller-kept g2d buffer is consumed (left zero) instead of cleared for every group
+        gbuf = g2d[:max(1, 9 * st.proj.n_pairs)] if g2d is not None else None
+        g2d_g = render_backward(g, st, d_image, grads, stream=stream, timer=timer, g2d=gbuf, densify=densify,
+                                consume_g2d=g2d is not None)
         if on_group is not None:
             on_group(f0, st)
-        del st, d_image, g2d
+        del st, d_image, g2d_g
     if fuse_l1:
         torch.sum(slots, 0, keepdim=True, out=loss_acc)
     loss = float(loss_acc.item()) if read_loss else float("nan")

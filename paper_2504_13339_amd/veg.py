@@ -19,7 +19,7 @@ __all__ = [
     "Gaussians", "Proj", "Bins", "default_opts", "make_opts", "veg_project", "veg_bin_count", "veg_bin_sort",
     "veg_bin_overflow", "veg_bin_status", "veg_render_fwd", "veg_render_bwd", "veg_project_bwd", "veg_l1_loss", "veg_fill_u32",
     "veg_debug_math", "veg_bin_hit_words", "alloc_proj", "alloc_bins", "alloc_bin_workspace", "stream_handle",
-    "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_image_loss", "veg_adam_step", "veg_densify_stats", "veg_project_views",
+    "veg_ssim_workspace_bytes", "veg_ssim_loss", "veg_image_loss", "veg_project_bwd_fused", "veg_adam_step", "veg_densify_stats", "veg_project_views",
     "veg_vq_decode", "decode_vq_model", "veg_densify_plan", "veg_densify_apply", "veg_densify_workspace_bytes",
     "KEEP", "CLONE", "SPLIT", "PRUNE", "FIELD_COPY", "FIELD_MEANS", "FIELD_LOG_SCALES", "FIELD_ZERO_NEW",
 ]
@@ -296,6 +296,21 @@ def veg_project_bwd(g: Gaussians, proj: Proj, opts, g2d: torch.Tensor, d_means, 
                         *(_ptr(t) for t in lg))
     check(load().veg_project_bwd(ctypes.byref(gs), ctypes.byref(proj.struct), ctypes.byref(o), _ptr(g2d),
                                  ctypes.byref(gr), stream_handle(stream)), "veg_project_bwd")
+
+
+def veg_project_bwd_fused(g: Gaussians, proj: Proj, opts, g2d: torch.Tensor, d_means, d_log_scales, d_quats,
+                          d_scalars, d_weights=None, stream=None, d_lighting=None, grad_accum=None, vis_count=None,
+                          consume_g2d: bool = False):
+    """veg_project_bwd plus, from the same g2d reads, the densification statistics (when
+    ``grad_accum`` and ``vis_count`` are given) and, with ``consume_g2d``, g2d left zero."""
+    o = opts if isinstance(opts, _lib.veg_opts) else make_opts(opts)
+    gs = g.struct()
+    lg = (None,) * 5 if d_lighting is None else tuple(d_lighting)
+    gr = _lib.veg_grads(_ptr(d_means), _ptr(d_log_scales), _ptr(d_quats), _ptr(d_scalars), _ptr(d_weights),
+                        *(_ptr(t) for t in lg))
+    check(load().veg_project_bwd_fused(ctypes.byref(gs), ctypes.byref(proj.struct), ctypes.byref(o), _ptr(g2d),
+                                       ctypes.byref(gr), _ptr(grad_accum), _ptr(vis_count), int(bool(consume_g2d)),
+                                       stream_handle(stream)), "veg_project_bwd_fused")
 
 
 def veg_l1_loss(image: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.Tensor, d_image: torch.Tensor,

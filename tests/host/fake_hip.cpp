@@ -205,8 +205,8 @@ hipError_t write_blob(void* dst, const void* src, size_t bytes, hipStream_t s) {
 hipError_t launch_project(const FrameDesc*, int, int, const KOpts&, float4*, uint32_t*, uint32_t*, bool, hipStream_t) {
   return hipSuccess;
 }
-hipError_t launch_project_bwd(const FrameDesc*, int, int, const KOpts&, const float*, uint32_t, const veg_grads&,
-                              hipStream_t) {
+hipError_t launch_project_bwd(const FrameDesc*, int, int, const KOpts&, float*, uint32_t, const veg_grads&,
+                              hipStream_t, const BwdFused&) {
   return hipSuccess;
 }
 hipError_t launch_bin_count(const float4*, const uint32_t*, const uint32_t*, uint32_t, const BinWs& ws, hipStream_t s,

@@ -164,6 +164,17 @@ def test_densify_arguments_are_checked_on_host():
                                 ctypes.c_float(0.0), fake, None, fake, 4, None) == 1          # small workspace
 
 
+def test_fused_projection_backward_arguments_are_checked_on_host():
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    # the densification outputs come as a pair: one without the other is refused first
+    assert lib.veg_project_bwd_fused(None, None, None, fake, None, fake, None, 1, None) == 1
+    assert b"both" in lib.veg_last_error()
+    assert lib.veg_project_bwd_fused(None, None, None, fake, None, None, fake, 0, None) == 1
+
+
 def test_shared_runs_must_share_a_camera():
     import pytest
     from paper_2504_13339_amd import render as R

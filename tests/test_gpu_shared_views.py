@@ -295,3 +295,37 @@ def test_densify_visibility_on_a_view_of_34_tables_equals_own_lists():
         vis[shared] = dens.vis_count.cpu().numpy()
     assert vis[False].sum() > 0
     assert np.array_equal(vis[True], vis[False])
+
+
+@pytest.mark.parametrize("K,tents,views", [(1, False, 2), (3, False, 2), (34, True, 1)])
+def test_fused_projection_backward_equals_the_separate_passes(K, tents, views):
+    """veg_project_bwd_fused: parameter gradients and densification statistics bit for bit
+    those of veg_project_bwd followed by veg_densify_stats (own lists, a view of three
+    tables, a view of 34 tent maps whose slots from 31 on test the record), and the consumed
+    g2d left all zero."""
+    V, R = hip()
+    w = _case(n=1500, views=views, K=K, res=64, tents=tents)
+    g = to_dev(w.gaussians)
+    luts = luts_to_dev(w.tfs)
+    cams = w.cameras if K > 1 else [w.cameras[c] for c, _ in w.frames]
+    st = R.render(g, cams, [luts[t] for _, t in w.frames], OPTS, shared=K > 1)
+    rng = np.random.default_rng(41)
+    d_img = torch.as_tensor(rng.standard_normal(tuple(st.image.shape)).astype(np.float32)).cuda()
+    g2d = R.alloc_g2d(st.proj)
+    V.veg_render_bwd(st.proj, st.bins, st.opts, st.t_final, st.n_last, d_img, g2d)
+    g2d_b = g2d.clone()
+    n = w.gaussians.n
+    ga, da = R.Grads.zeros(g), R.DensifyStats.zeros(n)
+    V.veg_project_bwd(g, st.proj, st.opts, g2d, ga.d_means, ga.d_log_scales, ga.d_quats, ga.d_scalars, ga.d_weights)
+    V.veg_densify_stats(st.proj, g2d, da.grad_accum, da.vis_count)
+    gb, db = R.Grads.zeros(g), R.DensifyStats.zeros(n)
+    V.veg_project_bwd_fused(g, st.proj, st.opts, g2d_b, gb.d_means, gb.d_log_scales, gb.d_quats, gb.d_scalars,
+                            gb.d_weights, grad_accum=db.grad_accum, vis_count=db.vis_count, consume_g2d=True)
+    torch.cuda.synchronize()
+    for name in ("d_means", "d_log_scales", "d_quats", "d_scalars", "d_weights"):
+        a, b = getattr(ga, name), getattr(gb, name)
+        if a is not None:
+            assert torch.equal(a, b), name
+    assert torch.equal(da.grad_accum, db.grad_accum)
+    assert torch.equal(da.vis_count, db.vis_count) and int(da.vis_count.sum()) > 0
+    assert float(g2d.abs().sum()) > 0 and not bool(g2d_b.any())
