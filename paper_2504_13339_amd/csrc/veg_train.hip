@@ -33,34 +33,72 @@ __device__ __forceinline__ float win11(const float* v, const Win& w) {
   return a;
 }
 
-// Input tile of one plane with zeros outside the image.  When rows are 16-byte aligned (W a
-// multiple of 4 and an aligned plane; x0 is a multiple of 32) each tile row is read as 12 aligned float4 covering
-// columns x0 - 8 .. x0 + 39, of which the 42 in x0 - 5 .. x0 + 36 are kept; a float4 then lies
-// wholly inside or wholly outside the image.
-__device__ __forceinline__ void load_tile(const float* __restrict__ src, int W, int H, int x0, int y0,
-                                          float (*dst)[kPadIn]) {
-  if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15u) == 0) {
-    constexpr int kVec = 12;
-    for (int k = threadIdx.x; k < kIn * kVec; k += blockDim.x) {
+// Input tile of one plane with zeros outside the image, in two steps so that a block can
+// have the next tile's loads in flight while it works on the current one: fetch (global ->
+// registers) and put (registers -> LDS).  When rows are 16-byte aligned (W a multiple of 4
+// and an aligned plane; x0 is a multiple of 32) each tile row is read as 12 aligned float4
+// covering columns x0 - 8 .. x0 + 39, of which the 42 in x0 - 5 .. x0 + 36 are kept; a
+// float4 then lies wholly inside or wholly outside the image (2 float4 per thread).  Else
+// the 42 x 42 values are read one by one (7 per thread).
+constexpr int kVec = 12;
+struct Fetch {
+  float v[8];
+};
+
+template <bool kAligned>
+__device__ __forceinline__ void fetch_tile(const float* __restrict__ src, int W, int H, int x0, int y0, Fetch& f) {
+  if (kAligned) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = threadIdx.x + 256 * j;
       const int ly = k / kVec, c = k - ly * kVec;
       const int gy = y0 - kHalf + ly, gx = x0 - 8 + 4 * c;
       float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = *reinterpret_cast<const float4*>(src + (size_t)gy * W + gx);
-      const float e[4] = {v.x, v.y, v.z, v.w};
+      if (k < kIn * kVec && gy >= 0 && gy < H && gx >= 0 && gx < W)
+        v = *reinterpret_cast<const float4*>(src + (size_t)gy * W + gx);
+      f.v[4 * j + 0] = v.x;
+      f.v[4 * j + 1] = v.y;
+      f.v[4 * j + 2] = v.z;
+      f.v[4 * j + 3] = v.w;
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const int k = threadIdx.x + 256 * j;
+    const int ly = k / kIn, lx = k - ly * kIn;
+    const int gx = x0 - kHalf + lx, gy = y0 - kHalf + ly;
+    f.v[j] = (k < kIn * kIn && gx >= 0 && gx < W && gy >= 0 && gy < H) ? src[(size_t)gy * W + gx] : 0.0f;
+  }
+}
+
+template <bool kAligned>
+__device__ __forceinline__ void put_tile(const Fetch& f, float (*dst)[kPadIn]) {
+  if (kAligned) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = threadIdx.x + 256 * j;
+      if (k >= kIn * kVec) continue;
+      const int ly = k / kVec, c = k - ly * kVec;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int lx = 4 * c + i - 3;
-        if (lx >= 0 && lx < kIn) dst[ly][lx] = e[i];
+        if (lx >= 0 && lx < kIn) dst[ly][lx] = f.v[4 * j + i];
       }
     }
     return;
   }
-  for (int k = threadIdx.x; k < kIn * kIn; k += blockDim.x) {
-    const int ly = k / kIn, lx = k - ly * kIn;
-    const int gx = x0 - kHalf + lx, gy = y0 - kHalf + ly;
-    dst[ly][lx] = (gx >= 0 && gx < W && gy >= 0 && gy < H) ? src[(size_t)gy * W + gx] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const int k = threadIdx.x + 256 * j;
+    if (k < kIn * kIn) dst[k / kIn][k % kIn] = f.v[j];
   }
 }
+
+
+// Tiles along x per block: each block walks kTilesX output tiles of one row of tiles,
+// fetching the next tile's inputs before it runs the current tile's window passes.
+constexpr int kTilesX = 4;
 
 // Per tile: windowed means of x, y, x^2, y^2, x y, the SSIM map S and its partial
 // derivatives with respect to mu_x, E[x^2] and E[x y] at every pixel:
@@ -69,7 +107,7 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ src, int W, 
 //   dS/dE[xy] = 2 A1 / D.
 // The three maps are stored multiplied by dL/dS = -weight for the backward pass.  With kL1
 // the L1 term l1_scale * sum |x - y| over the tile's own pixels joins the loss.
-template <bool kL1>
+template <bool kL1, bool kAligned>
 __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
                                                        int W, int H, float weight, float l1_scale,
                                                        double* __restrict__ loss, float* __restrict__ dmaps,
@@ -77,68 +115,81 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
   __shared__ float s_x[kIn][kPadIn], s_y[kIn][kPadIn];
   __shared__ float s_h[5][kIn][kPadT];
   __shared__ double s_part[2][4];
-  const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
+  const int y0 = blockIdx.y * kT;
   const size_t plane = blockIdx.z;
   const size_t HW = (size_t)W * H;
-  load_tile(img + plane * HW, W, H, x0, y0, s_x);
-  load_tile(tgt + plane * HW, W, H, x0, y0, s_y);
-  __syncthreads();
-  // horizontal: 42 rows x 8 groups of 4 columns
-  for (int task = threadIdx.x; task < kIn * (kT / kB); task += blockDim.x) {
-    const int r = task / (kT / kB), c0 = (task - r * (kT / kB)) * kB;
-    float p[5][kB + 2 * kHalf];
-#pragma unroll
-    for (int i = 0; i < kB + 2 * kHalf; ++i) {
-      const float xv = s_x[r][c0 + i], yv = s_y[r][c0 + i];
-      p[0][i] = xv;
-      p[1][i] = yv;
-      p[2][i] = xv * xv;
-      p[3][i] = yv * yv;
-      p[4][i] = xv * yv;
-    }
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-#pragma unroll
-      for (int i = 0; i < kB; ++i) s_h[q][r][c0 + i] = win11(&p[q][i], win);
-  }
-  __syncthreads();
-  // vertical: 32 columns x 8 groups of 4 rows, one task per thread
+  const float* ip = img + plane * HW;
+  const float* tp = tgt + plane * HW;
+  Fetch fx, fy;
+  int x0 = blockIdx.x * kTilesX * kT;
+  fetch_tile<kAligned>(ip, W, H, x0, y0, fx);
+  fetch_tile<kAligned>(tp, W, H, x0, y0, fy);
   double part = 0.0, part_l1 = 0.0;
-  {
-    const int c = threadIdx.x & (kT - 1), r0 = (threadIdx.x / kT) * kB;
-    float m[5][kB];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      float v[kB + 2 * kHalf];
-#pragma unroll
-      for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_h[q][r0 + i][c];
-#pragma unroll
-      for (int i = 0; i < kB; ++i) m[q][i] = win11(&v[i], win);
+  for (int t = 0; t < kTilesX && x0 < W; ++t, x0 += kT) {
+    put_tile<kAligned>(fx, s_x);
+    put_tile<kAligned>(fy, s_y);
+    __syncthreads();
+    if (t + 1 < kTilesX && x0 + kT < W) {   // the next tile's loads overlap this tile's passes
+      fetch_tile<kAligned>(ip, W, H, x0 + kT, y0, fx);
+      fetch_tile<kAligned>(tp, W, H, x0 + kT, y0, fy);
     }
-    const int gx = x0 + c;
+    // horizontal: 42 rows x 8 groups of 4 columns
+    for (int task = threadIdx.x; task < kIn * (kT / kB); task += blockDim.x) {
+      const int r = task / (kT / kB), c0 = (task - r * (kT / kB)) * kB;
+      float p[5][kB + 2 * kHalf];
 #pragma unroll
-    for (int i = 0; i < kB; ++i) {
-      const int gy = y0 + r0 + i;
-      if (gx >= W || gy >= H) continue;
-      const float mx = m[0][i], my = m[1][i];
-      const float sx = m[2][i] - mx * mx, sy = m[3][i] - my * my, sxy = m[4][i] - mx * my;
-      const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * sxy + kC2;
-      const float B1 = mx * mx + my * my + kC1, B2 = sx + sy + kC2;
-      const float D = B1 * B2;
-      const float S = (A1 * A2) / D;
-      part += (double)(1.0f - S);
-      if (kL1) part_l1 += (double)fabsf(s_x[r0 + i + kHalf][c + kHalf] - s_y[r0 + i + kHalf][c + kHalf]);
-      // one reciprocal for the three maps (S keeps its division: identical images give
-      // S = 1 exactly, and then dex2 = -(B1 rD) and dexy = 2 (B1 rD) cancel in the adjoint)
-      const float rD = 1.0f / D;
-      const float dmu = (2.0f * my * (A2 - A1) - 2.0f * mx * S * (B2 - B1)) * rD;
-      const float dex2 = -S * B1 * rD;
-      const float dexy = 2.0f * A1 * rD;
-      const size_t pi = plane * HW + (size_t)gy * W + gx;
-      dmaps[pi] = -weight * dmu;
-      dmaps[plane_stride + pi] = -weight * dex2;
-      dmaps[2 * plane_stride + pi] = -weight * dexy;
+      for (int i = 0; i < kB + 2 * kHalf; ++i) {
+        const float xv = s_x[r][c0 + i], yv = s_y[r][c0 + i];
+        p[0][i] = xv;
+        p[1][i] = yv;
+        p[2][i] = xv * xv;
+        p[3][i] = yv * yv;
+        p[4][i] = xv * yv;
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int i = 0; i < kB; ++i) s_h[q][r][c0 + i] = win11(&p[q][i], win);
     }
+    __syncthreads();
+    // vertical: 32 columns x 8 groups of 4 rows, one task per thread
+    {
+      const int c = threadIdx.x & (kT - 1), r0 = (threadIdx.x / kT) * kB;
+      float m[5][kB];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        float v[kB + 2 * kHalf];
+#pragma unroll
+        for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_h[q][r0 + i][c];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) m[q][i] = win11(&v[i], win);
+      }
+      const int gx = x0 + c;
+#pragma unroll
+      for (int i = 0; i < kB; ++i) {
+        const int gy = y0 + r0 + i;
+        if (gx >= W || gy >= H) continue;
+        const float mx = m[0][i], my = m[1][i];
+        const float sx = m[2][i] - mx * mx, sy = m[3][i] - my * my, sxy = m[4][i] - mx * my;
+        const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * sxy + kC2;
+        const float B1 = mx * mx + my * my + kC1, B2 = sx + sy + kC2;
+        const float D = B1 * B2;
+        const float S = (A1 * A2) / D;
+        part += (double)(1.0f - S);
+        if (kL1) part_l1 += (double)fabsf(s_x[r0 + i + kHalf][c + kHalf] - s_y[r0 + i + kHalf][c + kHalf]);
+        // one reciprocal for the three maps (S keeps its division: identical images give
+        // S = 1 exactly, and then dex2 = -(B1 rD) and dexy = 2 (B1 rD) cancel in the adjoint)
+        const float rD = 1.0f / D;
+        const float dmu = (2.0f * my * (A2 - A1) - 2.0f * mx * S * (B2 - B1)) * rD;
+        const float dex2 = -S * B1 * rD;
+        const float dexy = 2.0f * A1 * rD;
+        const size_t pi = plane * HW + (size_t)gy * W + gx;
+        dmaps[pi] = -weight * dmu;
+        dmaps[plane_stride + pi] = -weight * dex2;
+        dmaps[2 * plane_stride + pi] = -weight * dexy;
+      }
+    }
+    __syncthreads();   // s_x, s_y and s_h are rewritten for the next tile
   }
   for (int off = 32; off > 0; off >>= 1) {
     part += __shfl_xor(part, off);
@@ -162,54 +213,77 @@ __global__ __launch_bounds__(256) void ssim_fwd_kernel(const float* __restrict__
 // d_image.  With kL1, d_image is not read: it is written as the L1 term's gradient
 // l1_scale * sign(x - y) plus that sum, the same value, rounding included, as the L1 pass
 // followed by the SSIM pass.
-template <bool kL1>
+template <bool kL1, bool kAligned>
 __global__ __launch_bounds__(256) void ssim_bwd_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
                                                        int W, int H, const float* __restrict__ dmaps,
                                                        size_t plane_stride, float* __restrict__ dimg, float l1_scale,
                                                        Win win) {
   __shared__ float s_m[3][kIn][kPadIn];
   __shared__ float s_h[3][kIn][kPadT];
-  const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
+  const int y0 = blockIdx.y * kT;
   const size_t plane = blockIdx.z;
   const size_t HW = (size_t)W * H;
-  for (int q = 0; q < 3; ++q) load_tile(dmaps + q * plane_stride + plane * HW, W, H, x0, y0, s_m[q]);
-  __syncthreads();
-  for (int task = threadIdx.x; task < kIn * (kT / kB); task += blockDim.x) {
-    const int r = task / (kT / kB), c0 = (task - r * (kT / kB)) * kB;
+  const float* mp = dmaps + plane * HW;
+  Fetch fm[3];
+  int x0 = blockIdx.x * kTilesX * kT;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) fetch_tile<kAligned>(mp + q * plane_stride, W, H, x0, y0, fm[q]);
+  const int c = threadIdx.x & (kT - 1), r0 = (threadIdx.x / kT) * kB;
+  for (int t = 0; t < kTilesX && x0 < W; ++t, x0 += kT) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) put_tile<kAligned>(fm[q], s_m[q]);
+    __syncthreads();
+    if (t + 1 < kTilesX && x0 + kT < W) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) fetch_tile<kAligned>(mp + q * plane_stride, W, H, x0 + kT, y0, fm[q]);
+    }
+    // this tile's own pixels of image and target, read ahead of the window passes
+    const int gx = x0 + c;
+    float xi[kB], yi[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int gy = y0 + r0 + i;
+      const bool in = gx < W && gy < H;
+      const size_t pi = plane * HW + (size_t)gy * W + gx;
+      xi[i] = in ? img[pi] : 0.0f;
+      yi[i] = in ? tgt[pi] : 0.0f;
+    }
+    for (int task = threadIdx.x; task < kIn * (kT / kB); task += blockDim.x) {
+      const int r = task / (kT / kB), c0 = (task - r * (kT / kB)) * kB;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        float v[kB + 2 * kHalf];
+#pragma unroll
+        for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_m[q][r][c0 + i];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) s_h[q][r][c0 + i] = win11(&v[i], win);
+      }
+    }
+    __syncthreads();
+    float m[3][kB];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       float v[kB + 2 * kHalf];
 #pragma unroll
-      for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_m[q][r][c0 + i];
+      for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_h[q][r0 + i][c];
 #pragma unroll
-      for (int i = 0; i < kB; ++i) s_h[q][r][c0 + i] = win11(&v[i], win);
+      for (int i = 0; i < kB; ++i) m[q][i] = win11(&v[i], win);
     }
-  }
-  __syncthreads();
-  const int c = threadIdx.x & (kT - 1), r0 = (threadIdx.x / kT) * kB;
-  float m[3][kB];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    float v[kB + 2 * kHalf];
-#pragma unroll
-    for (int i = 0; i < kB + 2 * kHalf; ++i) v[i] = s_h[q][r0 + i][c];
-#pragma unroll
-    for (int i = 0; i < kB; ++i) m[q][i] = win11(&v[i], win);
-  }
-  const int gx = x0 + c;
-#pragma unroll
-  for (int i = 0; i < kB; ++i) {
-    const int gy = y0 + r0 + i;
-    if (gx >= W || gy >= H) continue;
-    const size_t pi = plane * HW + (size_t)gy * W + gx;
-    const float x = img[pi], y = tgt[pi];
-    const float g = (m[0][i] + 2.0f * x * m[1][i]) + y * m[2][i];
-    if (kL1) {
-      const float d = x - y;
-      dimg[pi] = (d > 0.0f ? l1_scale : (d < 0.0f ? -l1_scale : 0.0f)) + g;
-    } else {
-      dimg[pi] += g;
+    for (int i = 0; i < kB; ++i) {
+      const int gy = y0 + r0 + i;
+      if (gx >= W || gy >= H) continue;
+      const size_t pi = plane * HW + (size_t)gy * W + gx;
+      const float x = xi[i], y = yi[i];
+      const float g = (m[0][i] + 2.0f * x * m[1][i]) + y * m[2][i];
+      if (kL1) {
+        const float d = x - y;
+        dimg[pi] = (d > 0.0f ? l1_scale : (d < 0.0f ? -l1_scale : 0.0f)) + g;
+      } else {
+        dimg[pi] += g;
+      }
     }
+    __syncthreads();   // s_m and s_h are rewritten for the next tile
   }
 }
 
@@ -423,23 +497,37 @@ static Win ssim_window() {
   return w;
 }
 
+template <bool kL1, bool kAligned>
+static void ssim_pair(dim3 grid, hipStream_t stream, const float* image, const float* target, int W, int H,
+                      float weight, float l1_scale, double* loss, float* d_image, float* dmaps, size_t plane_stride,
+                      const Win& win) {
+  hipLaunchKernelGGL((ssim_fwd_kernel<kL1, kAligned>), grid, dim3(256), 0, stream, image, target, W, H, weight,
+                     l1_scale, loss, dmaps, plane_stride, win);
+  hipLaunchKernelGGL((ssim_bwd_kernel<kL1, kAligned>), grid, dim3(256), 0, stream, image, target, W, H, dmaps,
+                     plane_stride, d_image, l1_scale, win);
+}
+
 hipError_t launch_ssim(const float* image, const float* target, int64_t n_planes, int W, int H, float weight,
                        double* loss, float* d_image, float* dmaps, hipStream_t stream, bool with_l1,
                        float l1_scale) {
   if (n_planes <= 0 || W <= 0 || H <= 0) return hipSuccess;
   const size_t plane_stride = (size_t)n_planes * W * H;
-  const dim3 grid((W + kT - 1) / kT, (H + kT - 1) / kT, (unsigned)n_planes);
+  const int tiles_x = (W + kT - 1) / kT;
+  const dim3 grid((tiles_x + kTilesX - 1) / kTilesX, (H + kT - 1) / kT, (unsigned)n_planes);
   const Win win = ssim_window();
+  // rows of 16-byte aligned float4 in every plane of the image, the target and the maps
+  const bool aligned = (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(image) | reinterpret_cast<uintptr_t>(target) |
+                                         reinterpret_cast<uintptr_t>(dmaps)) & 15u) == 0;
   if (with_l1) {
-    hipLaunchKernelGGL(ssim_fwd_kernel<true>, grid, dim3(256), 0, stream, image, target, W, H, weight, l1_scale, loss,
-                       dmaps, plane_stride, win);
-    hipLaunchKernelGGL(ssim_bwd_kernel<true>, grid, dim3(256), 0, stream, image, target, W, H, dmaps, plane_stride,
-                       d_image, l1_scale, win);
+    if (aligned) ssim_pair<true, true>(grid, stream, image, target, W, H, weight, l1_scale, loss, d_image, dmaps,
+                                       plane_stride, win);
+    else ssim_pair<true, false>(grid, stream, image, target, W, H, weight, l1_scale, loss, d_image, dmaps,
+                                plane_stride, win);
   } else {
-    hipLaunchKernelGGL(ssim_fwd_kernel<false>, grid, dim3(256), 0, stream, image, target, W, H, weight, 0.0f, loss,
-                       dmaps, plane_stride, win);
-    hipLaunchKernelGGL(ssim_bwd_kernel<false>, grid, dim3(256), 0, stream, image, target, W, H, dmaps, plane_stride,
-                       d_image, 0.0f, win);
+    if (aligned) ssim_pair<false, true>(grid, stream, image, target, W, H, weight, 0.0f, loss, d_image, dmaps,
+                                        plane_stride, win);
+    else ssim_pair<false, false>(grid, stream, image, target, W, H, weight, 0.0f, loss, d_image, dmaps,
+                                 plane_stride, win);
   }
   return hipGetLastError();
 }
