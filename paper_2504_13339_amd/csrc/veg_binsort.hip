@@ -497,9 +497,10 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep_kernel(const uint32_t* __
   }
 }
 
-// Stable scatter of one digit pass.  Each tile of 2048 items is ranked in LDS (per-wave
+// Stable scatter of one digit pass.  Each tile of 4096 items is ranked in LDS (per-wave
 // digit counters updated by the lowest lane of each equal-digit group), reordered by digit
-// in LDS, and written out so that equal digits land in consecutive global slots.
+// in LDS, and written out so that equal digits land in consecutive global slots.  The next
+// tile's keys and values are loaded while the current one is scanned and scattered.
 __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* n_ptr, uint32_t n_cap, int shift, int nbits,
@@ -518,16 +519,22 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
   const uint32_t mask = (1u << nbits) - 1u;
   const uint64_t lt = lanemask_lt();
   s_glob[t] = hist[(size_t)t * G + blockIdx.x];
+  uint32_t key[kSortIpt], val[kSortIpt];
+#pragma unroll
+  for (int r = 0; r < kSortIpt; ++r) {
+    const uint32_t i = begin + (uint32_t)(w * (kSortTile / kWaves) + r * 64 + lane);
+    const bool valid = i < end;
+    key[r] = valid ? kin[i] : 0u;
+    val[r] = valid ? vin[i] : 0u;
+  }
   for (uint32_t t0 = begin; t0 < end; t0 += kSortTile) {
     for (int k = t; k < kWaves * kRadix; k += kThreads) (&s_cnt[0][0])[k] = 0u;
     __syncthreads();
-    uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
+    uint32_t rank[kSortIpt];
 #pragma unroll
     for (int r = 0; r < kSortIpt; ++r) {
       const uint32_t i = t0 + (uint32_t)(w * (kSortTile / kWaves) + r * 64 + lane);
       const bool valid = i < end;
-      key[r] = valid ? kin[i] : 0u;
-      val[r] = valid ? vin[i] : 0u;
       const uint32_t d = (key[r] >> shift) & mask;
       const uint64_t peers = match_digit(d, valid, nbits);
       const uint32_t below = (uint32_t)__popcll(peers & lt);
@@ -536,6 +543,15 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
       rank[r] = valid ? old + below : 0xffffffffu;
     }
     __syncthreads();
+    // the next tile's keys and values, in flight during this tile's scan and scatters
+    uint32_t nkey[kSortIpt], nval[kSortIpt];
+#pragma unroll
+    for (int r = 0; r < kSortIpt; ++r) {
+      const uint32_t i = t0 + kSortTile + (uint32_t)(w * (kSortTile / kWaves) + r * 64 + lane);
+      const bool valid = i < end;
+      nkey[r] = valid ? kin[i] : 0u;
+      nval[r] = valid ? vin[i] : 0u;
+    }
     uint32_t c[kWaves], tot = 0;
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) {
@@ -573,6 +589,11 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
     __syncthreads();
     s_glob[t] += tot;
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortIpt; ++r) {
+      key[r] = nkey[r];
+      val[r] = nval[r];
+    }
   }
 }
 
