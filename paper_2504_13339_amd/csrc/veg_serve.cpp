@@ -29,6 +29,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <sys/prctl.h>
+
 #include "veg_internal.h"
 
 namespace veg {
@@ -495,6 +497,9 @@ bool try_launch(veg_server* s, Slot& sl) {
 
 void scheduler(veg_server* s) {
   (void)hipSetDevice(s->device);
+  // Timed waits of this thread end within a microsecond of their deadline instead of the
+  // default 50 us timer slack: the 20 us completion polls below then take 20 us, not 70.
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     const double t = now_s();
