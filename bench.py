@@ -372,13 +372,12 @@ def serve_bench(rates, min_requests=2000, max_seconds=30.0, max_batch=8, n_strea
         ids = []
         for r in reqs:
             target = t0 + r.arrival_s
-            while True:
-                d = target - time.perf_counter()
-                if d <= 0:
-                    break
-                time.sleep(d - 0.0005 if d > 0.001 else 0)
+            while time.perf_counter() < target:   # the same busy-wait pacing as the plain loop
+                pass
             key = (r.camera.width, r.camera.height)
-            bufs = ring.setdefault(key, [torch.empty((3, key[1], key[0]), device="cuda") for _ in range(RING)])
+            bufs = ring.get(key)
+            if bufs is None:   # (allocated once per resolution, not on every request)
+                bufs = ring[key] = [torch.empty((3, key[1], key[0]), device="cuda") for _ in range(RING)]
             used = users.setdefault(key, [])
             k = len(used) % RING
             if len(used) >= RING and used[len(used) - RING] is not None:
