@@ -513,7 +513,9 @@ def main():
     group_frames = max(K, args.group // K * K)
     # one zeroed g2d buffer for every group of every step: each group's projection backward
     # reads its records and leaves them zero (no clear per group)
-    g2d_buf = torch.zeros(9 * w.gaussians.n * min(F, group_frames), dtype=torch.float32, device="cuda")
+    # (the counting step's groups, on own lists, are not rounded to whole views)
+    g2d_buf = torch.zeros(9 * w.gaussians.n * min(F, max(args.group, group_frames)), dtype=torch.float32,
+                          device="cuda")
 
     # warm-up; the first warm-up step also counts the visited evaluations per group
     counts = {"fwd": 0, "bwd": 0, "blended": 0}
