@@ -54,6 +54,26 @@ def test_host_side_argument_errors_without_gpu():
     assert lib.veg_status_str(6) == b"HIP error"
 
 
+def test_image_loss_arguments_are_checked_on_host():
+    """veg_image_loss refuses bad sizes, NULL buffers, non-finite weights and a small
+    workspace before anything is enqueued; an empty image is a no-op."""
+    import ctypes
+    from paper_2504_13339_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    f = ctypes.c_float
+    need = lib.veg_ssim_workspace_bytes(2, 8, 8)
+    assert lib.veg_image_loss(fake, fake, 70000, 8, 8, f(0.5), f(0.5), fake, fake, fake, need, None) == 1
+    assert b"sizes" in lib.veg_last_error()
+    assert lib.veg_image_loss(None, fake, 2, 8, 8, f(0.5), f(0.5), fake, fake, fake, need, None) == 1
+    assert b"NULL" in lib.veg_last_error()
+    assert lib.veg_image_loss(fake, fake, 2, 8, 8, f(float("nan")), f(0.5), fake, fake, fake, need, None) == 1
+    assert b"finite" in lib.veg_last_error()
+    assert lib.veg_image_loss(fake, fake, 2, 8, 8, f(0.5), f(0.5), fake, fake, fake, need - 4, None) == 1
+    assert b"workspace" in lib.veg_last_error()
+    assert lib.veg_image_loss(None, None, 0, 8, 8, f(0.5), f(0.5), None, None, None, 0, None) == 0
+
+
 def test_bin_status_arguments_are_checked_on_host():
     """veg_bin_status rejects a missing or small workspace and a NULL or misaligned
     destination before any device call (host pointers stand in for device ones)."""
