@@ -223,14 +223,20 @@ __device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbits) {
-  uint64_t peers = __ballot(valid);
-  for (int b = 0; b < nbits; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t m = __ballot(bit);
-    peers &= bit ? m : ~m;
+// Lanes whose digit equals this lane's (valid lanes only).  Digits are below kRadix, so
+// all kRadixBits bits are compared whatever the pass's width (the bits above it are zero in
+// every lane); the fixed count lets the loop unroll.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  const uint64_t v = __ballot(valid);
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const uint32_t t = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // all ones where the bit is set
+    const uint64_t m = __ballot(t != 0u);
+    lo &= ~((uint32_t)m ^ t);                  // lanes whose bit equals this lane's
+    hi &= ~((uint32_t)(m >> 32) ^ t);
   }
-  return valid ? peers : 0ull;
+  return valid ? ((uint64_t)hi << 32 | lo) : 0ull;
 }
 
 constexpr int kEmitItems = 1024;   // items per LDS tile of the emission
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(kThreads) void emit_radix_kernel(const FrameDesc* _
           const uint32_t sl = (uint32_t)(w * (kChunk / kWaves) + r * 64 + lane);
           const bool valid = sl < nvalid;
           const uint32_t d = key[r] & mask;
-          const uint64_t peers = match_digit(d, valid, nbits);
+          const uint64_t peers = match_digit(d, valid);
           const uint32_t below = (uint32_t)__popcll(peers & lt);
           const uint32_t old = valid ? s_cnt[w][d] : 0u;
           if (valid && below == 0u) s_cnt[w][d] = old + (uint32_t)__popcll(peers);
@@ -536,7 +542,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
       const uint32_t i = t0 + (uint32_t)(w * (kSortTile / kWaves) + r * 64 + lane);
       const bool valid = i < end;
       const uint32_t d = (key[r] >> shift) & mask;
-      const uint64_t peers = match_digit(d, valid, nbits);
+      const uint64_t peers = match_digit(d, valid);
       const uint32_t below = (uint32_t)__popcll(peers & lt);
       const uint32_t old = valid ? s_cnt[w][d] : 0u;
       if (valid && below == 0u) s_cnt[w][d] = old + (uint32_t)__popcll(peers);
