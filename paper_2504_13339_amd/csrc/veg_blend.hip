@@ -275,10 +275,13 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
       s_k[slot] = (int)(lane | (qm << 8));
     }
     __syncthreads();
-    uint64_t lq[4] = {0ull, 0ull, 0ull, 0ull};   // bit k: pixel r of this lane blended entry base + k
-    for (int k = 0; k < n; ++k) {
+    // Bit k of lq[r]: pixel r of this lane blended entry base + k.  The packed entries from
+    // batch positions 0-31 come first (n_lo of them), so the walk goes in two runs, each
+    // setting bits of one 32-bit half: one OR per blend instead of two.
+    uint32_t lq_lo[4] = {0u, 0u, 0u, 0u}, lq_hi[4] = {0u, 0u, 0u, 0u};
+    auto walk = [&](const int k, uint32_t (&lq)[4]) {
       const uint32_t kq = (uint32_t)__builtin_amdgcn_readfirstlane(s_k[k]);
-      const int kk = (int)(kq & 0xffu);       // position in the batch
+      const uint32_t bit = 1u << (kq & 31u);   // position in the batch, modulo 32
       const float4 g = s_geo[k];
       const float4 c = s_col[k];
       const float cb = s_b[k];
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
         if (!(kq & (0x100u << r))) continue;   // quadrant out of the entry's reach (uniform)
         const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, c.x, (r >> 1) ? dy1 : dy0);
         if (T[r] >= tmin && e >= l2min) {
-          lq[r] |= 1ull << kk;
+          lq[r] |= bit;
           const float alpha = __uint_as_float(min(__float_as_uint(__builtin_amdgcn_exp2f(e)), aclamp_bits));
           const float w = alpha * T[r];
           C[r][0] = fmaf(w, c.z, C[r][0]);
@@ -301,10 +304,16 @@ __global__ __launch_bounds__(64) void blend_fwd_kernel(const FrameDesc* __restri
           if (kCount) ++cnt[r];
         }
       }
-    }
+    };
+    const int n_lo = __builtin_amdgcn_readfirstlane(__popc((uint32_t)m));
+    for (int k = 0; k < n_lo; ++k) walk(k, lq_lo);
+    for (int k = n_lo; k < n; ++k) walk(k, lq_hi);
+    uint64_t lq[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
+      lq[r] = (uint64_t)lq_hi[r] << 32 | lq_lo[r];
       if (lq[r]) last[r] = (int)base + 63 - __clzll(lq[r]);
+    }
     if (kHits) {
       const uint64_t word = wave_or_u64(lq[0] | lq[1] | lq[2] | lq[3]);
       if (lane == 63) fhits[hit_word(rg.x, dl.tile_base + tile, (base - rg.x) >> 6)] = word;
