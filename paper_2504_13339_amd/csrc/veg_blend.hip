@@ -78,6 +78,9 @@ __device__ __forceinline__ uint32_t quad_mask(const Staged& s, float l2min) {
 // log2 of A exp(-sigma) for a pixel centre at (px, py) in tile-local coordinates:
 //   base = l2A - q0 dx^2,  e = base - dy (q2 dy + q1 dx).
 __device__ __forceinline__ float exponent_base(float q0, float l2A, float dx) { return fmaf(-q0 * dx, dx, l2A); }
+// The same from nq0 = -q0 (the backward stages it negated): negation is exact, so the
+// product and the result are bit for bit those of exponent_base.
+__device__ __forceinline__ float exponent_base_neg(float nq0, float l2A, float dx) { return fmaf(nq0 * dx, dx, l2A); }
 __device__ __forceinline__ float exponent(float base, float q1dx, float q2, float dy) {
   return fmaf(-dy, fmaf(q2, dy, q1dx), base);
 }
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
   const int32_t* nlp = nlast + (size_t)frame * HW;
   const float* dip = dimage + (size_t)frame * 3 * HW;
 
-  __shared__ float4 s_geo[kBatch];   // mx, my, q0, q1
+  __shared__ float4 s_geo[kBatch];   // mx, my, -q0, q1
   __shared__ float4 s_q[kBatch];     // q2, l2A, R, G
   __shared__ float4 s_con[kBatch];   // conic a, b, c, B
   __shared__ float2 s_pa[kBatch];    // pair id (bits), 1/A
@@ -528,7 +531,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     if (mine) {
       const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(todo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)todo, 0u));
       const Staged s = stage(r0, r1, r2, tx, ty);
-      s_geo[slot] = make_float4(s.mx, s.my, s.q0, s.q1);
+      s_geo[slot] = make_float4(s.mx, s.my, -s.q0, s.q1);
       s_q[slot] = make_float4(s.q2, s.l2A, r1.z, r1.w);
       s_con[slot] = make_float4(r0.z, r0.w, r1.x, r2.x);
       // A = 0 marks an entry this frame's footprint culls (shared lists): never blended, and
@@ -545,7 +548,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
       const float cbv = s_con[k].w;
       const float rgbv[3] = {q.z, q.w, cbv};
       const float dx0 = pxl0 - g.x, dx1 = pxl1 - g.x;
-      const float eb0 = exponent_base(g.z, q.y, dx0), eb1 = exponent_base(g.z, q.y, dx1);
+      const float eb0 = exponent_base_neg(g.z, q.y, dx0), eb1 = exponent_base_neg(g.z, q.y, dx1);
       const float q1dx0 = g.w * dx0, q1dx1 = g.w * dx1;
       const float dy0 = pyl0 - g.y, dy1 = pyl1 - g.y;
 #pragma unroll
@@ -565,7 +568,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
           const float dalpha = grgb - GS[r];
           GS[r] = fmaf(alpha, dalpha, GS[r]);
           T[r] = Tk;
-          const float dsig = clamped ? 0.0f : -(dalpha * Tk) * a;   // dL/dsigma
+          // dL/dsigma = -dL/dalpha * a = -(dalpha Tk) a, and unclamped a Tk is w
+          const float dsig = clamped ? 0.0f : -(dalpha * w);
           const float u = dsig * dx, v = dsig * dy;
           acc[0] += u;
           acc[1] += v;
