@@ -312,6 +312,7 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
     TfSample tf;
     uint32_t x0 = 0u, x1 = 0u, y0 = 0u, y1 = 0u;
     float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, mxr = 0.0f, myr = 0.0f;
+    float A = 0.0f;   // the largest A over the frames sharing the list
     if (act) {
       if (d.means != cur || d.scalars != cur_v || d.weights != cur_w || d.normals != cur_n) {
         load_params(d, i, g);
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
       tf_lookup(d, keep ? g.v : 0.0f, tf);
       // Frames sharing this list: the footprint at the largest A over their tables contains
       // each frame's own, so it decides the list; only the owner's pair is counted.
-      float A = tf.O * g.w;
+      A = tf.O * g.w;
       for (int k = 1; k < n_share; ++k) {
         const FrameDesc& dk = descs[f + k];
         count[dk.pair_base + (uint32_t)i] = 0u;
@@ -369,7 +370,8 @@ __global__ __launch_bounds__(256) void project_kernel(const FrameDesc* __restric
         float Ak = tk.O * g.w;
         if (!(Ak >= o.alpha_min)) Ak = 0.0f;
         uint32_t inset = 0u;   // own tile rectangle inside the shared one
-        if (n_share > 1 && Ak > 0.0f) {
+        // the frame whose A is the largest has the shared footprint itself (no insets)
+        if (n_share > 1 && Ak > 0.0f && Ak != A) {
           double a0, a1, b0, b1;
           if (!pixel_range(p, Ak, o, d.W, d.H, a0, a1, b0, b1)) {
             Ak = 0.0f;
