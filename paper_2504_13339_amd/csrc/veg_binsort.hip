@@ -505,8 +505,9 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep_kernel(const uint32_t* __
 
 // Stable scatter of one digit pass.  Each tile of 4096 items is ranked in LDS (per-wave
 // digit counters updated by the lowest lane of each equal-digit group), reordered by digit
-// in LDS, and written out so that equal digits land in consecutive global slots.  The next
-// tile's keys and values are loaded while the current one is scanned and scattered.
+// in LDS, and written out so that equal digits land in consecutive global slots (kout NULL:
+// values only).  The next tile's keys and values are loaded while the current one is
+// scanned and scattered.
 __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* n_ptr, uint32_t n_cap, int shift, int nbits,
@@ -589,7 +590,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
       const uint32_t k2 = s_keys[i];
       const uint32_t d = (k2 >> shift) & mask;
       const uint32_t g = s_glob[d] + (i - s_off[d]);
-      kout[g] = k2;
+      if (kout) kout[g] = k2;
       vout[g] = s_vals[i];
     }
     __syncthreads();
@@ -673,11 +674,14 @@ int sort_blocks(int64_t n) { return blocks_for(n, 2 * kSortTile, kMaxSortBlocks)
 
 // LSD radix sort of (key, val) over bits [first_bit, bits): ping-pongs between (k0,v0) and
 // (k1,v1); the result ends in (k0,v0) when the number of passes is even, else in (k1,v1).
+// Without final_keys the last pass writes only the values (its keys are not needed).
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_ptr, uint32_t n_cap,
-                      int bits, uint32_t* hist, uint64_t* partials, hipStream_t stream, int first_bit = 0) {
+                      int bits, uint32_t* hist, uint64_t* partials, hipStream_t stream, int first_bit = 0,
+                      bool final_keys = true) {
   const int G = sort_blocks(n_cap);
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   for (int shift = first_bit; shift < bits; shift += kRadixBits) {
+    const bool last = shift + kRadixBits >= bits;
     const int nb = min(kRadixBits, bits - shift);
     hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, n_ptr, n_cap, shift, nb, hist, G);
     // exclusive scan of the digit-major histogram (kRadix * G values)
@@ -687,8 +691,8 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, co
     hipLaunchKernelGGL(scan_reduce_kernel<kRaw>, dim3(Gs), dim3(kThreads), 0, stream, src, nullptr, hn, partials, Gs);
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, partials, Gs, nullptr, nullptr);
     hipLaunchKernelGGL(hist_scan_down_kernel, dim3(Gs), dim3(kThreads), 0, stream, hist, hn, partials, Gs);
-    hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, vi, ko, vo, n_ptr, n_cap, shift,
-                       nb, hist, G);
+    hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, vi,
+                       (last && !final_keys) ? nullptr : ko, vo, n_ptr, n_cap, shift, nb, hist, G);
     uint32_t* tk = ki; ki = ko; ko = tk;
     uint32_t* tv = vi; vi = vo; vo = tv;
   }
@@ -769,9 +773,9 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint
                      Gv, ws.dkeyA, ws.dvalA);
   // 2. front-to-back order: 31 depth-key bits (camera z > 0)
   hipError_t e = radix_sort(ws.dkeyA, ws.dvalA, ws.dkeyB, ws.dvalB, ws.counters + 0, n_pairs, 31, ws.hist, ptmp,
-                            stream);
+                            stream, 0, false);
   if (e != hipSuccess) return e;
-  // 4 passes: the sorted list is back in (dkeyA, dvalA)
+  // 4 passes: the sorted values are back in dvalA (the sorted keys are not kept)
   // 3. item records and tile counts in that order (counts reuse dkeyB)
   hipLaunchKernelGGL(gather_items_kernel, dim3(blocks_for(n_pairs, kThreads * 4, 8192)), dim3(kThreads), 0, stream,
                      (const float4*)rec, ws.dvalA, ws.counters + 0, n_pairs, (uint4*)ws.items, ws.dkeyB);
