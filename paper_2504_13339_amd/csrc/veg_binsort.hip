@@ -60,12 +60,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp,
   return base + incl - v;
 }
 
-__device__ __forceinline__ uint32_t block_reduce(uint32_t v, uint32_t* s_tmp) {
-  uint32_t tot;
-  block_excl_scan(v, s_tmp, &tot);
-  return tot;
-}
-
 // ------------------------------------------------------------------------------ scans
 // Three item kinds share the reduce-then-scan machinery:
 //   kVis : item i of the pairs, value = count[i] > 0   (compaction of kept pairs)
@@ -74,36 +68,50 @@ __device__ __forceinline__ uint32_t block_reduce(uint32_t v, uint32_t* s_tmp) {
 enum ScanKind { kVis = 0, kCnt = 1, kRaw = 2 };
 
 struct ScanSrc {
-  const uint32_t* count;   // kVis, kCnt
-  const uint32_t* vals;    // kCnt
-  const uint32_t* data;    // kRaw
+  const uint32_t* count;   // kVis
+  const uint32_t* data;    // kCnt, kRaw
 };
 
+
 template <int KIND>
-__device__ __forceinline__ uint32_t item_value(const ScanSrc& s, uint32_t i) {
-  if (KIND == kVis) return s.count[i] > 0u ? 1u : 0u;
-  if (KIND == kCnt) return s.data[i];
-  return s.data[i];
+__device__ __forceinline__ uint32_t item_of_word(uint32_t w) {
+  return KIND == kVis ? (w > 0u ? 1u : 0u) : w;
 }
 
+// Block b's total over its segment.  Each thread sums its share of the whole segment (16-byte
+// loads where the array is 16-byte aligned; segments start at multiples of kTileItems), and
+// the block adds the threads' sums once at the end.
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(ScanSrc src, const uint32_t* n_ptr, uint32_t n_cap,
                                                                uint64_t* partials, int G) {
-  __shared__ uint32_t s_tmp[kWaves];
+  __shared__ uint64_t s_w[kWaves];
   const uint32_t n = read_count(n_ptr, n_cap);
   uint32_t begin, end;
   segment_of(n, G, blockIdx.x, begin, end);
+  const uint32_t* __restrict__ a = KIND == kVis ? src.count : src.data;
   uint64_t acc = 0;
-  for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kIpt; ++k) {
-      const uint32_t i = t0 + k * kThreads + threadIdx.x;
-      if (i < end) s += item_value<KIND>(src, i);
+  uint32_t i = begin + threadIdx.x;
+  if ((reinterpret_cast<uintptr_t>(a) & 15u) == 0) {
+    const uint32_t nv = (end - begin) / 4;
+    const uint4* a4 = reinterpret_cast<const uint4*>(a + begin);
+#pragma unroll 4
+    for (uint32_t v = threadIdx.x; v < nv; v += kThreads) {
+      const uint4 q = a4[v];
+      acc += (uint64_t)((item_of_word<KIND>(q.x) + item_of_word<KIND>(q.y)) +
+                        (item_of_word<KIND>(q.z) + item_of_word<KIND>(q.w)));
     }
-    acc += block_reduce(s, s_tmp);
+    i = begin + 4 * nv + threadIdx.x;
   }
-  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+  for (; i < end; i += kThreads) acc += item_of_word<KIND>(a[i]);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) t += s_w[k];
+    partials[blockIdx.x] = t;
+  }
 }
 
 // Exclusive scan of G <= 4096 partial sums in place (one block of 1024 threads).  The total
@@ -244,22 +252,101 @@ constexpr int kEIpt = kEmitItems / kThreads;
 
 // Emission fused with the first digit pass of the tile sort.  The j-th depth-sorted kept
 // pair p owns `count` consecutive output slots starting at its offset, holding (global tile,
-// p) for its rectangle's tiles in row-major order.  A block walks its items in tiles of
-// 1024 (offsets and rectangles in LDS) and their slots in chunks of 2048: every item
-// starting inside the chunk marks its first slot and a block-wide prefix maximum turns the
-// marks into the owner of every slot.  kPhase 0 counts the low `nbits` bits of the slots'
-// tile ids into the block's digit histogram (hist[d * G + b]); kPhase 1, after that
-// histogram has been scanned, regenerates the same slots, ranks each chunk by digit
-// (stable: slot order) and writes the entries straight to their place after the pass, so
-// the unsorted list is never stored.  Slots at or beyond `capacity` are dropped (overflow).
-template <int kPhase>
+// p) for its rectangle's tiles in row-major order.  Slots at or beyond `capacity` are
+// dropped (overflow).  Two kernels over the same block segments of the items:
+// emit_hist_kernel counts the low `nbits` bits of the slots' tile ids into each block's
+// digit histogram (hist[d * G + b]); after that histogram has been scanned,
+// emit_radix_kernel generates the slots, ranks them by digit and writes every entry
+// straight to its place after the pass, so the unsorted list is never stored.
+
+// The histogram needs no slots: a row of an item's rectangle holds the consecutive tile ids
+// base + q tiles_x + [0, w), whose digits form a run of w consecutive values modulo 2^nbits,
+// so each row adds one to a (wrapping) range of bins, kept as a difference array (two
+// updates per row; rows of 2^nbits tiles or more add whole turns to every bin).  An item
+// crossing `capacity` counts only its slots below it: whole rows, then the part of the next.
+__global__ __launch_bounds__(kThreads) void emit_hist_kernel(const FrameDesc* __restrict__ descs,
+                                                             const uint4* __restrict__ items,
+                                                             const uint32_t* __restrict__ counts,
+                                                             const uint32_t* __restrict__ v_ptr, uint32_t v_cap,
+                                                             const uint64_t* __restrict__ partials, int G,
+                                                             uint32_t capacity, int nbits, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_tmp[kWaves];
+  __shared__ int s_diff[kWaves][kRadix + 1];   // per wave; entry nb absorbs a range's end at nb
+  __shared__ uint32_t s_turns[kWaves];         // per wave: added to every bin
+  const uint32_t t = threadIdx.x;
+  const int w = (int)(t >> 6);
+  for (int k = (int)t; k < kWaves * (kRadix + 1); k += kThreads) (&s_diff[0][0])[k] = 0;
+  if (t < kWaves) s_turns[t] = 0u;
+  __syncthreads();
+  const uint32_t n = read_count(v_ptr, v_cap);
+  uint32_t begin, end;
+  segment_of(n, G, blockIdx.x, begin, end);
+  uint64_t base = partials[blockIdx.x];
+  const uint32_t nb = 1u << nbits, mask = nb - 1u;
+  const uint32_t i0 = t * kEIpt;
+  for (uint32_t t0 = begin; t0 < end; t0 += kEmitItems) {
+    uint32_t cn[kEIpt], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kEIpt; ++k) {
+      const uint32_t j = t0 + i0 + k;
+      cn[k] = j < end ? counts[j] : 0u;
+      sum += cn[k];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(sum, s_tmp, &tot);
+#pragma unroll
+    for (int k = 0; k < kEIpt; ++k) {
+      const uint64_t o = base + off;
+      off += cn[k];
+      if (cn[k] == 0u || o >= (uint64_t)capacity) continue;
+      const uint32_t lim = (uint32_t)min((uint64_t)cn[k], (uint64_t)capacity - o);
+      const uint4 it = items[t0 + i0 + k];
+      const FrameDesc& d = descs[it.w];
+      const uint32_t x0 = it.y & 0xffffu, y0 = it.y >> 16, x1 = it.z & 0xffffu;
+      const uint32_t wd = x1 - x0 + 1u, txn = (uint32_t)d.tiles_x;
+      const uint32_t rows = lim / wd, part = lim - rows * wd;
+      uint32_t row0 = d.tile_base + y0 * txn + x0;
+      for (uint32_t q = 0; q <= rows; ++q, row0 += txn) {
+        const uint32_t width = q < rows ? wd : part;
+        if (width == 0u) break;
+        if (width >> nbits) atomicAdd(&s_turns[w], width >> nbits);
+        const uint32_t r = width & mask;
+        if (r == 0u) continue;
+        const uint32_t a = row0 & mask, e = a + r;
+        atomicAdd(&s_diff[w][a], 1);
+        if (e <= nb) {
+          atomicAdd(&s_diff[w][e], -1);
+        } else {   // wraps: [a, nb) and [0, e - nb)
+          atomicAdd(&s_diff[w][0], 1);
+          atomicAdd(&s_diff[w][e - nb], -1);
+        }
+      }
+    }
+    base += tot;
+  }
+  __syncthreads();
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) v += s_diff[k][t];
+  uint32_t turns = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) turns += s_turns[k];
+  uint32_t dummy;
+  const uint32_t incl = block_excl_scan((uint32_t)v, s_tmp, &dummy) + (uint32_t)v;   // running sum of the differences
+  hist[(size_t)t * G + blockIdx.x] = t < nb ? incl + turns : 0u;
+}
+
+// The scatter: a block walks its items in tiles of 1024 (offsets and rectangles in LDS) and
+// their slots in chunks of 2048: every item starting inside the chunk marks its first slot
+// and a block-wide prefix maximum turns the marks into the owner of every slot; the chunk is
+// ranked by digit (stable: slot order) and written to the places the scanned histogram gives.
 __global__ __launch_bounds__(kThreads) void emit_radix_kernel(const FrameDesc* __restrict__ descs,
                                                               const uint4* __restrict__ items,
                                                               const uint32_t* __restrict__ counts,
                                                               const uint32_t* __restrict__ v_ptr, uint32_t v_cap,
                                                               const uint64_t* __restrict__ partials, int G,
                                                               uint32_t capacity, int nbits,
-                                                              uint32_t* __restrict__ hist,
+                                                              const uint32_t* __restrict__ hist,
                                                               uint32_t* __restrict__ keys,
                                                               uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_tmp[kWaves];
@@ -268,10 +355,10 @@ __global__ __launch_bounds__(kThreads) void emit_radix_kernel(const FrameDesc* _
   __shared__ uint32_t s_base[kEmitItems];   // global tile id of the rectangle's first tile
   __shared__ uint32_t s_shape[kEmitItems];  // rectangle width | tiles_x << 16
   __shared__ uint32_t s_own[kChunk];        // 1 + owning item of each slot; then sorted keys
-  __shared__ uint32_t s_sval[kChunk];       // sorted values (phase 1)
+  __shared__ uint32_t s_sval[kChunk];       // sorted values
   __shared__ uint32_t s_cnt[kWaves][kRadix];
-  __shared__ uint32_t s_doff[kRadix];       // chunk-local start of each digit (phase 1)
-  __shared__ uint32_t s_glob[kRadix];       // running global start of each digit (phase 1)
+  __shared__ uint32_t s_doff[kRadix];       // chunk-local start of each digit
+  __shared__ uint32_t s_glob[kRadix];       // running global start of each digit
   const uint32_t n = read_count(v_ptr, v_cap);
   uint32_t begin, end;
   segment_of(n, G, blockIdx.x, begin, end);
@@ -280,12 +367,7 @@ __global__ __launch_bounds__(kThreads) void emit_radix_kernel(const FrameDesc* _
   const int lane = t & 63, w = t >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
   const uint64_t lt = lanemask_lt();
-  if (kPhase == 0) {
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) s_cnt[k][t] = 0u;
-  } else {
-    s_glob[t] = hist[(size_t)t * G + blockIdx.x];
-  }
+  s_glob[t] = hist[(size_t)t * G + blockIdx.x];
   __syncthreads();
   const uint32_t i0 = t * kEIpt;
   for (uint32_t t0 = begin; t0 < end; t0 += kEmitItems) {
@@ -370,14 +452,7 @@ __global__ __launch_bounds__(kThreads) void emit_radix_kernel(const FrameDesc* _
           val[r] = s_pair[i];
         }
       }
-      if (kPhase == 0) {
-#pragma unroll
-        for (int r = 0; r < kR; ++r) {
-          const uint32_t sl = (uint32_t)(w * (kChunk / kWaves) + r * 64 + lane);
-          if (sl < nvalid) atomicAdd(&s_cnt[w][key[r] & mask], 1u);
-        }
-        __syncthreads();   // s_own is rewritten by the next chunk
-      } else {
+      {
 #pragma unroll
         for (int k = 0; k < kWaves; ++k) s_cnt[k][t] = 0u;
         __syncthreads();   // also: every thread has read its owners and the carry
@@ -433,12 +508,6 @@ __global__ __launch_bounds__(kThreads) void emit_radix_kernel(const FrameDesc* _
     }
     base += tot;
     __syncthreads();
-  }
-  if (kPhase == 0) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) c += s_cnt[k][t];
-    hist[(size_t)t * G + blockIdx.x] = c;
   }
 }
 
@@ -687,7 +756,7 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, co
     // exclusive scan of the digit-major histogram (kRadix * G values)
     const uint32_t hn = (uint32_t)(kRadix * G);
     const int Gs = scan_blocks(hn);
-    ScanSrc src{nullptr, nullptr, hist};
+    ScanSrc src{nullptr, hist};
     hipLaunchKernelGGL(scan_reduce_kernel<kRaw>, dim3(Gs), dim3(kThreads), 0, stream, src, nullptr, hn, partials, Gs);
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, partials, Gs, nullptr, nullptr);
     hipLaunchKernelGGL(hist_scan_down_kernel, dim3(Gs), dim3(kThreads), 0, stream, hist, hn, partials, Gs);
@@ -764,7 +833,7 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, stream, ws.counters, (int64_t)64, 0u);
   // 1. compaction of kept pairs
   const int Gv = scan_blocks(n_pairs);
-  ScanSrc vis{count, nullptr, nullptr};
+  ScanSrc vis{count, nullptr};
   hipLaunchKernelGGL(scan_reduce_kernel<kVis>, dim3(Gv), dim3(kThreads), 0, stream, vis, n_pairs_dev, n_pairs, ptmp,
                      Gv);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, ptmp, Gv, ws.counters + 8,
@@ -781,7 +850,7 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint
                      (const float4*)rec, ws.dvalA, ws.counters + 0, n_pairs, (uint4*)ws.items, ws.dkeyB);
   // 4. entry offsets in that order; block offsets stay in `partials` for the emission
   const int Gc = scan_blocks(n_pairs);
-  ScanSrc cnt{nullptr, nullptr, ws.dkeyB};
+  ScanSrc cnt{nullptr, ws.dkeyB};
   hipLaunchKernelGGL(scan_reduce_kernel<kCnt>, dim3(Gc), dim3(kThreads), 0, stream, cnt, ws.counters + 0, n_pairs,
                      partials, Gc);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, partials, Gc, ws.counters + 1, nullptr);
@@ -812,15 +881,15 @@ hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* r
   uint32_t* ov = (passes % 2) ? vals_alt : vals;
   const int Gc = scan_blocks(n_pairs);
   if (capacity > 0) {
-    hipLaunchKernelGGL(emit_radix_kernel<0>, dim3(Gc), dim3(kThreads), 0, stream, descs, (const uint4*)ws.items,
-                       ws.dkeyB, ws.counters + 0, n_pairs, partials, Gc, capacity, nb0, ws.hist, nullptr, nullptr);
+    hipLaunchKernelGGL(emit_hist_kernel, dim3(Gc), dim3(kThreads), 0, stream, descs, (const uint4*)ws.items,
+                       ws.dkeyB, ws.counters + 0, n_pairs, partials, Gc, capacity, nb0, ws.hist);
     const uint32_t hn = (uint32_t)(kRadix * Gc);
     const int Gs = scan_blocks(hn);
-    ScanSrc src{nullptr, nullptr, ws.hist};
+    ScanSrc src{nullptr, ws.hist};
     hipLaunchKernelGGL(scan_reduce_kernel<kRaw>, dim3(Gs), dim3(kThreads), 0, stream, src, nullptr, hn, ptmp, Gs);
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, ptmp, Gs, nullptr, nullptr);
     hipLaunchKernelGGL(hist_scan_down_kernel, dim3(Gs), dim3(kThreads), 0, stream, ws.hist, hn, ptmp, Gs);
-    hipLaunchKernelGGL(emit_radix_kernel<1>, dim3(Gc), dim3(kThreads), 0, stream, descs, (const uint4*)ws.items,
+    hipLaunchKernelGGL(emit_radix_kernel, dim3(Gc), dim3(kThreads), 0, stream, descs, (const uint4*)ws.items,
                        ws.dkeyB, ws.counters + 0, n_pairs, partials, Gc, capacity, nb0, ws.hist, ek, ev);
     if (passes > 1) {
       hipError_t e = radix_sort(ek, ev, ok, ov, ws.counters + 4, capacity, bits, ws.hist, ptmp, stream, nb0);
