@@ -106,6 +106,8 @@ veg_status check_gaussians(const veg_gaussians* g) {
 }
 
 size_t pairs_of(const veg_proj* p) { return (size_t)p->n_frames * (size_t)p->n; }
+// Frames a key list is shared by (1 for veg_project).
+static int per_view_of(const veg_proj* proj) { return proj->tfs_per_view > 1 ? proj->tfs_per_view : 1; }
 
 }  // namespace
 
@@ -260,7 +262,9 @@ veg_status veg_bin_count(const veg_proj* proj, void* ws, size_t ws_bytes, int64_
   carve_bin_ws(ws, (int64_t)pairs, &w);
   hipStream_t st = (hipStream_t)stream;
   if (pairs > 0) {
-    VEG_CHECK_HIP(launch_bin_count((const float4*)proj->rec, proj->count, proj->depth, (uint32_t)pairs, w, st), "veg_bin_count");
+    VEG_CHECK_HIP(launch_bin_count((const float4*)proj->rec, proj->count, proj->depth, (uint32_t)pairs, w, st, nullptr,
+                                   (uint32_t)proj->n, per_view_of(proj)),
+                  "veg_bin_count");
   } else {
     VEG_CHECK_HIP(launch_fill_u32(w.counters, 64, 0u, st), "veg_bin_count");
   }
@@ -317,7 +321,8 @@ veg_status veg_bin_static(const veg_proj* proj, const veg_bins* bins, int64_t* s
   carve_bin_ws(ws, (int64_t)pairs, &w);
   hipStream_t st = (hipStream_t)stream;
   if (pairs > 0) {
-    VEG_CHECK_HIP(launch_bin_count((const float4*)proj->rec, proj->count, proj->depth, (uint32_t)pairs, w, st),
+    VEG_CHECK_HIP(launch_bin_count((const float4*)proj->rec, proj->count, proj->depth, (uint32_t)pairs, w, st, nullptr,
+                                   (uint32_t)proj->n, per_view_of(proj)),
                   "veg_bin_static: count");
   } else {
     VEG_CHECK_HIP(launch_fill_u32(w.counters, 64, 0u, st), "veg_bin_static: count");
@@ -361,7 +366,6 @@ int64_t veg_bin_hit_words(int64_t capacity, int64_t total_tiles) {
 }
 
 // Frames per shared key list (0 in a struct not filled by veg_project_views means 1).
-static int per_view_of(const veg_proj* proj) { return proj->tfs_per_view > 1 ? proj->tfs_per_view : 1; }
 
 // Words of one frame slot's hit bits.
 static uint64_t hit_stride_of(const veg_proj* proj, const veg_bins* bins) {

@@ -73,6 +73,22 @@ struct ScanSrc {
 };
 
 
+// The pair slots a compaction walks.  When the frames of each view share the first frame's
+// key list (per_view frames a view), only that frame's slots can hold a kept pair: list
+// slot o = view * n + i is pair view * per_view * n + i, and skip = (per_view - 1) n is
+// what each earlier view adds (skip 0: every slot, in order).
+struct ListMap {
+  uint32_t n, skip;
+  double inv_n;
+};
+__device__ __forceinline__ uint32_t list_pair(uint32_t o, const ListMap& m) {
+  if (m.skip == 0u) return o;
+  uint64_t q = (uint64_t)((double)o * m.inv_n);   // within one of o / n
+  if (q * m.n > o) --q;
+  else if ((q + 1) * m.n <= o) ++q;
+  return o + (uint32_t)q * m.skip;
+}
+
 template <int KIND>
 __device__ __forceinline__ uint32_t item_of_word(uint32_t w) {
   return KIND == kVis ? (w > 0u ? 1u : 0u) : w;
@@ -83,7 +99,7 @@ __device__ __forceinline__ uint32_t item_of_word(uint32_t w) {
 // the block adds the threads' sums once at the end.
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(ScanSrc src, const uint32_t* n_ptr, uint32_t n_cap,
-                                                               uint64_t* partials, int G) {
+                                                               uint64_t* partials, int G, ListMap lm = ListMap{}) {
   __shared__ uint64_t s_w[kWaves];
   const uint32_t n = read_count(n_ptr, n_cap);
   uint32_t begin, end;
@@ -91,18 +107,18 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(ScanSrc src, cons
   const uint32_t* __restrict__ a = KIND == kVis ? src.count : src.data;
   uint64_t acc = 0;
   uint32_t i = begin + threadIdx.x;
-  if ((reinterpret_cast<uintptr_t>(a) & 15u) == 0) {
+  // groups of four slots stay consecutive pairs when n is a multiple of four
+  if ((reinterpret_cast<uintptr_t>(a) & 15u) == 0 && (lm.skip == 0u || (lm.n & 3u) == 0u)) {
     const uint32_t nv = (end - begin) / 4;
-    const uint4* a4 = reinterpret_cast<const uint4*>(a + begin);
 #pragma unroll 4
     for (uint32_t v = threadIdx.x; v < nv; v += kThreads) {
-      const uint4 q = a4[v];
+      const uint4 q = *reinterpret_cast<const uint4*>(a + list_pair(begin + 4 * v, lm));
       acc += (uint64_t)((item_of_word<KIND>(q.x) + item_of_word<KIND>(q.y)) +
                         (item_of_word<KIND>(q.z) + item_of_word<KIND>(q.w)));
     }
     i = begin + 4 * nv + threadIdx.x;
   }
-  for (; i < end; i += kThreads) acc += item_of_word<KIND>(a[i]);
+  for (; i < end; i += kThreads) acc += item_of_word<KIND>(a[list_pair(i, lm)]);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -155,7 +171,7 @@ __global__ __launch_bounds__(1024) void scan_partials_kernel(uint64_t* partials,
 }
 
 // Downsweep of the compaction: kept pair i goes to (dkey, dval)[pos] = (depth[i], i), in
-// index order.  A tile's items are read lane-strided (item t0 + k * 256 + thread, so every
+// index order (the list slots of `lm`).  A tile's items are read lane-strided (item t0 + k * 256 + thread, so every
 // load is coalesced); each wave ranks its 64 items of round k with a ballot, and the rounds'
 // and waves' kept counts are scanned in (round, wave) order -- index order -- so the kept
 // items of one wave and round land in consecutive slots and every store is contiguous.
@@ -163,7 +179,8 @@ __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __res
                                                            const uint32_t* __restrict__ depth,
                                                            const uint32_t* __restrict__ n_ptr, uint32_t n_cap,
                                                            const uint64_t* __restrict__ partials, int G,
-                                                           uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval) {
+                                                           uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
+                                                           ListMap lm) {
   __shared__ uint32_t s_wc[kIpt][kWaves];
   const uint32_t n = read_count(n_ptr, n_cap);
   uint32_t begin, end;
@@ -173,10 +190,12 @@ __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __res
   const uint64_t lt = lanemask_lt();
   for (uint32_t t0 = begin; t0 < end; t0 += kTileItems) {
     uint64_t m[kIpt];
+    uint32_t pr[kIpt];
 #pragma unroll
     for (int k = 0; k < kIpt; ++k) {
       const uint32_t i = t0 + k * kThreads + threadIdx.x;
-      m[k] = __ballot(i < end && count[i] > 0u);
+      pr[k] = list_pair(i, lm);
+      m[k] = __ballot(i < end && count[pr[k]] > 0u);
       if (lane == 0) s_wc[k][w] = (uint32_t)__popcll(m[k]);
     }
     __syncthreads();
@@ -193,10 +212,9 @@ __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __res
 #pragma unroll
     for (int k = 0; k < kIpt; ++k) {
       if ((m[k] >> lane) & 1ull) {
-        const uint32_t i = t0 + k * kThreads + threadIdx.x;
         const uint64_t pos = base + off[k] + (uint32_t)__popcll(m[k] & lt);
-        dkey[pos] = depth[i];
-        dval[pos] = i;
+        dkey[pos] = depth[pr[k]];
+        dval[pos] = pr[k];
       }
     }
     base += run;
@@ -827,19 +845,29 @@ void carve_bin_ws(void* ws, int64_t pairs, BinWs* out) {
 }
 
 hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,
-                            const BinWs& ws, hipStream_t stream, const uint32_t* n_pairs_dev) {
+                            const BinWs& ws, hipStream_t stream, const uint32_t* n_pairs_dev, uint32_t list_n,
+                            int per_view) {
   uint64_t* partials = (uint64_t*)ws.partials;
   uint64_t* ptmp = (uint64_t*)ws.partials_tmp;
+  // the slots the compaction walks: only list owners' when views share lists
+  ListMap lm{0u, 0u, 0.0};
+  uint32_t n_slots = n_pairs;
+  if (per_view > 1) {
+    if (n_pairs_dev || list_n == 0u || n_pairs % ((uint64_t)list_n * (uint32_t)per_view) != 0u)
+      return hipErrorInvalidValue;
+    lm = ListMap{list_n, (uint32_t)(per_view - 1) * list_n, 1.0 / (double)list_n};
+    n_slots = n_pairs / (uint32_t)per_view;
+  }
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kThreads), 0, stream, ws.counters, (int64_t)64, 0u);
   // 1. compaction of kept pairs
-  const int Gv = scan_blocks(n_pairs);
+  const int Gv = scan_blocks(n_slots);
   ScanSrc vis{count, nullptr};
-  hipLaunchKernelGGL(scan_reduce_kernel<kVis>, dim3(Gv), dim3(kThreads), 0, stream, vis, n_pairs_dev, n_pairs, ptmp,
-                     Gv);
+  hipLaunchKernelGGL(scan_reduce_kernel<kVis>, dim3(Gv), dim3(kThreads), 0, stream, vis, n_pairs_dev, n_slots, ptmp,
+                     Gv, lm);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, ptmp, Gv, ws.counters + 8,
                      ws.counters + 0);
-  hipLaunchKernelGGL(compact_kernel, dim3(Gv), dim3(kThreads), 0, stream, count, depth, n_pairs_dev, n_pairs, ptmp,
-                     Gv, ws.dkeyA, ws.dvalA);
+  hipLaunchKernelGGL(compact_kernel, dim3(Gv), dim3(kThreads), 0, stream, count, depth, n_pairs_dev, n_slots, ptmp,
+                     Gv, ws.dkeyA, ws.dvalA, lm);
   // 2. front-to-back order: 31 depth-key bits (camera z > 0)
   hipError_t e = radix_sort(ws.dkeyA, ws.dvalA, ws.dkeyB, ws.dvalB, ws.counters + 0, n_pairs, 31, ws.hist, ptmp,
                             stream, 0, false);

@@ -142,9 +142,12 @@ constexpr int kStaticBinMaxDevices = 64;
 hipError_t static_bin_scratch(void** out);
 
 // n_pairs bounds the pair count; when n_pairs_dev is non-null the actual count is read
-// from device memory (capacity mode, used by the server's captured graphs).
+// from device memory (capacity mode, used by the server's captured graphs).  With views of
+// per_view > 1 frames of list_n Gaussians sharing the first frame's list, only those first
+// frames' pair slots are compacted (n_pairs a multiple of list_n * per_view, no n_pairs_dev).
 hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,
-                            const BinWs& ws, hipStream_t stream, const uint32_t* n_pairs_dev = nullptr);
+                            const BinWs& ws, hipStream_t stream, const uint32_t* n_pairs_dev = nullptr,
+                            uint32_t list_n = 0, int per_view = 1);
 hipError_t launch_bin_sort(const FrameDesc* descs, int n_frames, const float4* rec,
                            const uint32_t* count, uint32_t n_pairs, uint32_t total_tiles,
                            const BinWs& ws, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,

@@ -210,7 +210,7 @@ hipError_t launch_project_bwd(const FrameDesc*, int, int, const KOpts&, float*, 
   return hipSuccess;
 }
 hipError_t launch_bin_count(const float4*, const uint32_t*, const uint32_t*, uint32_t, const BinWs& ws, hipStream_t s,
-                            const uint32_t*) {
+                            const uint32_t*, uint32_t, int) {
   uint32_t* c = ws.counters;
   return on_stream(s, [=] { std::memset(c, 0, 64 * sizeof(uint32_t)); });
 }
