@@ -89,6 +89,15 @@ __device__ __forceinline__ uint32_t list_pair(uint32_t o, const ListMap& m) {
   return o + (uint32_t)q * m.skip;
 }
 
+// Depth keys relative to the smallest kept one.  The compaction leaves, in range[0..1], the
+// complement of the smallest kept depth key and the largest (two maxima, from zero).  The
+// depth passes rank key - min: the same order, and when every kept key lies within 2^24 of
+// the smallest, the last pass (bits 24-31) would leave it unchanged and is skipped.
+__device__ __forceinline__ uint32_t key_base(const uint32_t* range) { return range ? ~range[0] : 0u; }
+__device__ __forceinline__ bool keys_narrow(const uint32_t* range) {
+  return range && ((range[1] - ~range[0]) >> 24) == 0u;
+}
+
 template <int KIND>
 __device__ __forceinline__ uint32_t item_of_word(uint32_t w) {
   return KIND == kVis ? (w > 0u ? 1u : 0u) : w;
@@ -180,8 +189,10 @@ __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __res
                                                            const uint32_t* __restrict__ n_ptr, uint32_t n_cap,
                                                            const uint64_t* __restrict__ partials, int G,
                                                            uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
-                                                           ListMap lm) {
+                                                           ListMap lm, uint32_t* __restrict__ block_range) {
   __shared__ uint32_t s_wc[kIpt][kWaves];
+  __shared__ uint32_t s_r[kWaves][2];
+  uint32_t kmax = 0u, kcmax = 0u;   // largest kept key and largest complement (smallest key)
   const uint32_t n = read_count(n_ptr, n_cap);
   uint32_t begin, end;
   segment_of(n, G, blockIdx.x, begin, end);
@@ -213,11 +224,56 @@ __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __res
     for (int k = 0; k < kIpt; ++k) {
       if ((m[k] >> lane) & 1ull) {
         const uint64_t pos = base + off[k] + (uint32_t)__popcll(m[k] & lt);
-        dkey[pos] = depth[pr[k]];
+        const uint32_t key = depth[pr[k]];
+        dkey[pos] = key;
         dval[pos] = pr[k];
+        kmax = max(kmax, key);
+        kcmax = max(kcmax, ~key);
       }
     }
     base += run;
+  }
+  // the block's extremes (both maxima from zero: a block without kept pairs leaves zeros)
+  for (int off = 32; off > 0; off >>= 1) {
+    kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, off));
+    kcmax = max(kcmax, (uint32_t)__shfl_xor((int)kcmax, off));
+  }
+  if (lane == 0) {
+    s_r[w][0] = kcmax;
+    s_r[w][1] = kmax;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    uint32_t v = 0u;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) v = max(v, s_r[k][threadIdx.x]);
+    block_range[2 * blockIdx.x + threadIdx.x] = v;
+  }
+}
+
+// range[0..1] = maxima over the G blocks' (complement of the smallest, largest) kept depth
+// keys (one block of 1024 threads).
+__global__ __launch_bounds__(1024) void key_range_kernel(const uint32_t* __restrict__ block_range, int G,
+                                                         uint32_t* __restrict__ range) {
+  __shared__ uint32_t s_r[16][2];
+  uint32_t a = 0u, b = 0u;
+  for (int i = threadIdx.x; i < G; i += 1024) {
+    a = max(a, block_range[2 * i]);
+    b = max(b, block_range[2 * i + 1]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a = max(a, (uint32_t)__shfl_xor((int)a, off));
+    b = max(b, (uint32_t)__shfl_xor((int)b, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_r[threadIdx.x >> 6][0] = a;
+    s_r[threadIdx.x >> 6][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    uint32_t v = 0u;
+    for (int k = 0; k < 16; ++k) v = max(v, s_r[k][threadIdx.x]);
+    range[threadIdx.x] = v;
   }
 }
 
@@ -225,11 +281,14 @@ __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __res
 // count scan and the emission need (pair id, tile rectangle, frame) and of its tile count,
 // so both later passes read sequentially.
 __global__ __launch_bounds__(kThreads) void gather_items_kernel(const float4* __restrict__ rec,
-                                                                const uint32_t* __restrict__ sorted_vals,
+                                                                const uint32_t* __restrict__ vals_a,
+                                                                const uint32_t* __restrict__ vals_b,
+                                                                const uint32_t* __restrict__ range,
                                                                 const uint32_t* __restrict__ v_ptr, uint32_t v_cap,
                                                                 uint4* __restrict__ items,
                                                                 uint32_t* __restrict__ counts) {
   const uint32_t n = read_count(v_ptr, v_cap);
+  const uint32_t* __restrict__ sorted_vals = keys_narrow(range) ? vals_b : vals_a;   // where the depth sort ended
   for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < n; j += gridDim.x * kThreads) {
     const uint32_t p = sorted_vals[j];
     const float4 r2 = rec[3 * (size_t)p + 2];
@@ -558,10 +617,13 @@ __global__ __launch_bounds__(kThreads) void hist_scan_down_kernel(uint32_t* __re
 // ------------------------------------------------------------------------------ radix sort
 
 // Per-block digit histogram of its segment, hist[d * G + b], counted with per-wave LDS
-// atomics (a skewed digit serialises one wave's atomics, which stays cheap).
+// atomics (a skewed digit serialises one wave's atomics, which stays cheap).  Digits are
+// those of key - key_base(range); with skip_narrow the pass does nothing on narrow keys.
 __global__ __launch_bounds__(kThreads) void rs_upsweep_kernel(const uint32_t* __restrict__ keys,
                                                               const uint32_t* n_ptr, uint32_t n_cap, int shift,
-                                                              int nbits, uint32_t* __restrict__ hist, int G) {
+                                                              int nbits, uint32_t* __restrict__ hist, int G,
+                                                              const uint32_t* range, int skip_narrow) {
+  if (skip_narrow && keys_narrow(range)) return;
   __shared__ uint32_t s_h[kWaves][kRadix];
   for (int k = threadIdx.x; k < kWaves * kRadix; k += kThreads) (&s_h[0][0])[k] = 0u;
   __syncthreads();
@@ -570,17 +632,18 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep_kernel(const uint32_t* __
   segment_of<kSortTile>(n, G, blockIdx.x, begin, end);
   const int w = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
+  const uint32_t kb = key_base(range);
   // segments start at multiples of kSortTile, so the 4-key vector loads are aligned
   const uint32_t nvec = (end - begin) / 4;
   for (uint32_t v = threadIdx.x; v < nvec; v += kThreads) {
     const uint4 k4 = *reinterpret_cast<const uint4*>(keys + begin + 4 * v);
-    atomicAdd(&s_h[w][(k4.x >> shift) & mask], 1u);
-    atomicAdd(&s_h[w][(k4.y >> shift) & mask], 1u);
-    atomicAdd(&s_h[w][(k4.z >> shift) & mask], 1u);
-    atomicAdd(&s_h[w][(k4.w >> shift) & mask], 1u);
+    atomicAdd(&s_h[w][((k4.x - kb) >> shift) & mask], 1u);
+    atomicAdd(&s_h[w][((k4.y - kb) >> shift) & mask], 1u);
+    atomicAdd(&s_h[w][((k4.z - kb) >> shift) & mask], 1u);
+    atomicAdd(&s_h[w][((k4.w - kb) >> shift) & mask], 1u);
   }
   const uint32_t tail = begin + 4 * nvec + threadIdx.x;
-  if (tail < end) atomicAdd(&s_h[w][(keys[tail] >> shift) & mask], 1u);
+  if (tail < end) atomicAdd(&s_h[w][((keys[tail] - kb) >> shift) & mask], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kThreads) {
     uint32_t c = 0;
@@ -598,7 +661,8 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep_kernel(const uint32_t* __
 __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* n_ptr, uint32_t n_cap, int shift, int nbits,
-    const uint32_t* __restrict__ hist, int G) {
+    const uint32_t* __restrict__ hist, int G, const uint32_t* range, int skip_narrow) {
+  if (skip_narrow && keys_narrow(range)) return;
   __shared__ uint32_t s_cnt[kWaves][kRadix];
   __shared__ uint32_t s_off[kRadix];
   __shared__ uint32_t s_glob[kRadix];
@@ -611,6 +675,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
   if (begin >= end) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
+  const uint32_t kb = key_base(range);
   const uint64_t lt = lanemask_lt();
   s_glob[t] = hist[(size_t)t * G + blockIdx.x];
   uint32_t key[kSortIpt], val[kSortIpt];
@@ -629,7 +694,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
     for (int r = 0; r < kSortIpt; ++r) {
       const uint32_t i = t0 + (uint32_t)(w * (kSortTile / kWaves) + r * 64 + lane);
       const bool valid = i < end;
-      const uint32_t d = (key[r] >> shift) & mask;
+      const uint32_t d = ((key[r] - kb) >> shift) & mask;
       const uint64_t peers = match_digit(d, valid);
       const uint32_t below = (uint32_t)__popcll(peers & lt);
       const uint32_t old = valid ? s_cnt[w][d] : 0u;
@@ -665,7 +730,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
 #pragma unroll
     for (int r = 0; r < kSortIpt; ++r) {
       if (rank[r] != 0xffffffffu) {
-        const uint32_t d = (key[r] >> shift) & mask;
+        const uint32_t d = ((key[r] - kb) >> shift) & mask;
         const uint32_t pos = s_cnt[w][d] + rank[r];
         s_keys[pos] = key[r];
         s_vals[pos] = val[r];
@@ -675,7 +740,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep_kernel(
     const uint32_t nt = min((uint32_t)kSortTile, end - t0);
     for (uint32_t i = t; i < nt; i += kThreads) {
       const uint32_t k2 = s_keys[i];
-      const uint32_t d = (k2 >> shift) & mask;
+      const uint32_t d = ((k2 - kb) >> shift) & mask;
       const uint32_t g = s_glob[d] + (i - s_off[d]);
       if (kout) kout[g] = k2;
       vout[g] = s_vals[i];
@@ -762,15 +827,20 @@ int sort_blocks(int64_t n) { return blocks_for(n, 2 * kSortTile, kMaxSortBlocks)
 // LSD radix sort of (key, val) over bits [first_bit, bits): ping-pongs between (k0,v0) and
 // (k1,v1); the result ends in (k0,v0) when the number of passes is even, else in (k1,v1).
 // Without final_keys the last pass writes only the values (its keys are not needed).
+// With `range` (depth keys) the digits are those of key - the smallest key, and the passes
+// from bit 24 on do nothing when the keys are narrow (the result then ends in the buffers
+// of the last pass that ran).
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_ptr, uint32_t n_cap,
                       int bits, uint32_t* hist, uint64_t* partials, hipStream_t stream, int first_bit = 0,
-                      bool final_keys = true) {
+                      bool final_keys = true, const uint32_t* range = nullptr) {
   const int G = sort_blocks(n_cap);
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   for (int shift = first_bit; shift < bits; shift += kRadixBits) {
     const bool last = shift + kRadixBits >= bits;
     const int nb = min(kRadixBits, bits - shift);
-    hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, n_ptr, n_cap, shift, nb, hist, G);
+    const int skip = range && shift >= 24 ? 1 : 0;
+    hipLaunchKernelGGL(rs_upsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, n_ptr, n_cap, shift, nb, hist, G,
+                       range, skip);
     // exclusive scan of the digit-major histogram (kRadix * G values)
     const uint32_t hn = (uint32_t)(kRadix * G);
     const int Gs = scan_blocks(hn);
@@ -779,7 +849,7 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, co
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, partials, Gs, nullptr, nullptr);
     hipLaunchKernelGGL(hist_scan_down_kernel, dim3(Gs), dim3(kThreads), 0, stream, hist, hn, partials, Gs);
     hipLaunchKernelGGL(rs_downsweep_kernel, dim3(G), dim3(kThreads), 0, stream, ki, vi,
-                       (last && !final_keys) ? nullptr : ko, vo, n_ptr, n_cap, shift, nb, hist, G);
+                       (last && !final_keys) ? nullptr : ko, vo, n_ptr, n_cap, shift, nb, hist, G, range, skip);
     uint32_t* tk = ki; ki = ko; ko = tk;
     uint32_t* tv = vi; vi = vo; vo = tv;
   }
@@ -841,7 +911,6 @@ void carve_bin_ws(void* ws, int64_t pairs, BinWs* out) {
   out->dkeyB = (uint32_t*)take(p * 4);
   out->dvalB = (uint32_t*)take(p * 4);
   out->items = (uint32_t*)take(p * 16);
-  out->depth_sorted_vals = out->dvalA;
 }
 
 hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint32_t* depth, uint32_t n_pairs,
@@ -866,16 +935,20 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint
                      Gv, lm);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, stream, ptmp, Gv, ws.counters + 8,
                      ws.counters + 0);
+  // (the blocks' depth-key extremes go through the radix histogram area, free until the sort)
   hipLaunchKernelGGL(compact_kernel, dim3(Gv), dim3(kThreads), 0, stream, count, depth, n_pairs_dev, n_slots, ptmp,
-                     Gv, ws.dkeyA, ws.dvalA, lm);
+                     Gv, ws.dkeyA, ws.dvalA, lm, ws.hist);
+  hipLaunchKernelGGL(key_range_kernel, dim3(1), dim3(1024), 0, stream, ws.hist, Gv, ws.counters + kDepthRange);
   // 2. front-to-back order: 31 depth-key bits (camera z > 0)
   hipError_t e = radix_sort(ws.dkeyA, ws.dvalA, ws.dkeyB, ws.dvalB, ws.counters + 0, n_pairs, 31, ws.hist, ptmp,
-                            stream, 0, false);
+                            stream, 0, false, ws.counters + kDepthRange);
   if (e != hipSuccess) return e;
-  // 4 passes: the sorted values are back in dvalA (the sorted keys are not kept)
+  // 4 passes: the sorted values are back in dvalA (the sorted keys are not kept), or in dvalB
+  // when the fourth pass was skipped on narrow keys
   // 3. item records and tile counts in that order (counts reuse dkeyB)
   hipLaunchKernelGGL(gather_items_kernel, dim3(blocks_for(n_pairs, kThreads * 4, 8192)), dim3(kThreads), 0, stream,
-                     (const float4*)rec, ws.dvalA, ws.counters + 0, n_pairs, (uint4*)ws.items, ws.dkeyB);
+                     (const float4*)rec, ws.dvalA, ws.dvalB, ws.counters + kDepthRange, ws.counters + 0, n_pairs,
+                     (uint4*)ws.items, ws.dkeyB);
   // 4. entry offsets in that order; block offsets stay in `partials` for the emission
   const int Gc = scan_blocks(n_pairs);
   ScanSrc cnt{nullptr, ws.dkeyB};

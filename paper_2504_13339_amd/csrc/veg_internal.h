@@ -125,9 +125,10 @@ struct BinWs {
   uint32_t* partials_tmp;   // [kMaxScanBlocks] uint64: scratch for the other scans
   uint32_t* hist;       // [kRadix * kMaxHistBlocks]
   uint32_t* counters;   // [0] kept pairs V, [1..2] entries E (uint64), [3] overflow flag,
-                        // [4] entries written min(E, capacity), [8..9] V (uint64)
-  uint32_t* depth_sorted_vals;  // points at whichever of dvalA/dvalB holds the sorted result
+                        // [4] entries written min(E, capacity), [8..9] V (uint64),
+                        // [kDepthRange..+1] ~smallest and largest kept depth key
 };
+constexpr int kDepthRange = 12;
 constexpr int kMaxScanBlocks = 4096;
 constexpr int kMaxSortBlocks = 2048;
 constexpr int kMaxHistBlocks = kMaxScanBlocks > kMaxSortBlocks ? kMaxScanBlocks : kMaxSortBlocks;

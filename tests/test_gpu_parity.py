@@ -113,10 +113,12 @@ def _check_keys(w, st, frames):
     assert np.array_equal(rg, ranges)
 
 
-@pytest.mark.parametrize("case", ["c0", "c1_small", "odd_size", "large_2048x2000", "large_2064x2000"])
+@pytest.mark.parametrize("case", ["c0", "c1_small", "odd_size", "large_2048x2000", "large_2064x2000", "wide_depth"])
 def test_projection_and_key_list_bit_exact(case):
-    """Small frames, a ragged one, and two frames of 16,000 and 16,125 tiles (14-bit tile ids,
-    two tile-id passes)."""
+    """Small frames, a ragged one, two frames of 16,000 and 16,125 tiles (14-bit tile ids,
+    two tile-id passes), and cameras inside the scene's extent, whose kept depth keys span
+    more than 2^24 (every depth-key pass runs; the other scenes span less, and their key
+    lists come from the passes below bit 24 alone)."""
     if case == "c0":
         w = synth.workload(0)
     elif case == "c1_small":
@@ -125,6 +127,12 @@ def test_projection_and_key_list_bit_exact(case):
         w = synth.workload(1, n_override=20000, views_override=2, tfs_override=1, res_override=200)
         width = 2048 if case == "large_2048x2000" else 2064
         w.cameras = [synth.look_at_camera(d, 3.0, width, 2000) for d in synth.fibonacci_directions(2)]
+    elif case == "wide_depth":
+        w = synth.workload(0, n_override=3000)
+        w.cameras = [synth.look_at_camera(d, 1.0, 160, 120) for d in synth.fibonacci_directions(2)]
+        bits = [oracle.footprint_f32(w.gaussians, w.cameras[ci], w.tfs[ti], OPTS) for ci, ti in w.frames]
+        span = max(int(fp.depth_bits[fp.count > 0].max()) - int(fp.depth_bits[fp.count > 0].min()) for fp in bits)
+        assert span >= 1 << 24, span
     else:
         w = synth.workload(0, n_override=3000)
         w.cameras = [synth.look_at_camera(synth.random_direction(synth.rng_for(0, 7)), 2.5, 97, 61)]
