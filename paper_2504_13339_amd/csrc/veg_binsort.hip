@@ -2,7 +2,8 @@
 // the 2D Gaussians intersecting the screen are rasterized tile by tile, blended front to
 // back).  The key list is built depth-first:
 //   1. compact the kept (frame, Gaussian) pairs and sort them by (depth key, pair id)
-//      with a stable LSD radix sort over the 31 depth-key bits;
+//      with a stable LSD radix sort of the keys relative to the smallest kept one (three
+//      8-bit passes when they span less than 2^24, else four over the 31 key bits);
 //   2. prefix-sum their tile counts in that order and emit one (tile, pair) entry per
 //      covered tile -- so within each tile the entries are already front to back;
 //   3. stable LSD radix sort by tile id over just the bits of the largest tile id;
@@ -62,7 +63,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_tmp,
 
 // ------------------------------------------------------------------------------ scans
 // Three item kinds share the reduce-then-scan machinery:
-//   kVis : item i of the pairs, value = count[i] > 0   (compaction of kept pairs)
+//   kVis : list slot i (pair list_pair(i)), value = count of that pair > 0   (compaction)
 //   kCnt : item j of the depth-sorted kept pairs, value = its tile count   (entry offsets)
 //   kRaw : value = data[i]   (radix histogram scan)
 enum ScanKind { kVis = 0, kCnt = 1, kRaw = 2 };
@@ -71,7 +72,6 @@ struct ScanSrc {
   const uint32_t* count;   // kVis
   const uint32_t* data;    // kCnt, kRaw
 };
-
 
 // The pair slots a compaction walks.  When the frames of each view share the first frame's
 // key list (per_view frames a view), only that frame's slots can hold a kept pair: list
@@ -89,10 +89,11 @@ __device__ __forceinline__ uint32_t list_pair(uint32_t o, const ListMap& m) {
   return o + (uint32_t)q * m.skip;
 }
 
-// Depth keys relative to the smallest kept one.  The compaction leaves, in range[0..1], the
-// complement of the smallest kept depth key and the largest (two maxima, from zero).  The
-// depth passes rank key - min: the same order, and when every kept key lies within 2^24 of
-// the smallest, the last pass (bits 24-31) would leave it unchanged and is skipped.
+// Depth keys relative to the smallest kept one.  The compaction and key_range_kernel leave,
+// in range[0..1], the complement of the smallest kept depth key and the largest (two
+// maxima, from zero).  The depth passes rank key - min: the same order, and when every kept
+// key lies within 2^24 of the smallest, the last pass (bits 24-31) would leave it unchanged
+// and is skipped.
 __device__ __forceinline__ uint32_t key_base(const uint32_t* range) { return range ? ~range[0] : 0u; }
 __device__ __forceinline__ bool keys_narrow(const uint32_t* range) {
   return range && ((range[1] - ~range[0]) >> 24) == 0u;
@@ -180,10 +181,12 @@ __global__ __launch_bounds__(1024) void scan_partials_kernel(uint64_t* partials,
 }
 
 // Downsweep of the compaction: kept pair i goes to (dkey, dval)[pos] = (depth[i], i), in
-// index order (the list slots of `lm`).  A tile's items are read lane-strided (item t0 + k * 256 + thread, so every
-// load is coalesced); each wave ranks its 64 items of round k with a ballot, and the rounds'
-// and waves' kept counts are scanned in (round, wave) order -- index order -- so the kept
-// items of one wave and round land in consecutive slots and every store is contiguous.
+// index order over the list slots of `lm`.  A tile's items are read lane-strided (item
+// t0 + k * 256 + thread, so every load is coalesced); each wave ranks its 64 items of round
+// k with a ballot, and the rounds' and waves' kept counts are scanned in (round, wave) order
+// -- index order -- so the kept items of one wave and round land in consecutive slots and
+// every store is contiguous.  Each block also leaves, in block_range[2b..2b+1], the
+// complement of its smallest kept depth key and its largest (zeros without kept pairs).
 __global__ __launch_bounds__(kThreads) void compact_kernel(const uint32_t* __restrict__ count,
                                                            const uint32_t* __restrict__ depth,
                                                            const uint32_t* __restrict__ n_ptr, uint32_t n_cap,
