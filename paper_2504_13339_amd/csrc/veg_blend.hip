@@ -541,6 +541,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     }
     __syncthreads();
     // adjoint of entry k of the staged batch for this lane's four pixels (updates T, S)
+    // The first quadrant's body only yields the blend weight w and dL/dsigma (both zero
+    // where the pixel does not blend); the entry's nine sums are then written from them for
+    // every lane, which needs two zeros instead of nine before the branch.  The other
+    // quadrants add inside their bodies.
     auto entry_adjoint = [&](const int k, float (&acc)[9], bool& contrib) {
       const int jj = lo + s_pos[k];
       const float4 g = s_geo[k];
@@ -555,28 +559,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
       for (int r = 0; r < 4; ++r) {
         const float dx = (r & 1) ? dx1 : dx0, dy = (r >> 1) ? dy1 : dy0;
         const float e = exponent((r & 1) ? eb1 : eb0, (r & 1) ? q1dx1 : q1dx0, q.x, dy);
+        float w = 0.0f, dsig = 0.0f;
         if (jj <= last[r] && e >= l2min) {
           if (!kHits) contrib = true;
           const float a = __builtin_amdgcn_exp2f(e);
           const bool clamped = !(a < aclamp);
           const float alpha = __uint_as_float(min(__float_as_uint(a), aclamp_bits));   // a, aclamp > 0
           const float Tk = T[r] * __builtin_amdgcn_rcpf(1.0f - alpha);
-          const float w = alpha * Tk;
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) acc[5 + ch] = fmaf(w, gr[r][ch], acc[5 + ch]);
+          w = alpha * Tk;
           const float grgb = fmaf(gr[r][2], rgbv[2], fmaf(gr[r][1], rgbv[1], gr[r][0] * rgbv[0]));
           const float dalpha = grgb - GS[r];
           GS[r] = fmaf(alpha, dalpha, GS[r]);
           T[r] = Tk;
           // dL/dsigma = -dL/dalpha * a = -(dalpha Tk) a, and unclamped a Tk is w
-          const float dsig = clamped ? 0.0f : -(dalpha * w);
+          dsig = clamped ? 0.0f : -(dalpha * w);
+          if (r > 0) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) acc[5 + ch] = fmaf(w, gr[r][ch], acc[5 + ch]);
+            const float u = dsig * dx, v = dsig * dy;
+            acc[0] += u;
+            acc[1] += v;
+            acc[2] = fmaf(u, dx, acc[2]);
+            acc[3] = fmaf(u, dy, acc[3]);
+            acc[4] = fmaf(v, dy, acc[4]);
+            acc[8] += dsig;
+          }
+        }
+        if (r == 0) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) acc[5 + ch] = w * gr[0][ch];
           const float u = dsig * dx, v = dsig * dy;
-          acc[0] += u;
-          acc[1] += v;
-          acc[2] = fmaf(u, dx, acc[2]);
-          acc[3] = fmaf(u, dy, acc[3]);
-          acc[4] = fmaf(v, dy, acc[4]);
-          acc[8] += dsig;
+          acc[0] = u;
+          acc[1] = v;
+          acc[2] = u * dx;
+          acc[3] = u * dy;
+          acc[4] = v * dy;
+          acc[8] = dsig;
         }
       }
     };
@@ -586,11 +604,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
       const int kb = has_b ? ka - 1 : ka;
       // acc: 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 R, 6 G, 7 B, 8 S_d
       float acc_a[9], acc_b[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) acc_a[c] = acc_b[c] = 0.0f;
       bool con_a = false, con_b = false;
       entry_adjoint(ka, acc_a, con_a);
-      if (has_b) entry_adjoint(kb, acc_b, con_b);
+      if (has_b) {
+        entry_adjoint(kb, acc_b, con_b);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc_b[c] = 0.0f;
+      }
       // an entry with a hit bit is blended in some pixel of the tile (the backward's test is
       // the forward's), so only without hit bits can a pair contribute nothing
       if (!kHits && __ballot(con_a || con_b) == 0ull) continue;
