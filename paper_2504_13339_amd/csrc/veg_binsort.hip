@@ -774,16 +774,23 @@ __global__ void status_kernel(const uint32_t* __restrict__ counters, int64_t* __
 }
 
 // Per-tile [start, end) from the boundaries of the sorted keys; each thread takes 4
-// consecutive keys (one vector load) and compares with its neighbours.
+// consecutive keys (one vector load) and compares them with its neighbours', which come
+// from the adjacent lanes (the wave's edge lanes load theirs).
 __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ e_ptr, uint32_t capacity,
                                                           uint32_t* __restrict__ ranges) {
   const uint32_t E = read_count(e_ptr, capacity);
   const uint32_t nq = (E + 3) / 4;
-  for (uint32_t q = blockIdx.x * kThreads + threadIdx.x; q < nq; q += gridDim.x * kThreads) {
+  const int lane = threadIdx.x & 63;
+  // the loop runs the same number of times in every lane of a wave, so the shuffles see
+  // their neighbours (lanes past the end carry sentinels)
+  const uint32_t stride = gridDim.x * kThreads;
+  const uint32_t q0 = blockIdx.x * kThreads + threadIdx.x;
+  const uint32_t wave_q0 = q0 - (uint32_t)lane;
+  for (uint32_t wq = wave_q0; wq < nq; wq += stride) {
+    const uint32_t q = wq + (uint32_t)lane;
     const uint32_t j0 = 4 * q;
     uint32_t k[6];
-    k[0] = j0 > 0 ? keys[j0 - 1] : 0xffffffffu;
     if (j0 + 3 < E) {
       const uint4 v = *reinterpret_cast<const uint4*>(keys + j0);
       k[1] = v.x; k[2] = v.y; k[3] = v.z; k[4] = v.w;
@@ -791,7 +798,10 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __rest
 #pragma unroll
       for (int i = 0; i < 4; ++i) k[1 + i] = j0 + i < E ? keys[j0 + i] : 0xffffffffu;
     }
-    k[5] = j0 + 4 < E ? keys[j0 + 4] : 0xffffffffu;
+    const uint32_t up = (uint32_t)__shfl_up((int)k[4], 1);     // lane - 1's last key
+    const uint32_t down = (uint32_t)__shfl_down((int)k[1], 1);   // lane + 1's first key
+    k[0] = lane > 0 ? up : (j0 > 0 && j0 - 1 < E ? keys[j0 - 1] : 0xffffffffu);
+    k[5] = lane < 63 ? (j0 + 4 < E ? down : 0xffffffffu) : (j0 + 4 < E ? keys[j0 + 4] : 0xffffffffu);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t j = j0 + i;
