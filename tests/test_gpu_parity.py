@@ -6,6 +6,8 @@ per-tile ranges) bit-exact against the oracle's float32 footprint mirror; images
 decision-margin flag; gradients within 1e-3 relative (max-abs error over max-abs value,
 per parameter tensor) of the oracle's float64 autograd adjoint.
 """
+import types
+
 import numpy as np
 import pytest
 import torch
@@ -277,6 +279,21 @@ def test_gaussian_larger_than_the_image():
     assert st.proj.count.cpu().numpy()[0] == 5 * 3
     res, *_ = oracle.render_image(g, cam, lut, OPTS)
     compare_image(image_pixels(st.image[0]), res)
+
+
+def test_key_list_with_tile_rows_wider_than_a_digit():
+    """A 4160-pixel-wide frame (260 tile columns, 780 tiles, so the first tile-id pass takes 8
+    bits) with a Gaussian whose footprint covers every column: its tile rows hold more tiles
+    than a digit has values, which the emission's digit histogram counts as whole turns of
+    the 256 bins.  Key list and ranges bit for bit against the oracle."""
+    g, cam, lut = _tiny([[0, 0, 0], [0.5, 0, 0], [-1.0, 0.1, 0]], [[150.0, 0.3, 1.0], [0.05] * 3, [0.2, 0.1, 0.1]],
+                        [0.9, 0.6, 0.7], W=4160, H=40)
+    fp = oracle.footprint_f32(g, cam, lut, OPTS)
+    assert fp.rect[0, 2] - fp.rect[0, 0] + 1 >= 256
+    w = types.SimpleNamespace(gaussians=g, cameras=[cam], tfs=[lut])
+    _, st = _run(g, [cam], [lut])
+    _check_footprint(w, st, [(0, 0)])
+    _check_keys(w, st, [(0, 0)])
 
 
 # ----------------------------------------------------------------------------- backward
