@@ -296,6 +296,33 @@ def test_key_list_with_tile_rows_wider_than_a_digit():
     _check_keys(w, st, [(0, 0)])
 
 
+@pytest.mark.parametrize("W,H", [(1, 1), (300, 1), (1, 200)])
+def test_degenerate_frame_shapes(W, H):
+    """Frames of one pixel, one row and one column (a single tile, or one row or column of
+    mostly empty tiles): footprints, key list and ranges bit for bit, every pixel of the image
+    and the gradients of the screen-space quantities and of the parameters against the
+    oracle.  The single pixel reaches the transmittance stop."""
+    w = synth.workload(0, n_override=3000)
+    w.cameras = [synth.look_at_camera(synth.fibonacci_directions(2)[0], 2.5, W, H)]
+    w.tfs = w.tfs[:1]
+    _, st = _run(w.gaussians, w.cameras, w.tfs)
+    _check_footprint(w, st, [(0, 0)])
+    _check_keys(w, st, [(0, 0)])
+    d = np.random.default_rng(23).standard_normal((W * H, 3))
+    st, grads, g2d, ref = _grads_case(w, d)
+    res, *_ = _frame_result(w, 0, 0)
+    compare_image(image_pixels(st.image[0]), res)
+    n = w.gaussians.n
+    g2 = g2d.cpu().numpy().reshape(-1, 9)[:n].T
+    assert np.abs(ref.d_rgb).max() > 0.0
+    assert rel_err(g2[0:2].T, ref.d_mean2d) <= 1e-3
+    assert rel_err(g2[2:5].T, ref.d_conic) <= 1e-3
+    assert rel_err(g2[5:8].T, ref.d_rgb) <= 1e-3
+    assert rel_err(g2[8], ref.d_A) <= 1e-3
+    for name in ("d_means", "d_log_scales", "d_quats", "d_scalars"):
+        assert rel_err(getattr(grads, name).cpu().numpy(), getattr(ref, name)) <= 1e-3, name
+
+
 # ----------------------------------------------------------------------------- backward
 
 def _grads_case(w, d, ci=0, ti=0):
