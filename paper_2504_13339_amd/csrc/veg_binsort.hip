@@ -282,7 +282,11 @@ __global__ __launch_bounds__(1024) void key_range_kernel(const uint32_t* __restr
 
 // After the depth sort: one gather per kept pair, in front-to-back order, of what the
 // count scan and the emission need (pair id, tile rectangle, frame) and of its tile count,
-// so both later passes read sequentially.
+// so both later passes read sequentially.  The record reads land at random addresses, so
+// each thread takes kGatherIpt items a round (block-strided, coalesced for the sequential
+// arrays) and issues all their loads before using any.
+constexpr int kGatherIpt = 4;
+
 __global__ __launch_bounds__(kThreads) void gather_items_kernel(const float4* __restrict__ rec,
                                                                 const uint32_t* __restrict__ vals_a,
                                                                 const uint32_t* __restrict__ vals_b,
@@ -292,12 +296,30 @@ __global__ __launch_bounds__(kThreads) void gather_items_kernel(const float4* __
                                                                 uint32_t* __restrict__ counts) {
   const uint32_t n = read_count(v_ptr, v_cap);
   const uint32_t* __restrict__ sorted_vals = keys_narrow(range) ? vals_b : vals_a;   // where the depth sort ended
-  for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < n; j += gridDim.x * kThreads) {
-    const uint32_t p = sorted_vals[j];
-    const float4 r2 = rec[3 * (size_t)p + 2];
-    const uint32_t a = __float_as_uint(r2.y), b = __float_as_uint(r2.z);
-    items[j] = make_uint4(p, a, b, __float_as_uint(r2.w) & kFrameMask);
-    counts[j] = ((b & 0xffffu) - (a & 0xffffu) + 1u) * ((b >> 16) - (a >> 16) + 1u);
+  const uint32_t step = gridDim.x * kThreads * kGatherIpt;
+  for (uint32_t j0 = blockIdx.x * kThreads * kGatherIpt + threadIdx.x; j0 < n; j0 += step) {
+    uint32_t p[kGatherIpt];
+    float4 r2[kGatherIpt];
+    // indices past the end repeat the last item (j0 < n), so every load is unconditional
+#pragma unroll
+    for (int u = 0; u < kGatherIpt; ++u) p[u] = sorted_vals[min(j0 + u * kThreads, n - 1u)];
+#pragma unroll
+    for (int u = 0; u < kGatherIpt; ++u) r2[u] = rec[3 * (size_t)p[u] + 2];
+    auto put = [&](int u, uint32_t j) {
+      const uint32_t a = __float_as_uint(r2[u].y), b = __float_as_uint(r2[u].z);
+      items[j] = make_uint4(p[u], a, b, __float_as_uint(r2[u].w) & kFrameMask);
+      counts[j] = ((b & 0xffffu) - (a & 0xffffu) + 1u) * ((b >> 16) - (a >> 16) + 1u);
+    };
+    // a block's whole round in range (all but the last) stores without per-lane tests, which
+    // keeps the compiler from sinking loads into them
+    if (j0 - threadIdx.x + kThreads * kGatherIpt <= n) {
+#pragma unroll
+      for (int u = 0; u < kGatherIpt; ++u) put(u, j0 + u * kThreads);
+    } else {
+#pragma unroll
+      for (int u = 0; u < kGatherIpt; ++u)
+        if (j0 + u * kThreads < n) put(u, j0 + u * kThreads);
+    }
   }
 }
 
@@ -959,7 +981,7 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* count, const uint
   // 4 passes: the sorted values are back in dvalA (the sorted keys are not kept), or in dvalB
   // when the fourth pass was skipped on narrow keys
   // 3. item records and tile counts in that order (counts reuse dkeyB)
-  hipLaunchKernelGGL(gather_items_kernel, dim3(blocks_for(n_pairs, kThreads * 4, 8192)), dim3(kThreads), 0, stream,
+  hipLaunchKernelGGL(gather_items_kernel, dim3(blocks_for(n_pairs, kThreads * kGatherIpt, 8192)), dim3(kThreads), 0, stream,
                      (const float4*)rec, ws.dvalA, ws.dvalB, ws.counters + kDepthRange, ws.counters + 0, n_pairs,
                      (uint4*)ws.items, ws.dkeyB);
   // 4. entry offsets in that order; block offsets stay in `partials` for the emission
